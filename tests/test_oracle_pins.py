@@ -1,0 +1,269 @@
+"""Pins of the CPU oracle to values fixed by the paper and by mathematics.
+
+Nothing here runs on the GPU. Each test names the passage or fact it checks.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2605_03603_amd import generators as G
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def C3(n):
+    return math.comb(n, 3)
+
+
+# ------------------------------------------------------------- figure pins
+def test_fig2_butterfly_balance(oracle):
+    for case in load("fig2_butterflies.json")["cases"]:
+        assert oracle.butterfly_balanced(*case["signs"]) == case["balanced"], case["label"]
+
+
+def test_fig3b_wedge_types(oracle):
+    for case in load("fig3b_wedge_types.json")["cases"]:
+        assert oracle.wedge_type(*case["signs"]) == case["type"], case["label"]
+        # negating every sign does not change the type (it compares signs)
+        assert oracle.wedge_type(*[-s for s in case["signs"]]) == case["type"]
+
+
+def test_fig1b_signed_k44(oracle):
+    fx = load("fig1b.json")
+    g = G.from_rows(fx["rows"])
+    total, pu, pv = oracle.count_bruteforce(g, per_vertex=True)
+    assert total == fx["balanced_33"]
+    assert list(pu) == fx["per_u"] and list(pv) == fx["per_v"]
+    for side, key in ((0, "per_u"), (1, "per_v")):
+        r = oracle.count_bbvp(g, side=side, per_vertex=True)
+        assert r["total"] == fx["balanced_33"]
+        assert list(r["per_vertex"]) == fx[key]
+    unsigned = G.from_rows(["++++"] * 4)
+    assert oracle.count_bruteforce(unsigned) == fx["unsigned_33"]
+    assert oracle.count_bbvp(unsigned)["total"] == fx["unsigned_33"]
+
+
+def _fig4_graph(fx, signs=None):
+    us = sorted(fx["adjacency"])
+    vs = sorted({v for lst in fx["adjacency"].values() for v in lst})
+    eu, ev = [], []
+    for u in us:
+        for v in fx["adjacency"][u]:
+            eu.append(us.index(u)); ev.append(vs.index(v))
+    s = np.ones(len(eu), np.int8) if signs is None else np.asarray(signs, np.int8)
+    return G._finish(len(us), len(vs), np.array(eu), np.array(ev), s), us, vs
+
+
+def test_fig4_worked_example(oracle):
+    fx = load("fig4.json")
+    g, us, vs = _fig4_graph(fx)
+    a = us.index(fx["anchor"])
+    # the figure takes u1 as the anchor with every other U vertex as partner
+    d = oracle.anchor_detail(g, side=0, u=a, oriented=False)
+    assert sorted(us[c] for c in d["candidates"]) == fx["candidate_set"]
+    assert len(d["pairs"]) == fx["triplets"]
+    for (w1, w2, size_t, *x) in d["pairs"]:
+        key = ",".join(sorted([us[w1], us[w2]]))
+        assert size_t == fx["wedge_pair_counts"][key]
+        trip = ",".join(sorted([fx["anchor"], us[w1], us[w2]]))
+        assert size_t == len(fx["common_neighbours"][trip])
+        assert sum(x) == size_t
+    # wedges from the anchor as Algorithm 1 would enumerate them
+    adj = fx["adjacency"]
+    wedges = sum(math.comb(sum(1 for u in us if v in adj[u] and u != fx["anchor"]), 2)
+                 for v in adj[fx["anchor"]])
+    assert wedges == fx["wedges_from_anchor"]
+    # zero balanced (3,3)-bicliques for every one of the 2^12 sign assignments
+    m = g.m
+    for bits in range(1 << m):
+        s = [1 if (bits >> i) & 1 else -1 for i in range(m)]
+        gs, _, _ = _fig4_graph(fx, s)
+        assert oracle.count_bruteforce(gs) == fx["balanced_33"]
+        if bits % 97 == 0:
+            assert oracle.count_bbvp(gs)["total"] == 0
+            assert oracle.count_bbvp(gs, side=1)["total"] == 0
+
+
+# ------------------------------------------------------------ closed forms
+def complete(n, m, sign_fn):
+    rows = ["".join("+" if sign_fn(i, j) > 0 else "-" for j in range(m)) for i in range(n)]
+    return G.from_rows(rows)
+
+
+@pytest.mark.parametrize("n,m", [(3, 3), (4, 5), (6, 4), (7, 7), (3, 9)])
+def test_complete_all_positive(oracle, n, m):
+    """All-positive K_{n,m}: every (3,3)-biclique is balanced: C(n,3) C(m,3)."""
+    g = complete(n, m, lambda i, j: 1)
+    want = C3(n) * C3(m)
+    assert oracle.count_bruteforce(g) == want
+    r0 = oracle.count_bbvp(g, 0, per_vertex=True)
+    r1 = oracle.count_bbvp(g, 1, per_vertex=True)
+    assert r0["total"] == r1["total"] == want
+    # each U vertex lies in C(n-1,2) C(m,3) of them
+    assert list(r0["per_vertex"]) == [math.comb(n - 1, 2) * C3(m)] * n
+    assert list(r1["per_vertex"]) == [math.comb(m - 1, 2) * C3(n)] * m
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_rank_one_signs(oracle, seed):
+    """Signs a(u) b(v) are a vertex switching of all-positive: same count."""
+    rng = np.random.default_rng(seed)
+    n, m = int(rng.integers(3, 9)), int(rng.integers(3, 9))
+    a = rng.choice([-1, 1], n); b = rng.choice([-1, 1], m)
+    g = complete(n, m, lambda i, j: a[i] * b[j])
+    assert oracle.count_bbvp(g, 0)["total"] == C3(n) * C3(m)
+    assert oracle.count_bruteforce(g) == C3(n) * C3(m)
+
+
+@pytest.mark.parametrize("n1,n2,m1,m2", [(3, 4, 4, 3), (2, 5, 3, 3), (4, 4, 5, 2), (1, 6, 6, 1), (5, 3, 3, 5)])
+def test_two_block_closed_form(oracle, n1, n2, m1, m2):
+    """K_{n,m} with U = U1+U2, V = V1+V2 and sign -1 exactly on U2 x V2.
+    Triples inside U1 or inside U2 have identical rows: any 3 columns.
+    Mixed triples have rows equal on V1 and opposite on V2: columns all in V1
+    or all in V2."""
+    n, m = n1 + n2, m1 + m2
+    g = complete(n, m, lambda i, j: -1 if (i >= n1 and j >= m1) else 1)
+    pure = C3(n1) + C3(n2)
+    want = pure * C3(m) + (C3(n) - pure) * (C3(m1) + C3(m2))
+    if n1 == 3 and n2 == 4 and m1 == 4 and m2 == 3:
+        assert want == 325
+    assert oracle.count_bruteforce(g) == want
+    assert oracle.count_bbvp(g, 0)["total"] == want
+    assert oracle.count_bbvp(g, 1)["total"] == want
+
+
+def test_disjoint_planted_blocks_additive(oracle):
+    """Disjoint complete blocks with rank-1 signs on an empty graph:
+    sum of C(k,3) C(k',3) (6x6: 400, 12x12: 48400, 5x5: 100)."""
+    rng = np.random.default_rng(7)
+    sizes = [(6, 6), (12, 12), (5, 5), (3, 4)]
+    n_u = sum(a for a, _ in sizes) + 5
+    n_v = sum(b for _, b in sizes) + 3
+    u, v, s, _ = G.plant_blocks(rng, n_u, n_v, np.zeros(0, np.int64), np.zeros(0, np.int64),
+                                np.zeros(0, np.int8), [(a, b, "balanced") for a, b in sizes])
+    g = G._finish(n_u, n_v, u, v, s)
+    want = sum(C3(a) * C3(b) for a, b in sizes)
+    assert [C3(6) * C3(6), C3(12) * C3(12), C3(5) * C3(5)] == [400, 48400, 100]
+    assert oracle.count_bbvp(g, 0)["total"] == want
+    assert oracle.count_bbvp(g, 1)["total"] == want
+
+
+def test_choose3_exact(oracle):
+    for n in list(range(0, 40)) + [2642245, 2642246, 10**6]:
+        assert oracle.choose3(n) == C3(n)
+
+
+# ----------------------------------------- brute force on random tiny graphs
+def test_bruteforce_equals_bbvp_tiny(oracle):
+    """O1 (definition) = O2 (Algorithm 2 on U) = O3 (on V), totals and every
+    per-vertex count, on random tiny graphs of all densities and sign mixes."""
+    rng = np.random.default_rng(2026)
+    nonzero = 0
+    for it in range(3000):
+        g = G.tiny_random(rng, 8, 8)
+        b, pu, pv = oracle.count_bruteforce(g, per_vertex=True)
+        r0 = oracle.count_bbvp(g, 0, per_vertex=True)
+        r1 = oracle.count_bbvp(g, 1, per_vertex=True)
+        assert r0["total"] == b and r1["total"] == b, it
+        assert (r0["per_vertex"] == pu).all() and (r1["per_vertex"] == pv).all(), it
+        assert int(pu.sum()) == 3 * b and int(pv.sum()) == 3 * b
+        nonzero += b > 0
+    assert nonzero > 300
+
+
+def test_bruteforce_equals_bbvp_denser(oracle):
+    rng = np.random.default_rng(99)
+    for it in range(60):
+        g = G.tiny_random(rng, 11, 11, density=float(rng.choice([0.7, 0.85, 1.0])))
+        b = oracle.count_bruteforce(g)
+        assert oracle.count_bbvp(g, 0)["total"] == b
+        assert oracle.count_bbvp(g, 1)["total"] == b
+
+
+def test_vertex_counts_match_per_vertex(oracle):
+    g = G.config1(3)
+    for side in (0, 1):
+        r = oracle.count_bbvp(g, side, per_vertex=True)
+        n = g.n_u if side == 0 else g.n_v
+        xs = list(range(0, n, 7))
+        assert oracle.vertex_counts(g, side, xs) == [int(r["per_vertex"][x]) for x in xs]
+        assert int(r["per_vertex"].sum()) == 3 * r["total"]
+
+
+# --------------------------------------------------------------- invariants
+def _switch(g, rng):
+    fu = rng.choice([-1, 1], g.n_u).astype(np.int8)
+    fv = rng.choice([-1, 1], g.n_v).astype(np.int8)
+    return G._finish(g.n_u, g.n_v, g.eu, g.ev, (g.sign * fu[g.eu] * fv[g.ev]).astype(np.int8))
+
+
+def _relabel(g, rng):
+    pu = rng.permutation(g.n_u); pv = rng.permutation(g.n_v)
+    order = rng.permutation(g.m)
+    return G._finish(g.n_u, g.n_v, pu[g.eu][order], pv[g.ev][order], g.sign[order]), pu, pv
+
+
+@pytest.mark.parametrize("maker", ["config1", "config2_small"])
+def test_invariants(oracle, maker):
+    g = G.config1(1) if maker == "config1" else G.config2(1, scale=0.02)
+    rng = np.random.default_rng(5)
+    base = oracle.count_bbvp(g, 0, threads=4, per_vertex=True)
+    B = base["total"]
+    assert B > 0
+    # U <-> V transpose
+    assert oracle.count_bbvp(g, 1, threads=4)["total"] == B
+    assert oracle.count_bbvp(g.transpose(), 0, threads=4)["total"] == B
+    # vertex switching (any set of vertices) and global negation
+    sw = _switch(g, rng)
+    r = oracle.count_bbvp(sw, 0, threads=4, per_vertex=True)
+    assert r["total"] == B and (r["per_vertex"] == base["per_vertex"]).all()
+    neg = G._finish(g.n_u, g.n_v, g.eu, g.ev, (-g.sign).astype(np.int8))
+    assert oracle.count_bbvp(neg, 0, threads=4)["total"] == B
+    # relabelling vertices and reordering the edge list
+    rl, pu, pv = _relabel(g, rng)
+    r = oracle.count_bbvp(rl, 0, threads=4, per_vertex=True)
+    assert r["total"] == B
+    assert (r["per_vertex"][pu] == base["per_vertex"]).all()
+    # inserting an edge never lowers the count
+    present = set(zip(g.eu.tolist(), g.ev.tolist()))
+    for _ in range(3):
+        while True:
+            a, b = int(rng.integers(g.n_u)), int(rng.integers(g.n_v))
+            if (a, b) not in present:
+                break
+        g2 = G._finish(g.n_u, g.n_v, np.append(g.eu, a), np.append(g.ev, b),
+                       np.append(g.sign, np.int8(rng.choice([-1, 1]))))
+        assert oracle.count_bbvp(g2, 0, threads=4)["total"] >= B
+    # the planted balanced blocks alone give a lower bound
+    if maker == "config1":
+        assert B >= 3 * C3(6) * C3(6)
+
+
+def test_config3_switching_reduction(oracle):
+    """Signs l(u) l(v) flip are a switching of the flip signs alone."""
+    g = G.config3(1, scale=0.0005)
+    lu, lv = g.meta["label_u"], g.meta["label_v"]
+    unsw = G._finish(g.n_u, g.n_v, g.eu, g.ev, (g.sign * lu[g.eu] * lv[g.ev]).astype(np.int8))
+    assert oracle.count_bbvp(g, 0, threads=4)["total"] == oracle.count_bbvp(unsw, 0, threads=4)["total"]
+
+
+def test_bad_edges_rejected(oracle):
+    g = G.from_rows(["++", "+-"])
+    dup = G._finish(2, 2, np.array([0, 0]), np.array([1, 1]), np.array([1, 1], np.int8))
+    with pytest.raises(ValueError):
+        oracle.count_bbvp(dup)
+    oob = G._finish(2, 2, np.array([0, 2]), np.array([1, 1]), np.array([1, 1], np.int8))
+    with pytest.raises(ValueError):
+        oracle.count_bbvp(oob)
+    assert oracle.count_bbvp(g)["total"] == 0
+    empty = G._finish(0, 0, np.zeros(0), np.zeros(0), np.zeros(0, np.int8))
+    assert oracle.count_bbvp(empty)["total"] == 0
