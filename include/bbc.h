@@ -1,0 +1,168 @@
+/*
+ * bbc.h -- C ABI of libbbc: exact counting of balanced (3,3)-bicliques in
+ * signed bipartite graphs on an AMD MI355X (gfx950) GPU.
+ *
+ * Problem (Section 3 of "Counting Small Balanced (p,q)-bicliques in Signed
+ * Bipartite Graphs", arXiv 2605.03603): G = (U, V, E) with E a subset of
+ * U x V and a sign +1 or -1 on every edge. A (p,q)-biclique (L, R) has
+ * |L| = p vertices of one side and |R| = q of the other, all p*q edges
+ * present; it is balanced when none of its butterflies (2x2 sub-bicliques)
+ * has an odd number of negative edges (Section 1, Fig. 2). The library
+ * returns the number of balanced (3,3)-bicliques. p = q = 3 is the only
+ * supported pair.
+ *
+ * Method (Section 4, Lemma 1 and Algorithm 2): every same-side triple
+ * {u1,u2,u3} is visited once, from its lowest-priority vertex (priority:
+ * higher degree first, ties by the larger id; Definition 4.1); each common
+ * neighbour v is put in one of 4 classes by (s(u1,v)s(u2,v), s(u1,v)s(u3,v));
+ * the triple adds sum over classes of C(n_class, 3).
+ *
+ * Conventions for every call:
+ *   - Every call returns a bbc_status; out-parameters are written only on
+ *     BBC_OK.
+ *   - Input arrays are borrowed for the duration of the call; the library
+ *     copies what it keeps. With BBC_IN_DEVICE_PTRS they are device pointers
+ *     on the context's device, otherwise host pointers.
+ *   - Validation errors are reported before any count is produced. A HIP
+ *     runtime failure returns BBC_E_HIP and bbc_last_error() holds the detail.
+ *   - A context is used by one thread at a time, except bbc_submit*,
+ *     bbc_poll and bbc_wait, which may be called from any thread.
+ *   - Degenerate inputs (fewer than 3 vertices on a side, no edges, isolated
+ *     vertices) are valid and count 0.
+ */
+#ifndef BBC_H
+#define BBC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BBC_OK = 0,
+    BBC_E_INVAL = 1,         /* null pointer, bad flag combination or size */
+    BBC_E_RANGE = 2,         /* an edge endpoint u >= n_u or v >= n_v */
+    BBC_E_SIGN = 3,          /* a sign that is not +1 / -1 (or 1 / 0 with BBC_SIGNS_01) */
+    BBC_E_DUP_EDGE = 4,      /* the same (u, v) pair twice (E is a set) */
+    BBC_E_NOMEM = 5,         /* device memory, or the context's memory cap */
+    BBC_E_OVERFLOW = 6,      /* a count does not fit in int64 */
+    BBC_E_UNSUPPORTED = 7,   /* (p, q) other than (3, 3) */
+    BBC_E_NOT_READY = 8,     /* bbc_poll: the request is still queued or running */
+    BBC_E_UNKNOWN_TICKET = 9,
+    BBC_E_HIP = 10           /* HIP runtime error; see bbc_last_error */
+} bbc_status;
+
+typedef struct bbc_ctx bbc_ctx;
+typedef struct bbc_graph bbc_graph;
+typedef uint64_t bbc_ticket;
+
+/* Flags of bbc_build_csr / bbc_build_csr_batch / bbc_submit_coo. */
+#define BBC_IN_DEVICE_PTRS    (1u << 0)  /* eu, ev, sign are device pointers */
+#define BBC_SIGNS_2BIT_PACKED (1u << 1)  /* sign holds 2-bit codes, 4 per byte, edge e in
+                                            bits 2*(e%4)..: 01 = +1, 11 = -1 (00, 10 invalid) */
+#define BBC_SIGNS_01          (1u << 2)  /* int8 signs 1 = +, 0 = - (the paper's dataset
+                                            encoding, Section 5) instead of +1 / -1 */
+#define BBC_ANCHOR_U          (1u << 4)  /* anchor triples on U (default: chosen per graph
+                                            from degree statistics) */
+#define BBC_ANCHOR_V          (1u << 5)  /* anchor triples on V */
+#define BBC_ANCHOR_SMALLER    (1u << 6)  /* the paper's rule: the smaller side */
+
+/* Context on one device. hip_stream: a hipStream_t to run on (e.g. torch's
+ * current stream), or NULL for a stream the context creates. mem_cap_bytes
+ * bounds the device memory the context allocates (0 = no cap); exceeding it
+ * returns BBC_E_NOMEM. */
+bbc_status bbc_ctx_create(int device, void *hip_stream, uint64_t mem_cap_bytes, bbc_ctx **out);
+/* Destroys the context and every graph, request and buffer it owns. */
+void bbc_ctx_destroy(bbc_ctx *ctx);
+
+/* Validate a COO edge list and build the device CSR of one graph (Section 3
+ * input model; degree ordering of Definition 4.1).
+ *   eu[e] < n_u, ev[e] < n_v (uint32), sign[e] per flags; n_edges edges.
+ * The graph stays resident on the device and is owned by the context until
+ * bbc_graph_free. Errors: BBC_E_INVAL, BBC_E_RANGE, BBC_E_SIGN,
+ * BBC_E_DUP_EDGE, BBC_E_NOMEM, BBC_E_HIP. */
+bbc_status bbc_build_csr(bbc_ctx *ctx, uint32_t n_u, uint32_t n_v, uint64_t n_edges,
+                         const uint32_t *eu, const uint32_t *ev, const void *sign,
+                         uint32_t flags, bbc_graph **out);
+
+/* Build n_graphs graphs from one concatenated COO in a single device pass.
+ *   n_u[i], n_v[i]: host arrays; edge_offsets: host array of n_graphs+1
+ *   offsets into eu/ev/sign (graph i owns edges [edge_offsets[i],
+ *   edge_offsets[i+1])), vertex ids local to each graph.
+ * out_graphs receives n_graphs handles sharing one device allocation (freed
+ * when the last of them is freed). On error no handle is returned; the
+ * status is the first error found over all graphs. */
+bbc_status bbc_build_csr_batch(bbc_ctx *ctx, uint32_t n_graphs, const uint32_t *n_u,
+                               const uint32_t *n_v, const uint64_t *edge_offsets,
+                               const uint32_t *eu, const uint32_t *ev, const void *sign,
+                               uint32_t flags, bbc_graph **out_graphs);
+
+bbc_status bbc_graph_free(bbc_ctx *ctx, bbc_graph *g);
+
+typedef struct {
+    uint32_t n_u, n_v;
+    uint64_t n_edges;
+    int32_t anchor_side;      /* 0 = U, 1 = V */
+    uint64_t device_bytes;    /* CSR footprint on the device */
+} bbc_graph_info;
+bbc_status bbc_get_graph_info(bbc_ctx *ctx, const bbc_graph *g, bbc_graph_info *out);
+
+/* Number of balanced (p,q)-bicliques of g (Problem statement, Section 3),
+ * for p = q = 3. out_count: host int64. Errors: BBC_E_UNSUPPORTED,
+ * BBC_E_OVERFLOW, BBC_E_NOMEM, BBC_E_HIP. */
+bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int64_t *out_count);
+
+/* Per-vertex counts: out_per_vertex[x] (caller-owned, n_u or n_v int64
+ * entries, host memory) = number of balanced (3,3)-bicliques that contain
+ * vertex x of the requested side (0 = U, 1 = V); their sum is 3 * count.
+ * out_count (optional) receives the global count. The triples are anchored
+ * on the requested side for this call. */
+bbc_status bbc_count_per_vertex(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int side,
+                                int64_t *out_per_vertex, int64_t *out_count);
+
+/* Count many graphs in one persistent launch (replayed from a captured HIP
+ * graph when the same set of graphs is counted again). out_counts: host
+ * int64[n_graphs]. */
+bbc_status bbc_count_batch(bbc_ctx *ctx, const bbc_graph *const *graphs, uint32_t n_graphs,
+                           int64_t *out_counts);
+
+/* Serving: queue a count request and return at once. A scheduler thread
+ * admits queued requests while their device footprint fits under the
+ * context's memory cap, batches every admitted request into the next launch
+ * and overlaps launches on several streams (continuous batching).
+ *   bbc_submit: a graph already built (it must stay alive until the result
+ *     has been polled).
+ *   bbc_submit_coo: a COO edge list (host pointers, copied before return);
+ *     the scheduler builds and frees its CSR.
+ * A result is independent of the other requests in flight. */
+bbc_status bbc_submit(bbc_ctx *ctx, const bbc_graph *g, bbc_ticket *out);
+bbc_status bbc_submit_coo(bbc_ctx *ctx, uint32_t n_u, uint32_t n_v, uint64_t n_edges,
+                          const uint32_t *eu, const uint32_t *ev, const void *sign,
+                          uint32_t flags, bbc_ticket *out);
+/* BBC_OK with the count (the ticket is then retired), BBC_E_NOT_READY, the
+ * request's own error (ticket retired), or BBC_E_UNKNOWN_TICKET. */
+bbc_status bbc_poll(bbc_ctx *ctx, bbc_ticket t, int64_t *out_count);
+/* Blocks until the request is done; same results as bbc_poll otherwise. */
+bbc_status bbc_wait(bbc_ctx *ctx, bbc_ticket t, int64_t *out_count);
+
+/* Statistics of the last count on this context (for measurement). */
+typedef struct {
+    uint64_t active_anchors;    /* anchors with at least two candidate classes */
+    uint64_t virtual_candidates;/* (partner, sign class) pairs with >= 3 shared neighbours */
+    uint64_t pair_units;        /* triplet-kernel work units */
+    uint64_t candidate_pairs;   /* pairs of candidate classes examined */
+    uint64_t mask_words;        /* 32-bit mask words written by the pair-table kernel */
+    uint64_t wedges;            /* 2-hop wedges scanned (oriented, pruned) */
+} bbc_count_stats;
+bbc_status bbc_get_last_stats(bbc_ctx *ctx, bbc_count_stats *out);
+
+const char *bbc_status_string(bbc_status s);
+/* Detail of the last error on this context (empty string if none). */
+const char *bbc_last_error(bbc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BBC_H */

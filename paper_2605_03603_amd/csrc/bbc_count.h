@@ -1,0 +1,36 @@
+// bbc_count.h -- arguments of the counting kernels (internal).
+#pragma once
+
+#include "bbc_dev.h"
+
+namespace bbc {
+
+struct PairArgs {
+    CsrView g;
+    Workspace ws;
+    uint32_t a0, a1;        // anchor range (global ranks) of the first tier
+    int tier;               // 0: LDS 4096-slot tables, 1: LDS 16384, 2: global tables
+    uint32_t chunk_base;    // triplet unit width in columns for 1-word masks (<= 2048)
+    uint32_t gH;            // tier-2 table slots (power of two)
+    int glog2h;
+    uint32_t gmaxd, gkmax;  // tier-2 limits
+};
+
+struct TriArgs {
+    CsrView g;
+    Workspace ws;
+};
+
+struct LaunchShape {
+    uint32_t grid_a, grid_b, grid_c, grid_t;
+};
+
+hipError_t count_pairs(const PairArgs &P, const LaunchShape &sh, hipStream_t s);
+// mode 0: totals only; 1: also per vertex of the anchor side; 2: per vertex of
+// the opposite side
+hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t s);
+uint32_t tier_c_max_degree();
+uint32_t tier_c_max_k();
+uint32_t max_unit_chunk();
+
+}  // namespace bbc

@@ -1,0 +1,258 @@
+// build.hip -- device CSR builder: COO validation, degrees, vertex priority,
+// and both adjacency orientations with the edge sign folded into bit 0.
+//
+// Vertex priority follows Definition 4.1 of the paper (higher degree first,
+// ties broken by the larger id); sorting is the paper's O(m) counting-sort
+// step (proof of Theorem 1) done as a stable LSD radix sort on the GPU.
+#include "bbc_build.h"
+
+namespace bbc {
+
+namespace {
+
+constexpr int kT = 256;
+
+__device__ __forceinline__ uint32_t find_graph(const uint64_t *__restrict__ off, uint32_t G,
+                                               uint64_t x)
+{
+    // largest g with off[g] <= x (off has G+1 entries, off[0] = 0)
+    uint32_t lo = 0, hi = G;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t find_graph32(const uint32_t *__restrict__ base, uint32_t G,
+                                                 uint32_t x)
+{
+    uint32_t lo = 0, hi = G;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (base[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Sum over a wave when every lane belongs to the same graph, else per lane.
+__device__ __forceinline__ void seg_atomic_add(unsigned long long *dst, uint32_t g, uint64_t v,
+                                               bool active)
+{
+    uint32_t g0 = __shfl(g, 0, kWave);
+    bool same = __all(!active || g == g0) && __any(active);
+    if (same) {
+        uint64_t s = wave_sum<uint64_t>(active ? v : 0);
+        if (__lane_id() == 0 && s) atomicAdd(dst + g0, (unsigned long long)s);
+    } else if (active && v) {
+        atomicAdd(dst + g, (unsigned long long)v);
+    }
+}
+
+__global__ void __launch_bounds__(kT) k_ingest(BuildArgs a)
+{
+    for (uint64_t e = (uint64_t)blockIdx.x * kT + threadIdx.x; e < a.M;
+         e += (uint64_t)gridDim.x * kT) {
+        uint32_t g = a.G == 1 ? 0 : find_graph(a.edge_off, a.G, e);
+        const GraphDesc &d = a.desc[g];
+        uint32_t u = a.eu[e], v = a.ev[e];
+        int neg = 0;
+        bool ok_sign;
+        if (a.flags & kSigns2Bit) {
+            uint32_t code = (((const uint8_t *)a.sign)[e >> 2] >> (2 * (e & 3))) & 3u;
+            ok_sign = code == 1u || code == 3u;
+            neg = code == 3u;
+        } else {
+            int s = ((const int8_t *)a.sign)[e];
+            if (a.flags & kSigns01) { ok_sign = s == 0 || s == 1; neg = s == 0; }
+            else { ok_sign = s == 1 || s == -1; neg = s < 0; }
+        }
+        bool ok_range = u < d.n_u && v < d.n_v;
+        if (!ok_range) { atomicOr(a.err, kErrRange); atomicMin(a.first_bad, (unsigned long long)e); }
+        if (!ok_sign) { atomicOr(a.err, kErrSign); atomicMin(a.first_bad, (unsigned long long)e); }
+        a.eg[e] = (g << 1) | (uint32_t)neg;
+        if (ok_range) {
+            atomicAdd(&a.deg_u[d.u_base + u], 1u);
+            atomicAdd(&a.deg_v[d.v_base + v], 1u);
+        }
+    }
+}
+
+// Per-graph degree statistics of one side (side 0: U slots, 1: V slots).
+__global__ void __launch_bounds__(kT) k_side_stats(BuildArgs a, int side, uint32_t n_slots)
+{
+    const uint32_t *deg = side ? a.deg_v : a.deg_u;
+    const uint32_t *base = side ? a.v_base_arr : a.u_base_arr;
+    unsigned long long *c2 = side ? a.stat_c2_v : a.stat_c2_u;
+    unsigned long long *d2 = side ? a.stat_d2_v : a.stat_d2_u;
+    uint32_t local_max = 0;
+    uint32_t n_iter = (n_slots + gridDim.x * kT - 1) / (gridDim.x * kT);
+    for (uint32_t it = 0; it < n_iter; it++) {
+        uint32_t i = (it * gridDim.x + blockIdx.x) * kT + threadIdx.x;
+        bool act = i < n_slots;
+        uint32_t g = 0, dg = 0;
+        if (act) {
+            g = a.G == 1 ? 0 : find_graph32(base, a.G, i);
+            dg = deg[i];
+            local_max = max(local_max, dg);
+        }
+        seg_atomic_add(c2, g, choose2(dg), act);
+        seg_atomic_add(d2, g, (uint64_t)dg * dg, act);
+    }
+    for (int o = 32; o > 0; o >>= 1) local_max = max(local_max, (uint32_t)__shfl_xor(local_max, o, kWave));
+    if (__lane_id() == 0) atomicMax(side ? a.max_deg_v : a.max_deg_u, local_max);
+}
+
+// One thread per global S slot / O slot: degree in the chosen orientation
+// and the rank-sort key (graph, degree) with the vertex id as value.
+__global__ void __launch_bounds__(kT) k_gather(BuildArgs a)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x; i < (uint64_t)a.NS + a.NO;
+         i += (uint64_t)gridDim.x * kT) {
+        if (i < a.NS) {
+            uint32_t g = a.G == 1 ? 0 : find_graph32(a.s_base_arr, a.G, (uint32_t)i);
+            const GraphDesc &d = a.desc[g];
+            uint32_t x = (uint32_t)i - d.s_base;
+            uint32_t dg = d.side ? a.deg_v[d.v_base + x] : a.deg_u[d.u_base + x];
+            a.key0[i] = (uint64_t)g * (a.max_deg_s + 1ull) + dg;
+            a.val0[i] = x;
+        } else {
+            uint32_t j = (uint32_t)(i - a.NS);
+            uint32_t g = a.G == 1 ? 0 : find_graph32(a.o_base_arr, a.G, j);
+            const GraphDesc &d = a.desc[g];
+            uint32_t x = j - d.o_base;
+            a.deg_o[j] = d.side ? a.deg_u[d.u_base + x] : a.deg_v[d.v_base + x];
+        }
+    }
+}
+
+// After the stable sort by (graph, degree) position p is the global rank.
+__global__ void __launch_bounds__(kT) k_rank_scatter(BuildArgs a)
+{
+    for (uint64_t p = (uint64_t)blockIdx.x * kT + threadIdx.x; p < a.NS;
+         p += (uint64_t)gridDim.x * kT) {
+        uint64_t key = a.key0[p];
+        uint32_t g = (uint32_t)(key / (a.max_deg_s + 1ull));
+        uint32_t dg = (uint32_t)(key % (a.max_deg_s + 1ull));
+        uint32_t x = a.val0[p];
+        a.rank_of[a.desc[g].s_base + x] = (uint32_t)p;
+        a.s_vert[p] = x;
+        a.s_graph[p] = g;
+        a.deg_rank[p] = dg;
+    }
+}
+
+__global__ void __launch_bounds__(kT) k_edge_keys(BuildArgs a)
+{
+    for (uint64_t e = (uint64_t)blockIdx.x * kT + threadIdx.x; e < a.M;
+         e += (uint64_t)gridDim.x * kT) {
+        uint32_t ge = a.eg[e];
+        uint32_t g = ge >> 1, neg = ge & 1;
+        const GraphDesc &d = a.desc[g];
+        uint32_t u = a.eu[e], v = a.ev[e];
+        uint32_t s_loc = d.side ? v : u, o_loc = d.side ? u : v;
+        uint32_t r = a.rank_of[d.s_base + s_loc];
+        a.key0[e] = ((uint64_t)r << a.obits) | o_loc;
+        a.val0[e] = ((d.o_base + o_loc) << 1) | neg;
+    }
+}
+
+// Sorted by (rank, O id): emit s_adj, flag repeated pairs, and prepare the
+// (O index -> rank) keys whose stable sort yields the O-side lists in rank
+// order.
+__global__ void __launch_bounds__(kT) k_s_finish(BuildArgs a)
+{
+    for (uint64_t t = (uint64_t)blockIdx.x * kT + threadIdx.x; t < a.M;
+         t += (uint64_t)gridDim.x * kT) {
+        uint64_t key = a.key0[t];
+        uint32_t val = a.val0[t];
+        a.s_adj[t] = val;
+        if (t > 0 && a.key0[t - 1] == key) atomicOr(a.err, kErrDup);
+        uint32_t r = (uint32_t)(key >> a.obits);
+        a.key1[t] = val >> 1;
+        a.val1[t] = (r << 1) | (val & 1);
+    }
+}
+
+__global__ void __launch_bounds__(kT) k_copy_u32(const uint32_t *__restrict__ src,
+                                                 uint32_t *__restrict__ dst, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * kT)
+        dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(kT) k_fill_u32(uint32_t *p, uint32_t v, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * kT)
+        p[i] = v;
+}
+
+__global__ void __launch_bounds__(kT) k_fill_u64(unsigned long long *p, unsigned long long v,
+                                                 uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * kT)
+        p[i] = v;
+}
+
+inline uint32_t grid_for(uint64_t n, uint32_t cap = 8192)
+{
+    uint64_t b = (n + kT - 1) / kT;
+    if (b < 1) b = 1;
+    return (uint32_t)(b < cap ? b : cap);
+}
+
+}  // namespace
+
+hipError_t fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kT), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t fill_u64(void *p, uint64_t v, uint64_t n, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n)), dim3(kT), 0, s, (unsigned long long *)p,
+                       (unsigned long long)v, n);
+    return hipGetLastError();
+}
+
+hipError_t build_ingest(const BuildArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ingest, dim3(grid_for(a.M)), dim3(kT), 0, s, a);
+    hipLaunchKernelGGL(k_side_stats, dim3(grid_for(a.NU, 2048)), dim3(kT), 0, s, a, 0, a.NU);
+    hipLaunchKernelGGL(k_side_stats, dim3(grid_for(a.NV, 2048)), dim3(kT), 0, s, a, 1, a.NV);
+    return hipGetLastError();
+}
+
+hipError_t build_rank(const BuildArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather, dim3(grid_for((uint64_t)a.NS + a.NO)), dim3(kT), 0, s, a);
+    hipError_t e = radix_sort(a.key0, a.val0, a.key1, a.val1, a.NS, a.rank_bits, a.tmp,
+                              a.tmp_bytes, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rank_scatter, dim3(grid_for(a.NS)), dim3(kT), 0, s, a);
+    e = scan_u32_to_u64(a.deg_rank, a.s_off, a.NS, a.tmp, a.tmp_bytes, s);
+    if (e != hipSuccess) return e;
+    e = scan_u32_to_u64(a.deg_o, a.o_off, a.NO, a.tmp, a.tmp_bytes, s);
+    return e;
+}
+
+hipError_t build_adjacency(const BuildArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_edge_keys, dim3(grid_for(a.M)), dim3(kT), 0, s, a);
+    hipError_t e = radix_sort(a.key0, a.val0, a.key1, a.val1, a.M, a.s_bits, a.tmp, a.tmp_bytes, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_s_finish, dim3(grid_for(a.M)), dim3(kT), 0, s, a);
+    // key0/val0 are free again and serve as the ping-pong buffers
+    e = radix_sort(a.key1, a.val1, a.key0, a.val0, a.M, a.o_bits, a.tmp, a.tmp_bytes, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_copy_u32, dim3(grid_for(a.M)), dim3(kT), 0, s, a.val1, a.o_adj, a.M);
+    return hipGetLastError();
+}
+
+}  // namespace bbc

@@ -1,0 +1,1259 @@
+// runtime.cpp -- host runtime and C ABI of libbbc.
+//
+// Owns device memory (a caching allocator under the context's cap), graph
+// sets, count workspaces, the batched path (persistent kernels replayed from
+// a captured HIP graph, launch shape chosen by a small autotuner), and the
+// serving loop (continuous batching over several streams).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/bbc.h"
+#include "bbc_build.h"
+#include "bbc_count.h"
+
+using namespace bbc;
+
+namespace {
+
+struct HipError {
+    hipError_t e;
+    const char *what;
+};
+
+#define HIP_OK(expr)                                                 \
+    do {                                                             \
+        hipError_t e_ = (expr);                                      \
+        if (e_ != hipSuccess) throw HipError{e_, #expr};             \
+    } while (0)
+
+struct StatusError {
+    bbc_status s;
+    std::string msg;
+};
+
+[[noreturn]] void fail(bbc_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    throw StatusError{s, buf};
+}
+
+int bit_width(uint64_t x)
+{
+    int b = 0;
+    while (x) { b++; x >>= 1; }
+    return b;
+}
+
+uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------- allocator
+class Allocator {
+  public:
+    Allocator(uint64_t cap) : cap_(cap) {}
+    ~Allocator() { release_all(); }
+
+    void *alloc(uint64_t bytes)
+    {
+        if (bytes == 0) bytes = 256;
+        bytes = round_up(bytes, 256);
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = free_.lower_bound(bytes);
+        if (it != free_.end() && it->first <= bytes * 2 + (4u << 20)) {
+            void *p = it->second;
+            live_[p] = it->first;
+            free_.erase(it);
+            return p;
+        }
+        uint64_t sz = bytes < (1u << 20) ? bytes : round_up(bytes, 2u << 20);
+        if (cap_ && used_ + sz > cap_) {
+            trim_locked();
+            if (used_ + sz > cap_)
+                fail(BBC_E_NOMEM, "device memory cap %llu bytes reached (need %llu more, %llu in use)",
+                     (unsigned long long)cap_, (unsigned long long)sz, (unsigned long long)used_);
+        }
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, sz);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim_locked();
+            e = hipMalloc(&p, sz);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                fail(BBC_E_NOMEM, "hipMalloc of %llu bytes failed", (unsigned long long)sz);
+            }
+        }
+        used_ += sz;
+        live_[p] = sz;
+        return p;
+    }
+
+    void free(void *p)
+    {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = live_.find(p);
+        if (it == live_.end()) return;
+        free_.emplace(it->second, p);
+        live_.erase(it);
+    }
+
+    uint64_t used() const { return used_; }
+    uint64_t cap() const { return cap_; }
+    uint64_t live_bytes()
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        uint64_t s = 0;
+        for (auto &kv : live_) s += kv.second;
+        return s;
+    }
+
+    void release_all()
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        trim_locked();
+    }
+
+  private:
+    void trim_locked()
+    {
+        for (auto &kv : free_) {
+            (void)hipFree(kv.second);
+            used_ -= kv.first;
+        }
+        free_.clear();
+    }
+    std::mutex mu_;
+    uint64_t cap_, used_ = 0;
+    std::multimap<uint64_t, void *> free_;
+    std::unordered_map<void *, uint64_t> live_;
+};
+
+// A device buffer that returns its memory to the allocator.
+struct DBuf {
+    Allocator *al = nullptr;
+    void *p = nullptr;
+    uint64_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { reset(); }
+    void reset()
+    {
+        if (p && al) al->free(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void ensure(Allocator *a, uint64_t n)
+    {
+        if (p && bytes >= n) return;
+        reset();
+        al = a;
+        p = a->alloc(n);
+        bytes = n;
+    }
+    template <typename T>
+    T *as() const { return (T *)p; }
+};
+
+// Pinned host staging area.
+struct HBuf {
+    void *p = nullptr;
+    uint64_t bytes = 0;
+    ~HBuf() { if (p) (void)hipHostFree(p); }
+    void ensure(uint64_t n)
+    {
+        if (p && bytes >= n) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        HIP_OK(hipHostMalloc(&p, n, hipHostMallocDefault));
+        bytes = n;
+    }
+    template <typename T>
+    T *as() const { return (T *)p; }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------- graph set
+struct GraphSet {
+    Allocator *al;
+    uint32_t G = 0, NS = 0, NO = 0;
+    uint64_t M = 0;
+    std::vector<GraphDesc> desc;
+    DBuf d_desc, s_off, o_off, s_adj, o_adj, s_graph, s_vert;
+    // sizing hints learnt by earlier counts
+    uint64_t hint_masks = 0, hint_cands = 0, hint_units = 0;
+    bool hint_tier_c = false;
+    uint64_t device_bytes() const
+    {
+        return d_desc.bytes + s_off.bytes + o_off.bytes + s_adj.bytes + o_adj.bytes +
+               s_graph.bytes + s_vert.bytes;
+    }
+    CsrView view() const
+    {
+        CsrView v;
+        v.G = G; v.NS = NS; v.NO = NO; v.M = M;
+        v.s_off = s_off.as<uint64_t>(); v.s_adj = s_adj.as<uint32_t>();
+        v.o_off = o_off.as<uint64_t>(); v.o_adj = o_adj.as<uint32_t>();
+        v.s_graph = s_graph.as<uint32_t>(); v.s_vert = s_vert.as<uint32_t>();
+        v.desc = d_desc.as<GraphDesc>();
+        return v;
+    }
+};
+
+struct bbc_graph {
+    std::shared_ptr<GraphSet> set;
+    uint32_t idx;
+};
+
+namespace {
+
+// Count workspace (one per stream that counts).
+struct Work {
+    DBuf ctr, anchors, units, masks, cands, defer0, defer1, gtab, count, carry, pv, pv_o;
+    HBuf host;          // counters + counts + carries read back
+    uint64_t cap_anchors = 0, cap_units = 0, cap_masks = 0, cap_cands = 0, cap_defer = 0;
+    uint32_t gtab_blocks = 0;
+    uint64_t gtab_words = 0;
+    uint32_t gH = 0;
+    int glog2 = 0;
+    uint32_t gmaxd = 0, gkmax = 0;
+    // captured replay of a batched count
+    hipGraphExec_t exec = nullptr;
+    const GraphSet *exec_set = nullptr;
+    uint64_t exec_key = 0;
+    ~Work()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+
+struct Shape {
+    uint32_t chunk_base = 512;
+    uint32_t grid_a_per_cu = 2;
+    uint32_t grid_t_per_cu = 6;
+};
+
+}  // namespace
+
+struct Request {
+    bbc_ticket id;
+    std::shared_ptr<GraphSet> set;   // prebuilt graph (set + index) or null
+    uint32_t idx = 0;
+    // COO request
+    uint32_t n_u = 0, n_v = 0, flags = 0;
+    std::vector<uint32_t> eu, ev;
+    std::vector<uint8_t> sign;
+    uint64_t m = 0;
+    uint64_t footprint = 0;
+    bool done = false;
+    bbc_status status = BBC_OK;
+    int64_t result = 0;
+};
+
+struct bbc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int num_cus = 256;
+    std::unique_ptr<Allocator> al;
+    std::string last_error;
+    std::mutex err_mu;
+    Work work;
+    bbc_count_stats stats{};
+    std::map<uint64_t, Shape> tuned;   // autotuner cache by size class
+    // serving
+    std::mutex q_mu;
+    std::condition_variable q_cv, done_cv;
+    std::deque<std::shared_ptr<Request>> queue;
+    std::unordered_map<bbc_ticket, std::shared_ptr<Request>> requests;
+    uint64_t next_ticket = 1;
+    uint64_t admitted_bytes = 0;
+    bool stopping = false;
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> serve_streams;
+};
+
+namespace {
+
+void set_error(bbc_ctx *ctx, const std::string &m)
+{
+    if (!ctx) return;
+    std::lock_guard<std::mutex> lk(ctx->err_mu);
+    ctx->last_error = m;
+}
+
+template <typename F>
+bbc_status guard(bbc_ctx *ctx, F &&f)
+{
+    try {
+        f();
+        set_error(ctx, "");
+        return BBC_OK;
+    } catch (const StatusError &e) {
+        set_error(ctx, e.msg);
+        return e.s;
+    } catch (const HipError &e) {
+        set_error(ctx, std::string(e.what) + ": " + hipGetErrorString(e.e));
+        (void)hipGetLastError();
+        return BBC_E_HIP;
+    } catch (const std::bad_alloc &) {
+        set_error(ctx, "host allocation failed");
+        return BBC_E_NOMEM;
+    }
+}
+
+// -------------------------------------------------------------- building
+struct CooIn {
+    uint32_t G;
+    const uint32_t *n_u, *n_v;
+    const uint64_t *edge_off;    // host [G+1]
+    const uint32_t *eu, *ev;
+    const void *sign;
+    uint32_t flags;
+};
+
+uint64_t sign_bytes(uint64_t m, uint32_t flags)
+{
+    return (flags & BBC_SIGNS_2BIT_PACKED) ? (m + 3) / 4 : m;
+}
+
+void check_flags(uint32_t flags)
+{
+    const uint32_t known = BBC_IN_DEVICE_PTRS | BBC_SIGNS_2BIT_PACKED | BBC_SIGNS_01 |
+                           BBC_ANCHOR_U | BBC_ANCHOR_V | BBC_ANCHOR_SMALLER;
+    if (flags & ~known) fail(BBC_E_INVAL, "unknown flag bits 0x%x", flags & ~known);
+    if ((flags & BBC_SIGNS_2BIT_PACKED) && (flags & BBC_SIGNS_01))
+        fail(BBC_E_INVAL, "BBC_SIGNS_2BIT_PACKED and BBC_SIGNS_01 are exclusive");
+    int a = !!(flags & BBC_ANCHOR_U) + !!(flags & BBC_ANCHOR_V) + !!(flags & BBC_ANCHOR_SMALLER);
+    if (a > 1) fail(BBC_E_INVAL, "at most one BBC_ANCHOR_* flag");
+}
+
+// Anchor side of one graph. Work of the pair table anchored on S is about the
+// number of 2-hop wedges through O, sum_o C(d_o, 2); work of the triplet
+// phase grows with the mask width, about the edge-weighted mean degree of S.
+uint32_t choose_side(uint32_t flags, uint32_t n_u, uint32_t n_v, uint64_t m, uint64_t c2_u,
+                     uint64_t c2_v, uint64_t d2_u, uint64_t d2_v)
+{
+    if (flags & BBC_ANCHOR_U) return 0;
+    if (flags & BBC_ANCHOR_V) return 1;
+    if (flags & BBC_ANCHOR_SMALLER) return n_v < n_u ? 1 : 0;
+    if (m == 0) return 0;
+    double wu = (double)d2_u / (double)m, wv = (double)d2_v / (double)m;
+    double cost_u = (double)c2_v * (1.0 + wu / 32.0);   // anchored on U: wedges centred in V
+    double cost_v = (double)c2_u * (1.0 + wv / 32.0);
+    return cost_v < cost_u ? 1 : 0;
+}
+
+std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s)
+{
+    Allocator *al = ctx->al.get();
+    const uint32_t G = in.G;
+    if (G == 0) fail(BBC_E_INVAL, "no graphs");
+    check_flags(in.flags);
+    const uint64_t M = in.edge_off[G];
+    uint64_t NU = 0, NV = 0;
+    for (uint32_t g = 0; g < G; g++) {
+        if (in.edge_off[g + 1] < in.edge_off[g]) fail(BBC_E_INVAL, "edge offsets decrease at graph %u", g);
+        NU += in.n_u[g];
+        NV += in.n_v[g];
+    }
+    if (in.edge_off[0] != 0) fail(BBC_E_INVAL, "edge_offsets[0] must be 0");
+    if (M > 0 && (!in.eu || !in.ev || !in.sign)) fail(BBC_E_INVAL, "null edge array");
+    if (M >= (1ull << 32) - 1) fail(BBC_E_UNSUPPORTED, "more than 2^32-2 edges in one build");
+    if (NU >= (1ull << 31) || NV >= (1ull << 31)) fail(BBC_E_UNSUPPORTED, "more than 2^31-1 vertices per side");
+
+    auto set = std::make_shared<GraphSet>();
+    set->al = al;
+    set->G = G;
+    set->M = M;
+    set->desc.resize(G);
+
+    // inputs on the device
+    DBuf d_eu, d_ev, d_sign;
+    const uint32_t *eu = in.eu, *ev = in.ev;
+    const void *sign = in.sign;
+    const uint64_t sb = sign_bytes(M, in.flags);
+    if (!(in.flags & BBC_IN_DEVICE_PTRS) && M > 0) {
+        d_eu.ensure(al, M * 4); d_ev.ensure(al, M * 4); d_sign.ensure(al, sb);
+        HIP_OK(hipMemcpyAsync(d_eu.p, in.eu, M * 4, hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(d_ev.p, in.ev, M * 4, hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(d_sign.p, in.sign, sb, hipMemcpyHostToDevice, s));
+        eu = d_eu.as<uint32_t>(); ev = d_ev.as<uint32_t>(); sign = d_sign.p;
+    }
+
+    // per-graph descriptors: U/V slot bases
+    std::vector<uint32_t> ub(G), vb(G);
+    {
+        uint64_t u = 0, v = 0;
+        for (uint32_t g = 0; g < G; g++) {
+            GraphDesc &d = set->desc[g];
+            memset(&d, 0, sizeof(d));
+            d.n_u = in.n_u[g]; d.n_v = in.n_v[g];
+            d.u_base = (uint32_t)u; d.v_base = (uint32_t)v;
+            d.e_base = in.edge_off[g]; d.m = in.edge_off[g + 1] - in.edge_off[g];
+            ub[g] = (uint32_t)u; vb[g] = (uint32_t)v;
+            u += d.n_u; v += d.n_v;
+        }
+    }
+    // small per-graph arrays in one device block
+    const uint64_t small_bytes = (G + 1) * 8 + G * sizeof(GraphDesc) + 4 * G * 4 + 4 * G * 8 + 64;
+    DBuf d_small;
+    d_small.ensure(al, small_bytes);
+    char *sp = d_small.as<char>();
+    uint64_t *d_eoff = (uint64_t *)sp; sp += (G + 1) * 8;
+    GraphDesc *d_desc_tmp = (GraphDesc *)sp; sp += G * sizeof(GraphDesc);
+    uint32_t *d_ub = (uint32_t *)sp; sp += G * 4;
+    uint32_t *d_vb = (uint32_t *)sp; sp += G * 4;
+    uint32_t *d_sbase = (uint32_t *)sp; sp += G * 4;
+    uint32_t *d_obase = (uint32_t *)sp; sp += G * 4;
+    unsigned long long *d_stats = (unsigned long long *)sp; sp += 4 * G * 8;
+    uint32_t *d_flags = (uint32_t *)sp;   // err, max_deg_u, max_deg_v, pad, first_bad (u64)
+
+    HBuf hb;
+    hb.ensure((G + 1) * 8 + G * sizeof(GraphDesc) + 4 * G * 4 + 4 * G * 8 + 64);
+    {
+        char *hp = hb.as<char>();
+        memcpy(hp, in.edge_off, (G + 1) * 8);
+        memcpy(hp + (G + 1) * 8, set->desc.data(), G * sizeof(GraphDesc));
+        memcpy(hp + (G + 1) * 8 + G * sizeof(GraphDesc), ub.data(), G * 4);
+        memcpy(hp + (G + 1) * 8 + G * sizeof(GraphDesc) + G * 4, vb.data(), G * 4);
+        HIP_OK(hipMemcpyAsync(d_small.p, hp, (G + 1) * 8 + G * sizeof(GraphDesc) + 2 * G * 4,
+                              hipMemcpyHostToDevice, s));
+    }
+    DBuf eg, deg_u, deg_v;
+    eg.ensure(al, std::max<uint64_t>(M, 1) * 4);
+    deg_u.ensure(al, std::max<uint64_t>(NU, 1) * 4);
+    deg_v.ensure(al, std::max<uint64_t>(NV, 1) * 4);
+    HIP_OK(fill_u32(deg_u.as<uint32_t>(), 0, NU, s));
+    HIP_OK(fill_u32(deg_v.as<uint32_t>(), 0, NV, s));
+    HIP_OK(fill_u64(d_stats, 0, 4ull * G, s));
+    HIP_OK(fill_u32(d_flags, 0, 4, s));
+    HIP_OK(fill_u64(d_flags + 4, ~0ull, 1, s));
+
+    BuildArgs a;
+    memset(&a, 0, sizeof(a));
+    a.eu = eu; a.ev = ev; a.sign = sign; a.flags = in.flags; a.M = M; a.G = G;
+    a.edge_off = d_eoff; a.desc = d_desc_tmp; a.u_base_arr = d_ub; a.v_base_arr = d_vb;
+    a.NU = (uint32_t)NU; a.NV = (uint32_t)NV;
+    a.eg = eg.as<uint32_t>(); a.deg_u = deg_u.as<uint32_t>(); a.deg_v = deg_v.as<uint32_t>();
+    a.err = d_flags; a.max_deg_u = d_flags + 1; a.max_deg_v = d_flags + 2;
+    a.first_bad = (unsigned long long *)(d_flags + 4);
+    a.stat_c2_u = d_stats; a.stat_c2_v = d_stats + G; a.stat_d2_u = d_stats + 2 * G;
+    a.stat_d2_v = d_stats + 3 * G;
+    HIP_OK(build_ingest(a, s));
+
+    // read back validation flags and degree statistics
+    char *hp = hb.as<char>();
+    unsigned long long *h_stats = (unsigned long long *)hp;
+    uint32_t *h_flags = (uint32_t *)(hp + 4 * G * 8);
+    HIP_OK(hipMemcpyAsync(h_stats, d_stats, 4 * G * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(h_flags, d_flags, 24, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const uint32_t err = h_flags[0];
+    const uint64_t first_bad = *(uint64_t *)(h_flags + 4);
+    if (err & kErrRange) fail(BBC_E_RANGE, "edge %llu has an endpoint out of range", (unsigned long long)first_bad);
+    if (err & kErrSign) fail(BBC_E_SIGN, "edge %llu has an invalid sign", (unsigned long long)first_bad);
+    const uint32_t maxdu = h_flags[1], maxdv = h_flags[2];
+
+    // side choice and S/O numbering
+    uint64_t ns = 0, no = 0;
+    uint32_t max_no = 0;
+    std::vector<uint32_t> sbase(G), obase(G);
+    bool any_u = false, any_v = false;
+    for (uint32_t g = 0; g < G; g++) {
+        GraphDesc &d = set->desc[g];
+        d.side = choose_side(in.flags, d.n_u, d.n_v, d.m, h_stats[g], h_stats[G + g],
+                             h_stats[2 * G + g], h_stats[3 * G + g]);
+        d.n_s = d.side ? d.n_v : d.n_u;
+        d.n_o = d.side ? d.n_u : d.n_v;
+        d.s_base = (uint32_t)ns; d.o_base = (uint32_t)no;
+        sbase[g] = d.s_base; obase[g] = d.o_base;
+        ns += d.n_s; no += d.n_o;
+        max_no = std::max(max_no, d.n_o);
+        (d.side ? any_v : any_u) = true;
+    }
+    set->NS = (uint32_t)ns;
+    set->NO = (uint32_t)no;
+    {
+        char *p2 = hp;
+        memcpy(p2, set->desc.data(), G * sizeof(GraphDesc));
+        memcpy(p2 + G * sizeof(GraphDesc), sbase.data(), G * 4);
+        memcpy(p2 + G * sizeof(GraphDesc) + G * 4, obase.data(), G * 4);
+        HIP_OK(hipMemcpyAsync(d_desc_tmp, p2, G * sizeof(GraphDesc), hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(d_sbase, p2 + G * sizeof(GraphDesc), G * 4, hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(d_obase, p2 + G * sizeof(GraphDesc) + G * 4, G * 4,
+                              hipMemcpyHostToDevice, s));
+    }
+    const uint32_t max_deg_s = std::max(any_u ? maxdu : 0u, any_v ? maxdv : 0u);
+    const uint64_t NS = ns, NO = no;
+    const uint64_t nkv = std::max<uint64_t>(std::max(NS, M), 1);
+    DBuf key0, key1, val0, val1, deg_o, deg_rank, rank_of, tmp;
+    key0.ensure(al, nkv * 8); key1.ensure(al, nkv * 8);
+    val0.ensure(al, nkv * 4); val1.ensure(al, nkv * 4);
+    deg_o.ensure(al, std::max<uint64_t>(NO, 1) * 4);
+    deg_rank.ensure(al, std::max<uint64_t>(NS, 1) * 4);
+    rank_of.ensure(al, std::max<uint64_t>(NS, 1) * 4);
+    const size_t tmp_bytes = std::max(radix_tmp_bytes(nkv), scan_tmp_bytes(nkv + 1)) + 1024;
+    tmp.ensure(al, tmp_bytes);
+
+    set->d_desc.ensure(al, G * sizeof(GraphDesc));
+    set->s_off.ensure(al, (NS + 1) * 8);
+    set->o_off.ensure(al, (NO + 1) * 8);
+    set->s_adj.ensure(al, std::max<uint64_t>(M, 1) * 4);
+    set->o_adj.ensure(al, std::max<uint64_t>(M, 1) * 4);
+    set->s_graph.ensure(al, std::max<uint64_t>(NS, 1) * 4);
+    set->s_vert.ensure(al, std::max<uint64_t>(NS, 1) * 4);
+    HIP_OK(hipMemcpyAsync(set->d_desc.p, d_desc_tmp, G * sizeof(GraphDesc),
+                          hipMemcpyDeviceToDevice, s));
+
+    a.desc = d_desc_tmp; a.s_base_arr = d_sbase; a.o_base_arr = d_obase;
+    a.NS = (uint32_t)NS; a.NO = (uint32_t)NO;
+    a.max_deg_s = max_deg_s;
+    a.rank_bits = bit_width((uint64_t)G * (max_deg_s + 1ull) - 1);
+    a.obits = max_no > 1 ? bit_width(max_no - 1) : 0;
+    a.s_bits = (NS > 1 ? bit_width(NS - 1) : 0) + a.obits;
+    a.o_bits = NO > 1 ? bit_width(NO - 1) : 0;
+    a.key0 = key0.as<uint64_t>(); a.key1 = key1.as<uint64_t>();
+    a.val0 = val0.as<uint32_t>(); a.val1 = val1.as<uint32_t>();
+    a.deg_o = deg_o.as<uint32_t>(); a.deg_rank = deg_rank.as<uint32_t>();
+    a.rank_of = rank_of.as<uint32_t>();
+    a.s_off = set->s_off.as<uint64_t>(); a.o_off = set->o_off.as<uint64_t>();
+    a.s_adj = set->s_adj.as<uint32_t>(); a.o_adj = set->o_adj.as<uint32_t>();
+    a.s_graph = set->s_graph.as<uint32_t>(); a.s_vert = set->s_vert.as<uint32_t>();
+    a.tmp = tmp.p; a.tmp_bytes = tmp_bytes;
+    HIP_OK(build_rank(a, s));
+    HIP_OK(build_adjacency(a, s));
+    HIP_OK(hipMemcpyAsync(h_flags, d_flags, 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (h_flags[0] & kErrDup) fail(BBC_E_DUP_EDGE, "an edge (u, v) appears more than once");
+    return set;
+}
+
+// -------------------------------------------------------------- counting
+struct CountReq {
+    const GraphSet *set;
+    uint32_t g0, g1;        // graph range
+    int mode;               // 0 totals, 1 per vertex of S, 2 per vertex of O
+};
+
+void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set, bool tier_c)
+{
+    Allocator *al = ctx->al.get();
+    uint64_t M = std::max<uint64_t>(set.M, 1);
+    uint64_t want_anchors = std::max<uint64_t>(set.NS, 1);
+    uint64_t want_masks = std::max<uint64_t>({set.hint_masks, 8 * M, 1ull << 20});
+    uint64_t want_cands = std::max<uint64_t>({set.hint_cands, 2 * M, 1ull << 18});
+    uint64_t want_units = std::max<uint64_t>({set.hint_units, M / 4, 1ull << 16});
+    if (w.cap_anchors < want_anchors) { w.anchors.ensure(al, want_anchors * sizeof(AnchorRec)); w.cap_anchors = want_anchors; }
+    if (w.cap_masks < want_masks) { w.masks.ensure(al, want_masks * 4); w.cap_masks = want_masks; }
+    if (w.cap_cands < want_cands) { w.cands.ensure(al, want_cands * 4); w.cap_cands = want_cands; }
+    if (w.cap_units < want_units) { w.units.ensure(al, want_units * sizeof(Unit)); w.cap_units = want_units; }
+    if (w.cap_defer < want_anchors) {
+        w.defer0.ensure(al, want_anchors * 4); w.defer1.ensure(al, want_anchors * 4);
+        w.cap_defer = want_anchors;
+    }
+    w.ctr.ensure(al, sizeof(Counters));
+    w.count.ensure(al, std::max<uint32_t>(set.G, 1) * 8);
+    w.carry.ensure(al, std::max<uint32_t>(set.G, 1) * 4);
+    w.host.ensure(sizeof(Counters) + 12ull * std::max<uint32_t>(set.G, 1) + 64);
+    if (tier_c) {
+        // tier-C tables: sized for the largest anchor side of any graph
+        uint32_t max_ns = 0;
+        for (auto &d : set.desc) max_ns = std::max(max_ns, d.n_s);
+        uint32_t H = 1024;
+        int lg = 10;
+        while (H < 2ull * max_ns + 64 && lg < 24) { H <<= 1; lg++; }
+        uint32_t maxd = tier_c_max_degree(), kmax = tier_c_max_k();
+        uint64_t words = 2ull * H + 2ull * maxd + kmax + 64;
+        uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ctx->num_cus / 2, (4ull << 30) / (words * 4)));
+        if (!w.gtab.p || w.gH != H || w.gtab_blocks < blocks) {
+            w.gtab.ensure(al, words * 4 * blocks);
+            w.gH = H; w.glog2 = lg; w.gmaxd = maxd; w.gkmax = kmax;
+            w.gtab_words = words; w.gtab_blocks = blocks;
+        }
+    }
+}
+
+Workspace ws_view(Work &w, bool pv, bool pvo)
+{
+    Workspace ws;
+    memset(&ws, 0, sizeof(ws));
+    ws.ctr = w.ctr.as<Counters>();
+    ws.anchors = w.anchors.as<AnchorRec>(); ws.cap_anchors = w.cap_anchors;
+    ws.units = w.units.as<Unit>(); ws.cap_units = w.cap_units;
+    ws.masks = w.masks.as<uint32_t>(); ws.cap_mask_words = w.cap_masks;
+    ws.cands = w.cands.as<uint32_t>(); ws.cap_cands = w.cap_cands;
+    ws.defer[0] = w.defer0.as<uint32_t>(); ws.defer[1] = w.defer1.as<uint32_t>();
+    ws.cap_defer = w.cap_defer;
+    ws.gtab = w.gtab.as<uint32_t>(); ws.gtab_words_per_block = w.gtab_words;
+    ws.gtab_blocks = w.gtab_blocks;
+    ws.count = w.count.as<unsigned long long>();
+    ws.carry = w.carry.as<uint32_t>();
+    ws.pv = pv ? w.pv.as<unsigned long long>() : nullptr;
+    ws.pv_o = pvo ? w.pv_o.as<unsigned long long>() : nullptr;
+    return ws;
+}
+
+// Enqueue one full count (zeroing, pair tiers, triplets) on stream s.
+// Nothing here reads back, so the sequence can be captured.
+void enqueue_count(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp, bool tier_c,
+                   hipStream_t s)
+{
+    const GraphSet &set = *r.set;
+    const bool pv = r.mode == 1, pvo = r.mode == 2;
+    Workspace ws = ws_view(w, pv, pvo);
+    HIP_OK(fill_u32((uint32_t *)ws.ctr, 0, sizeof(Counters) / 4, s));
+    HIP_OK(fill_u64(ws.count, 0, set.G, s));
+    HIP_OK(fill_u32(ws.carry, 0, set.G, s));
+    if (pv) HIP_OK(fill_u64(ws.pv, 0, set.NS, s));
+    if (pvo) HIP_OK(fill_u64(ws.pv_o, 0, set.NO, s));
+    PairArgs P;
+    memset(&P, 0, sizeof(P));
+    P.g = set.view();
+    P.ws = ws;
+    P.a0 = set.desc[r.g0].s_base;
+    P.a1 = set.desc[r.g1 - 1].s_base + set.desc[r.g1 - 1].n_s;
+    P.chunk_base = std::min(shp.chunk_base, max_unit_chunk());
+    P.gH = w.gH; P.glog2h = w.glog2; P.gmaxd = w.gmaxd; P.gkmax = w.gkmax;
+    LaunchShape ls;
+    ls.grid_a = std::max(1u, ctx->num_cus * shp.grid_a_per_cu);
+    ls.grid_b = std::max(1u, (uint32_t)ctx->num_cus);
+    ls.grid_c = tier_c ? w.gtab_blocks : 0;
+    ls.grid_t = std::max(1u, ctx->num_cus * shp.grid_t_per_cu);
+    HIP_OK(count_pairs(P, ls, s));
+    TriArgs T;
+    T.g = P.g;
+    T.ws = ws;
+    HIP_OK(count_triplets(T, r.mode, ls.grid_t, s));
+}
+
+void enqueue_readback(Work &w, const GraphSet &set, hipStream_t s)
+{
+    char *hp = w.host.as<char>();
+    HIP_OK(hipMemcpyAsync(hp, w.ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(hp + sizeof(Counters), w.count.p, 8ull * set.G, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(hp + sizeof(Counters) + 8ull * set.G, w.carry.p, 4ull * set.G,
+                          hipMemcpyDeviceToHost, s));
+}
+
+// After a readback: true if the count is complete, false if buffers must grow.
+bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set, bool tier_c, bool *need_c)
+{
+    const Counters *c = w.host.as<Counters>();
+    *need_c = false;
+    if (c->over_cap & 8u) fail(BBC_E_HIP, "internal error: pair table lookup failed");
+    if (c->over_cap & 4u)
+        fail(BBC_E_UNSUPPORTED, "an anchor has degree above %u or more than %u candidate classes",
+             tier_c_max_degree(), tier_c_max_k());
+    bool ok = true;
+    if (c->over_cap & 3u) {
+        set.hint_masks = std::max<uint64_t>(set.hint_masks, std::max<uint64_t>(c->mask_cursor, w.cap_masks) * 2);
+        set.hint_cands = std::max<uint64_t>(set.hint_cands, std::max<uint64_t>(c->cand_cursor, w.cap_cands) * 2);
+        set.hint_units = std::max<uint64_t>(set.hint_units, std::max<uint64_t>(c->n_units, w.cap_units) * 2);
+        ok = false;
+    }
+    if (c->n_list[1] > 0 && !tier_c) {
+        set.hint_tier_c = true;
+        *need_c = true;
+        ok = false;
+    }
+    if (ok) {
+        set.hint_masks = std::max<uint64_t>(set.hint_masks, c->mask_cursor + c->mask_cursor / 8);
+        set.hint_cands = std::max<uint64_t>(set.hint_cands, c->cand_cursor + c->cand_cursor / 8);
+        set.hint_units = std::max<uint64_t>(set.hint_units, (uint64_t)c->n_units + c->n_units / 8);
+        ctx->stats.active_anchors = c->n_anchor;
+        ctx->stats.virtual_candidates = c->cand_cursor;
+        ctx->stats.pair_units = c->n_units;
+        ctx->stats.candidate_pairs = c->pairs_examined;
+        ctx->stats.mask_words = c->mask_cursor;
+        ctx->stats.wedges = c->wedges;
+    }
+    return ok;
+}
+
+void results_from_host(Work &w, const GraphSet &set, uint32_t g0, uint32_t g1, int64_t *out)
+{
+    const char *hp = w.host.as<char>();
+    const uint64_t *cnt = (const uint64_t *)(hp + sizeof(Counters));
+    const uint32_t *car = (const uint32_t *)(hp + sizeof(Counters) + 8ull * set.G);
+    for (uint32_t g = g0; g < g1; g++) {
+        if (car[g] || cnt[g] > (uint64_t)INT64_MAX)
+            fail(BBC_E_OVERFLOW, "graph %u: count does not fit in int64", g);
+        out[g - g0] = (int64_t)cnt[g];
+    }
+}
+
+Shape default_shape() { return Shape(); }
+
+// One synchronous count of a graph range; grows buffers and retries as needed.
+void count_sync(bbc_ctx *ctx, Work &w, GraphSet &set, uint32_t g0, uint32_t g1, int mode,
+                const Shape &shp, hipStream_t s, int64_t *out)
+{
+    CountReq r{&set, g0, g1, mode};
+    for (int attempt = 0; attempt < 8; attempt++) {
+        bool tier_c = set.hint_tier_c;
+        ensure_work(ctx, w, set, tier_c);
+        if (mode == 1) w.pv.ensure(ctx->al.get(), std::max<uint64_t>(set.NS, 1) * 8);
+        if (mode == 2) w.pv_o.ensure(ctx->al.get(), std::max<uint64_t>(set.NO, 1) * 8);
+        enqueue_count(ctx, w, r, shp, tier_c, s);
+        enqueue_readback(w, set, s);
+        HIP_OK(hipStreamSynchronize(s));
+        bool need_c;
+        if (check_counters(ctx, w, set, tier_c, &need_c)) {
+            results_from_host(w, set, g0, g1, out);
+            return;
+        }
+    }
+    fail(BBC_E_NOMEM, "count workspace kept overflowing");
+}
+
+uint64_t size_class(const GraphSet &set)
+{
+    return ((uint64_t)bit_width(set.NS) << 16) | ((uint64_t)bit_width(set.M) << 8) |
+           (uint64_t)std::min(set.G, 255u);
+}
+
+// Autotuner: time a few launch shapes on this graph set and keep the best
+// per size class.
+Shape tune_shape(bbc_ctx *ctx, Work &w, GraphSet &set, hipStream_t s)
+{
+    const uint64_t key = size_class(set);
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) return it->second;
+    std::vector<Shape> cands;
+    for (uint32_t cb : {256u, 512u, 1024u})
+        for (uint32_t gt : {4u, 8u}) {
+            Shape sh;
+            sh.chunk_base = cb;
+            sh.grid_t_per_cu = gt;
+            cands.push_back(sh);
+        }
+    std::vector<int64_t> tmp(set.G);
+    count_sync(ctx, w, set, 0, set.G, 0, cands[0], s, tmp.data());   // sizes the workspace
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    Shape best = cands[0];
+    float best_ms = 1e30f;
+    for (const Shape &sh : cands) {
+        CountReq r{&set, 0, set.G, 0};
+        HIP_OK(hipEventRecord(e0, s));
+        enqueue_count(ctx, w, r, sh, set.hint_tier_c, s);
+        HIP_OK(hipEventRecord(e1, s));
+        HIP_OK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) { best_ms = ms; best = sh; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->tuned[key] = best;
+    return best;
+}
+
+// Batched count of a whole graph set: the launch sequence is captured once
+// into a HIP graph and replayed.
+void count_set_batched(bbc_ctx *ctx, Work &w, GraphSet &set, hipStream_t s, int64_t *out)
+{
+    Shape shp = tune_shape(ctx, w, set, s);
+    const uint64_t key = size_class(set) ^ ((uint64_t)shp.chunk_base << 40) ^ ((uint64_t)shp.grid_t_per_cu << 52);
+    for (int attempt = 0; attempt < 4; attempt++) {
+        bool tier_c = set.hint_tier_c;
+        void *before[4] = {w.masks.p, w.units.p, w.cands.p, w.gtab.p};
+        ensure_work(ctx, w, set, tier_c);
+        bool moved = before[0] != w.masks.p || before[1] != w.units.p || before[2] != w.cands.p ||
+                     before[3] != w.gtab.p;
+        if (!w.exec || w.exec_set != &set || w.exec_key != key || moved) {
+            if (w.exec) { (void)hipGraphExecDestroy(w.exec); w.exec = nullptr; }
+            hipGraph_t graph;
+            HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            CountReq r{&set, 0, set.G, 0};
+            try {
+                enqueue_count(ctx, w, r, shp, tier_c, s);
+            } catch (...) {
+                hipGraph_t junk;
+                (void)hipStreamEndCapture(s, &junk);
+                if (junk) (void)hipGraphDestroy(junk);
+                throw;
+            }
+            HIP_OK(hipStreamEndCapture(s, &graph));
+            hipError_t e = hipGraphInstantiate(&w.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIP_OK(e);
+            w.exec_set = &set;
+            w.exec_key = key;
+        }
+        HIP_OK(hipGraphLaunch(w.exec, s));
+        enqueue_readback(w, set, s);
+        HIP_OK(hipStreamSynchronize(s));
+        bool need_c;
+        if (check_counters(ctx, w, set, tier_c, &need_c)) {
+            results_from_host(w, set, 0, set.G, out);
+            return;
+        }
+        (void)hipGraphExecDestroy(w.exec);
+        w.exec = nullptr;
+    }
+    fail(BBC_E_NOMEM, "batched count workspace kept overflowing");
+}
+
+// ---------------------------------------------------------------- serving
+constexpr int kServeStreams = 4;
+constexpr size_t kServeBatchMax = 4096;
+
+uint64_t footprint_estimate(uint64_t m, uint64_t nu, uint64_t nv)
+{
+    return 96ull * m + 48ull * (nu + nv) + (4ull << 20);
+}
+
+void serve_worker(bbc_ctx *ctx, int slot)
+{
+    hipStream_t s = ctx->serve_streams[slot];
+    Work w;
+    (void)hipSetDevice(ctx->device);
+    for (;;) {
+        std::vector<std::shared_ptr<Request>> batch;
+        uint64_t batch_bytes = 0;
+        {
+            std::unique_lock<std::mutex> lk(ctx->q_mu);
+            ctx->q_cv.wait(lk, [&] { return ctx->stopping || !ctx->queue.empty(); });
+            if (ctx->stopping && ctx->queue.empty()) return;
+            // admission in arrival order while the footprint fits under the cap
+            const uint64_t cap = ctx->al->cap();
+            while (!ctx->queue.empty() && batch.size() < kServeBatchMax) {
+                auto &r = ctx->queue.front();
+                bool fits = !cap || ctx->admitted_bytes + r->footprint <= cap || ctx->admitted_bytes == 0;
+                if (!fits) break;
+                ctx->admitted_bytes += r->footprint;
+                batch_bytes += r->footprint;
+                batch.push_back(r);
+                ctx->queue.pop_front();
+            }
+            if (batch.empty()) {
+                // wait until another worker releases memory
+                ctx->q_cv.wait_for(lk, std::chrono::milliseconds(1));
+                continue;
+            }
+        }
+        // COO requests of the batch are built together; prebuilt graphs are
+        // counted through their own sets
+        std::vector<std::shared_ptr<Request>> coo, pre;
+        for (auto &r : batch) (r->set ? pre : coo).push_back(r);
+        auto finish = [&](const std::shared_ptr<Request> &r, bbc_status st, int64_t v) {
+            std::lock_guard<std::mutex> lk(ctx->q_mu);
+            r->status = st;
+            r->result = v;
+            r->done = true;
+            r->eu.clear(); r->eu.shrink_to_fit();
+            r->ev.clear(); r->ev.shrink_to_fit();
+            r->sign.clear(); r->sign.shrink_to_fit();
+        };
+        if (!coo.empty()) {
+            // group by sign encoding / anchor flags
+            std::map<uint32_t, std::vector<std::shared_ptr<Request>>> by_flags;
+            for (auto &r : coo) by_flags[r->flags].push_back(r);
+            for (auto &kv : by_flags) {
+                auto &rs = kv.second;
+                const uint32_t flags = kv.first;
+                std::vector<uint32_t> nu(rs.size()), nv(rs.size());
+                std::vector<uint64_t> off(rs.size() + 1, 0);
+                for (size_t i = 0; i < rs.size(); i++) {
+                    nu[i] = rs[i]->n_u; nv[i] = rs[i]->n_v;
+                    off[i + 1] = off[i] + rs[i]->m;
+                }
+                const uint64_t M = off.back();
+                std::vector<uint32_t> eu(M), ev(M);
+                std::vector<uint8_t> sg(sign_bytes(M, flags));
+                bool packed = flags & BBC_SIGNS_2BIT_PACKED;
+                for (size_t i = 0; i < rs.size(); i++) {
+                    std::copy(rs[i]->eu.begin(), rs[i]->eu.end(), eu.begin() + off[i]);
+                    std::copy(rs[i]->ev.begin(), rs[i]->ev.end(), ev.begin() + off[i]);
+                    if (!packed) {
+                        std::copy(rs[i]->sign.begin(), rs[i]->sign.end(), sg.begin() + off[i]);
+                    } else {
+                        for (uint64_t e = 0; e < rs[i]->m; e++) {
+                            uint32_t code = (rs[i]->sign[e >> 2] >> (2 * (e & 3))) & 3u;
+                            uint64_t t = off[i] + e;
+                            sg[t >> 2] |= (uint8_t)(code << (2 * (t & 3)));
+                        }
+                    }
+                }
+                CooIn in{(uint32_t)rs.size(), nu.data(), nv.data(), off.data(), eu.data(), ev.data(),
+                         sg.data(), flags & ~BBC_IN_DEVICE_PTRS};
+                std::vector<int64_t> res(rs.size());
+                bbc_status st = guard(nullptr, [&] {
+                    auto set = build_set(ctx, in, s);
+                    count_sync(ctx, w, *set, 0, set->G, 0, default_shape(), s, res.data());
+                });
+                if (st != BBC_OK && rs.size() > 1) {
+                    // isolate the failing request: count each alone
+                    for (size_t i = 0; i < rs.size(); i++) {
+                        uint64_t o2[2] = {0, rs[i]->m};
+                        CooIn one{1, &nu[i], &nv[i], o2, rs[i]->eu.data(), rs[i]->ev.data(),
+                                  rs[i]->sign.data(), flags & ~BBC_IN_DEVICE_PTRS};
+                        int64_t v = 0;
+                        bbc_status st1 = guard(nullptr, [&] {
+                            auto set = build_set(ctx, one, s);
+                            count_sync(ctx, w, *set, 0, 1, 0, default_shape(), s, &v);
+                        });
+                        finish(rs[i], st1, v);
+                    }
+                } else {
+                    for (size_t i = 0; i < rs.size(); i++) finish(rs[i], st, res[i]);
+                }
+            }
+        }
+        for (auto &r : pre) {
+            int64_t v = 0;
+            bbc_status st = guard(nullptr, [&] {
+                count_sync(ctx, w, *r->set, r->idx, r->idx + 1, 0, default_shape(), s, &v);
+            });
+            finish(r, st, v);
+        }
+        {
+            std::lock_guard<std::mutex> lk(ctx->q_mu);
+            ctx->admitted_bytes -= batch_bytes;
+        }
+        ctx->done_cv.notify_all();
+        ctx->q_cv.notify_all();
+    }
+}
+
+void start_serving(bbc_ctx *ctx)
+{
+    if (!ctx->workers.empty()) return;
+    for (int i = 0; i < kServeStreams; i++) {
+        hipStream_t s;
+        HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        ctx->serve_streams.push_back(s);
+    }
+    for (int i = 0; i < kServeStreams; i++) ctx->workers.emplace_back(serve_worker, ctx, i);
+}
+
+bbc_ticket enqueue_request(bbc_ctx *ctx, std::shared_ptr<Request> r)
+{
+    std::lock_guard<std::mutex> lk(ctx->q_mu);
+    if (ctx->workers.empty()) start_serving(ctx);
+    r->id = ctx->next_ticket++;
+    ctx->requests[r->id] = r;
+    ctx->queue.push_back(r);
+    ctx->q_cv.notify_one();
+    return r->id;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char *bbc_status_string(bbc_status s)
+{
+    switch (s) {
+        case BBC_OK: return "ok";
+        case BBC_E_INVAL: return "invalid argument";
+        case BBC_E_RANGE: return "edge endpoint out of range";
+        case BBC_E_SIGN: return "invalid edge sign";
+        case BBC_E_DUP_EDGE: return "duplicate edge";
+        case BBC_E_NOMEM: return "out of device memory or over the memory cap";
+        case BBC_E_OVERFLOW: return "count does not fit in int64";
+        case BBC_E_UNSUPPORTED: return "unsupported (only p = q = 3)";
+        case BBC_E_NOT_READY: return "request not finished";
+        case BBC_E_UNKNOWN_TICKET: return "unknown ticket";
+        case BBC_E_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *bbc_last_error(bbc_ctx *ctx)
+{
+    if (!ctx) return "null context";
+    return ctx->last_error.c_str();
+}
+
+bbc_status bbc_ctx_create(int device, void *hip_stream, uint64_t mem_cap_bytes, bbc_ctx **out)
+{
+    if (!out) return BBC_E_INVAL;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) { (void)hipGetLastError(); return BBC_E_HIP; }
+    if (device < 0 || device >= n) return BBC_E_INVAL;
+    std::unique_ptr<bbc_ctx> ctx(new (std::nothrow) bbc_ctx());
+    if (!ctx) return BBC_E_NOMEM;
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess) { (void)hipGetLastError(); return BBC_E_HIP; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
+    ctx->al.reset(new Allocator(mem_cap_bytes));
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return BBC_E_HIP;
+        }
+        ctx->own_stream = true;
+    }
+    *out = ctx.release();
+    return BBC_OK;
+}
+
+void bbc_ctx_destroy(bbc_ctx *ctx)
+{
+    if (!ctx) return;
+    {
+        std::lock_guard<std::mutex> lk(ctx->q_mu);
+        ctx->stopping = true;
+    }
+    ctx->q_cv.notify_all();
+    for (auto &t : ctx->workers) t.join();
+    for (auto s : ctx->serve_streams) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->requests.clear();
+    ctx->queue.clear();
+    if (ctx->work.exec) { (void)hipGraphExecDestroy(ctx->work.exec); ctx->work.exec = nullptr; }
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+bbc_status bbc_build_csr(bbc_ctx *ctx, uint32_t n_u, uint32_t n_v, uint64_t n_edges,
+                         const uint32_t *eu, const uint32_t *ev, const void *sign, uint32_t flags,
+                         bbc_graph **out)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return guard(ctx, [&] {
+        if (!out) fail(BBC_E_INVAL, "null output pointer");
+        (void)hipSetDevice(ctx->device);
+        uint64_t off[2] = {0, n_edges};
+        CooIn in{1, &n_u, &n_v, off, eu, ev, sign, flags};
+        auto set = build_set(ctx, in, ctx->stream);
+        *out = new bbc_graph{set, 0};
+    });
+}
+
+bbc_status bbc_build_csr_batch(bbc_ctx *ctx, uint32_t n_graphs, const uint32_t *n_u,
+                               const uint32_t *n_v, const uint64_t *edge_offsets,
+                               const uint32_t *eu, const uint32_t *ev, const void *sign,
+                               uint32_t flags, bbc_graph **out_graphs)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return guard(ctx, [&] {
+        if (!out_graphs || !n_u || !n_v || !edge_offsets) fail(BBC_E_INVAL, "null argument");
+        if (n_graphs == 0) fail(BBC_E_INVAL, "n_graphs is 0");
+        (void)hipSetDevice(ctx->device);
+        CooIn in{n_graphs, n_u, n_v, edge_offsets, eu, ev, sign, flags};
+        auto set = build_set(ctx, in, ctx->stream);
+        std::vector<bbc_graph *> hs(n_graphs, nullptr);
+        for (uint32_t i = 0; i < n_graphs; i++) hs[i] = new bbc_graph{set, i};
+        std::copy(hs.begin(), hs.end(), out_graphs);
+    });
+}
+
+bbc_status bbc_graph_free(bbc_ctx *ctx, bbc_graph *g)
+{
+    if (!ctx || !g) return BBC_E_INVAL;
+    delete g;
+    return BBC_OK;
+}
+
+bbc_status bbc_get_graph_info(bbc_ctx *ctx, const bbc_graph *g, bbc_graph_info *out)
+{
+    if (!ctx || !g || !out) return BBC_E_INVAL;
+    const GraphDesc &d = g->set->desc[g->idx];
+    out->n_u = d.n_u;
+    out->n_v = d.n_v;
+    out->n_edges = d.m;
+    out->anchor_side = (int32_t)d.side;
+    out->device_bytes = g->set->G == 1 ? g->set->device_bytes()
+                                       : (uint64_t)((double)g->set->device_bytes() * d.m /
+                                                    std::max<uint64_t>(g->set->M, 1));
+    return BBC_OK;
+}
+
+bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int64_t *out_count)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return guard(ctx, [&] {
+        if (!g || !out_count) fail(BBC_E_INVAL, "null argument");
+        if (p != 3 || q != 3) fail(BBC_E_UNSUPPORTED, "only (p, q) = (3, 3) is supported");
+        (void)hipSetDevice(ctx->device);
+        int64_t v = 0;
+        count_sync(ctx, ctx->work, *g->set, g->idx, g->idx + 1, 0, default_shape(), ctx->stream, &v);
+        *out_count = v;
+    });
+}
+
+bbc_status bbc_count_per_vertex(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int side,
+                                int64_t *out_per_vertex, int64_t *out_count)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return guard(ctx, [&] {
+        if (!g || !out_per_vertex) fail(BBC_E_INVAL, "null argument");
+        if (p != 3 || q != 3) fail(BBC_E_UNSUPPORTED, "only (p, q) = (3, 3) is supported");
+        if (side != 0 && side != 1) fail(BBC_E_INVAL, "side must be 0 (U) or 1 (V)");
+        (void)hipSetDevice(ctx->device);
+        GraphSet &set = *g->set;
+        const GraphDesc &d = set.desc[g->idx];
+        const int mode = (uint32_t)side == d.side ? 1 : 2;
+        int64_t v = 0;
+        count_sync(ctx, ctx->work, set, g->idx, g->idx + 1, mode, default_shape(), ctx->stream, &v);
+        Work &w = ctx->work;
+        if (mode == 1) {
+            const uint32_t n = d.n_s;
+            std::vector<uint64_t> pv(n);
+            std::vector<uint32_t> vert(n);
+            if (n) {
+                HIP_OK(hipMemcpyAsync(pv.data(), w.pv.as<uint64_t>() + d.s_base, n * 8ull,
+                                      hipMemcpyDeviceToHost, ctx->stream));
+                HIP_OK(hipMemcpyAsync(vert.data(), set.s_vert.as<uint32_t>() + d.s_base, n * 4ull,
+                                      hipMemcpyDeviceToHost, ctx->stream));
+                HIP_OK(hipStreamSynchronize(ctx->stream));
+            }
+            std::vector<int64_t> res(n, 0);
+            for (uint32_t i = 0; i < n; i++) {
+                if (pv[i] > (uint64_t)INT64_MAX) fail(BBC_E_OVERFLOW, "per-vertex count exceeds int64");
+                res[vert[i]] = (int64_t)pv[i];
+            }
+            std::copy(res.begin(), res.end(), out_per_vertex);
+        } else {
+            const uint32_t n = d.n_o;
+            std::vector<uint64_t> pv(n);
+            if (n) {
+                HIP_OK(hipMemcpyAsync(pv.data(), w.pv_o.as<uint64_t>() + d.o_base, n * 8ull,
+                                      hipMemcpyDeviceToHost, ctx->stream));
+                HIP_OK(hipStreamSynchronize(ctx->stream));
+            }
+            for (uint32_t i = 0; i < n; i++) {
+                if (pv[i] > (uint64_t)INT64_MAX) fail(BBC_E_OVERFLOW, "per-vertex count exceeds int64");
+                out_per_vertex[i] = (int64_t)pv[i];
+            }
+        }
+        if (out_count) *out_count = v;
+    });
+}
+
+bbc_status bbc_count_batch(bbc_ctx *ctx, const bbc_graph *const *graphs, uint32_t n_graphs,
+                           int64_t *out_counts)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return guard(ctx, [&] {
+        if ((!graphs || !out_counts) && n_graphs) fail(BBC_E_INVAL, "null argument");
+        for (uint32_t i = 0; i < n_graphs; i++)
+            if (!graphs[i]) fail(BBC_E_INVAL, "null graph %u", i);
+        (void)hipSetDevice(ctx->device);
+        std::vector<int64_t> res(n_graphs, 0);
+        uint32_t i = 0;
+        while (i < n_graphs) {
+            GraphSet *set = graphs[i]->set.get();
+            // the whole set in its own order: one batched replay
+            if (graphs[i]->idx == 0 && i + set->G <= n_graphs) {
+                bool whole = true;
+                for (uint32_t j = 0; j < set->G && whole; j++)
+                    whole = graphs[i + j]->set.get() == set && graphs[i + j]->idx == j;
+                if (whole) {
+                    count_set_batched(ctx, ctx->work, *set, ctx->stream, res.data() + i);
+                    i += set->G;
+                    continue;
+                }
+            }
+            // otherwise a contiguous run of one set
+            uint32_t j = i + 1;
+            while (j < n_graphs && graphs[j]->set.get() == set && graphs[j]->idx == graphs[j - 1]->idx + 1) j++;
+            count_sync(ctx, ctx->work, *set, graphs[i]->idx, graphs[j - 1]->idx + 1, 0,
+                       default_shape(), ctx->stream, res.data() + i);
+            i = j;
+        }
+        std::copy(res.begin(), res.end(), out_counts);
+    });
+}
+
+bbc_status bbc_submit(bbc_ctx *ctx, const bbc_graph *g, bbc_ticket *out)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return guard(ctx, [&] {
+        if (!g || !out) fail(BBC_E_INVAL, "null argument");
+        auto r = std::make_shared<Request>();
+        r->set = g->set;
+        r->idx = g->idx;
+        const GraphDesc &d = g->set->desc[g->idx];
+        r->footprint = footprint_estimate(d.m, 0, 0);
+        *out = enqueue_request(ctx, r);
+    });
+}
+
+bbc_status bbc_submit_coo(bbc_ctx *ctx, uint32_t n_u, uint32_t n_v, uint64_t n_edges,
+                          const uint32_t *eu, const uint32_t *ev, const void *sign, uint32_t flags,
+                          bbc_ticket *out)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return guard(ctx, [&] {
+        if (!out) fail(BBC_E_INVAL, "null output pointer");
+        check_flags(flags);
+        if (flags & BBC_IN_DEVICE_PTRS) fail(BBC_E_INVAL, "bbc_submit_coo takes host arrays");
+        if (n_edges && (!eu || !ev || !sign)) fail(BBC_E_INVAL, "null edge array");
+        auto r = std::make_shared<Request>();
+        r->n_u = n_u; r->n_v = n_v; r->m = n_edges; r->flags = flags;
+        r->eu.assign(eu, eu + n_edges);
+        r->ev.assign(ev, ev + n_edges);
+        const uint8_t *sp = (const uint8_t *)sign;
+        r->sign.assign(sp, sp + sign_bytes(n_edges, flags));
+        r->footprint = footprint_estimate(n_edges, n_u, n_v);
+        *out = enqueue_request(ctx, r);
+    });
+}
+
+static bbc_status take_result(bbc_ctx *ctx, bbc_ticket t, int64_t *out_count, bool block)
+{
+    std::unique_lock<std::mutex> lk(ctx->q_mu);
+    auto it = ctx->requests.find(t);
+    if (it == ctx->requests.end()) return BBC_E_UNKNOWN_TICKET;
+    std::shared_ptr<Request> r = it->second;
+    if (block) ctx->done_cv.wait(lk, [&] { return r->done; });
+    if (!r->done) return BBC_E_NOT_READY;
+    ctx->requests.erase(it);
+    if (r->status == BBC_OK && out_count) *out_count = r->result;
+    return r->status;
+}
+
+bbc_status bbc_poll(bbc_ctx *ctx, bbc_ticket t, int64_t *out_count)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return take_result(ctx, t, out_count, false);
+}
+
+bbc_status bbc_wait(bbc_ctx *ctx, bbc_ticket t, int64_t *out_count)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return take_result(ctx, t, out_count, true);
+}
+
+bbc_status bbc_get_last_stats(bbc_ctx *ctx, bbc_count_stats *out)
+{
+    if (!ctx || !out) return BBC_E_INVAL;
+    *out = ctx->stats;
+    return BBC_OK;
+}
+
+}  // extern "C"

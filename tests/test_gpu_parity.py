@@ -1,0 +1,311 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Counts are integers, so every comparison is exact (tolerance 0).
+"""
+import hashlib
+import math
+
+import numpy as np
+import pytest
+
+from paper_2605_03603_amd import generators as G
+from tests.gpu_common import build, golden, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    from paper_2605_03603_amd import bbc
+    c = bbc.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2605_03603_amd import bbc
+    return bbc
+
+
+def C3(n):
+    return math.comb(n, 3)
+
+
+# ------------------------------------------------------------ paper pins
+def test_fig1b_and_fig4(ctx, oracle):
+    say("fig1b")
+    g = G.from_rows(["++++", "++++", "-+++", "--++"])
+    h = build(ctx, g)
+    assert ctx.count_global(h) == 1
+    pu, tot = ctx.count_per_vertex(h, 0)
+    assert tot == 1 and list(pu) == [1, 1, 1, 0]
+    pv, _ = ctx.count_per_vertex(h, 1)
+    assert list(pv) == [0, 1, 1, 1]
+    say("fig4")
+    g4 = G.from_rows(["++++", "+++.", "++.+", "+.++"])
+    assert ctx.count_global(build(ctx, g4)) == 0
+
+
+@pytest.mark.parametrize("n,m", [(3, 3), (5, 7), (40, 3), (70, 70), (130, 20)])
+def test_complete_bipartite(ctx, n, m):
+    say("complete", n, m)
+    rows = ["+" * m] * n
+    g = G.from_rows(rows)
+    assert ctx.count_global(build(ctx, g)) == C3(n) * C3(m)
+    for side in (0, 1):
+        pv, tot = ctx.count_per_vertex(build(ctx, g), side)
+        k, other = (n, m) if side == 0 else (m, n)
+        assert tot == C3(n) * C3(m)
+        assert (pv == math.comb(k - 1, 2) * C3(other)).all()
+
+
+def test_two_block_closed_form(ctx):
+    say("two-block")
+    for (n1, n2, m1, m2) in [(3, 4, 4, 3), (10, 20, 15, 5), (33, 31, 40, 2)]:
+        n, m = n1 + n2, m1 + m2
+        rows = ["".join("-" if (i >= n1 and j >= m1) else "+" for j in range(m)) for i in range(n)]
+        g = G.from_rows(rows)
+        pure = C3(n1) + C3(n2)
+        want = pure * C3(m) + (C3(n) - pure) * (C3(m1) + C3(m2))
+        for flags in (0, 1 << 4, 1 << 5):
+            assert ctx.count_global(build(ctx, g, flags)) == want
+
+
+# --------------------------------------------------------- random tiny
+def test_tiny_random_batch_vs_bruteforce(ctx, oracle):
+    say("tiny batch")
+    rng = np.random.default_rng(4242)
+    gs = [G.tiny_random(rng, 9, 9) for _ in range(1500)]
+    want = [oracle.count_bruteforce(g) for g in gs]
+    nu, nv, off, eu, ev, sg = G.concat(gs)
+    hs = ctx.build_csr_batch(nu, nv, off, eu, ev, sg)
+    got = ctx.count_batch(hs)
+    assert list(got) == want
+    # the same graphs one at a time, forced to each side
+    for i in range(0, 1500, 37):
+        for flags in (1 << 4, 1 << 5):
+            assert ctx.count_global(build(ctx, gs[i], flags)) == want[i], i
+
+
+def test_tiny_per_vertex(ctx, oracle):
+    say("tiny per-vertex")
+    rng = np.random.default_rng(77)
+    for it in range(120):
+        g = G.tiny_random(rng, 8, 8, density=0.8)
+        b, pu, pv = oracle.count_bruteforce(g, per_vertex=True)
+        h = build(ctx, g, 1 << (4 + it % 2))
+        gu, t = ctx.count_per_vertex(h, 0)
+        gv, _ = ctx.count_per_vertex(h, 1)
+        assert t == b and (gu == pu).all() and (gv == pv).all(), it
+
+
+# -------------------------------------------------------- config sizes
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_config1(ctx, oracle, seed):
+    say("config1 seed", seed)
+    g = G.config1(seed)
+    r0 = oracle.count_bbvp(g, 0, per_vertex=True)
+    r1 = oracle.count_bbvp(g, 1, per_vertex=True)
+    for flags in (0, 1 << 4, 1 << 5, 1 << 6):
+        h = build(ctx, g, flags)
+        assert ctx.count_global(h) == r0["total"]
+    h = build(ctx, g)
+    pu, t = ctx.count_per_vertex(h, 0)
+    pv, _ = ctx.count_per_vertex(h, 1)
+    assert t == r0["total"]
+    assert (pu == r0["per_vertex"]).all() and (pv == r1["per_vertex"]).all()
+
+
+@pytest.mark.parametrize("scale", [0.02, 0.1])
+def test_config2_scaled(ctx, oracle, scale):
+    say("config2 scale", scale)
+    g = G.config2(3, scale=scale)
+    r = oracle.count_bbvp(g, 0, threads=8, per_vertex=True)
+    for flags in (0, 1 << 4, 1 << 5):
+        assert ctx.count_global(build(ctx, g, flags)) == r["total"]
+    pu, t = ctx.count_per_vertex(build(ctx, g), 0)
+    assert t == r["total"] and (pu == r["per_vertex"]).all()
+
+
+def test_sign_encodings(ctx, B):
+    say("sign encodings")
+    g = G.config2(5, scale=0.02)
+    want = ctx.count_global(build(ctx, g))
+    packed = B.pack_signs_2bit(g.sign)
+    h = ctx.build_csr(g.n_u, g.n_v, g.eu, g.ev, packed, B.BBC_SIGNS_2BIT_PACKED)
+    assert ctx.count_global(h) == want
+    s01 = (g.sign > 0).astype(np.int8)
+    h = ctx.build_csr(g.n_u, g.n_v, g.eu, g.ev, s01, B.BBC_SIGNS_01)
+    assert ctx.count_global(h) == want
+
+
+def test_device_pointer_input(ctx):
+    say("device pointers")
+    import torch
+    g = G.config1(2)
+    want = ctx.count_global(build(ctx, g))
+    d = torch.device("cuda:0")
+    eu = torch.from_numpy(g.eu.astype(np.int32)).to(d)
+    ev = torch.from_numpy(g.ev.astype(np.int32)).to(d)
+    sg = torch.from_numpy(g.sign).to(d)
+    torch.cuda.synchronize()
+    h = ctx.build_csr(g.n_u, g.n_v, eu, ev, sg)
+    assert ctx.count_global(h) == want
+
+
+# ------------------------------------------------ edge and error cases
+def test_degenerate_inputs(ctx):
+    say("degenerate")
+    e = np.zeros(0, np.uint32)
+    s = np.zeros(0, np.int8)
+    assert ctx.count_global(ctx.build_csr(0, 0, e, e, s)) == 0
+    assert ctx.count_global(ctx.build_csr(5, 7, e, e, s)) == 0
+    assert ctx.count_global(build(ctx, G.from_rows(["+++", "+++"]))) == 0
+    one = ctx.build_csr(3, 3, np.array([1], np.uint32), np.array([2], np.uint32), np.array([-1], np.int8))
+    assert ctx.count_global(one) == 0
+    pv, t = ctx.count_per_vertex(ctx.build_csr(4, 0, e, e, s), 0)
+    assert t == 0 and list(pv) == [0, 0, 0, 0]
+
+
+def test_invalid_inputs(ctx, B):
+    say("invalid inputs")
+    u = np.array([0, 1, 1], np.uint32)
+    v = np.array([0, 0, 0], np.uint32)
+    s = np.array([1, 1, -1], np.int8)
+    with pytest.raises(B.BBCError) as ei:
+        ctx.build_csr(2, 2, u, v, s)
+    assert ei.value.name == "BBC_E_DUP_EDGE"
+    with pytest.raises(B.BBCError) as ei:
+        ctx.build_csr(2, 2, np.array([0, 2], np.uint32), np.array([0, 1], np.uint32), np.array([1, 1], np.int8))
+    assert ei.value.name == "BBC_E_RANGE"
+    with pytest.raises(B.BBCError) as ei:
+        ctx.build_csr(2, 2, np.array([0, 1], np.uint32), np.array([0, 1], np.uint32), np.array([1, 0], np.int8))
+    assert ei.value.name == "BBC_E_SIGN"
+    h = build(ctx, G.config1(1))
+    with pytest.raises(B.BBCError) as ei:
+        ctx.count_global(h, 4, 3)
+    assert ei.value.name == "BBC_E_UNSUPPORTED"
+    # the context is still usable after errors
+    assert ctx.count_global(h) > 0
+
+
+def test_heavy_anchors_all_tiers(ctx, oracle):
+    """Anchors whose tables overflow the 4096-slot tier, masks wider than 16
+    words, and degrees above 1024 (global-memory tier)."""
+    say("heavy anchors")
+    rng = np.random.default_rng(8)
+    # a dense core: 40 U vertices adjacent to ~1100 V vertices each
+    n_u, n_v = 60, 1300
+    dense = rng.random((n_u, n_v)) < np.where(np.arange(n_u)[:, None] < 40, 0.9, 0.05)
+    u, v = np.nonzero(dense)
+    s = np.where(rng.random(u.size) < 0.8, 1, -1).astype(np.int8)
+    g = G._finish(n_u, n_v, u, v, s)
+    r = oracle.count_bbvp(g, 0, threads=8)
+    assert ctx.count_global(build(ctx, g, 1 << 4)) == r["total"]
+    # V-anchored: many distinct 2-hop partners per anchor (hash overflow tiers)
+    assert ctx.count_global(build(ctx, g, 1 << 5)) == r["total"]
+    pu, t = ctx.count_per_vertex(build(ctx, g), 0)
+    assert t == r["total"]
+    assert (pu == oracle.count_bbvp(g, 0, threads=8, per_vertex=True)["per_vertex"]).all()
+
+
+def test_two_hop_overflow(ctx, oracle):
+    """Low-degree anchors adjacent to hubs: > 3072 distinct higher-priority
+    partners per anchor."""
+    say("two-hop overflow")
+    rng = np.random.default_rng(9)
+    n_u, n_v = 20000, 400
+    eu, ev = [], []
+    hubs = np.arange(6)
+    for h in hubs:                       # 6 hub V vertices adjacent to most U
+        us = rng.choice(n_u, 6000, replace=False)
+        eu.append(us); ev.append(np.full(us.size, h))
+    others = rng.integers(6, n_v, size=40000)
+    eu.append(rng.integers(0, n_u, size=others.size)); ev.append(others)
+    u = np.concatenate(eu); v = np.concatenate(ev)
+    key = np.unique(u.astype(np.int64) * n_v + v)
+    u, v = key // n_v, key % n_v
+    s = np.where(rng.random(u.size) < 0.7, 1, -1).astype(np.int8)
+    g = G._finish(n_u, n_v, u, v, s)
+    r = oracle.count_bbvp(g, 0, threads=8)
+    assert ctx.count_global(build(ctx, g, 1 << 4)) == r["total"]
+    assert ctx.count_global(build(ctx, g, 1 << 5)) == r["total"]
+    st = ctx.last_stats()
+    say("stats", st)
+
+
+# ------------------------------------------------------------ batching
+def test_config4_batch(ctx, oracle):
+    say("config4 batch of 200")
+    gs = G.config4(7, n_graphs=200)
+    want = [oracle.count_bbvp(g, 0, threads=8)["total"] for g in gs]
+    nu, nv, off, eu, ev, sg = G.concat(gs)
+    hs = ctx.build_csr_batch(nu, nv, off, eu, ev, sg)
+    got = ctx.count_batch(hs)
+    assert list(got) == want
+    again = ctx.count_batch(hs)          # replay of the captured launch
+    assert list(again) == want
+    for i in range(0, 200, 23):
+        assert ctx.count_global(hs[i]) == want[i]
+    # a sub-range and a permuted list of the same graphs
+    sub = ctx.count_batch(hs[10:50])
+    assert list(sub) == want[10:50]
+    perm = list(range(199, -1, -3))
+    assert list(ctx.count_batch([hs[i] for i in perm])) == [want[i] for i in perm]
+    assert sum(want) > 0
+
+
+# -------------------------------------------------------------- serving
+def test_serving_mix_matches_alone(ctx, oracle, B):
+    say("serving")
+    rng = np.random.default_rng(31)
+    gs = G.config4(11, n_graphs=60) + [G.config2(2, scale=0.05)]
+    want = [oracle.count_bbvp(g, 0, threads=8)["total"] for g in gs]
+    order = rng.permutation(len(gs))
+    tickets = {}
+    for i in order:
+        g = gs[i]
+        tickets[i] = ctx.submit_coo(g.n_u, g.n_v, g.eu, g.ev, g.sign)
+    got = {i: ctx.wait(t) for i, t in tickets.items()}
+    assert [got[i] for i in range(len(gs))] == want
+    # poll semantics
+    t = ctx.submit_coo(gs[0].n_u, gs[0].n_v, gs[0].eu, gs[0].ev, gs[0].sign)
+    while True:
+        v = ctx.poll(t)
+        if v is not None:
+            break
+    assert v == want[0]
+    with pytest.raises(B.BBCError) as ei:
+        ctx.poll(t)
+    assert ei.value.name == "BBC_E_UNKNOWN_TICKET"
+    # a bad request fails alone
+    bad = ctx.submit_coo(2, 2, np.array([0, 0], np.uint32), np.array([1, 1], np.uint32),
+                         np.array([1, 1], np.int8))
+    good = ctx.submit_coo(gs[1].n_u, gs[1].n_v, gs[1].eu, gs[1].ev, gs[1].sign)
+    with pytest.raises(B.BBCError) as ei:
+        ctx.wait(bad)
+    assert ei.value.name == "BBC_E_DUP_EDGE"
+    assert ctx.wait(good) == want[1]
+    # prebuilt graphs through submit
+    hs = [build(ctx, gs[i]) for i in range(5)]
+    ts = [ctx.submit(h) for h in hs]
+    assert [ctx.wait(t) for t in ts] == want[:5]
+
+
+# --------------------------------------------------- full-size configs
+def test_config2_full(ctx):
+    gold = golden("cfg2_seed1.json")
+    say("config2 full")
+    g = G.config2(1)
+    assert g.m == gold["m"]
+    h = build(ctx, g)
+    assert ctx.count_global(h) == gold["total"]
+    pu, t = ctx.count_per_vertex(h, 0)
+    assert t == gold["total"]
+    assert hashlib.sha256(pu.astype("<i8").tobytes()).hexdigest() == gold["per_u_sha256"]
+    pv, _ = ctx.count_per_vertex(h, 1)
+    assert hashlib.sha256(pv.astype("<i8").tobytes()).hexdigest() == gold["per_v_sha256"]
+    for flags in (1 << 4, 1 << 5):
+        assert ctx.count_global(build(ctx, g, flags)) == gold["total"]
