@@ -146,16 +146,27 @@ bbc_status bbc_poll(bbc_ctx *ctx, bbc_ticket t, int64_t *out_count);
 /* Blocks until the request is done; same results as bbc_poll otherwise. */
 bbc_status bbc_wait(bbc_ctx *ctx, bbc_ticket t, int64_t *out_count);
 
-/* Statistics of the last count on this context (for measurement). */
+/* Statistics of the last count on this context (for measurement). The
+ * kernel times are filled only while timing is enabled (bbc_set_timing):
+ * they come from HIP events recorded on the context's stream around each
+ * phase of the last synchronous build and count. */
 typedef struct {
-    uint64_t active_anchors;    /* anchors with at least two candidate classes */
+    uint64_t active_anchors;    /* anchor records written (anchors with >= 2 candidate classes) */
     uint64_t virtual_candidates;/* (partner, sign class) pairs with >= 3 shared neighbours */
     uint64_t pair_units;        /* triplet-kernel work units */
     uint64_t candidate_pairs;   /* pairs of candidate classes examined */
-    uint64_t mask_words;        /* 32-bit mask words written by the pair-table kernel */
+    uint64_t mask_words;        /* 32-bit mask words reserved by the pair-table kernel */
     uint64_t wedges;            /* 2-hop wedges scanned (oriented, pruned) */
+    uint64_t pair_words;        /* sum over examined pairs of the mask width in words */
+    float ms_build;             /* last bbc_build_csr: ingest .. adjacency kernels */
+    float ms_pair;              /* pair-table kernels (all tiers) */
+    float ms_plan;              /* unit planning */
+    float ms_triplet;           /* triplet kernel */
+    uint32_t attempts;          /* launches of the count sequence (1 unless buffers grew) */
 } bbc_count_stats;
 bbc_status bbc_get_last_stats(bbc_ctx *ctx, bbc_count_stats *out);
+/* Enable (1) or disable (0) per-phase event timing on this context. */
+bbc_status bbc_set_timing(bbc_ctx *ctx, int enable);
 
 const char *bbc_status_string(bbc_status s);
 /* Detail of the last error on this context (empty string if none). */

@@ -36,7 +36,7 @@ BBC_ANCHOR_SMALLER = 1 << 6
 EXPORTED = ["bbc_ctx_create", "bbc_ctx_destroy", "bbc_build_csr", "bbc_build_csr_batch",
             "bbc_graph_free", "bbc_get_graph_info", "bbc_count_global", "bbc_count_per_vertex",
             "bbc_count_batch", "bbc_submit", "bbc_submit_coo", "bbc_poll", "bbc_wait",
-            "bbc_get_last_stats", "bbc_status_string", "bbc_last_error"]
+            "bbc_get_last_stats", "bbc_set_timing", "bbc_status_string", "bbc_last_error"]
 
 
 class BBCError(RuntimeError):
@@ -54,7 +54,10 @@ class GraphInfo(ctypes.Structure):
 class CountStats(ctypes.Structure):
     _fields_ = [("active_anchors", ctypes.c_uint64), ("virtual_candidates", ctypes.c_uint64),
                 ("pair_units", ctypes.c_uint64), ("candidate_pairs", ctypes.c_uint64),
-                ("mask_words", ctypes.c_uint64), ("wedges", ctypes.c_uint64)]
+                ("mask_words", ctypes.c_uint64), ("wedges", ctypes.c_uint64),
+                ("pair_words", ctypes.c_uint64), ("ms_build", ctypes.c_float),
+                ("ms_pair", ctypes.c_float), ("ms_plan", ctypes.c_float),
+                ("ms_triplet", ctypes.c_float), ("attempts", ctypes.c_uint32)]
 
 
 _vp = ctypes.c_void_p
@@ -88,6 +91,7 @@ def _load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.bbc_poll.argtypes = [_vp, _u64, ctypes.POINTER(ctypes.c_int64)]
     L.bbc_wait.argtypes = [_vp, _u64, ctypes.POINTER(ctypes.c_int64)]
     L.bbc_get_last_stats.argtypes = [_vp, ctypes.POINTER(CountStats)]
+    L.bbc_set_timing.argtypes = [_vp, _i32]
     for name in EXPORTED:
         fn = getattr(L, name)
         if name not in ("bbc_status_string", "bbc_last_error", "bbc_ctx_destroy"):
@@ -222,7 +226,11 @@ class Context:
     def last_stats(self) -> dict:
         s = CountStats()
         self._check(lib.bbc_get_last_stats(self.handle, ctypes.byref(s)))
-        return {k: int(getattr(s, k)) for k, _ in CountStats._fields_}
+        return {k: (float(getattr(s, k)) if k.startswith("ms_") else int(getattr(s, k)))
+                for k, _ in CountStats._fields_}
+
+    def set_timing(self, enable: bool = True):
+        self._check(lib.bbc_set_timing(self.handle, 1 if enable else 0))
 
     # -- serving
     def submit(self, g: Graph) -> int:

@@ -13,7 +13,7 @@ struct PairArgs {
     uint32_t chunk_base;    // triplet unit width in columns for 1-word masks (<= 2048)
     uint32_t gH;            // tier-2 table slots (power of two)
     int glog2h;
-    uint32_t gmaxd, gkmax;  // tier-2 limits
+    uint32_t gmaxd, gkmax;  // degree and candidate limits of tiers 1 and 2
 };
 
 struct TriArgs {
@@ -26,6 +26,9 @@ struct LaunchShape {
 };
 
 hipError_t count_pairs(const PairArgs &P, const LaunchShape &sh, hipStream_t s);
+// cut the anchors' pair matrices into triplet work units
+hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_t tmp_bytes,
+                      hipStream_t s);
 // mode 0: totals only; 1: also per vertex of the anchor side; 2: per vertex of
 // the opposite side
 hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t s);

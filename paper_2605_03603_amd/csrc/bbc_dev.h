@@ -22,6 +22,9 @@ constexpr int kWave = 64;
 //                          entry = (global O index << 1) | (sign < 0)
 //   o_off[NO+1], o_adj[M]: neighbours of O vertex v, sorted by rank;
 //                          entry = (global rank << 1) | (sign < 0)
+//   s_rev[M]               for S position t (edge (r, v)), the position of the
+//                          same edge in o_adj: the neighbours of v ranked above
+//                          r are o_adj[s_rev[t]+1 .. o_off[v+1])
 //   s_graph[NS]            graph of each global rank
 //   s_vert[NS]             the vertex's id inside its graph (input numbering)
 //   o_vert (implicit)      O index - o_base is the id inside the graph
@@ -42,6 +45,7 @@ struct CsrView {
     const uint32_t *s_adj;
     const uint64_t *o_off;
     const uint32_t *o_adj;
+    const uint32_t *s_rev;
     const uint32_t *s_graph;
     const uint32_t *s_vert;
     const GraphDesc *desc;
@@ -77,19 +81,27 @@ struct Unit {
     uint32_t c0, c1;
 };
 
+constexpr int kXcd = 8;   // MI355X: 8 XCDs; workgroup i runs on XCD i % 8
+
+struct alignas(64) Cursor {
+    uint32_t v;
+    uint32_t pad[15];
+};
+
 struct Counters {           // device-side cursors and flags, zeroed per count
     unsigned long long mask_cursor;
     unsigned long long cand_cursor;
     unsigned long long wedges;
-    unsigned long long pairs;
     unsigned long long pairs_examined;
-    uint32_t n_anchor;
-    uint32_t n_units;
-    uint32_t unit_next;
-    uint32_t over_cap;      // a workspace capacity was exceeded
+    unsigned long long pair_words;
+    uint32_t n_anchor;      // anchor records reserved (including unused slots)
+    uint32_t over_cap;      // 1, 2: a workspace capacity was exceeded; 4: unsupported anchor
     uint32_t n_list[3];     // anchors deferred to the next pair tier
-    uint32_t next[4];       // work-queue cursors of the pair tiers
-    uint32_t pad[4];
+    uint32_t n_units;       // written by the plan kernel
+    uint32_t pad0;
+    unsigned long long need_masks, need_cands, need_recs, need_units;   // exact demand
+    Cursor q_pair[3][kXcd]; // work-queue cursors of the pair tiers, one per XCD slice
+    Cursor q_tri[kXcd];
 };
 
 struct Workspace {
@@ -100,6 +112,9 @@ struct Workspace {
     uint32_t *cands;     uint64_t cap_cands;
     uint32_t *defer[2];  uint64_t cap_defer;     // anchors for tier B, tier C
     uint32_t *gtab;      uint64_t gtab_words_per_block; uint32_t gtab_blocks;  // tier C tables
+    uint32_t *bscr;      uint64_t bscr_words_per_block;   // tier B per-block position lists
+    uint32_t *ucnt;      // [cap_anchors] units per anchor record
+    uint64_t *uoff;      // [cap_anchors + 1] exclusive prefix of ucnt
     unsigned long long *count;   // [G] totals
     uint32_t *carry;             // [G] carries out of 64 bits
     unsigned long long *pv;      // [NS] per-vertex (by global rank) or null

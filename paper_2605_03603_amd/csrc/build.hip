@@ -158,8 +158,8 @@ __global__ void __launch_bounds__(kT) k_edge_keys(BuildArgs a)
 }
 
 // Sorted by (rank, O id): emit s_adj, flag repeated pairs, and prepare the
-// (O index -> rank) keys whose stable sort yields the O-side lists in rank
-// order.
+// (O index -> S position) keys whose stable sort yields the O-side lists in
+// rank order. o_ent[t] is the O-side entry of S position t.
 __global__ void __launch_bounds__(kT) k_s_finish(BuildArgs a)
 {
     for (uint64_t t = (uint64_t)blockIdx.x * kT + threadIdx.x; t < a.M;
@@ -170,16 +170,21 @@ __global__ void __launch_bounds__(kT) k_s_finish(BuildArgs a)
         if (t > 0 && a.key0[t - 1] == key) atomicOr(a.err, kErrDup);
         uint32_t r = (uint32_t)(key >> a.obits);
         a.key1[t] = val >> 1;
-        a.val1[t] = (r << 1) | (val & 1);
+        a.val1[t] = (uint32_t)t;
+        a.o_ent[t] = (r << 1) | (val & 1);
     }
 }
 
-__global__ void __launch_bounds__(kT) k_copy_u32(const uint32_t *__restrict__ src,
-                                                 uint32_t *__restrict__ dst, uint64_t n)
+// Sorted by O index (stably, so each O list is in rank order): emit o_adj
+// and, for every S position, the position of the same edge in o_adj.
+__global__ void __launch_bounds__(kT) k_o_finish(BuildArgs a)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * kT)
-        dst[i] = src[i];
+    for (uint64_t t = (uint64_t)blockIdx.x * kT + threadIdx.x; t < a.M;
+         t += (uint64_t)gridDim.x * kT) {
+        uint32_t ts = a.val1[t];
+        a.o_adj[t] = a.o_ent[ts];
+        a.s_rev[ts] = (uint32_t)t;
+    }
 }
 
 __global__ void __launch_bounds__(kT) k_fill_u32(uint32_t *p, uint32_t v, uint64_t n)
@@ -251,7 +256,7 @@ hipError_t build_adjacency(const BuildArgs &a, hipStream_t s)
     // key0/val0 are free again and serve as the ping-pong buffers
     e = radix_sort(a.key1, a.val1, a.key0, a.val0, a.M, a.o_bits, a.tmp, a.tmp_bytes, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_copy_u32, dim3(grid_for(a.M)), dim3(kT), 0, s, a.val1, a.o_adj, a.M);
+    hipLaunchKernelGGL(k_o_finish, dim3(grid_for(a.M)), dim3(kT), 0, s, a);
     return hipGetLastError();
 }
 

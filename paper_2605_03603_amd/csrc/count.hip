@@ -1,5 +1,5 @@
-// count.hip -- the counting kernels: signed pair table and triplet
-// intersection, for balanced (3,3)-bicliques.
+// count.hip -- the counting kernels: signed pair table, unit planning and
+// triplet intersection, for balanced (3,3)-bicliques.
 //
 // For an anchor u1 (the lowest-priority vertex of a triple, Definition 4.1
 // and the orientation rho(w) > rho(u) of Algorithm 2) and a common neighbour v
@@ -10,7 +10,7 @@
 // With M_w^c = { v in N(u1) n N(w) : s(u1,v) s(w,v) = c } for c in {+,-}:
 //     n_(c2,c3) = | M_u2^c2  n  M_u3^c3 |,
 // so the triple's contribution is the sum over the 4 sign choices of
-// C(|M_u2^c2 n M_u3^c3|, 3). This kernel pair therefore works on "virtual
+// C(|M_u2^c2 n M_u3^c3|, 3). The kernels therefore work on "virtual
 // candidates" (w, c): a class set M_w^c with at least 3 members (a smaller
 // one cannot reach C(.,3) > 0 -- this is the pair prune of Algorithm 2 split
 // by sign class). Two virtual candidates of the same w never share a member
@@ -20,17 +20,23 @@
 // M_x is a bitmask over the positions of N(u1); |M_x n M_y| is an AND and a
 // popcount per 32-bit word.
 //
-// k_pair (the signed pair table, Algorithm 2's cnt map split by sign class):
-//   per anchor, 2-hop walk over the higher-priority part of each neighbour
-//   list, counting (same, different) per partner in an LDS hash table; keep
-//   the classes with >= 3; a second walk sets the mask bits; emit masks and
-//   work units. Three tiers: LDS tables of 4096 and 16384 slots, then tables
-//   in global memory for the anchors that overflow them.
-// k_triplet (Algorithm 2's loop over pairs A of C with T = intersection and
-//   the type histogram): one wave per work unit of 64 rows x up to a few
-//   hundred columns of an anchor's lower-triangular pair matrix; row masks in
-//   VGPRs, column masks through scalar loads (wave-uniform), C(n,3) from an
-//   LDS table, 64-bit accumulation, one atomic per unit.
+// k_pair (the signed pair table: Algorithm 2's cnt map split by sign class)
+//   one workgroup per anchor: walk the higher-priority part of each
+//   neighbour's list (found through s_rev, no search), count (same,
+//   different) per partner in an LDS hash table, keep the classes with >= 3,
+//   walk again to set the mask bits, emit masks. Three tiers: 4096- and
+//   16384-slot LDS tables, then global-memory tables for anchors that
+//   overflow them.
+// k_plan_* cut every anchor's lower-triangular pair matrix into work units
+//   (64 rows x up to a few hundred columns), without atomics.
+// k_triplet (Algorithm 2's loop over pairs A of C, T = intersection and the
+//   type histogram): one wave per unit; row masks in VGPRs, column masks by
+//   scalar loads (wave-uniform addresses), C(n,3) from an LDS table; totals
+//   stay in registers until the wave finishes or changes graph.
+//
+// Work queues are split into 8 slices, one per XCD (workgroup i runs on XCD
+// i % 8): a workgroup drains its own slice first, so consecutive anchors
+// and the units of one anchor share an L2, then steals from the others.
 #include "bbc_count.h"
 
 namespace bbc {
@@ -64,15 +70,20 @@ __device__ __forceinline__ AnchorRec load_anchor(const AnchorRec *p)
 }
 
 constexpr uint32_t kEmpty = 0xffffffffu;
-constexpr uint32_t kC3Max = 512;   // C(n,3) table covers masks of up to 16 words
+constexpr uint32_t kC3Max = 512;       // C(n,3) table covers masks of up to 16 words
+constexpr uint32_t kRegW = 16;         // widest mask kept in registers per row
+constexpr uint32_t kWideCols = 32;     // unit width (columns) for wider masks
+constexpr uint32_t kMaskChunk = 1u << 16;   // mask words reserved per workgroup at a time
+constexpr uint32_t kCandChunk = 1u << 13;
+constexpr uint32_t kRecChunk = 16;
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t x, int log2h)
 {
     return (x * 0x9E3779B1u) >> (32 - log2h);
 }
 
-// Insert-or-add into an open-addressing table (linear probing). Returns
-// false when the table is too full (the anchor goes to the next tier).
+// Insert-or-add into an open-addressing table (linear probing); sets *over
+// when the table is too full (the anchor then goes to the next tier).
 __device__ __forceinline__ void hash_add(uint32_t *keys, uint32_t *vals, uint32_t H, int log2h,
                                          uint32_t x, uint32_t inc, uint32_t *used, uint32_t limit,
                                          volatile uint32_t *over)
@@ -108,16 +119,61 @@ __device__ __forceinline__ uint32_t hash_find(const uint32_t *keys, uint32_t H, 
     return H;
 }
 
-__device__ __forceinline__ uint32_t unit_chunk(uint32_t w32, uint32_t base)
+// Columns per work unit for masks of w32 words.
+__host__ __device__ __forceinline__ uint32_t unit_cols(uint32_t w32, uint32_t base)
 {
+    if (w32 > kRegW) return kWideCols;
     uint32_t c = base / w32;
     c = c < 32 ? 32 : c;
     return (c + 7) & ~7u;
 }
 
+__device__ __forceinline__ uint32_t slice_lo(uint32_t n, uint32_t s)
+{
+    return (uint32_t)(((uint64_t)n * s) / kXcd);
+}
+
+// Next chunk [*lo, *hi) of a work range [0, n) split into kXcd slices; the
+// caller starts at its home slice and moves on when a slice is drained.
+// Returns false when every slice is drained.
+__device__ __forceinline__ bool queue_take(Cursor *cur, uint32_t n, uint32_t chunk,
+                                           uint32_t *slice, uint32_t *tried, uint32_t *lo,
+                                           uint32_t *hi)
+{
+    while (*tried < kXcd) {
+        const uint32_t s = *slice;
+        const uint32_t a = slice_lo(n, s), b = slice_lo(n, s + 1);
+        const uint32_t t = atomicAdd(&cur[s].v, chunk);
+        if (t < b - a) {
+            *lo = a + t;
+            *hi = min(a + t + chunk, b);
+            return true;
+        }
+        *slice = (s + 1) % kXcd;
+        (*tried)++;
+    }
+    return false;
+}
+
+__device__ __forceinline__ uint32_t anchor_units(uint32_t k, uint32_t w32, uint32_t base)
+{
+    if (k < 2) return 0;
+    const uint32_t CH = unit_cols(w32, base);
+    const uint32_t nb = (k + kWave - 1) / kWave;
+    uint32_t tot = 0;
+    for (uint32_t b = 0; b < nb; b++) {
+        const uint32_t ncols = min(kWave * (b + 1), k) - 1;
+        tot += (ncols + CH - 1) / CH;
+    }
+    return tot;
+}
+
 struct PairShared {
-    uint32_t item, over, used, nv, skip, aidx, uoff, nunits, wedges;
-    unsigned long long moff, coff;
+    uint32_t item, over, used, nv, skip, wedges;
+    uint32_t qlo, qhi, qslice, qtried;
+    uint32_t aidx, arec_end;
+    unsigned long long moff, mres_end, coff, cres_end;
+    unsigned long long need_m, need_c, need_r, need_u;   // this workgroup's demand
 };
 
 // The per-anchor procedure shared by all tiers. Table storage is passed as
@@ -127,7 +183,7 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
                                           const uint32_t H, const int log2h, uint32_t *pst,
                                           uint32_t *pln, const uint32_t maxd, uint32_t *vc,
                                           const uint32_t kmax, uint32_t *msk,
-                                          const uint32_t maskw, uint32_t *bpre, PairShared &sh)
+                                          const uint32_t maskw, PairShared &sh)
 {
     constexpr int NW = THREADS / kWave;
     const int tid = threadIdx.x, lane = __lane_id(), wv = tid / kWave;
@@ -136,18 +192,40 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
     const uint32_t limit = H - H / 4;
     uint64_t my_wedges = 0;
 
-    for (uint32_t i = tid; i < H; i += THREADS) { keys[i] = kEmpty; vals[i] = 0; }
     const uint32_t n_items =
         P.tier ? (uint32_t)min((uint64_t)__atomic_load_n(&C->n_list[P.tier - 1], __ATOMIC_RELAXED),
                                P.ws.cap_defer)
                : P.a1 - P.a0;
+    if (n_items == 0) return;
     const uint32_t *list = P.tier ? P.ws.defer[P.tier - 1] : nullptr;
     uint32_t *next_list = P.tier < 2 ? P.ws.defer[P.tier] : nullptr;
+
+    for (uint32_t i = tid; i < H; i += THREADS) { keys[i] = kEmpty; vals[i] = 0; }
+    if (tid == 0) {
+        sh.qlo = sh.qhi = 0; sh.qslice = blockIdx.x % kXcd; sh.qtried = 0;
+        sh.moff = sh.mres_end = 0; sh.coff = sh.cres_end = 0;
+        sh.aidx = sh.arec_end = 0;
+        sh.need_m = sh.need_c = sh.need_r = sh.need_u = 0;
+    }
+
+    auto defer_anchor = [&](uint32_t r) {
+        if (next_list) {
+            uint32_t t = atomicAdd(&C->n_list[P.tier], 1u);
+            if (t < P.ws.cap_defer) next_list[t] = r; else atomicOr(&C->over_cap, 1u);
+        } else {
+            atomicOr(&C->over_cap, 4u);
+        }
+    };
 
     for (;;) {
         __syncthreads();
         if (tid == 0) {
-            sh.item = atomicAdd(&C->next[P.tier], 1u);
+            if (sh.qlo >= sh.qhi) {
+                uint32_t lo = 0, hi = 0, s = sh.qslice, tr = sh.qtried;
+                if (!queue_take(C->q_pair[P.tier], n_items, 1, &s, &tr, &lo, &hi)) lo = hi = n_items;
+                sh.qslice = s; sh.qtried = tr; sh.qlo = lo; sh.qhi = hi;
+            }
+            sh.item = sh.qlo < sh.qhi ? sh.qlo++ : n_items;
             sh.over = 0; sh.used = 0; sh.nv = 0; sh.skip = 0; sh.wedges = 0;
         }
         __syncthreads();
@@ -158,31 +236,17 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
         const uint32_t d = (uint32_t)(g.s_off[r + 1] - s0);
         if (d < 3) continue;
         if (d > maxd) {
-            if (tid == 0) {
-                if (next_list) {
-                    uint32_t t = atomicAdd(&C->n_list[P.tier], 1u);
-                    if (t < P.ws.cap_defer) next_list[t] = r; else atomicOr(&C->over_cap, 1u);
-                } else {
-                    atomicOr(&C->over_cap, 4u);
-                }
-            }
+            if (tid == 0) defer_anchor(r);
             continue;
         }
-        // phase 0: the part of each neighbour list above the anchor's rank
+        // phase 0: the part of each neighbour's list ranked above the anchor
         for (uint32_t p = tid; p < d; p += THREADS) {
             const uint32_t e = g.s_adj[s0 + p];
-            const uint32_t v = e >> 1;
-            uint64_t lo = g.o_off[v];
-            const uint64_t hi = g.o_off[v + 1];
-            const uint32_t target = (r + 1) << 1;
-            uint64_t b = hi;
-            while (lo < b) {
-                uint64_t mid = (lo + b) >> 1;
-                if (g.o_adj[mid] < target) lo = mid + 1; else b = mid;
-            }
-            uint32_t len = (uint32_t)(hi - lo);
+            const uint32_t st = g.s_rev[s0 + p] + 1;
+            const uint32_t hi = (uint32_t)g.o_off[(e >> 1) + 1];
+            uint32_t len = hi - st;
             if (len < 2) len = 0;   // v needs 2 higher partners to lie in any T
-            pst[p] = (uint32_t)lo;
+            pst[p] = st;
             pln[p] = len | ((e & 1u) << 31);
             if (len) atomicAdd(&sh.wedges, len);
         }
@@ -227,14 +291,7 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
             defer = sh.nv > kmax;
         }
         if (defer) {
-            if (tid == 0) {
-                if (next_list) {
-                    uint32_t t = atomicAdd(&C->n_list[P.tier], 1u);
-                    if (t < P.ws.cap_defer) next_list[t] = r; else atomicOr(&C->over_cap, 1u);
-                } else {
-                    atomicOr(&C->over_cap, 4u);
-                }
-            }
+            if (tid == 0) defer_anchor(r);
             for (uint32_t i = tid; i < H; i += THREADS) { keys[i] = kEmpty; vals[i] = 0; }
             continue;
         }
@@ -245,26 +302,40 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
         }
         const uint32_t W = (d + 31) >> 5;
         const uint64_t words = (uint64_t)k * W;
-        const uint32_t CH = unit_chunk(W, P.chunk_base);
-        const uint32_t nb = (k + kWave - 1) / kWave;
         if (tid == 0) {
-            uint32_t tot = 0;
-            for (uint32_t b = 0; b < nb; b++) {
-                bpre[b] = tot;
-                uint32_t ncols = min(kWave * (b + 1), k) - 1;
-                tot += (ncols + CH - 1) / CH;
+            // workgroup-local bump reservations (few global atomics)
+            sh.need_m += words;
+            sh.need_c += k;
+            sh.need_r += 1;
+            sh.need_u += anchor_units(k, W, P.chunk_base);
+            bool bad = (__atomic_load_n(&C->over_cap, __ATOMIC_RELAXED) & 2u) != 0;
+            if (bad) {
+                // a buffer already overflowed: only the demand is recorded
+            } else {
+            if (sh.moff + words > sh.mres_end) {
+                uint64_t want = words > kMaskChunk ? words : kMaskChunk;
+                uint64_t o = atomicAdd(&C->mask_cursor, (unsigned long long)want);
+                sh.moff = o; sh.mres_end = o + want;
+                if (o + want > P.ws.cap_mask_words) bad = true;
             }
-            bpre[nb] = tot;
-            sh.nunits = tot;
-            sh.moff = atomicAdd(&C->mask_cursor, (unsigned long long)words);
-            sh.coff = atomicAdd(&C->cand_cursor, (unsigned long long)k);
-            sh.aidx = atomicAdd(&C->n_anchor, 1u);
-            sh.uoff = atomicAdd(&C->n_units, tot);
-            atomicAdd(&C->pairs, (unsigned long long)k * (k - 1) / 2);
-            bool bad = sh.moff + words > P.ws.cap_mask_words || sh.coff + k > P.ws.cap_cands ||
-                       sh.aidx >= P.ws.cap_anchors || (uint64_t)sh.uoff + tot > P.ws.cap_units;
+            if (sh.coff + k > sh.cres_end) {
+                uint64_t want = k > kCandChunk ? k : kCandChunk;
+                uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)want);
+                sh.coff = o; sh.cres_end = o + want;
+                if (o + want > P.ws.cap_cands) bad = true;
+            }
+            if (sh.aidx >= sh.arec_end) {
+                uint32_t o = atomicAdd(&C->n_anchor, kRecChunk);
+                sh.aidx = o; sh.arec_end = o + kRecChunk;
+                if ((uint64_t)o + kRecChunk > P.ws.cap_anchors) bad = true;
+            }
+            }
             sh.skip = bad;
-            if (bad) atomicOr(&C->over_cap, 2u);
+            if (bad) {
+                atomicOr(&C->over_cap, 2u);
+                sh.moff = sh.mres_end = sh.coff = sh.cres_end = 0;
+                sh.aidx = sh.arec_end = 0;
+            }
         }
         __syncthreads();
         if (sh.skip) {
@@ -272,7 +343,9 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
             continue;
         }
         const bool in_lds = words <= maskw;
-        uint32_t *mp = in_lds ? msk : P.ws.masks + sh.moff;
+        const uint64_t moff = sh.moff, coff = sh.coff;
+        const uint32_t aidx = sh.aidx;
+        uint32_t *mp = in_lds ? msk : P.ws.masks + moff;
         for (uint64_t i = tid; i < words; i += THREADS) mp[i] = 0;
         if (!in_lds) __threadfence();
         __syncthreads();
@@ -292,7 +365,6 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
             }
         }
         __syncthreads();
-        const uint64_t moff = sh.moff, coff = sh.coff;
         if (in_lds)
             for (uint64_t i = tid; i < words; i += THREADS) P.ws.masks[moff + i] = msk[i];
         for (uint32_t i = tid; i < k; i += THREADS) P.ws.cands[coff + i] = vc[i];
@@ -300,22 +372,24 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
             AnchorRec a;
             a.rank = r; a.k = k; a.w32 = W; a.graph = g.s_graph[r];
             a.mask_off = moff; a.cand_off = coff;
-            P.ws.anchors[sh.aidx] = a;
-        }
-        const uint32_t nunits = sh.nunits, uoff = sh.uoff, aidx = sh.aidx;
-        for (uint32_t u = tid; u < nunits; u += THREADS) {
-            uint32_t lo = 0, hi = nb;   // largest b with bpre[b] <= u
-            while (hi - lo > 1) {
-                uint32_t mid = (lo + hi) >> 1;
-                if (bpre[mid] <= u) lo = mid; else hi = mid;
-            }
-            const uint32_t c = u - bpre[lo];
-            const uint32_t ncols = min(kWave * (lo + 1), k) - 1;
-            Unit un;
-            un.anchor = aidx; un.rb = lo; un.c0 = c * CH; un.c1 = min(un.c0 + CH, ncols);
-            P.ws.units[uoff + u] = un;
+            P.ws.anchors[aidx] = a;
+            sh.moff = moff + words;
+            sh.coff = coff + k;
+            sh.aidx = aidx + 1;
         }
         for (uint32_t i = tid; i < H; i += THREADS) { keys[i] = kEmpty; vals[i] = 0; }
+    }
+    // unused reserved anchor records are marked empty
+    if (tid == 0) {
+        if (sh.need_m) atomicAdd(&C->need_masks, sh.need_m);
+        if (sh.need_c) atomicAdd(&C->need_cands, sh.need_c);
+        if (sh.need_r) atomicAdd(&C->need_recs, sh.need_r);
+        if (sh.need_u) atomicAdd(&C->need_units, sh.need_u);
+        for (uint32_t i = sh.aidx; i < sh.arec_end; i++) {
+            AnchorRec a;
+            a.rank = 0; a.k = 0; a.w32 = 0; a.graph = 0; a.mask_off = 0; a.cand_off = 0;
+            P.ws.anchors[i] = a;
+        }
     }
     my_wedges = wave_sum<uint64_t>(my_wedges);
     if (lane == 0 && my_wedges) atomicAdd(&C->wedges, (unsigned long long)my_wedges);
@@ -325,16 +399,25 @@ template <int THREADS, int H, int LOG2H, int MAXD, int KMAX, int MASKW>
 __global__ void __launch_bounds__(THREADS) k_pair_lds(PairArgs P)
 {
     __shared__ uint32_t keys[H], vals[H], pst[MAXD], pln[MAXD], vc[KMAX], msk[MASKW];
-    __shared__ uint32_t bpre[KMAX / kWave + 2];
     __shared__ PairShared sh;
-    pair_loop<THREADS>(P, keys, vals, H, LOG2H, pst, pln, MAXD, vc, KMAX, msk, MASKW, bpre, sh);
+    pair_loop<THREADS>(P, keys, vals, H, LOG2H, pst, pln, MAXD, vc, KMAX, msk, MASKW, sh);
+}
+
+// Tier B: LDS table, position lists in global memory (any degree below 2^16).
+template <int THREADS, int H, int LOG2H, int KMAX>
+__global__ void __launch_bounds__(THREADS) k_pair_big(PairArgs P)
+{
+    __shared__ uint32_t keys[H], vals[H], vc[KMAX];
+    __shared__ PairShared sh;
+    uint32_t *pst = P.ws.bscr + (uint64_t)blockIdx.x * P.ws.bscr_words_per_block;
+    uint32_t *pln = pst + P.gmaxd;
+    pair_loop<THREADS>(P, keys, vals, H, LOG2H, pst, pln, P.gmaxd, vc, KMAX, nullptr, 0, sh);
 }
 
 constexpr int kGThreads = 1024;
 
 __global__ void __launch_bounds__(kGThreads) k_pair_global(PairArgs P)
 {
-    __shared__ uint32_t bpre[65536 / kWave + 2];
     __shared__ PairShared sh;
     uint32_t *base = P.ws.gtab + (uint64_t)blockIdx.x * P.ws.gtab_words_per_block;
     const uint32_t H = P.gH;
@@ -344,21 +427,69 @@ __global__ void __launch_bounds__(kGThreads) k_pair_global(PairArgs P)
     uint32_t *pln = pst + P.gmaxd;
     uint32_t *vc = pln + P.gmaxd;
     pair_loop<kGThreads>(P, keys, vals, H, P.glog2h, pst, pln, P.gmaxd, vc, P.gkmax, nullptr, 0,
-                         bpre, sh);
+                         sh);
+}
+
+// ------------------------------------------------------------- planning
+__global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk_base)
+{
+    // after a capacity overflow the records are incomplete: plan nothing
+    const uint32_t n_rec = ws.ctr->over_cap ? 0u
+                                            : (uint32_t)min((uint64_t)ws.ctr->n_anchor, ws.cap_anchors);
+    for (uint64_t a = (uint64_t)blockIdx.x * 256 + threadIdx.x; a < ws.cap_anchors;
+         a += (uint64_t)gridDim.x * 256) {
+        uint32_t c = 0;
+        if (a < n_rec) {
+            const AnchorRec &r = ws.anchors[a];
+            if (r.k <= 65535u) c = anchor_units(r.k, r.w32, chunk_base);
+        }
+        ws.ucnt[a] = c;
+    }
+}
+
+// One wave per anchor record writes its units.
+__global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk_base)
+{
+    Counters *C = ws.ctr;
+    const uint32_t n_rec = C->over_cap ? 0u : (uint32_t)min((uint64_t)C->n_anchor, ws.cap_anchors);
+    const uint64_t total = ws.uoff[ws.cap_anchors];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        C->n_units = (uint32_t)min(total, ws.cap_units);
+        if (total > ws.cap_units) atomicOr(&C->over_cap, 2u);
+    }
+    const uint32_t lane = __lane_id();
+    const uint32_t wave = (blockIdx.x * 256 + threadIdx.x) / kWave;
+    const uint32_t nwaves = gridDim.x * 256 / kWave;
+    for (uint32_t a = wave; a < n_rec; a += nwaves) {
+        const AnchorRec r = ws.anchors[a];
+        if (r.k < 2 || r.k > 65535u) continue;
+        const uint64_t base = ws.uoff[a];
+        const uint32_t CH = unit_cols(r.w32, chunk_base);
+        const uint32_t nb = (r.k + kWave - 1) / kWave;
+        uint32_t u0 = 0;
+        for (uint32_t b = 0; b < nb; b++) {
+            const uint32_t ncols = min(kWave * (b + 1), r.k) - 1;
+            const uint32_t nu = (ncols + CH - 1) / CH;
+            for (uint32_t c = lane; c < nu; c += kWave) {
+                const uint64_t idx = base + u0 + c;
+                if (idx < ws.cap_units) {
+                    Unit un;
+                    un.anchor = a; un.rb = b; un.c0 = c * CH; un.c1 = min(un.c0 + CH, ncols);
+                    ws.units[idx] = un;
+                }
+            }
+            u0 += nu;
+        }
+    }
 }
 
 // ------------------------------------------------------------ triplets
-struct TriCtx {
-    const uint32_t *masks;
-    const uint32_t *c3;
-    uint32_t i;        // this lane's row
-    bool vi;
-};
-
-template <int W>
+// Rows in lanes, masks of W <= 16 words in registers; columns through
+// scalar loads, 8 at a time.
+template <int W, int MODE>
 __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
                                              const uint32_t *__restrict__ masks,
-                                             const uint32_t *c3, uint64_t *colacc, int mode,
+                                             const uint32_t *c3, uint64_t *colacc,
                                              const TriArgs &T)
 {
     const uint32_t lane = __lane_id();
@@ -372,7 +503,7 @@ __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
     const bool diag = un.c1 > un.rb * kWave;
     uint64_t acc = 0;
     uint32_t j = un.c0;
-    if (mode == 0) {
+    if (MODE == 0) {
         for (; j + 8 <= un.c1; j += 8) {
             uint32_t s = 0;
 #pragma unroll
@@ -396,7 +527,6 @@ __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
         }
         return acc;
     }
-    // per-vertex modes
     for (; j < un.c1; j++) {
         uint32_t cw[W];
         uint32_t n = 0;
@@ -409,10 +539,10 @@ __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
         if (diag) t = (j < i) ? t : 0u;
         acc += t;
         if (t) {
-            if (mode == 1) {
+            if (MODE == 1) {
                 atomicAdd((unsigned long long *)&colacc[j - un.c0], (unsigned long long)t);
             } else {
-                // every member of the common class is in C(n-1, 2) of these bicliques
+                // every member of the common class lies in C(n-1, 2) of these bicliques
                 const uint64_t each = choose2(n - 1);
                 const uint64_t s0 = T.g.s_off[a.rank];
 #pragma unroll
@@ -431,9 +561,11 @@ __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
     return acc;
 }
 
-// Masks wider than 16 words: row words are re-read per column.
+// Masks wider than 16 words: 32 columns per unit, one counter per column in
+// registers, words streamed 16 at a time.
+template <int MODE>
 __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
-                                  const uint32_t *__restrict__ masks, uint64_t *colacc, int mode,
+                                  const uint32_t *__restrict__ masks, uint64_t *colacc,
                                   const TriArgs &T)
 {
     const uint32_t lane = __lane_id();
@@ -442,27 +574,53 @@ __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
     const uint32_t W = a.w32;
     const uint32_t *M = masks + a.mask_off;
     const BBC_CONST uint32_t *MS = as_const(M);
-    const bool diag = un.c1 > un.rb * kWave;
+    const uint32_t ncol = un.c1 - un.c0;
+    uint32_t n[kWideCols];
+#pragma unroll
+    for (int c = 0; c < (int)kWideCols; c++) n[c] = 0;
+    for (uint32_t w0 = 0; w0 < W; w0 += kRegW) {
+        const uint32_t wn = min(kRegW, W - w0);
+        uint32_t row[kRegW];
+#pragma unroll
+        for (int w = 0; w < (int)kRegW; w++)
+            row[w] = (vi && (uint32_t)w < wn) ? M[(uint64_t)i * W + w0 + w] : 0u;
+#pragma unroll
+        for (int c = 0; c < (int)kWideCols; c++) {
+            if ((uint32_t)c < ncol) {
+                const BBC_CONST uint32_t *col = MS + (uint64_t)(un.c0 + c) * W + w0;
+                uint32_t s = 0;
+                if (wn == kRegW) {
+#pragma unroll
+                    for (int w = 0; w < (int)kRegW; w++) s += __popc(row[w] & col[w]);
+                } else {
+#pragma unroll
+                    for (int w = 0; w < (int)kRegW; w++)
+                        if ((uint32_t)w < wn) s += __popc(row[w] & col[w]);
+                }
+                n[c] += s;
+            }
+        }
+    }
     uint64_t acc = 0;
-    for (uint32_t j = un.c0; j < un.c1; j++) {
-        uint32_t n = 0;
-        if (vi)
-            for (uint32_t w = 0; w < W; w++)
-                n += __popc(M[(uint64_t)i * W + w] & MS[(uint64_t)j * W + w]);
-        uint64_t t = choose3(n);
-        if (diag && !(j < i)) t = 0;
+#pragma unroll
+    for (int c = 0; c < (int)kWideCols; c++) {
+        const uint32_t j = un.c0 + c;
+        uint64_t t = ((uint32_t)c < ncol && j < i) ? choose3(n[c]) : 0;
         acc += t;
-        if (t && mode == 1) atomicAdd((unsigned long long *)&colacc[j - un.c0], (unsigned long long)t);
-        if (t && mode == 2) {
-            const uint64_t each = choose2(n - 1);
-            const uint64_t s0 = T.g.s_off[a.rank];
-            for (uint32_t w = 0; w < W; w++) {
-                uint32_t m = M[(uint64_t)i * W + w] & M[(uint64_t)j * W + w];
-                while (m) {
-                    const uint32_t b = __ffs(m) - 1;
-                    m &= m - 1;
-                    const uint32_t o = T.g.s_adj[s0 + w * 32 + b] >> 1;
-                    atomicAdd(&T.ws.pv_o[o], (unsigned long long)each);
+        if (MODE != 0 && t) {
+            if (MODE == 1) {
+                atomicAdd((unsigned long long *)&colacc[c], (unsigned long long)t);
+            } else {
+                const uint64_t each = choose2(n[c] - 1);
+                const uint64_t s0 = T.g.s_off[a.rank];
+                for (uint32_t w = 0; w < W; w++) {
+                    uint32_t m = M[(uint64_t)i * W + w] & M[(uint64_t)j * W + w];
+                    while (m) {
+                        const uint32_t b = __ffs(m) - 1;
+                        m &= m - 1;
+                        const uint32_t o = T.g.s_adj[s0 + w * 32 + b] >> 1;
+                        atomicAdd(&T.ws.pv_o[o], (unsigned long long)each);
+                    }
                 }
             }
         }
@@ -472,6 +630,7 @@ __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
 
 constexpr int kTThreads = 256;
 constexpr uint32_t kMaxChunk = 2048;
+constexpr uint32_t kUnitGrab = 4;
 
 template <int MODE>
 __global__ void __launch_bounds__(kTThreads) k_triplet(TriArgs T)
@@ -488,29 +647,56 @@ __global__ void __launch_bounds__(kTThreads) k_triplet(TriArgs T)
     const uint32_t n_units = __atomic_load_n(&C->n_units, __ATOMIC_RELAXED);
     const uint32_t lane = __lane_id();
     uint64_t *colacc = (uint64_t *)colacc_all[MODE == 1 ? threadIdx.x / kWave : 0];
-    uint64_t examined = 0;
+    uint64_t examined = 0, exwords = 0;
+    uint64_t total = 0;
+    uint32_t cur_graph = 0xffffffffu;
+    uint32_t slice = blockIdx.x % kXcd, tried = 0, qlo = 0, qhi = 0;
+
+    auto flush = [&]() {
+        const uint64_t tot = wave_sum<uint64_t>(total);
+        if (lane == 0 && tot) {
+            const unsigned long long old = atomicAdd(&T.ws.count[cur_graph], (unsigned long long)tot);
+            if (old + tot < old) atomicAdd(&T.ws.carry[cur_graph], 1u);
+        }
+        total = 0;
+    };
+
     for (;;) {
-        uint32_t u = 0;
-        if (lane == 0) u = atomicAdd(&C->unit_next, 1u);
-        u = __builtin_amdgcn_readfirstlane(u);
-        if (u >= n_units) break;
+        if (qlo >= qhi) {
+            uint32_t lo = 0, hi = 0;
+            bool ok = false;
+            if (lane == 0) ok = queue_take(C->q_tri, n_units, kUnitGrab, &slice, &tried, &lo, &hi);
+            ok = __shfl(ok ? 1 : 0, 0, kWave);
+            if (!ok) break;
+            qlo = __builtin_amdgcn_readfirstlane(__shfl(lo, 0, kWave));
+            qhi = __builtin_amdgcn_readfirstlane(__shfl(hi, 0, kWave));
+            slice = __shfl(slice, 0, kWave);
+            tried = __shfl(tried, 0, kWave);
+        }
+        const uint32_t u = qlo++;
         const Unit un = load_unit(T.ws.units + u);
         const AnchorRec a = load_anchor(T.ws.anchors + un.anchor);
+        if (a.graph != cur_graph) {
+            if (cur_graph != 0xffffffffu) flush();
+            cur_graph = a.graph;
+        }
         uint64_t acc;
         switch (a.w32) {
-#define BBC_W(n) case n: acc = tri_rows<n>(un, a, T.ws.masks, c3, colacc, MODE, T); break;
+#define BBC_W(n) case n: acc = tri_rows<n, MODE>(un, a, T.ws.masks, c3, colacc, T); break;
             BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) BBC_W(5) BBC_W(6) BBC_W(7) BBC_W(8)
             BBC_W(9) BBC_W(10) BBC_W(11) BBC_W(12) BBC_W(13) BBC_W(14) BBC_W(15) BBC_W(16)
 #undef BBC_W
-            default: acc = tri_rows_wide(un, a, T.ws.masks, colacc, MODE, T); break;
+            default: acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T); break;
         }
-        {
-            const uint32_t i = un.rb * kWave + lane;
-            if (i < a.k && i > un.c0) examined += min(i, un.c1) - un.c0;
+        const uint32_t i = un.rb * kWave + lane;
+        if (i < a.k && i > un.c0) {
+            const uint32_t ex = min(i, un.c1) - un.c0;
+            examined += ex;
+            exwords += (uint64_t)ex * a.w32;
         }
+        total += acc;
         if (MODE == 1) {
             // this lane's row total, the anchor's total, and the column totals
-            const uint32_t i = un.rb * kWave + lane;
             if (i < a.k && acc)
                 atomicAdd(&T.ws.pv[T.ws.cands[a.cand_off + i]], (unsigned long long)acc);
             const uint64_t tot = wave_sum<uint64_t>(acc);
@@ -523,24 +709,25 @@ __global__ void __launch_bounds__(kTThreads) k_triplet(TriArgs T)
                 }
             }
         }
-        const uint64_t tot = wave_sum<uint64_t>(acc);
-        if (lane == 0 && tot) {
-            const unsigned long long old = atomicAdd(&T.ws.count[a.graph], (unsigned long long)tot);
-            if (old + tot < old) atomicAdd(&T.ws.carry[a.graph], 1u);
-        }
     }
+    if (cur_graph != 0xffffffffu) flush();
     examined = wave_sum<uint64_t>(examined);
-    if (lane == 0 && examined) atomicAdd(&C->pairs_examined, (unsigned long long)examined);
+    exwords = wave_sum<uint64_t>(exwords);
+    if (lane == 0 && examined) {
+        atomicAdd(&C->pairs_examined, (unsigned long long)examined);
+        atomicAdd(&C->pair_words, (unsigned long long)exwords);
+    }
 }
 
 }  // namespace
 
-// Tier parameters (LDS use per block: tier A ~ 64 KiB, tier B ~ 152 KiB).
+// Tier parameters (LDS use per block: tier A ~ 64 KiB, tier B ~ 144 KiB).
 constexpr int kAThreads = 512, kAH = 4096, kALog = 12, kAMaxD = 1024, kAKmax = 2048, kAMaskW = 4096;
-constexpr int kBThreads = 1024, kBH = 16384, kBLog = 14, kBMaxD = 1024, kBKmax = 4096, kBMaskW = 1;
+constexpr int kBThreads = 1024, kBH = 16384, kBLog = 14, kBKmax = 4096;
 
 uint32_t tier_c_max_degree() { return 65535; }
 uint32_t tier_c_max_k() { return 65535; }
+uint32_t max_unit_chunk() { return kMaxChunk; }
 
 hipError_t count_pairs(const PairArgs &base, const LaunchShape &sh, hipStream_t s)
 {
@@ -549,12 +736,21 @@ hipError_t count_pairs(const PairArgs &base, const LaunchShape &sh, hipStream_t 
     hipLaunchKernelGGL((k_pair_lds<kAThreads, kAH, kALog, kAMaxD, kAKmax, kAMaskW>),
                        dim3(sh.grid_a), dim3(kAThreads), 0, s, P);
     P.tier = 1;
-    hipLaunchKernelGGL((k_pair_lds<kBThreads, kBH, kBLog, kBMaxD, kBKmax, kBMaskW>),
-                       dim3(sh.grid_b), dim3(kBThreads), 0, s, P);
-    if (sh.grid_c) {
-        P.tier = 2;
-        hipLaunchKernelGGL(k_pair_global, dim3(sh.grid_c), dim3(kGThreads), 0, s, P);
-    }
+    hipLaunchKernelGGL((k_pair_big<kBThreads, kBH, kBLog, kBKmax>), dim3(sh.grid_b),
+                       dim3(kBThreads), 0, s, P);
+    P.tier = 2;
+    hipLaunchKernelGGL(k_pair_global, dim3(sh.grid_c), dim3(kGThreads), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_t tmp_bytes,
+                      hipStream_t s)
+{
+    uint32_t grid = (uint32_t)std::min<uint64_t>((ws.cap_anchors + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_plan_count, dim3(grid), dim3(256), 0, s, ws, chunk_base);
+    hipError_t e = scan_u32_to_u64(ws.ucnt, ws.uoff, ws.cap_anchors, tmp, tmp_bytes, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_plan_write, dim3(1024), dim3(256), 0, s, ws, chunk_base);
     return hipGetLastError();
 }
 
@@ -565,7 +761,5 @@ hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t
     else hipLaunchKernelGGL(k_triplet<2>, dim3(grid), dim3(kTThreads), 0, s, T);
     return hipGetLastError();
 }
-
-uint32_t max_unit_chunk() { return kMaxChunk; }
 
 }  // namespace bbc

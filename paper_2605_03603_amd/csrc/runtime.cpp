@@ -200,20 +200,22 @@ struct GraphSet {
     uint64_t M = 0;
     std::vector<GraphDesc> desc;
     DBuf d_desc, s_off, o_off, s_adj, o_adj, s_graph, s_vert;
+    DBuf s_rev;
     // sizing hints learnt by earlier counts
     uint64_t hint_masks = 0, hint_cands = 0, hint_units = 0;
-    bool hint_tier_c = false;
     uint64_t device_bytes() const
     {
         return d_desc.bytes + s_off.bytes + o_off.bytes + s_adj.bytes + o_adj.bytes +
-               s_graph.bytes + s_vert.bytes;
+               s_rev.bytes + s_graph.bytes + s_vert.bytes;
     }
     CsrView view() const
     {
         CsrView v;
+        memset(&v, 0, sizeof(v));
         v.G = G; v.NS = NS; v.NO = NO; v.M = M;
         v.s_off = s_off.as<uint64_t>(); v.s_adj = s_adj.as<uint32_t>();
         v.o_off = o_off.as<uint64_t>(); v.o_adj = o_adj.as<uint32_t>();
+        v.s_rev = s_rev.as<uint32_t>();
         v.s_graph = s_graph.as<uint32_t>(); v.s_vert = s_vert.as<uint32_t>();
         v.desc = d_desc.as<GraphDesc>();
         return v;
@@ -229,18 +231,18 @@ namespace {
 
 // Count workspace (one per stream that counts).
 struct Work {
-    DBuf ctr, anchors, units, masks, cands, defer0, defer1, gtab, count, carry, pv, pv_o;
+    DBuf ctr, anchors, units, masks, cands, defer0, defer1, gtab, bscr, count, carry, pv, pv_o;
+    DBuf ucnt, uoff, ptmp;
     HBuf host;          // counters + counts + carries read back
     uint64_t cap_anchors = 0, cap_units = 0, cap_masks = 0, cap_cands = 0, cap_defer = 0;
-    uint32_t gtab_blocks = 0;
-    uint64_t gtab_words = 0;
+    uint32_t gtab_blocks = 0, bscr_blocks = 0;
+    uint64_t gtab_words = 0, bscr_words = 0, ptmp_bytes = 0;
     uint32_t gH = 0;
     int glog2 = 0;
     uint32_t gmaxd = 0, gkmax = 0;
     // captured replay of a batched count
     hipGraphExec_t exec = nullptr;
-    const GraphSet *exec_set = nullptr;
-    uint64_t exec_key = 0;
+    std::vector<unsigned char> exec_args;   // bytes of the LaunchArgs it was captured with
     ~Work()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -280,6 +282,8 @@ struct bbc_ctx {
     std::mutex err_mu;
     Work work;
     bbc_count_stats stats{};
+    bool timing = false;
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     std::map<uint64_t, Shape> tuned;   // autotuner cache by size class
     // serving
     std::mutex q_mu;
@@ -460,6 +464,8 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
     a.first_bad = (unsigned long long *)(d_flags + 4);
     a.stat_c2_u = d_stats; a.stat_c2_v = d_stats + G; a.stat_d2_u = d_stats + 2 * G;
     a.stat_d2_v = d_stats + 3 * G;
+    const bool timed = ctx->timing && s == ctx->stream;
+    if (timed) HIP_OK(hipEventRecord(ctx->ev[4], s));
     HIP_OK(build_ingest(a, s));
 
     // read back validation flags and degree statistics
@@ -521,6 +527,9 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
     set->o_off.ensure(al, (NO + 1) * 8);
     set->s_adj.ensure(al, std::max<uint64_t>(M, 1) * 4);
     set->o_adj.ensure(al, std::max<uint64_t>(M, 1) * 4);
+    set->s_rev.ensure(al, std::max<uint64_t>(M, 1) * 4);
+    DBuf o_ent;
+    o_ent.ensure(al, std::max<uint64_t>(M, 1) * 4);
     set->s_graph.ensure(al, std::max<uint64_t>(NS, 1) * 4);
     set->s_vert.ensure(al, std::max<uint64_t>(NS, 1) * 4);
     HIP_OK(hipMemcpyAsync(set->d_desc.p, d_desc_tmp, G * sizeof(GraphDesc),
@@ -539,12 +548,15 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
     a.rank_of = rank_of.as<uint32_t>();
     a.s_off = set->s_off.as<uint64_t>(); a.o_off = set->o_off.as<uint64_t>();
     a.s_adj = set->s_adj.as<uint32_t>(); a.o_adj = set->o_adj.as<uint32_t>();
+    a.s_rev = set->s_rev.as<uint32_t>(); a.o_ent = o_ent.as<uint32_t>();
     a.s_graph = set->s_graph.as<uint32_t>(); a.s_vert = set->s_vert.as<uint32_t>();
     a.tmp = tmp.p; a.tmp_bytes = tmp_bytes;
     HIP_OK(build_rank(a, s));
     HIP_OK(build_adjacency(a, s));
+    if (timed) HIP_OK(hipEventRecord(ctx->ev[5], s));
     HIP_OK(hipMemcpyAsync(h_flags, d_flags, 4, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    if (timed) HIP_OK(hipEventElapsedTime(&ctx->stats.ms_build, ctx->ev[4], ctx->ev[5]));
     if (h_flags[0] & kErrDup) fail(BBC_E_DUP_EDGE, "an edge (u, v) appears more than once");
     return set;
 }
@@ -556,41 +568,54 @@ struct CountReq {
     int mode;               // 0 totals, 1 per vertex of S, 2 per vertex of O
 };
 
-void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set, bool tier_c)
+void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set)
 {
     Allocator *al = ctx->al.get();
     uint64_t M = std::max<uint64_t>(set.M, 1);
-    uint64_t want_anchors = std::max<uint64_t>(set.NS, 1);
+    // records are reserved 16 at a time per workgroup
+    uint64_t want_anchors = std::max<uint64_t>(set.NS, 1) + 16ull * 4 * ctx->num_cus + 64;
     uint64_t want_masks = std::max<uint64_t>({set.hint_masks, 8 * M, 1ull << 20});
     uint64_t want_cands = std::max<uint64_t>({set.hint_cands, 2 * M, 1ull << 18});
     uint64_t want_units = std::max<uint64_t>({set.hint_units, M / 4, 1ull << 16});
-    if (w.cap_anchors < want_anchors) { w.anchors.ensure(al, want_anchors * sizeof(AnchorRec)); w.cap_anchors = want_anchors; }
+    if (w.cap_anchors < want_anchors) {
+        w.anchors.ensure(al, want_anchors * sizeof(AnchorRec));
+        w.ucnt.ensure(al, want_anchors * 4);
+        w.uoff.ensure(al, (want_anchors + 1) * 8);
+        w.ptmp_bytes = scan_tmp_bytes(want_anchors + 1) + 256;
+        w.ptmp.ensure(al, w.ptmp_bytes);
+        w.cap_anchors = want_anchors;
+    }
     if (w.cap_masks < want_masks) { w.masks.ensure(al, want_masks * 4); w.cap_masks = want_masks; }
     if (w.cap_cands < want_cands) { w.cands.ensure(al, want_cands * 4); w.cap_cands = want_cands; }
     if (w.cap_units < want_units) { w.units.ensure(al, want_units * sizeof(Unit)); w.cap_units = want_units; }
-    if (w.cap_defer < want_anchors) {
-        w.defer0.ensure(al, want_anchors * 4); w.defer1.ensure(al, want_anchors * 4);
-        w.cap_defer = want_anchors;
+    if (w.cap_defer < set.NS + 1ull) {
+        w.defer0.ensure(al, (set.NS + 1ull) * 4); w.defer1.ensure(al, (set.NS + 1ull) * 4);
+        w.cap_defer = set.NS + 1ull;
     }
     w.ctr.ensure(al, sizeof(Counters));
     w.count.ensure(al, std::max<uint32_t>(set.G, 1) * 8);
     w.carry.ensure(al, std::max<uint32_t>(set.G, 1) * 4);
     w.host.ensure(sizeof(Counters) + 12ull * std::max<uint32_t>(set.G, 1) + 64);
-    if (tier_c) {
-        // tier-C tables: sized for the largest anchor side of any graph
-        uint32_t max_ns = 0;
-        for (auto &d : set.desc) max_ns = std::max(max_ns, d.n_s);
-        uint32_t H = 1024;
-        int lg = 10;
-        while (H < 2ull * max_ns + 64 && lg < 24) { H <<= 1; lg++; }
-        uint32_t maxd = tier_c_max_degree(), kmax = tier_c_max_k();
-        uint64_t words = 2ull * H + 2ull * maxd + kmax + 64;
-        uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ctx->num_cus / 2, (4ull << 30) / (words * 4)));
-        if (!w.gtab.p || w.gH != H || w.gtab_blocks < blocks) {
-            w.gtab.ensure(al, words * 4 * blocks);
-            w.gH = H; w.glog2 = lg; w.gmaxd = maxd; w.gkmax = kmax;
-            w.gtab_words = words; w.gtab_blocks = blocks;
-        }
+    const uint32_t maxd = tier_c_max_degree(), kmax = tier_c_max_k();
+    // tier B: per-block position lists in global memory
+    if (!w.bscr.p || w.bscr_blocks < (uint32_t)ctx->num_cus) {
+        w.bscr_words = 2ull * (maxd + 1);
+        w.bscr_blocks = ctx->num_cus;
+        w.bscr.ensure(al, w.bscr_words * 4 * w.bscr_blocks);
+    }
+    // tier C: hash tables sized for the largest anchor side of any graph
+    uint32_t max_ns = 0;
+    for (auto &d : set.desc) max_ns = std::max(max_ns, d.n_s);
+    uint32_t H = 1024;
+    int lg = 10;
+    while (H < 2ull * max_ns + 64 && lg < 24) { H <<= 1; lg++; }
+    if (!w.gtab.p || w.gH < H) {
+        uint64_t words = 2ull * H + 2ull * (maxd + 1) + kmax + 64;
+        uint32_t blocks = (uint32_t)std::max<uint64_t>(
+            1, std::min<uint64_t>(32, (1ull << 30) / (words * 4)));
+        w.gtab.ensure(al, words * 4 * blocks);
+        w.gH = H; w.glog2 = lg; w.gmaxd = maxd; w.gkmax = kmax;
+        w.gtab_words = words; w.gtab_blocks = blocks;
     }
 }
 
@@ -607,6 +632,8 @@ Workspace ws_view(Work &w, bool pv, bool pvo)
     ws.cap_defer = w.cap_defer;
     ws.gtab = w.gtab.as<uint32_t>(); ws.gtab_words_per_block = w.gtab_words;
     ws.gtab_blocks = w.gtab_blocks;
+    ws.bscr = w.bscr.as<uint32_t>(); ws.bscr_words_per_block = w.bscr_words;
+    ws.ucnt = w.ucnt.as<uint32_t>(); ws.uoff = w.uoff.as<uint64_t>();
     ws.count = w.count.as<unsigned long long>();
     ws.carry = w.carry.as<uint32_t>();
     ws.pv = pv ? w.pv.as<unsigned long long>() : nullptr;
@@ -616,35 +643,67 @@ Workspace ws_view(Work &w, bool pv, bool pvo)
 
 // Enqueue one full count (zeroing, pair tiers, triplets) on stream s.
 // Nothing here reads back, so the sequence can be captured.
-void enqueue_count(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp, bool tier_c,
-                   hipStream_t s)
+// Every value the count sequence passes to a kernel. A captured replay is
+// valid only while this is byte-for-byte the same.
+struct LaunchArgs {
+    PairArgs P;
+    LaunchShape ls;
+    TriArgs T;
+    int mode;
+    uint32_t G, NS, NO;
+    void *ptmp;
+    uint64_t ptmp_bytes;
+};
+
+LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
 {
     const GraphSet &set = *r.set;
+    LaunchArgs L;
+    memset(&L, 0, sizeof(L));
     const bool pv = r.mode == 1, pvo = r.mode == 2;
     Workspace ws = ws_view(w, pv, pvo);
+    L.P.g = set.view();
+    L.P.ws = ws;
+    L.P.a0 = set.desc[r.g0].s_base;
+    L.P.a1 = set.desc[r.g1 - 1].s_base + set.desc[r.g1 - 1].n_s;
+    L.P.chunk_base = std::min(shp.chunk_base, max_unit_chunk());
+    L.P.gH = w.gH; L.P.glog2h = w.glog2; L.P.gmaxd = w.gmaxd; L.P.gkmax = w.gkmax;
+    L.ls.grid_a = std::max(1u, ctx->num_cus * shp.grid_a_per_cu);
+    L.ls.grid_b = std::max(1u, (uint32_t)ctx->num_cus);
+    L.ls.grid_c = w.gtab_blocks;
+    L.ls.grid_t = std::max(1u, ctx->num_cus * shp.grid_t_per_cu);
+    L.T.g = L.P.g;
+    L.T.ws = ws;
+    L.mode = r.mode;
+    L.G = set.G; L.NS = set.NS; L.NO = set.NO;
+    L.ptmp = w.ptmp.p;
+    L.ptmp_bytes = w.ptmp_bytes;
+    return L;
+}
+
+void enqueue_args(bbc_ctx *ctx, const LaunchArgs &L, hipStream_t s, bool timed)
+{
+    const Workspace &ws = L.P.ws;
     HIP_OK(fill_u32((uint32_t *)ws.ctr, 0, sizeof(Counters) / 4, s));
-    HIP_OK(fill_u64(ws.count, 0, set.G, s));
-    HIP_OK(fill_u32(ws.carry, 0, set.G, s));
-    if (pv) HIP_OK(fill_u64(ws.pv, 0, set.NS, s));
-    if (pvo) HIP_OK(fill_u64(ws.pv_o, 0, set.NO, s));
-    PairArgs P;
-    memset(&P, 0, sizeof(P));
-    P.g = set.view();
-    P.ws = ws;
-    P.a0 = set.desc[r.g0].s_base;
-    P.a1 = set.desc[r.g1 - 1].s_base + set.desc[r.g1 - 1].n_s;
-    P.chunk_base = std::min(shp.chunk_base, max_unit_chunk());
-    P.gH = w.gH; P.glog2h = w.glog2; P.gmaxd = w.gmaxd; P.gkmax = w.gkmax;
-    LaunchShape ls;
-    ls.grid_a = std::max(1u, ctx->num_cus * shp.grid_a_per_cu);
-    ls.grid_b = std::max(1u, (uint32_t)ctx->num_cus);
-    ls.grid_c = tier_c ? w.gtab_blocks : 0;
-    ls.grid_t = std::max(1u, ctx->num_cus * shp.grid_t_per_cu);
-    HIP_OK(count_pairs(P, ls, s));
-    TriArgs T;
-    T.g = P.g;
-    T.ws = ws;
-    HIP_OK(count_triplets(T, r.mode, ls.grid_t, s));
+    HIP_OK(fill_u64(ws.count, 0, L.G, s));
+    HIP_OK(fill_u32(ws.carry, 0, L.G, s));
+    if (L.mode == 1) HIP_OK(fill_u64(ws.pv, 0, L.NS, s));
+    if (L.mode == 2) HIP_OK(fill_u64(ws.pv_o, 0, L.NO, s));
+    if (timed) HIP_OK(hipEventRecord(ctx->ev[0], s));
+    HIP_OK(count_pairs(L.P, L.ls, s));
+    if (timed) HIP_OK(hipEventRecord(ctx->ev[1], s));
+    HIP_OK(count_plan(ws, L.P.chunk_base, L.ptmp, L.ptmp_bytes, s));
+    if (timed) HIP_OK(hipEventRecord(ctx->ev[2], s));
+    HIP_OK(count_triplets(L.T, L.mode, L.ls.grid_t, s));
+    if (timed) HIP_OK(hipEventRecord(ctx->ev[3], s));
+}
+
+// Enqueue one full count (zeroing, pair tiers, planning, triplets) on
+// stream s. Nothing here reads back, so the sequence can be captured.
+void enqueue_count(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp, hipStream_t s,
+                   bool timed = false)
+{
+    enqueue_args(ctx, make_args(ctx, w, r, shp), s, timed);
 }
 
 void enqueue_readback(Work &w, const GraphSet &set, hipStream_t s)
@@ -657,38 +716,30 @@ void enqueue_readback(Work &w, const GraphSet &set, hipStream_t s)
 }
 
 // After a readback: true if the count is complete, false if buffers must grow.
-bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set, bool tier_c, bool *need_c)
+bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set)
 {
     const Counters *c = w.host.as<Counters>();
-    *need_c = false;
     if (c->over_cap & 8u) fail(BBC_E_HIP, "internal error: pair table lookup failed");
     if (c->over_cap & 4u)
         fail(BBC_E_UNSUPPORTED, "an anchor has degree above %u or more than %u candidate classes",
              tier_c_max_degree(), tier_c_max_k());
-    bool ok = true;
+    // demand plus room for the per-workgroup reservation chunks
+    const uint64_t slack_m = 4ull * ctx->num_cus * (1u << 16), slack_c = 4ull * ctx->num_cus * (1u << 13);
+    set.hint_masks = std::max<uint64_t>(set.hint_masks, c->need_masks + c->need_masks / 16 + slack_m);
+    set.hint_cands = std::max<uint64_t>(set.hint_cands, c->need_cands + c->need_cands / 16 + slack_c);
     if (c->over_cap & 3u) {
-        set.hint_masks = std::max<uint64_t>(set.hint_masks, std::max<uint64_t>(c->mask_cursor, w.cap_masks) * 2);
-        set.hint_cands = std::max<uint64_t>(set.hint_cands, std::max<uint64_t>(c->cand_cursor, w.cap_cands) * 2);
-        set.hint_units = std::max<uint64_t>(set.hint_units, std::max<uint64_t>(c->n_units, w.cap_units) * 2);
-        ok = false;
+        set.hint_units = std::max<uint64_t>(set.hint_units, c->need_units + c->need_units / 16 + 1024);
+        return false;
     }
-    if (c->n_list[1] > 0 && !tier_c) {
-        set.hint_tier_c = true;
-        *need_c = true;
-        ok = false;
-    }
-    if (ok) {
-        set.hint_masks = std::max<uint64_t>(set.hint_masks, c->mask_cursor + c->mask_cursor / 8);
-        set.hint_cands = std::max<uint64_t>(set.hint_cands, c->cand_cursor + c->cand_cursor / 8);
-        set.hint_units = std::max<uint64_t>(set.hint_units, (uint64_t)c->n_units + c->n_units / 8);
-        ctx->stats.active_anchors = c->n_anchor;
-        ctx->stats.virtual_candidates = c->cand_cursor;
-        ctx->stats.pair_units = c->n_units;
-        ctx->stats.candidate_pairs = c->pairs_examined;
-        ctx->stats.mask_words = c->mask_cursor;
-        ctx->stats.wedges = c->wedges;
-    }
-    return ok;
+    set.hint_units = std::max<uint64_t>(set.hint_units, (uint64_t)c->n_units + c->n_units / 8);
+    ctx->stats.active_anchors = c->n_anchor;
+    ctx->stats.virtual_candidates = c->cand_cursor;
+    ctx->stats.pair_units = c->n_units;
+    ctx->stats.candidate_pairs = c->pairs_examined;
+    ctx->stats.mask_words = c->mask_cursor;
+    ctx->stats.wedges = c->wedges;
+    ctx->stats.pair_words = c->pair_words;
+    return true;
 }
 
 void results_from_host(Work &w, const GraphSet &set, uint32_t g0, uint32_t g1, int64_t *out)
@@ -710,16 +761,21 @@ void count_sync(bbc_ctx *ctx, Work &w, GraphSet &set, uint32_t g0, uint32_t g1, 
                 const Shape &shp, hipStream_t s, int64_t *out)
 {
     CountReq r{&set, g0, g1, mode};
+    const bool timed = ctx->timing && s == ctx->stream && &w == &ctx->work;
     for (int attempt = 0; attempt < 8; attempt++) {
-        bool tier_c = set.hint_tier_c;
-        ensure_work(ctx, w, set, tier_c);
+        ensure_work(ctx, w, set);
         if (mode == 1) w.pv.ensure(ctx->al.get(), std::max<uint64_t>(set.NS, 1) * 8);
         if (mode == 2) w.pv_o.ensure(ctx->al.get(), std::max<uint64_t>(set.NO, 1) * 8);
-        enqueue_count(ctx, w, r, shp, tier_c, s);
+        enqueue_count(ctx, w, r, shp, s, timed);
         enqueue_readback(w, set, s);
         HIP_OK(hipStreamSynchronize(s));
-        bool need_c;
-        if (check_counters(ctx, w, set, tier_c, &need_c)) {
+        if (check_counters(ctx, w, set)) {
+            if (&w == &ctx->work) ctx->stats.attempts = attempt + 1;
+            if (timed) {
+                HIP_OK(hipEventElapsedTime(&ctx->stats.ms_pair, ctx->ev[0], ctx->ev[1]));
+                HIP_OK(hipEventElapsedTime(&ctx->stats.ms_plan, ctx->ev[1], ctx->ev[2]));
+                HIP_OK(hipEventElapsedTime(&ctx->stats.ms_triplet, ctx->ev[2], ctx->ev[3]));
+            }
             results_from_host(w, set, g0, g1, out);
             return;
         }
@@ -758,7 +814,7 @@ Shape tune_shape(bbc_ctx *ctx, Work &w, GraphSet &set, hipStream_t s)
     for (const Shape &sh : cands) {
         CountReq r{&set, 0, set.G, 0};
         HIP_OK(hipEventRecord(e0, s));
-        enqueue_count(ctx, w, r, sh, set.hint_tier_c, s);
+        enqueue_count(ctx, w, r, sh, s);
         HIP_OK(hipEventRecord(e1, s));
         HIP_OK(hipEventSynchronize(e1));
         float ms = 0;
@@ -776,22 +832,22 @@ Shape tune_shape(bbc_ctx *ctx, Work &w, GraphSet &set, hipStream_t s)
 void count_set_batched(bbc_ctx *ctx, Work &w, GraphSet &set, hipStream_t s, int64_t *out)
 {
     Shape shp = tune_shape(ctx, w, set, s);
-    const uint64_t key = size_class(set) ^ ((uint64_t)shp.chunk_base << 40) ^ ((uint64_t)shp.grid_t_per_cu << 52);
+    CountReq r{&set, 0, set.G, 0};
     for (int attempt = 0; attempt < 4; attempt++) {
-        bool tier_c = set.hint_tier_c;
-        void *before[4] = {w.masks.p, w.units.p, w.cands.p, w.gtab.p};
-        ensure_work(ctx, w, set, tier_c);
-        bool moved = before[0] != w.masks.p || before[1] != w.units.p || before[2] != w.cands.p ||
-                     before[3] != w.gtab.p;
-        if (!w.exec || w.exec_set != &set || w.exec_key != key || moved) {
+        ensure_work(ctx, w, set);
+        const LaunchArgs L = make_args(ctx, w, r, shp);
+        const unsigned char *lb = (const unsigned char *)&L;
+        const bool same = w.exec && w.exec_args.size() == sizeof(L) &&
+                          memcmp(w.exec_args.data(), lb, sizeof(L)) == 0;
+        if (!same) {
             if (w.exec) { (void)hipGraphExecDestroy(w.exec); w.exec = nullptr; }
-            hipGraph_t graph;
+            w.exec_args.clear();
+            hipGraph_t graph = nullptr;
             HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            CountReq r{&set, 0, set.G, 0};
             try {
-                enqueue_count(ctx, w, r, shp, tier_c, s);
+                enqueue_args(ctx, L, s, false);
             } catch (...) {
-                hipGraph_t junk;
+                hipGraph_t junk = nullptr;
                 (void)hipStreamEndCapture(s, &junk);
                 if (junk) (void)hipGraphDestroy(junk);
                 throw;
@@ -800,19 +856,15 @@ void count_set_batched(bbc_ctx *ctx, Work &w, GraphSet &set, hipStream_t s, int6
             hipError_t e = hipGraphInstantiate(&w.exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             HIP_OK(e);
-            w.exec_set = &set;
-            w.exec_key = key;
+            w.exec_args.assign(lb, lb + sizeof(L));
         }
         HIP_OK(hipGraphLaunch(w.exec, s));
         enqueue_readback(w, set, s);
         HIP_OK(hipStreamSynchronize(s));
-        bool need_c;
-        if (check_counters(ctx, w, set, tier_c, &need_c)) {
+        if (check_counters(ctx, w, set)) {
             results_from_host(w, set, 0, set.G, out);
             return;
         }
-        (void)hipGraphExecDestroy(w.exec);
-        w.exec = nullptr;
     }
     fail(BBC_E_NOMEM, "batched count workspace kept overflowing");
 }
@@ -1034,6 +1086,8 @@ void bbc_ctx_destroy(bbc_ctx *ctx)
     ctx->requests.clear();
     ctx->queue.clear();
     if (ctx->work.exec) { (void)hipGraphExecDestroy(ctx->work.exec); ctx->work.exec = nullptr; }
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -1247,6 +1301,16 @@ bbc_status bbc_wait(bbc_ctx *ctx, bbc_ticket t, int64_t *out_count)
 {
     if (!ctx) return BBC_E_INVAL;
     return take_result(ctx, t, out_count, true);
+}
+
+bbc_status bbc_set_timing(bbc_ctx *ctx, int enable)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return guard(ctx, [&] {
+        if (enable && !ctx->ev[0])
+            for (auto &e : ctx->ev) HIP_OK(hipEventCreate(&e));
+        ctx->timing = enable != 0;
+    });
 }
 
 bbc_status bbc_get_last_stats(bbc_ctx *ctx, bbc_count_stats *out)

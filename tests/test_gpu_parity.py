@@ -257,6 +257,28 @@ def test_config4_batch(ctx, oracle):
     assert sum(want) > 0
 
 
+def test_batch_rebuild_cycles(ctx, oracle):
+    """Regression: batches built, counted, freed and rebuilt (new device
+    buffers each time) must not replay a launch captured for an earlier
+    batch; single-graph counts in between change the workspace too."""
+    say("batch rebuild cycles")
+    gs = G.config4(21, n_graphs=300)
+    want = [oracle.count_bbvp(g, 0, threads=8)["total"] for g in gs]
+    nu, nv, off, eu, ev, sg = G.concat(gs)
+    for cycle in range(3):
+        hs = ctx.build_csr_batch(nu, nv, off, eu, ev, sg)
+        assert list(ctx.count_batch(hs)) == want, cycle
+        assert list(ctx.count_batch(hs)) == want, cycle
+        for h in hs:
+            h.free()
+        one = build(ctx, gs[cycle])
+        assert ctx.count_global(one) == want[cycle]
+        one.free()
+    half = G.concat(gs[:150])
+    hs = ctx.build_csr_batch(*half)
+    assert list(ctx.count_batch(hs)) == want[:150]
+
+
 # -------------------------------------------------------------- serving
 def test_serving_mix_matches_alone(ctx, oracle, B):
     say("serving")
