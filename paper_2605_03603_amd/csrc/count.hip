@@ -76,35 +76,35 @@ constexpr uint32_t kWideCols = 32;     // unit width (columns) for wider masks
 constexpr uint32_t kMaskChunk = 1u << 16;   // mask words reserved per workgroup at a time
 constexpr uint32_t kCandChunk = 1u << 13;
 constexpr uint32_t kRecChunk = 16;
+constexpr int kUnroll = 4;              // independent neighbour-list loads per lane
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t x, int log2h)
 {
     return (x * 0x9E3779B1u) >> (32 - log2h);
 }
 
-// Insert-or-add into an open-addressing table (linear probing); sets *over
-// when the table is too full (the anchor then goes to the next tier).
-__device__ __forceinline__ void hash_add(uint32_t *keys, uint32_t *vals, uint32_t H, int log2h,
-                                         uint32_t x, uint32_t inc, uint32_t *used, uint32_t limit,
-                                         volatile uint32_t *over)
+// Insert-or-add into an open-addressing table (linear probing). Returns true
+// when this call inserted a new key (the caller counts new keys per wave);
+// sets *over when the probe run gets too long.
+__device__ __forceinline__ bool hash_add(uint32_t *keys, uint32_t *vals, uint32_t H, int log2h,
+                                         uint32_t x, uint32_t inc, volatile uint32_t *over)
 {
     uint32_t h = hash_slot(x, log2h);
-    for (uint32_t probe = 0; probe < H; probe++) {
+    // a probe run this long means the table is (nearly) full: the anchor
+    // moves to a bigger tier
+    const uint32_t max_probe = H < 256 ? H : 256;
+    for (uint32_t probe = 0; probe < max_probe; probe++) {
         uint32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
-        if (k == x) { atomicAdd(&vals[h], inc); return; }
+        if (k == x) { atomicAdd(&vals[h], inc); return false; }
         if (k == kEmpty) {
             uint32_t old = atomicCAS(&keys[h], kEmpty, x);
-            if (old == kEmpty) {
-                if (atomicAdd(used, 1u) >= limit) *over = 1;
-                atomicAdd(&vals[h], inc);
-                return;
-            }
-            if (old == x) { atomicAdd(&vals[h], inc); return; }
+            if (old == kEmpty) { atomicAdd(&vals[h], inc); return true; }
+            if (old == x) { atomicAdd(&vals[h], inc); return false; }
         }
         h = (h + 1) & (H - 1);
-        if (*over) return;
     }
     *over = 1;
+    return false;
 }
 
 // Slot of a key known to be present; H if absent (never expected).
@@ -172,24 +172,123 @@ struct PairShared {
     uint32_t item, over, used, nv, skip, wedges;
     uint32_t qlo, qhi, qslice, qtried;
     uint32_t aidx, arec_end;
+    unsigned long long top1, top2;               // (suffix length << 32) | position
     unsigned long long moff, mres_end, coff, cres_end;
     unsigned long long need_m, need_c, need_r, need_u;   // this workgroup's demand
 };
 
-// The per-anchor procedure shared by all tiers. Table storage is passed as
-// pointers (LDS arrays for tiers A and B, global memory for tier C).
-template <int THREADS>
-__device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uint32_t *vals,
-                                          const uint32_t H, const int log2h, uint32_t *pst,
-                                          uint32_t *pln, const uint32_t maxd, uint32_t *vc,
-                                          const uint32_t kmax, uint32_t *msk,
-                                          const uint32_t maskw, PairShared &sh)
+// Storage of one tier. `region` (2H words) holds the counting table (keys,
+// vals) while partners are counted; once the candidate classes are known it
+// is reused for a compact table of the selected partners (ckeys, cidx: 2HC
+// words) followed by the mask staging area (maskw words).
+struct PairMem {
+    uint32_t *region;
+    uint32_t H;
+    int log2h;
+    uint32_t HC;
+    int log2hc;
+    uint32_t maskw;
+    uint32_t *pst, *pln;   // per position: suffix start, suffix length | sign << 31
+    uint32_t maxd;
+    uint32_t *vc;          // per virtual candidate: partner rank | class << 31
+    uint32_t kmax;
+};
+
+// Increment an existing key; absent keys are ignored.
+__device__ __forceinline__ void hash_inc(const uint32_t *keys, uint32_t *vals, uint32_t H,
+                                         int log2h, uint32_t x, uint32_t inc)
+{
+    uint32_t h = hash_slot(x, log2h);
+    for (uint32_t probe = 0; probe < H; probe++) {
+        const uint32_t k = keys[h];
+        if (k == x) { atomicAdd(&vals[h], inc); return; }
+        if (k == kEmpty) return;
+        h = (h + 1) & (H - 1);
+    }
+}
+
+// Packed candidate indices of a partner in the compact table (0 if absent).
+__device__ __forceinline__ uint32_t compact_find(const uint32_t *ckeys, const uint32_t *cidx,
+                                                 uint32_t HC, int log2hc, uint32_t x)
+{
+    uint32_t h = hash_slot(x, log2hc);
+    for (uint32_t probe = 0; probe < HC; probe++) {
+        const uint32_t k = ckeys[h];
+        if (k == x) return cidx[h];
+        if (k == kEmpty) return 0;
+        h = (h + 1) & (HC - 1);
+    }
+    return 0;
+}
+
+// Visit the wedges of the anchor's positions: the ordinary positions one
+// wave per position, the two longest suffixes spread over the whole
+// workgroup. f(entry, position, sign of (anchor, v)) is called per wedge;
+// every lane keeps kUnroll independent loads in flight.
+template <int THREADS, typename F>
+__device__ __forceinline__ void walk_positions(const CsrView &g, const PairMem &m, uint32_t d,
+                                               uint32_t t1, uint32_t t2, bool ordinary,
+                                               bool top, F &&f)
 {
     constexpr int NW = THREADS / kWave;
     const int tid = threadIdx.x, lane = __lane_id(), wv = tid / kWave;
+    if (ordinary) {
+        for (uint32_t p = wv; p < d; p += NW) {
+            if (p == t1 || p == t2) continue;
+            const uint32_t ln = m.pln[p];
+            const uint32_t len = ln & 0x7fffffffu;
+            if (!len) continue;
+            const uint32_t st = m.pst[p], sg = ln >> 31;
+            for (uint32_t j0 = 0; j0 < len; j0 += kWave * kUnroll) {
+                uint32_t e2[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    const uint32_t j = j0 + u * kWave + lane;
+                    e2[u] = j < len ? g.o_adj[st + j] : kEmpty;
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++)
+                    if (e2[u] != kEmpty) f(e2[u], p, sg);
+            }
+        }
+    }
+    if (top) {
+        const uint32_t l1 = t1 < d ? (m.pln[t1] & 0x7fffffffu) : 0;
+        const uint32_t l2 = t2 < d ? (m.pln[t2] & 0x7fffffffu) : 0;
+        const uint32_t tot = l1 + l2;
+        for (uint32_t j0 = 0; j0 < tot; j0 += THREADS * kUnroll) {
+            uint32_t e2[kUnroll], pp[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; u++) {
+                const uint32_t j = j0 + u * THREADS + tid;
+                e2[u] = kEmpty;
+                pp[u] = 0;
+                if (j < tot) {
+                    const uint32_t p = j < l1 ? t1 : t2;
+                    const uint32_t jj = j < l1 ? j : j - l1;
+                    e2[u] = g.o_adj[m.pst[p] + jj];
+                    pp[u] = p;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; u++)
+                if (e2[u] != kEmpty) f(e2[u], pp[u], m.pln[pp[u]] >> 31);
+        }
+    }
+}
+
+// The per-anchor procedure shared by all tiers (LDS storage for tiers A and
+// B, global memory for tier C).
+template <int THREADS>
+__device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, PairShared &sh)
+{
+    const int tid = threadIdx.x, lane = __lane_id();
     const CsrView &g = P.g;
     Counters *C = P.ws.ctr;
-    const uint32_t limit = H - H / 4;
+    uint32_t *keys = m.region, *vals = m.region + m.H;
+    uint32_t *ckeys = m.region, *cidx = m.region + m.HC;
+    uint32_t *mstage = m.region + 2 * m.HC;
+    const uint32_t H = m.H, limit = m.H - m.H / 4;
     uint64_t my_wedges = 0;
 
     const uint32_t n_items =
@@ -200,7 +299,10 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
     const uint32_t *list = P.tier ? P.ws.defer[P.tier - 1] : nullptr;
     uint32_t *next_list = P.tier < 2 ? P.ws.defer[P.tier] : nullptr;
 
-    for (uint32_t i = tid; i < H; i += THREADS) { keys[i] = kEmpty; vals[i] = 0; }
+    auto clear_region = [&]() {
+        for (uint32_t i = tid; i < H; i += THREADS) { keys[i] = kEmpty; vals[i] = 0; }
+    };
+    clear_region();
     if (tid == 0) {
         sh.qlo = sh.qhi = 0; sh.qslice = blockIdx.x % kXcd; sh.qtried = 0;
         sh.moff = sh.mres_end = 0; sh.coff = sh.cres_end = 0;
@@ -227,6 +329,7 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
             }
             sh.item = sh.qlo < sh.qhi ? sh.qlo++ : n_items;
             sh.over = 0; sh.used = 0; sh.nv = 0; sh.skip = 0; sh.wedges = 0;
+            sh.top1 = 0; sh.top2 = 0;
         }
         __syncthreads();
         const uint32_t item = sh.item;
@@ -235,70 +338,98 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
         const uint64_t s0 = g.s_off[r];
         const uint32_t d = (uint32_t)(g.s_off[r + 1] - s0);
         if (d < 3) continue;
-        if (d > maxd) {
+        if (d > m.maxd) {
             if (tid == 0) defer_anchor(r);
             continue;
         }
-        // phase 0: the part of each neighbour's list ranked above the anchor
+        // phase 0: the part of each neighbour's list ranked above the anchor,
+        // and the position with the longest such suffix
         for (uint32_t p = tid; p < d; p += THREADS) {
             const uint32_t e = g.s_adj[s0 + p];
             const uint32_t st = g.s_rev[s0 + p] + 1;
             const uint32_t hi = (uint32_t)g.o_off[(e >> 1) + 1];
             uint32_t len = hi - st;
             if (len < 2) len = 0;   // v needs 2 higher partners to lie in any T
-            pst[p] = st;
-            pln[p] = len | ((e & 1u) << 31);
-            if (len) atomicAdd(&sh.wedges, len);
+            m.pst[p] = st;
+            m.pln[p] = len | ((e & 1u) << 31);
+            if (len) {
+                atomicAdd(&sh.wedges, len);
+                atomicMax(&sh.top1, ((unsigned long long)len << 32) | p);
+            }
         }
         __syncthreads();
         if (sh.wedges < 6) continue;   // fewer than 2 classes of 3 are impossible
-        // phase 1: (same, different) counts per higher-priority partner
-        for (uint32_t p = wv; p < d; p += NW) {
-            const uint32_t ln = pln[p];
-            const uint32_t len = ln & 0x7fffffffu;
-            if (!len) continue;
-            const uint32_t st = pst[p], sg = ln >> 31;
-            my_wedges += lane < len ? (len - lane + kWave - 1) / kWave : 0;
-            for (uint32_t j = lane; j < len; j += kWave) {
-                const uint32_t e2 = g.o_adj[st + j];
-                hash_add(keys, vals, H, log2h, e2 >> 1, ((e2 & 1u) ^ sg) ? 0x10000u : 1u,
-                         &sh.used, limit, &sh.over);
-            }
-            if (__atomic_load_n(&sh.over, __ATOMIC_RELAXED)) break;
+        const uint32_t t1 = sh.top1 ? (uint32_t)sh.top1 : kEmpty;
+        for (uint32_t p = tid; p < d; p += THREADS) {
+            const uint32_t len = m.pln[p] & 0x7fffffffu;
+            if (len && p != t1) atomicMax(&sh.top2, ((unsigned long long)len << 32) | p);
+        }
+        __syncthreads();
+        const uint32_t t2 = sh.top2 ? (uint32_t)sh.top2 : kEmpty;
+        // phase 1: (same, different) counts per higher-priority partner. A
+        // class needs 3 hits at distinct positions, so every partner that can
+        // qualify is hit at a position other than the two longest suffixes:
+        // only those positions insert keys, the two longest only add to them.
+        {
+            uint32_t fresh = 0;
+            walk_positions<THREADS>(g, m, d, t1, t2, true, false,
+                                    [&](uint32_t e2, uint32_t, uint32_t sg) {
+                                        my_wedges++;
+                                        fresh += hash_add(keys, vals, H, m.log2h, e2 >> 1,
+                                                          ((e2 & 1u) ^ sg) ? 0x10000u : 1u, &sh.over);
+                                    });
+            const uint32_t nf = wave_sum<uint32_t>(fresh);
+            if (lane == 0 && nf && atomicAdd(&sh.used, nf) + nf > limit) sh.over = 1;
         }
         __syncthreads();
         bool defer = sh.over != 0;
-        // phase 2: classes with >= 3 members become virtual candidates
         if (!defer) {
+            walk_positions<THREADS>(g, m, d, t1, t2, false, true,
+                                    [&](uint32_t e2, uint32_t, uint32_t sg) {
+                                        my_wedges++;
+                                        hash_inc(keys, vals, H, m.log2h, e2 >> 1,
+                                                 ((e2 & 1u) ^ sg) ? 0x10000u : 1u);
+                                    });
+            __syncthreads();
+            // phase 2: classes with >= 3 members become virtual candidates
             for (uint32_t slot = tid; slot < H; slot += THREADS) {
                 const uint32_t k = keys[slot];
                 if (k == kEmpty) continue;
                 const uint32_t v = vals[slot];
-                uint32_t is = 0, id = 0;
                 if ((v & 0xffffu) >= 3) {
-                    uint32_t t = atomicAdd(&sh.nv, 1u);
-                    if (t < kmax) vc[t] = k;
-                    is = t + 1;
+                    const uint32_t t = atomicAdd(&sh.nv, 1u);
+                    if (t < m.kmax) m.vc[t] = k;
                 }
                 if ((v >> 16) >= 3) {
-                    uint32_t t = atomicAdd(&sh.nv, 1u);
-                    if (t < kmax) vc[t] = k;
-                    id = t + 1;
+                    const uint32_t t = atomicAdd(&sh.nv, 1u);
+                    if (t < m.kmax) m.vc[t] = k | 0x80000000u;
                 }
-                vals[slot] = (is & 0xffffu) | (id << 16);
             }
             __syncthreads();
-            defer = sh.nv > kmax;
+            defer = sh.nv > m.kmax;
         }
         if (defer) {
             if (tid == 0) defer_anchor(r);
-            for (uint32_t i = tid; i < H; i += THREADS) { keys[i] = kEmpty; vals[i] = 0; }
+            clear_region();
             continue;
         }
         const uint32_t k = sh.nv;
         if (k < 2) {
-            for (uint32_t i = tid; i < H; i += THREADS) { keys[i] = kEmpty; vals[i] = 0; }
+            clear_region();
             continue;
+        }
+        // compact table: partner -> (same index + 1) | (different index + 1) << 16
+        for (uint32_t i = tid; i < 2 * m.HC; i += THREADS) m.region[i] = i < m.HC ? kEmpty : 0u;
+        __syncthreads();
+        for (uint32_t t = tid; t < k; t += THREADS) {
+            const uint32_t x = m.vc[t] & 0x7fffffffu;
+            const uint32_t bits = (t + 1) << ((m.vc[t] >> 31) ? 16 : 0);
+            uint32_t h = hash_slot(x, m.log2hc);
+            for (uint32_t probe = 0; probe < m.HC; probe++) {
+                const uint32_t old = atomicCAS(&ckeys[h], kEmpty, x);
+                if (old == kEmpty || old == x) { atomicOr(&cidx[h], bits); break; }
+                h = (h + 1) & (m.HC - 1);
+            }
         }
         const uint32_t W = (d + 31) >> 5;
         const uint64_t words = (uint64_t)k * W;
@@ -309,26 +440,24 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
             sh.need_r += 1;
             sh.need_u += anchor_units(k, W, P.chunk_base);
             bool bad = (__atomic_load_n(&C->over_cap, __ATOMIC_RELAXED) & 2u) != 0;
-            if (bad) {
-                // a buffer already overflowed: only the demand is recorded
-            } else {
-            if (sh.moff + words > sh.mres_end) {
-                uint64_t want = words > kMaskChunk ? words : kMaskChunk;
-                uint64_t o = atomicAdd(&C->mask_cursor, (unsigned long long)want);
-                sh.moff = o; sh.mres_end = o + want;
-                if (o + want > P.ws.cap_mask_words) bad = true;
-            }
-            if (sh.coff + k > sh.cres_end) {
-                uint64_t want = k > kCandChunk ? k : kCandChunk;
-                uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)want);
-                sh.coff = o; sh.cres_end = o + want;
-                if (o + want > P.ws.cap_cands) bad = true;
-            }
-            if (sh.aidx >= sh.arec_end) {
-                uint32_t o = atomicAdd(&C->n_anchor, kRecChunk);
-                sh.aidx = o; sh.arec_end = o + kRecChunk;
-                if ((uint64_t)o + kRecChunk > P.ws.cap_anchors) bad = true;
-            }
+            if (!bad) {
+                if (sh.moff + words > sh.mres_end) {
+                    uint64_t want = words > kMaskChunk ? words : kMaskChunk;
+                    uint64_t o = atomicAdd(&C->mask_cursor, (unsigned long long)want);
+                    sh.moff = o; sh.mres_end = o + want;
+                    if (o + want > P.ws.cap_mask_words) bad = true;
+                }
+                if (sh.coff + k > sh.cres_end) {
+                    uint64_t want = k > kCandChunk ? k : kCandChunk;
+                    uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)want);
+                    sh.coff = o; sh.cres_end = o + want;
+                    if (o + want > P.ws.cap_cands) bad = true;
+                }
+                if (sh.aidx >= sh.arec_end) {
+                    uint32_t o = atomicAdd(&C->n_anchor, kRecChunk);
+                    sh.aidx = o; sh.arec_end = o + kRecChunk;
+                    if ((uint64_t)o + kRecChunk > P.ws.cap_anchors) bad = true;
+                }
             }
             sh.skip = bad;
             if (bad) {
@@ -339,35 +468,27 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
         }
         __syncthreads();
         if (sh.skip) {
-            for (uint32_t i = tid; i < H; i += THREADS) { keys[i] = kEmpty; vals[i] = 0; }
+            clear_region();
             continue;
         }
-        const bool in_lds = words <= maskw;
+        const bool staged = words <= m.maskw;
         const uint64_t moff = sh.moff, coff = sh.coff;
         const uint32_t aidx = sh.aidx;
-        uint32_t *mp = in_lds ? msk : P.ws.masks + moff;
+        uint32_t *mp = staged ? mstage : P.ws.masks + moff;
         for (uint64_t i = tid; i < words; i += THREADS) mp[i] = 0;
-        if (!in_lds) __threadfence();
+        if (!staged) __threadfence();
         __syncthreads();
         // phase 3: bit p of M_(w,c) for every higher-priority wedge through position p
-        for (uint32_t p = wv; p < d; p += NW) {
-            const uint32_t ln = pln[p];
-            const uint32_t len = ln & 0x7fffffffu;
-            if (!len) continue;
-            const uint32_t st = pst[p], sg = ln >> 31;
-            for (uint32_t j = lane; j < len; j += kWave) {
-                const uint32_t e2 = g.o_adj[st + j];
-                const uint32_t h = hash_find(keys, H, log2h, e2 >> 1);
-                if (h == H) { atomicOr(&C->over_cap, 8u); continue; }
-                const uint32_t v = vals[h];
-                const uint32_t idx = ((e2 & 1u) ^ sg) ? (v >> 16) : (v & 0xffffu);
-                if (idx) atomicOr(&mp[(uint64_t)(idx - 1) * W + (p >> 5)], 1u << (p & 31));
-            }
-        }
+        walk_positions<THREADS>(g, m, d, t1, t2, true, true,
+                                [&](uint32_t e2, uint32_t p, uint32_t sg) {
+                                    const uint32_t v = compact_find(ckeys, cidx, m.HC, m.log2hc, e2 >> 1);
+                                    const uint32_t idx = ((e2 & 1u) ^ sg) ? (v >> 16) : (v & 0xffffu);
+                                    if (idx) atomicOr(&mp[(uint64_t)(idx - 1) * W + (p >> 5)], 1u << (p & 31));
+                                });
         __syncthreads();
-        if (in_lds)
-            for (uint64_t i = tid; i < words; i += THREADS) P.ws.masks[moff + i] = msk[i];
-        for (uint32_t i = tid; i < k; i += THREADS) P.ws.cands[coff + i] = vc[i];
+        if (staged)
+            for (uint64_t i = tid; i < words; i += THREADS) P.ws.masks[moff + i] = mstage[i];
+        for (uint32_t i = tid; i < k; i += THREADS) P.ws.cands[coff + i] = m.vc[i] & 0x7fffffffu;
         if (tid == 0) {
             AnchorRec a;
             a.rank = r; a.k = k; a.w32 = W; a.graph = g.s_graph[r];
@@ -377,14 +498,15 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
             sh.coff = coff + k;
             sh.aidx = aidx + 1;
         }
-        for (uint32_t i = tid; i < H; i += THREADS) { keys[i] = kEmpty; vals[i] = 0; }
+        __syncthreads();
+        clear_region();
     }
-    // unused reserved anchor records are marked empty
     if (tid == 0) {
         if (sh.need_m) atomicAdd(&C->need_masks, sh.need_m);
         if (sh.need_c) atomicAdd(&C->need_cands, sh.need_c);
         if (sh.need_r) atomicAdd(&C->need_recs, sh.need_r);
         if (sh.need_u) atomicAdd(&C->need_units, sh.need_u);
+        // unused reserved anchor records are marked empty
         for (uint32_t i = sh.aidx; i < sh.arec_end; i++) {
             AnchorRec a;
             a.rank = 0; a.k = 0; a.w32 = 0; a.graph = 0; a.mask_off = 0; a.cand_off = 0;
@@ -395,42 +517,65 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, uint32_t *keys, uin
     if (lane == 0 && my_wedges) atomicAdd(&C->wedges, (unsigned long long)my_wedges);
 }
 
-template <int THREADS, int H, int LOG2H, int MAXD, int KMAX, int MASKW>
+__host__ __device__ constexpr int ilog2(uint32_t x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+__host__ __device__ constexpr uint32_t compact_slots(uint32_t kmax, uint32_t H)
+{
+    uint32_t c = 1;
+    while (c < 2 * kmax) c <<= 1;
+    return c < H / 2 ? c : H / 2;
+}
+
+template <int THREADS, int H, int MAXD, int KMAX>
 __global__ void __launch_bounds__(THREADS) k_pair_lds(PairArgs P)
 {
-    __shared__ uint32_t keys[H], vals[H], pst[MAXD], pln[MAXD], vc[KMAX], msk[MASKW];
+    __shared__ uint32_t region[2 * H], pst[MAXD], pln[MAXD], vc[KMAX];
     __shared__ PairShared sh;
-    pair_loop<THREADS>(P, keys, vals, H, LOG2H, pst, pln, MAXD, vc, KMAX, msk, MASKW, sh);
+    constexpr uint32_t HC = compact_slots(KMAX, H);
+    PairMem m;
+    m.region = region; m.H = H; m.log2h = ilog2(H);
+    m.HC = HC; m.log2hc = ilog2(HC); m.maskw = 2 * H - 2 * HC;
+    m.pst = pst; m.pln = pln; m.maxd = MAXD; m.vc = vc; m.kmax = KMAX;
+    pair_loop<THREADS>(P, m, sh);
 }
 
 // Tier B: LDS table, position lists in global memory (any degree below 2^16).
-template <int THREADS, int H, int LOG2H, int KMAX>
+template <int THREADS, int H, int KMAX>
 __global__ void __launch_bounds__(THREADS) k_pair_big(PairArgs P)
 {
-    __shared__ uint32_t keys[H], vals[H], vc[KMAX];
+    __shared__ uint32_t region[2 * H], vc[KMAX];
     __shared__ PairShared sh;
-    uint32_t *pst = P.ws.bscr + (uint64_t)blockIdx.x * P.ws.bscr_words_per_block;
-    uint32_t *pln = pst + P.gmaxd;
-    pair_loop<THREADS>(P, keys, vals, H, LOG2H, pst, pln, P.gmaxd, vc, KMAX, nullptr, 0, sh);
+    constexpr uint32_t HC = compact_slots(KMAX, H);
+    PairMem m;
+    m.region = region; m.H = H; m.log2h = ilog2(H);
+    m.HC = HC; m.log2hc = ilog2(HC); m.maskw = 2 * H - 2 * HC;
+    m.pst = P.ws.bscr + (uint64_t)blockIdx.x * P.ws.bscr_words_per_block;
+    m.pln = m.pst + P.gmaxd;
+    m.maxd = P.gmaxd; m.vc = vc; m.kmax = KMAX;
+    pair_loop<THREADS>(P, m, sh);
 }
 
 constexpr int kGThreads = 1024;
 
+// Tier C: every table in global memory.
 __global__ void __launch_bounds__(kGThreads) k_pair_global(PairArgs P)
 {
     __shared__ PairShared sh;
     uint32_t *base = P.ws.gtab + (uint64_t)blockIdx.x * P.ws.gtab_words_per_block;
-    const uint32_t H = P.gH;
-    uint32_t *keys = base;
-    uint32_t *vals = keys + H;
-    uint32_t *pst = vals + H;
-    uint32_t *pln = pst + P.gmaxd;
-    uint32_t *vc = pln + P.gmaxd;
-    pair_loop<kGThreads>(P, keys, vals, H, P.glog2h, pst, pln, P.gmaxd, vc, P.gkmax, nullptr, 0,
-                         sh);
+    PairMem m;
+    m.region = base; m.H = P.gH; m.log2h = P.glog2h;
+    m.HC = compact_slots(P.gkmax, P.gH); m.log2hc = ilog2(m.HC);
+    m.maskw = 2 * m.H - 2 * m.HC;
+    m.pst = base + 2ull * P.gH;
+    m.pln = m.pst + P.gmaxd;
+    m.maxd = P.gmaxd;
+    m.vc = m.pln + P.gmaxd;
+    m.kmax = P.gkmax;
+    pair_loop<kGThreads>(P, m, sh);
 }
 
 // ------------------------------------------------------------- planning
+// Units per anchor record; units of masks wider than kRegW words are
+// counted in the second half so that they follow all the others.
 __global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk_base)
 {
     // after a capacity overflow the records are incomplete: plan nothing
@@ -438,12 +583,14 @@ __global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk
                                             : (uint32_t)min((uint64_t)ws.ctr->n_anchor, ws.cap_anchors);
     for (uint64_t a = (uint64_t)blockIdx.x * 256 + threadIdx.x; a < ws.cap_anchors;
          a += (uint64_t)gridDim.x * 256) {
-        uint32_t c = 0;
+        uint32_t c = 0, wide = 0;
         if (a < n_rec) {
             const AnchorRec &r = ws.anchors[a];
             if (r.k <= 65535u) c = anchor_units(r.k, r.w32, chunk_base);
+            wide = r.w32 > kRegW;
         }
-        ws.ucnt[a] = c;
+        ws.ucnt[a] = wide ? 0 : c;
+        ws.ucnt[ws.cap_anchors + a] = wide ? c : 0;
     }
 }
 
@@ -452,9 +599,10 @@ __global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk
 {
     Counters *C = ws.ctr;
     const uint32_t n_rec = C->over_cap ? 0u : (uint32_t)min((uint64_t)C->n_anchor, ws.cap_anchors);
-    const uint64_t total = ws.uoff[ws.cap_anchors];
+    const uint64_t total = ws.uoff[2 * ws.cap_anchors];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         C->n_units = (uint32_t)min(total, ws.cap_units);
+        C->n_narrow = (uint32_t)min(ws.uoff[ws.cap_anchors], ws.cap_units);
         if (total > ws.cap_units) atomicOr(&C->over_cap, 2u);
     }
     const uint32_t lane = __lane_id();
@@ -463,7 +611,7 @@ __global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk
     for (uint32_t a = wave; a < n_rec; a += nwaves) {
         const AnchorRec r = ws.anchors[a];
         if (r.k < 2 || r.k > 65535u) continue;
-        const uint64_t base = ws.uoff[a];
+        const uint64_t base = ws.uoff[(r.w32 > kRegW ? ws.cap_anchors : 0) + a];
         const uint32_t CH = unit_cols(r.w32, chunk_base);
         const uint32_t nb = (r.k + kWave - 1) / kWave;
         uint32_t u0 = 0;
@@ -632,8 +780,8 @@ constexpr int kTThreads = 256;
 constexpr uint32_t kMaxChunk = 2048;
 constexpr uint32_t kUnitGrab = 4;
 
-template <int MODE>
-__global__ void __launch_bounds__(kTThreads) k_triplet(TriArgs T)
+template <int MODE, bool WIDE>
+__global__ void __launch_bounds__(kTThreads, WIDE ? 1 : 5) k_triplet(TriArgs T)
 {
     __shared__ uint32_t c3[kC3Max + 1];
     __shared__ unsigned long long colacc_all[MODE == 1 ? kTThreads / kWave : 1][MODE == 1 ? kMaxChunk : 1];
@@ -644,7 +792,11 @@ __global__ void __launch_bounds__(kTThreads) k_triplet(TriArgs T)
     __syncthreads();
     Counters *C = T.ws.ctr;
     if (__atomic_load_n(&C->over_cap, __ATOMIC_RELAXED)) return;
-    const uint32_t n_units = __atomic_load_n(&C->n_units, __ATOMIC_RELAXED);
+    // narrow units are [0, n_narrow), wide ones [n_narrow, n_units)
+    const uint32_t n_narrow = __atomic_load_n(&C->n_narrow, __ATOMIC_RELAXED);
+    const uint32_t u_base = WIDE ? n_narrow : 0;
+    const uint32_t n_units = WIDE ? __atomic_load_n(&C->n_units, __ATOMIC_RELAXED) - n_narrow : n_narrow;
+    Cursor *queue = WIDE ? C->q_tri_wide : C->q_tri;
     const uint32_t lane = __lane_id();
     uint64_t *colacc = (uint64_t *)colacc_all[MODE == 1 ? threadIdx.x / kWave : 0];
     uint64_t examined = 0, exwords = 0;
@@ -665,7 +817,7 @@ __global__ void __launch_bounds__(kTThreads) k_triplet(TriArgs T)
         if (qlo >= qhi) {
             uint32_t lo = 0, hi = 0;
             bool ok = false;
-            if (lane == 0) ok = queue_take(C->q_tri, n_units, kUnitGrab, &slice, &tried, &lo, &hi);
+            if (lane == 0) ok = queue_take(queue, n_units, kUnitGrab, &slice, &tried, &lo, &hi);
             ok = __shfl(ok ? 1 : 0, 0, kWave);
             if (!ok) break;
             qlo = __builtin_amdgcn_readfirstlane(__shfl(lo, 0, kWave));
@@ -673,20 +825,24 @@ __global__ void __launch_bounds__(kTThreads) k_triplet(TriArgs T)
             slice = __shfl(slice, 0, kWave);
             tried = __shfl(tried, 0, kWave);
         }
-        const uint32_t u = qlo++;
+        const uint32_t u = u_base + qlo++;
         const Unit un = load_unit(T.ws.units + u);
         const AnchorRec a = load_anchor(T.ws.anchors + un.anchor);
         if (a.graph != cur_graph) {
             if (cur_graph != 0xffffffffu) flush();
             cur_graph = a.graph;
         }
-        uint64_t acc;
-        switch (a.w32) {
+        uint64_t acc = 0;
+        if (WIDE) {
+            acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T);
+        } else {
+            switch (a.w32) {
 #define BBC_W(n) case n: acc = tri_rows<n, MODE>(un, a, T.ws.masks, c3, colacc, T); break;
-            BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) BBC_W(5) BBC_W(6) BBC_W(7) BBC_W(8)
-            BBC_W(9) BBC_W(10) BBC_W(11) BBC_W(12) BBC_W(13) BBC_W(14) BBC_W(15) BBC_W(16)
+                BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) BBC_W(5) BBC_W(6) BBC_W(7) BBC_W(8)
+                BBC_W(9) BBC_W(10) BBC_W(11) BBC_W(12) BBC_W(13) BBC_W(14) BBC_W(15) BBC_W(16)
 #undef BBC_W
-            default: acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T); break;
+                default: break;
+            }
         }
         const uint32_t i = un.rb * kWave + lane;
         if (i < a.k && i > un.c0) {
@@ -721,9 +877,10 @@ __global__ void __launch_bounds__(kTThreads) k_triplet(TriArgs T)
 
 }  // namespace
 
-// Tier parameters (LDS use per block: tier A ~ 64 KiB, tier B ~ 144 KiB).
-constexpr int kAThreads = 512, kAH = 4096, kALog = 12, kAMaxD = 1024, kAKmax = 2048, kAMaskW = 4096;
-constexpr int kBThreads = 1024, kBH = 16384, kBLog = 14, kBKmax = 4096;
+// Tier parameters (LDS use per block: tier A ~ 80 KiB, two blocks per CU;
+// tier B ~ 144 KiB).
+constexpr int kAThreads = 512, kAH = 8192, kAMaxD = 1024, kAKmax = 1984;
+constexpr int kBThreads = 1024, kBH = 16384, kBKmax = 4096;
 
 uint32_t tier_c_max_degree() { return 65535; }
 uint32_t tier_c_max_k() { return 65535; }
@@ -733,10 +890,10 @@ hipError_t count_pairs(const PairArgs &base, const LaunchShape &sh, hipStream_t 
 {
     PairArgs P = base;
     P.tier = 0;
-    hipLaunchKernelGGL((k_pair_lds<kAThreads, kAH, kALog, kAMaxD, kAKmax, kAMaskW>),
+    hipLaunchKernelGGL((k_pair_lds<kAThreads, kAH, kAMaxD, kAKmax>),
                        dim3(sh.grid_a), dim3(kAThreads), 0, s, P);
     P.tier = 1;
-    hipLaunchKernelGGL((k_pair_big<kBThreads, kBH, kBLog, kBKmax>), dim3(sh.grid_b),
+    hipLaunchKernelGGL((k_pair_big<kBThreads, kBH, kBKmax>), dim3(sh.grid_b),
                        dim3(kBThreads), 0, s, P);
     P.tier = 2;
     hipLaunchKernelGGL(k_pair_global, dim3(sh.grid_c), dim3(kGThreads), 0, s, P);
@@ -748,7 +905,7 @@ hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_
 {
     uint32_t grid = (uint32_t)std::min<uint64_t>((ws.cap_anchors + 255) / 256, 4096);
     hipLaunchKernelGGL(k_plan_count, dim3(grid), dim3(256), 0, s, ws, chunk_base);
-    hipError_t e = scan_u32_to_u64(ws.ucnt, ws.uoff, ws.cap_anchors, tmp, tmp_bytes, s);
+    hipError_t e = scan_u32_to_u64(ws.ucnt, ws.uoff, 2 * ws.cap_anchors, tmp, tmp_bytes, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_plan_write, dim3(1024), dim3(256), 0, s, ws, chunk_base);
     return hipGetLastError();
@@ -756,9 +913,19 @@ hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_
 
 hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t s)
 {
-    if (mode == 0) hipLaunchKernelGGL(k_triplet<0>, dim3(grid), dim3(kTThreads), 0, s, T);
-    else if (mode == 1) hipLaunchKernelGGL(k_triplet<1>, dim3(grid), dim3(kTThreads), 0, s, T);
-    else hipLaunchKernelGGL(k_triplet<2>, dim3(grid), dim3(kTThreads), 0, s, T);
+    // masks of up to 16 words, then the wider ones (a kernel of their own:
+    // its register use would otherwise lower the occupancy of the first)
+    const uint32_t grid_w = grid / 4 > 0 ? grid / 4 : 1;
+    if (mode == 0) {
+        hipLaunchKernelGGL((k_triplet<0, false>), dim3(grid), dim3(kTThreads), 0, s, T);
+        hipLaunchKernelGGL((k_triplet<0, true>), dim3(grid_w), dim3(kTThreads), 0, s, T);
+    } else if (mode == 1) {
+        hipLaunchKernelGGL((k_triplet<1, false>), dim3(grid), dim3(kTThreads), 0, s, T);
+        hipLaunchKernelGGL((k_triplet<1, true>), dim3(grid_w), dim3(kTThreads), 0, s, T);
+    } else {
+        hipLaunchKernelGGL((k_triplet<2, false>), dim3(grid), dim3(kTThreads), 0, s, T);
+        hipLaunchKernelGGL((k_triplet<2, true>), dim3(grid_w), dim3(kTThreads), 0, s, T);
+    }
     return hipGetLastError();
 }
 

@@ -579,9 +579,9 @@ void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set)
     uint64_t want_units = std::max<uint64_t>({set.hint_units, M / 4, 1ull << 16});
     if (w.cap_anchors < want_anchors) {
         w.anchors.ensure(al, want_anchors * sizeof(AnchorRec));
-        w.ucnt.ensure(al, want_anchors * 4);
-        w.uoff.ensure(al, (want_anchors + 1) * 8);
-        w.ptmp_bytes = scan_tmp_bytes(want_anchors + 1) + 256;
+        w.ucnt.ensure(al, 2 * want_anchors * 4);
+        w.uoff.ensure(al, (2 * want_anchors + 1) * 8);
+        w.ptmp_bytes = scan_tmp_bytes(2 * want_anchors + 1) + 256;
         w.ptmp.ensure(al, w.ptmp_bytes);
         w.cap_anchors = want_anchors;
     }
@@ -606,11 +606,13 @@ void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set)
     // tier C: hash tables sized for the largest anchor side of any graph
     uint32_t max_ns = 0;
     for (auto &d : set.desc) max_ns = std::max(max_ns, d.n_s);
-    uint32_t H = 1024;
-    int lg = 10;
+    // at least 2^18 slots: the compact table of up to 65535 candidate classes
+    // takes half of the region
+    uint32_t H = 1u << 18;
+    int lg = 18;
     while (H < 2ull * max_ns + 64 && lg < 24) { H <<= 1; lg++; }
     if (!w.gtab.p || w.gH < H) {
-        uint64_t words = 2ull * H + 2ull * (maxd + 1) + kmax + 64;
+        uint64_t words = 2ull * H + 2ull * maxd + kmax + 64;
         uint32_t blocks = (uint32_t)std::max<uint64_t>(
             1, std::min<uint64_t>(32, (1ull << 30) / (words * 4)));
         w.gtab.ensure(al, words * 4 * blocks);
@@ -739,6 +741,8 @@ bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set)
     ctx->stats.mask_words = c->mask_cursor;
     ctx->stats.wedges = c->wedges;
     ctx->stats.pair_words = c->pair_words;
+    ctx->stats.deferred_b = c->n_list[0];
+    ctx->stats.deferred_c = c->n_list[1];
     return true;
 }
 
