@@ -141,7 +141,8 @@ def run_served(ctx, pool, pool_counts, large, large_counts, n_requests, qps, see
             picks.append(("L", int(rng.integers(0, len(large)))))
         else:
             picks.append(("S", int(rng.integers(0, len(pool)))))
-    pending = []          # (ticket, arrival time, kind, index) in submission order
+    from collections import deque
+    pending = deque()     # (ticket, arrival time, kind, index) in submission order
     lat = []
     wrong = 0
     t0 = time.time()
@@ -154,24 +155,19 @@ def run_served(ctx, pool, pool_counts, large, large_counts, n_requests, qps, see
             tk = ctx.submit_coo(g.n_u, g.n_v, g.eu, g.ev, g.sign)
             pending.append((tk, t0 + arrivals[nxt], kind, i))
             nxt += 1
-        # results come back batch by batch, roughly in submission order
-        keep = []
-        misses = 0
-        for item in pending:
-            if misses >= 8:
-                keep.append(item)
-                continue
-            tk, ta, kind, i = item
+        # results come back batch by batch, roughly in submission order: poll
+        # a bounded window at the front
+        progressed = False
+        for _ in range(min(64, len(pending))):
+            tk, ta, kind, i = pending.popleft()
             v = ctx.poll(tk)
             if v is None:
-                misses += 1
-                keep.append(item)
+                pending.append((tk, ta, kind, i))
                 continue
             lat.append(time.time() - ta)
             want = pool_counts[i] if kind == "S" else large_counts[i]
             wrong += int(v != want)
-        progressed = len(keep) != len(pending)
-        pending = keep
+            progressed = True
         if not progressed:
             time.sleep(0.0001)
     wall = time.time() - t0

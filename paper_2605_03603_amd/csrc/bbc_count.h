@@ -9,10 +9,12 @@ struct PairArgs {
     CsrView g;
     Workspace ws;
     uint32_t a0, a1;        // anchor range (global ranks) of the first tier
-    int tier;               // 0: LDS 4096-slot tables, 1: LDS 16384, 2: global tables
+    int tier;               // 0, 1: LDS tables; 2: bounded global tables; 3: full-size global tables
     uint32_t chunk_base;    // triplet unit width in columns for 1-word masks (<= 2048)
     uint32_t gH;            // tier-2 table slots (power of two)
     int glog2h;
+    uint32_t dH;            // tier-3 table slots
+    int dlog2h;
     uint32_t gmaxd, gkmax;  // degree and candidate limits of tiers 1 and 2
 };
 
@@ -22,7 +24,7 @@ struct TriArgs {
 };
 
 struct LaunchShape {
-    uint32_t grid_a, grid_b, grid_c, grid_t;
+    uint32_t grid_a, grid_b, grid_c, grid_d, grid_t;
 };
 
 hipError_t count_pairs(const PairArgs &P, const LaunchShape &sh, hipStream_t s);

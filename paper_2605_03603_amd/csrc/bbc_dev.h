@@ -96,11 +96,11 @@ struct Counters {           // device-side cursors and flags, zeroed per count
     unsigned long long pair_words;
     uint32_t n_anchor;      // anchor records reserved (including unused slots)
     uint32_t over_cap;      // 1, 2: a workspace capacity was exceeded; 4: unsupported anchor
-    uint32_t n_list[3];     // anchors deferred to the next pair tier
+    uint32_t n_list[3];     // anchors deferred to tiers B, C, D
     uint32_t n_units;       // written by the plan kernel: all units
     uint32_t n_narrow;      // units of masks up to 16 words come first
     unsigned long long need_masks, need_cands, need_recs, need_units;   // exact demand
-    Cursor q_pair[3][kXcd]; // work-queue cursors of the pair tiers, one per XCD slice
+    Cursor q_pair[4][kXcd]; // work-queue cursors of the pair tiers, one per XCD slice
     Cursor q_tri[kXcd];
     Cursor q_tri_wide[kXcd];
 };
@@ -111,8 +111,9 @@ struct Workspace {
     Unit *units;         uint64_t cap_units;
     uint32_t *masks;     uint64_t cap_mask_words;
     uint32_t *cands;     uint64_t cap_cands;
-    uint32_t *defer[2];  uint64_t cap_defer;     // anchors for tier B, tier C
+    uint32_t *defer[3];  uint64_t cap_defer;     // anchors for tiers B, C, D
     uint32_t *gtab;      uint64_t gtab_words_per_block; uint32_t gtab_blocks;  // tier C tables
+    uint32_t *dtab;      uint64_t dtab_words_per_block; uint32_t dtab_blocks;  // tier D tables
     uint32_t *bscr;      uint64_t bscr_words_per_block;   // tier B per-block position lists
     uint32_t *ucnt;      // [2 cap_anchors] units per anchor record: narrow masks, then wide
     uint64_t *uoff;      // [2 cap_anchors + 1] exclusive prefix of ucnt

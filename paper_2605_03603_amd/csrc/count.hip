@@ -174,6 +174,9 @@ struct PairShared {
     uint32_t aidx, arec_end;
     unsigned long long top1, top2;               // (suffix length << 32) | position
     unsigned long long moff, mres_end, coff, cres_end;
+    unsigned long long bm, bc;                   // own reservations of large outputs
+    uint32_t big_m, big_c;
+    unsigned long long vm, vm_end, vc, vc_end;   // chunk use as if room were unlimited
     unsigned long long need_m, need_c, need_r, need_u;   // this workgroup's demand
 };
 
@@ -203,6 +206,55 @@ __device__ __forceinline__ void hash_inc(const uint32_t *keys, uint32_t *vals, u
         const uint32_t k = keys[h];
         if (k == x) { atomicAdd(&vals[h], inc); return; }
         if (k == kEmpty) return;
+        h = (h + 1) & (H - 1);
+    }
+}
+
+// Packed counting slots (graphs with fewer than 2^24 - 1 anchor-side
+// vertices): one 32-bit word per partner, key in bits 0..23, then for each
+// sign class a 3-bit thermometer (bits 24..26 same, 27..29 different): hit i
+// (i = 1, 2, 3) sets bit i-1 of the class, further hits change nothing.
+// Selection only needs "at least 3", so the table holds twice the partners
+// of the (key, count) layout in the same memory.
+constexpr uint32_t kKeyMask = 0xffffffu;
+
+__device__ __forceinline__ void therm_inc(uint32_t *slot, uint32_t b0)
+{
+    const uint32_t old = atomicOr(slot, b0);
+    if (old & b0) {
+        const uint32_t old1 = atomicOr(slot, b0 << 1);
+        if (old1 & (b0 << 1)) atomicOr(slot, b0 << 2);
+    }
+}
+
+__device__ __forceinline__ bool phash_add(uint32_t *slots, uint32_t H, int log2h, uint32_t x,
+                                          uint32_t cls, volatile uint32_t *over)
+{
+    const uint32_t b0 = 1u << (24 + 3 * cls);
+    uint32_t h = hash_slot(x, log2h);
+    const uint32_t max_probe = H < 256 ? H : 256;
+    for (uint32_t probe = 0; probe < max_probe; probe++) {
+        uint32_t v = __atomic_load_n(&slots[h], __ATOMIC_RELAXED);
+        if (v == kEmpty) {
+            const uint32_t old = atomicCAS(&slots[h], kEmpty, x | b0);
+            if (old == kEmpty) return true;
+            v = old;
+        }
+        if ((v & kKeyMask) == x) { therm_inc(&slots[h], b0); return false; }
+        h = (h + 1) & (H - 1);
+    }
+    *over = 1;
+    return false;
+}
+
+__device__ __forceinline__ void phash_inc(uint32_t *slots, uint32_t H, int log2h, uint32_t x,
+                                          uint32_t cls)
+{
+    uint32_t h = hash_slot(x, log2h);
+    for (uint32_t probe = 0; probe < H; probe++) {
+        const uint32_t v = slots[h];
+        if (v == kEmpty) return;
+        if ((v & kKeyMask) == x) { therm_inc(&slots[h], 1u << (24 + 3 * cls)); return; }
         h = (h + 1) & (H - 1);
     }
 }
@@ -279,7 +331,7 @@ __device__ __forceinline__ void walk_positions(const CsrView &g, const PairMem &
 
 // The per-anchor procedure shared by all tiers (LDS storage for tiers A and
 // B, global memory for tier C).
-template <int THREADS>
+template <int THREADS, bool PACKED>
 __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, PairShared &sh)
 {
     const int tid = threadIdx.x, lane = __lane_id();
@@ -288,7 +340,11 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
     uint32_t *keys = m.region, *vals = m.region + m.H;
     uint32_t *ckeys = m.region, *cidx = m.region + m.HC;
     uint32_t *mstage = m.region + 2 * m.HC;
-    const uint32_t H = m.H, limit = m.H - m.H / 4;
+    const uint32_t H = m.H;
+    // counting slots: H (key, counts) pairs, or 2H packed words
+    const uint32_t HS = PACKED ? 2 * m.H : m.H;
+    const int log2hs = PACKED ? m.log2h + 1 : m.log2h;
+    const uint32_t limit = HS - HS / 4;
     uint64_t my_wedges = 0;
 
     const uint32_t n_items =
@@ -297,10 +353,14 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
                : P.a1 - P.a0;
     if (n_items == 0) return;
     const uint32_t *list = P.tier ? P.ws.defer[P.tier - 1] : nullptr;
-    uint32_t *next_list = P.tier < 2 ? P.ws.defer[P.tier] : nullptr;
+    uint32_t *next_list = P.tier < 3 ? P.ws.defer[P.tier] : nullptr;
 
     auto clear_region = [&]() {
-        for (uint32_t i = tid; i < H; i += THREADS) { keys[i] = kEmpty; vals[i] = 0; }
+        if (PACKED) {
+            for (uint32_t i = tid; i < 2 * H; i += THREADS) m.region[i] = kEmpty;
+        } else {
+            for (uint32_t i = tid; i < H; i += THREADS) { keys[i] = kEmpty; vals[i] = 0; }
+        }
     };
     clear_region();
     if (tid == 0) {
@@ -308,6 +368,7 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
         sh.moff = sh.mres_end = 0; sh.coff = sh.cres_end = 0;
         sh.aidx = sh.arec_end = 0;
         sh.need_m = sh.need_c = sh.need_r = sh.need_u = 0;
+        sh.vm = sh.vm_end = sh.vc = sh.vc_end = 0;
     }
 
     auto defer_anchor = [&](uint32_t r) {
@@ -375,8 +436,12 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
             walk_positions<THREADS>(g, m, d, t1, t2, true, false,
                                     [&](uint32_t e2, uint32_t, uint32_t sg) {
                                         my_wedges++;
-                                        fresh += hash_add(keys, vals, H, m.log2h, e2 >> 1,
-                                                          ((e2 & 1u) ^ sg) ? 0x10000u : 1u, &sh.over);
+                                        const uint32_t cls = (e2 & 1u) ^ sg;
+                                        if (PACKED)
+                                            fresh += phash_add(m.region, HS, log2hs, e2 >> 1, cls, &sh.over);
+                                        else
+                                            fresh += hash_add(keys, vals, H, m.log2h, e2 >> 1,
+                                                              cls ? 0x10000u : 1u, &sh.over);
                                     });
             const uint32_t nf = wave_sum<uint32_t>(fresh);
             if (lane == 0 && nf && atomicAdd(&sh.used, nf) + nf > limit) sh.over = 1;
@@ -387,20 +452,36 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
             walk_positions<THREADS>(g, m, d, t1, t2, false, true,
                                     [&](uint32_t e2, uint32_t, uint32_t sg) {
                                         my_wedges++;
-                                        hash_inc(keys, vals, H, m.log2h, e2 >> 1,
-                                                 ((e2 & 1u) ^ sg) ? 0x10000u : 1u);
+                                        const uint32_t cls = (e2 & 1u) ^ sg;
+                                        if (PACKED)
+                                            phash_inc(m.region, HS, log2hs, e2 >> 1, cls);
+                                        else
+                                            hash_inc(keys, vals, H, m.log2h, e2 >> 1,
+                                                     cls ? 0x10000u : 1u);
                                     });
             __syncthreads();
             // phase 2: classes with >= 3 members become virtual candidates
-            for (uint32_t slot = tid; slot < H; slot += THREADS) {
-                const uint32_t k = keys[slot];
-                if (k == kEmpty) continue;
-                const uint32_t v = vals[slot];
-                if ((v & 0xffffu) >= 3) {
+            for (uint32_t slot = tid; slot < HS; slot += THREADS) {
+                uint32_t k;
+                bool same3, diff3;
+                if (PACKED) {
+                    const uint32_t v = m.region[slot];
+                    if (v == kEmpty) continue;
+                    k = v & kKeyMask;
+                    same3 = (v >> 26) & 1u;
+                    diff3 = (v >> 29) & 1u;
+                } else {
+                    k = keys[slot];
+                    if (k == kEmpty) continue;
+                    const uint32_t v = vals[slot];
+                    same3 = (v & 0xffffu) >= 3;
+                    diff3 = (v >> 16) >= 3;
+                }
+                if (same3) {
                     const uint32_t t = atomicAdd(&sh.nv, 1u);
                     if (t < m.kmax) m.vc[t] = k;
                 }
-                if ((v >> 16) >= 3) {
+                if (diff3) {
                     const uint32_t t = atomicAdd(&sh.nv, 1u);
                     if (t < m.kmax) m.vc[t] = k | 0x80000000u;
                 }
@@ -435,23 +516,44 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
         const uint64_t words = (uint64_t)k * W;
         if (tid == 0) {
             // workgroup-local bump reservations (few global atomics)
-            sh.need_m += words;
-            sh.need_c += k;
+            // demand: what the reservations below consume with unlimited room
+            sh.big_m = words > kMaskChunk / 4;
+            sh.big_c = k > kCandChunk / 4;
+            if (sh.big_m) {
+                sh.need_m += words;
+            } else {
+                if (sh.vm + words > sh.vm_end) { sh.need_m += kMaskChunk; sh.vm = 0; sh.vm_end = kMaskChunk; }
+                sh.vm += words;
+            }
+            if (sh.big_c) {
+                sh.need_c += k;
+            } else {
+                if (sh.vc + k > sh.vc_end) { sh.need_c += kCandChunk; sh.vc = 0; sh.vc_end = kCandChunk; }
+                sh.vc += k;
+            }
             sh.need_r += 1;
             sh.need_u += anchor_units(k, W, P.chunk_base);
             bool bad = (__atomic_load_n(&C->over_cap, __ATOMIC_RELAXED) & 2u) != 0;
             if (!bad) {
-                if (sh.moff + words > sh.mres_end) {
-                    uint64_t want = words > kMaskChunk ? words : kMaskChunk;
-                    uint64_t o = atomicAdd(&C->mask_cursor, (unsigned long long)want);
-                    sh.moff = o; sh.mres_end = o + want;
-                    if (o + want > P.ws.cap_mask_words) bad = true;
+                // large outputs get a reservation of their own; small ones come
+                // from the workgroup's chunk, whose abandoned tail counts as demand
+                if (sh.big_m) {
+                    uint64_t o = atomicAdd(&C->mask_cursor, (unsigned long long)words);
+                    sh.bm = o;
+                    if (o + words > P.ws.cap_mask_words) bad = true;
+                } else if (sh.moff + words > sh.mres_end) {
+                    uint64_t o = atomicAdd(&C->mask_cursor, (unsigned long long)kMaskChunk);
+                    sh.moff = o; sh.mres_end = o + kMaskChunk;
+                    if (o + kMaskChunk > P.ws.cap_mask_words) bad = true;
                 }
-                if (sh.coff + k > sh.cres_end) {
-                    uint64_t want = k > kCandChunk ? k : kCandChunk;
-                    uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)want);
-                    sh.coff = o; sh.cres_end = o + want;
-                    if (o + want > P.ws.cap_cands) bad = true;
+                if (sh.big_c) {
+                    uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)k);
+                    sh.bc = o;
+                    if (o + k > P.ws.cap_cands) bad = true;
+                } else if (sh.coff + k > sh.cres_end) {
+                    uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)kCandChunk);
+                    sh.coff = o; sh.cres_end = o + kCandChunk;
+                    if (o + kCandChunk > P.ws.cap_cands) bad = true;
                 }
                 if (sh.aidx >= sh.arec_end) {
                     uint32_t o = atomicAdd(&C->n_anchor, kRecChunk);
@@ -472,7 +574,7 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
             continue;
         }
         const bool staged = words <= m.maskw;
-        const uint64_t moff = sh.moff, coff = sh.coff;
+        const uint64_t moff = sh.big_m ? sh.bm : sh.moff, coff = sh.big_c ? sh.bc : sh.coff;
         const uint32_t aidx = sh.aidx;
         uint32_t *mp = staged ? mstage : P.ws.masks + moff;
         for (uint64_t i = tid; i < words; i += THREADS) mp[i] = 0;
@@ -494,8 +596,8 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
             a.rank = r; a.k = k; a.w32 = W; a.graph = g.s_graph[r];
             a.mask_off = moff; a.cand_off = coff;
             P.ws.anchors[aidx] = a;
-            sh.moff = moff + words;
-            sh.coff = coff + k;
+            if (!sh.big_m) sh.moff = moff + words;
+            if (!sh.big_c) sh.coff = coff + k;
             sh.aidx = aidx + 1;
         }
         __syncthreads();
@@ -525,7 +627,7 @@ __host__ __device__ constexpr uint32_t compact_slots(uint32_t kmax, uint32_t H)
     return c < H / 2 ? c : H / 2;
 }
 
-template <int THREADS, int H, int MAXD, int KMAX>
+template <int THREADS, int H, int MAXD, int KMAX, bool PACKED>
 __global__ void __launch_bounds__(THREADS) k_pair_lds(PairArgs P)
 {
     __shared__ uint32_t region[2 * H], pst[MAXD], pln[MAXD], vc[KMAX];
@@ -535,11 +637,11 @@ __global__ void __launch_bounds__(THREADS) k_pair_lds(PairArgs P)
     m.region = region; m.H = H; m.log2h = ilog2(H);
     m.HC = HC; m.log2hc = ilog2(HC); m.maskw = 2 * H - 2 * HC;
     m.pst = pst; m.pln = pln; m.maxd = MAXD; m.vc = vc; m.kmax = KMAX;
-    pair_loop<THREADS>(P, m, sh);
+    pair_loop<THREADS, PACKED>(P, m, sh);
 }
 
 // Tier B: LDS table, position lists in global memory (any degree below 2^16).
-template <int THREADS, int H, int KMAX>
+template <int THREADS, int H, int KMAX, bool PACKED>
 __global__ void __launch_bounds__(THREADS) k_pair_big(PairArgs P)
 {
     __shared__ uint32_t region[2 * H], vc[KMAX];
@@ -551,26 +653,31 @@ __global__ void __launch_bounds__(THREADS) k_pair_big(PairArgs P)
     m.pst = P.ws.bscr + (uint64_t)blockIdx.x * P.ws.bscr_words_per_block;
     m.pln = m.pst + P.gmaxd;
     m.maxd = P.gmaxd; m.vc = vc; m.kmax = KMAX;
-    pair_loop<THREADS>(P, m, sh);
+    pair_loop<THREADS, PACKED>(P, m, sh);
 }
 
 constexpr int kGThreads = 1024;
 
-// Tier C: every table in global memory.
+// Tiers C and D: every table in global memory (C: bounded tables on many
+// blocks; D: tables sized for the whole anchor side on a few blocks).
+template <bool PACKED>
 __global__ void __launch_bounds__(kGThreads) k_pair_global(PairArgs P)
 {
     __shared__ PairShared sh;
-    uint32_t *base = P.ws.gtab + (uint64_t)blockIdx.x * P.ws.gtab_words_per_block;
+    const bool d = P.tier == 3;
+    uint32_t *base = (d ? P.ws.dtab : P.ws.gtab) +
+                     (uint64_t)blockIdx.x * (d ? P.ws.dtab_words_per_block : P.ws.gtab_words_per_block);
+    const uint32_t H = d ? P.dH : P.gH;
     PairMem m;
-    m.region = base; m.H = P.gH; m.log2h = P.glog2h;
-    m.HC = compact_slots(P.gkmax, P.gH); m.log2hc = ilog2(m.HC);
+    m.region = base; m.H = H; m.log2h = d ? P.dlog2h : P.glog2h;
+    m.HC = compact_slots(P.gkmax, H); m.log2hc = ilog2(m.HC);
     m.maskw = 2 * m.H - 2 * m.HC;
-    m.pst = base + 2ull * P.gH;
+    m.pst = base + 2ull * H;
     m.pln = m.pst + P.gmaxd;
     m.maxd = P.gmaxd;
     m.vc = m.pln + P.gmaxd;
     m.kmax = P.gkmax;
-    pair_loop<kGThreads>(P, m, sh);
+    pair_loop<kGThreads, PACKED>(P, m, sh);
 }
 
 // ------------------------------------------------------------- planning
@@ -652,23 +759,41 @@ __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
     uint64_t acc = 0;
     uint32_t j = un.c0;
     if (MODE == 0) {
-        for (; j + 8 <= un.c1; j += 8) {
-            uint32_t s = 0;
+        // 8 columns = 8*W consecutive words: one pointer, immediate offsets.
+        // Only units that reach the diagonal need the j < i test.
+        if (!diag) {
+            for (; j + 8 <= un.c1; j += 8) {
+                const BBC_CONST uint32_t *cp = MS + (uint64_t)j * W;
+                uint32_t s = 0;
 #pragma unroll
-            for (int jj = 0; jj < 8; jj++) {
-                uint32_t n = 0;
+                for (int jj = 0; jj < 8; jj++) {
+                    uint32_t n = 0;
 #pragma unroll
-                for (int w = 0; w < W; w++) n += __popc(row[w] & MS[(uint64_t)(j + jj) * W + w]);
-                uint32_t t = c3[n];
-                if (diag) t = (j + jj < i) ? t : 0u;
-                s += t;
+                    for (int w = 0; w < W; w++) n += __popc(row[w] & cp[jj * W + w]);
+                    s += c3[n];
+                }
+                acc += s;
             }
-            acc += s;
+        } else {
+            for (; j + 8 <= un.c1; j += 8) {
+                const BBC_CONST uint32_t *cp = MS + (uint64_t)j * W;
+                uint32_t s = 0;
+#pragma unroll
+                for (int jj = 0; jj < 8; jj++) {
+                    uint32_t n = 0;
+#pragma unroll
+                    for (int w = 0; w < W; w++) n += __popc(row[w] & cp[jj * W + w]);
+                    const uint32_t t = c3[n];
+                    s += (j + jj < i) ? t : 0u;
+                }
+                acc += s;
+            }
         }
         for (; j < un.c1; j++) {
+            const BBC_CONST uint32_t *cp = MS + (uint64_t)j * W;
             uint32_t n = 0;
 #pragma unroll
-            for (int w = 0; w < W; w++) n += __popc(row[w] & MS[(uint64_t)j * W + w]);
+            for (int w = 0; w < W; w++) n += __popc(row[w] & cp[w]);
             uint32_t t = c3[n];
             if (diag) t = (j < i) ? t : 0u;
             acc += t;
@@ -678,9 +803,10 @@ __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
     for (; j < un.c1; j++) {
         uint32_t cw[W];
         uint32_t n = 0;
+        const BBC_CONST uint32_t *cp = MS + (uint64_t)j * W;
 #pragma unroll
         for (int w = 0; w < W; w++) {
-            cw[w] = MS[(uint64_t)j * W + w];
+            cw[w] = cp[w];
             n += __popc(row[w] & cw[w]);
         }
         uint32_t t = c3[n];
@@ -709,8 +835,9 @@ __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
     return acc;
 }
 
-// Masks wider than 16 words: 32 columns per unit, one counter per column in
-// registers, words streamed 16 at a time.
+// Masks wider than 16 words: up to 32 columns per unit, taken 8 at a time
+// with one counter per column in registers; row words are streamed 16 at a
+// time (re-read per column group from L1/L2), column words by scalar loads.
 template <int MODE>
 __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
                                   const uint32_t *__restrict__ masks, uint64_t *colacc,
@@ -723,51 +850,49 @@ __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
     const uint32_t *M = masks + a.mask_off;
     const BBC_CONST uint32_t *MS = as_const(M);
     const uint32_t ncol = un.c1 - un.c0;
-    uint32_t n[kWideCols];
+    uint64_t acc = 0;
+    for (uint32_t cg = 0; cg < ncol; cg += 8) {
+        uint32_t n[8];
 #pragma unroll
-    for (int c = 0; c < (int)kWideCols; c++) n[c] = 0;
-    for (uint32_t w0 = 0; w0 < W; w0 += kRegW) {
-        const uint32_t wn = min(kRegW, W - w0);
-        uint32_t row[kRegW];
+        for (int c = 0; c < 8; c++) n[c] = 0;
+        for (uint32_t w0 = 0; w0 < W; w0 += kRegW) {
+            const uint32_t wn = min(kRegW, W - w0);
+            uint32_t row[kRegW];
 #pragma unroll
-        for (int w = 0; w < (int)kRegW; w++)
-            row[w] = (vi && (uint32_t)w < wn) ? M[(uint64_t)i * W + w0 + w] : 0u;
+            for (int w = 0; w < (int)kRegW; w++)
+                row[w] = (vi && (uint32_t)w < wn) ? M[(uint64_t)i * W + w0 + w] : 0u;
 #pragma unroll
-        for (int c = 0; c < (int)kWideCols; c++) {
-            if ((uint32_t)c < ncol) {
-                const BBC_CONST uint32_t *col = MS + (uint64_t)(un.c0 + c) * W + w0;
-                uint32_t s = 0;
-                if (wn == kRegW) {
-#pragma unroll
-                    for (int w = 0; w < (int)kRegW; w++) s += __popc(row[w] & col[w]);
-                } else {
+            for (int c = 0; c < 8; c++) {
+                if (cg + c < ncol) {
+                    const BBC_CONST uint32_t *col = MS + (uint64_t)(un.c0 + cg + c) * W + w0;
+                    uint32_t s = 0;
 #pragma unroll
                     for (int w = 0; w < (int)kRegW; w++)
                         if ((uint32_t)w < wn) s += __popc(row[w] & col[w]);
+                    n[c] += s;
                 }
-                n[c] += s;
             }
         }
-    }
-    uint64_t acc = 0;
 #pragma unroll
-    for (int c = 0; c < (int)kWideCols; c++) {
-        const uint32_t j = un.c0 + c;
-        uint64_t t = ((uint32_t)c < ncol && j < i) ? choose3(n[c]) : 0;
-        acc += t;
-        if (MODE != 0 && t) {
-            if (MODE == 1) {
-                atomicAdd((unsigned long long *)&colacc[c], (unsigned long long)t);
-            } else {
-                const uint64_t each = choose2(n[c] - 1);
-                const uint64_t s0 = T.g.s_off[a.rank];
-                for (uint32_t w = 0; w < W; w++) {
-                    uint32_t m = M[(uint64_t)i * W + w] & M[(uint64_t)j * W + w];
-                    while (m) {
-                        const uint32_t b = __ffs(m) - 1;
-                        m &= m - 1;
-                        const uint32_t o = T.g.s_adj[s0 + w * 32 + b] >> 1;
-                        atomicAdd(&T.ws.pv_o[o], (unsigned long long)each);
+        for (int c = 0; c < 8; c++) {
+            const uint32_t j = un.c0 + cg + c;
+            const uint64_t t = (cg + c < ncol && j < i) ? choose3(n[c]) : 0;
+            acc += t;
+            if (MODE != 0 && t) {
+                if (MODE == 1) {
+                    atomicAdd((unsigned long long *)&colacc[cg + c], (unsigned long long)t);
+                } else {
+                    // every member of the common class lies in C(n-1, 2) of these bicliques
+                    const uint64_t each = choose2(n[c] - 1);
+                    const uint64_t s0 = T.g.s_off[a.rank];
+                    for (uint32_t w = 0; w < W; w++) {
+                        uint32_t m = M[(uint64_t)i * W + w] & M[(uint64_t)j * W + w];
+                        while (m) {
+                            const uint32_t b = __ffs(m) - 1;
+                            m &= m - 1;
+                            const uint32_t o = T.g.s_adj[s0 + w * 32 + b] >> 1;
+                            atomicAdd(&T.ws.pv_o[o], (unsigned long long)each);
+                        }
                     }
                 }
             }
@@ -781,7 +906,7 @@ constexpr uint32_t kMaxChunk = 2048;
 constexpr uint32_t kUnitGrab = 4;
 
 template <int MODE, bool WIDE>
-__global__ void __launch_bounds__(kTThreads, WIDE ? 1 : 5) k_triplet(TriArgs T)
+__global__ void __launch_bounds__(kTThreads, 5) k_triplet(TriArgs T)
 {
     __shared__ uint32_t c3[kC3Max + 1];
     __shared__ unsigned long long colacc_all[MODE == 1 ? kTThreads / kWave : 1][MODE == 1 ? kMaxChunk : 1];
@@ -815,15 +940,17 @@ __global__ void __launch_bounds__(kTThreads, WIDE ? 1 : 5) k_triplet(TriArgs T)
 
     for (;;) {
         if (qlo >= qhi) {
-            uint32_t lo = 0, hi = 0;
-            bool ok = false;
-            if (lane == 0) ok = queue_take(queue, n_units, kUnitGrab, &slice, &tried, &lo, &hi);
-            ok = __shfl(ok ? 1 : 0, 0, kWave);
+            // lane 0 takes the next chunk; readfirstlane keeps every value (and
+            // so the loop) wave-uniform, which lets the column loads be scalar
+            uint32_t lo = 0, hi = 0, ok = 0;
+            if (lane == 0)
+                ok = queue_take(queue, n_units, kUnitGrab, &slice, &tried, &lo, &hi) ? 1u : 0u;
+            ok = __builtin_amdgcn_readfirstlane(ok);
             if (!ok) break;
-            qlo = __builtin_amdgcn_readfirstlane(__shfl(lo, 0, kWave));
-            qhi = __builtin_amdgcn_readfirstlane(__shfl(hi, 0, kWave));
-            slice = __shfl(slice, 0, kWave);
-            tried = __shfl(tried, 0, kWave);
+            qlo = __builtin_amdgcn_readfirstlane(lo);
+            qhi = __builtin_amdgcn_readfirstlane(hi);
+            slice = __builtin_amdgcn_readfirstlane(slice);
+            tried = __builtin_amdgcn_readfirstlane(tried);
         }
         const uint32_t u = u_base + qlo++;
         const Unit un = load_unit(T.ws.units + u);
@@ -886,17 +1013,27 @@ uint32_t tier_c_max_degree() { return 65535; }
 uint32_t tier_c_max_k() { return 65535; }
 uint32_t max_unit_chunk() { return kMaxChunk; }
 
-hipError_t count_pairs(const PairArgs &base, const LaunchShape &sh, hipStream_t s)
+template <bool PACKED>
+static void launch_pairs(const PairArgs &base, const LaunchShape &sh, hipStream_t s)
 {
     PairArgs P = base;
     P.tier = 0;
-    hipLaunchKernelGGL((k_pair_lds<kAThreads, kAH, kAMaxD, kAKmax>),
-                       dim3(sh.grid_a), dim3(kAThreads), 0, s, P);
+    hipLaunchKernelGGL((k_pair_lds<kAThreads, kAH, kAMaxD, kAKmax, PACKED>), dim3(sh.grid_a),
+                       dim3(kAThreads), 0, s, P);
     P.tier = 1;
-    hipLaunchKernelGGL((k_pair_big<kBThreads, kBH, kBKmax>), dim3(sh.grid_b),
+    hipLaunchKernelGGL((k_pair_big<kBThreads, kBH, kBKmax, PACKED>), dim3(sh.grid_b),
                        dim3(kBThreads), 0, s, P);
     P.tier = 2;
-    hipLaunchKernelGGL(k_pair_global, dim3(sh.grid_c), dim3(kGThreads), 0, s, P);
+    hipLaunchKernelGGL((k_pair_global<PACKED>), dim3(sh.grid_c), dim3(kGThreads), 0, s, P);
+    P.tier = 3;
+    hipLaunchKernelGGL((k_pair_global<PACKED>), dim3(sh.grid_d), dim3(kGThreads), 0, s, P);
+}
+
+hipError_t count_pairs(const PairArgs &base, const LaunchShape &sh, hipStream_t s)
+{
+    // packed counting slots need anchor ranks below 2^24 - 1
+    if (base.g.NS < kKeyMask) launch_pairs<true>(base, sh, s);
+    else launch_pairs<false>(base, sh, s);
     return hipGetLastError();
 }
 
@@ -915,7 +1052,7 @@ hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t
 {
     // masks of up to 16 words, then the wider ones (a kernel of their own:
     // its register use would otherwise lower the occupancy of the first)
-    const uint32_t grid_w = grid / 4 > 0 ? grid / 4 : 1;
+    const uint32_t grid_w = grid;
     if (mode == 0) {
         hipLaunchKernelGGL((k_triplet<0, false>), dim3(grid), dim3(kTThreads), 0, s, T);
         hipLaunchKernelGGL((k_triplet<0, true>), dim3(grid_w), dim3(kTThreads), 0, s, T);

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
@@ -203,6 +204,9 @@ struct GraphSet {
     DBuf s_rev;
     // sizing hints learnt by earlier counts
     uint64_t hint_masks = 0, hint_cands = 0, hint_units = 0;
+    // anchor-side tuning of a single large graph: shape key and side used
+    uint64_t tune_key = 0;
+    uint32_t tune_side = 0;
     uint64_t device_bytes() const
     {
         return d_desc.bytes + s_off.bytes + o_off.bytes + s_adj.bytes + o_adj.bytes +
@@ -231,14 +235,17 @@ namespace {
 
 // Count workspace (one per stream that counts).
 struct Work {
-    DBuf ctr, anchors, units, masks, cands, defer0, defer1, gtab, bscr, count, carry, pv, pv_o;
+    DBuf ctr, anchors, units, masks, cands, defer0, defer1, defer2, gtab, dtab, bscr, count,
+        carry, pv, pv_o;
     DBuf ucnt, uoff, ptmp;
     HBuf host;          // counters + counts + carries read back
+    HBuf bhost;         // small staging of the CSR builder
+    HBuf coo;           // pinned COO staging of the serving loop
     uint64_t cap_anchors = 0, cap_units = 0, cap_masks = 0, cap_cands = 0, cap_defer = 0;
-    uint32_t gtab_blocks = 0, bscr_blocks = 0;
-    uint64_t gtab_words = 0, bscr_words = 0, ptmp_bytes = 0;
-    uint32_t gH = 0;
-    int glog2 = 0;
+    uint32_t gtab_blocks = 0, dtab_blocks = 0, bscr_blocks = 0;
+    uint64_t gtab_words = 0, dtab_words = 0, bscr_words = 0, ptmp_bytes = 0;
+    uint32_t gH = 0, dH = 0;
+    int glog2 = 0, dlog2 = 0;
     uint32_t gmaxd = 0, gkmax = 0;
     // captured replay of a batched count
     hipGraphExec_t exec = nullptr;
@@ -285,6 +292,10 @@ struct bbc_ctx {
     bool timing = false;
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     std::map<uint64_t, Shape> tuned;   // autotuner cache by size class
+    struct SideTime { float ms[2] = {0, 0}; bool tried[2] = {false, false}; };
+    std::map<uint64_t, SideTime> side_tune;   // anchor side by graph shape
+    std::mutex tune_mu;
+    hipEvent_t tev[2] = {nullptr, nullptr};
     // serving
     std::mutex q_mu;
     std::condition_variable q_cv, done_cv;
@@ -368,7 +379,20 @@ uint32_t choose_side(uint32_t flags, uint32_t n_u, uint32_t n_v, uint64_t m, uin
     return cost_v < cost_u ? 1 : 0;
 }
 
-std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s)
+constexpr uint64_t kSideTuneMinEdges = 1u << 18;
+
+// Graphs with the same size classes and degree-statistic ratio share a key.
+uint64_t side_key(uint32_t n_u, uint32_t n_v, uint64_t m, uint64_t c2_u, uint64_t c2_v,
+                  uint64_t d2_u, uint64_t d2_v)
+{
+    auto lb = [](double x) { return x > 1 ? (int)std::lround(4.0 * std::log2(x)) : 0; };
+    const int r1 = lb(1.0 + (double)c2_u / (1.0 + (double)c2_v) * 64.0);
+    const int r2 = lb(1.0 + (double)d2_u / (1.0 + (double)d2_v) * 64.0);
+    return ((uint64_t)bit_width(n_u) << 56) | ((uint64_t)bit_width(n_v) << 48) |
+           ((uint64_t)bit_width(m) << 40) | ((uint64_t)(r1 & 0xfff) << 20) | (uint64_t)(r2 & 0xfff) | 1;
+}
+
+std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s, HBuf &hb)
 {
     Allocator *al = ctx->al.get();
     const uint32_t G = in.G;
@@ -433,7 +457,6 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
     unsigned long long *d_stats = (unsigned long long *)sp; sp += 4 * G * 8;
     uint32_t *d_flags = (uint32_t *)sp;   // err, max_deg_u, max_deg_v, pad, first_bad (u64)
 
-    HBuf hb;
     hb.ensure((G + 1) * 8 + G * sizeof(GraphDesc) + 4 * G * 4 + 4 * G * 8 + 64);
     {
         char *hp = hb.as<char>();
@@ -486,10 +509,22 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
     uint32_t max_no = 0;
     std::vector<uint32_t> sbase(G), obase(G);
     bool any_u = false, any_v = false;
+    const bool auto_side = !(in.flags & (BBC_ANCHOR_U | BBC_ANCHOR_V | BBC_ANCHOR_SMALLER));
     for (uint32_t g = 0; g < G; g++) {
         GraphDesc &d = set->desc[g];
         d.side = choose_side(in.flags, d.n_u, d.n_v, d.m, h_stats[g], h_stats[G + g],
                              h_stats[2 * G + g], h_stats[3 * G + g]);
+        if (G == 1 && auto_side && d.m >= kSideTuneMinEdges) {
+            // a recurring large shape: time each side once, then keep the faster
+            const uint64_t key = side_key(d.n_u, d.n_v, d.m, h_stats[0], h_stats[1],
+                                          h_stats[2], h_stats[3]);
+            std::lock_guard<std::mutex> lk(ctx->tune_mu);
+            auto &st = ctx->side_tune[key];
+            if (st.tried[0] && st.tried[1]) d.side = st.ms[1] < st.ms[0] ? 1 : 0;
+            else if (st.tried[d.side]) d.side ^= 1;
+            set->tune_key = key;
+            set->tune_side = d.side;
+        }
         d.n_s = d.side ? d.n_v : d.n_u;
         d.n_o = d.side ? d.n_u : d.n_v;
         d.s_base = (uint32_t)ns; d.o_base = (uint32_t)no;
@@ -574,9 +609,10 @@ void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set)
     uint64_t M = std::max<uint64_t>(set.M, 1);
     // records are reserved 16 at a time per workgroup
     uint64_t want_anchors = std::max<uint64_t>(set.NS, 1) + 16ull * 4 * ctx->num_cus + 64;
-    uint64_t want_masks = std::max<uint64_t>({set.hint_masks, 8 * M, 1ull << 20});
-    uint64_t want_cands = std::max<uint64_t>({set.hint_cands, 2 * M, 1ull << 18});
-    uint64_t want_units = std::max<uint64_t>({set.hint_units, M / 4, 1ull << 16});
+    // first guesses; an overflowing count records its exact demand and reruns once
+    uint64_t want_masks = std::max<uint64_t>({set.hint_masks, 2 * M, 1ull << 22});
+    uint64_t want_cands = std::max<uint64_t>({set.hint_cands, M / 2, 1ull << 20});
+    uint64_t want_units = std::max<uint64_t>({set.hint_units, M / 16, 1ull << 16});
     if (w.cap_anchors < want_anchors) {
         w.anchors.ensure(al, want_anchors * sizeof(AnchorRec));
         w.ucnt.ensure(al, 2 * want_anchors * 4);
@@ -585,11 +621,14 @@ void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set)
         w.ptmp.ensure(al, w.ptmp_bytes);
         w.cap_anchors = want_anchors;
     }
-    if (w.cap_masks < want_masks) { w.masks.ensure(al, want_masks * 4); w.cap_masks = want_masks; }
+    // 64 words of slack past the capacity: scalar column loads of the last
+    // mask may be issued for a full 16-word group
+    if (w.cap_masks < want_masks) { w.masks.ensure(al, (want_masks + 64) * 4); w.cap_masks = want_masks; }
     if (w.cap_cands < want_cands) { w.cands.ensure(al, want_cands * 4); w.cap_cands = want_cands; }
     if (w.cap_units < want_units) { w.units.ensure(al, want_units * sizeof(Unit)); w.cap_units = want_units; }
     if (w.cap_defer < set.NS + 1ull) {
         w.defer0.ensure(al, (set.NS + 1ull) * 4); w.defer1.ensure(al, (set.NS + 1ull) * 4);
+        w.defer2.ensure(al, (set.NS + 1ull) * 4);
         w.cap_defer = set.NS + 1ull;
     }
     w.ctr.ensure(al, sizeof(Counters));
@@ -603,21 +642,32 @@ void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set)
         w.bscr_blocks = ctx->num_cus;
         w.bscr.ensure(al, w.bscr_words * 4 * w.bscr_blocks);
     }
-    // tier C: hash tables sized for the largest anchor side of any graph
+    // tiers C and D: hash tables in global memory. C: up to 2^20 slots on
+    // one block per CU; D: sized for the largest anchor side of any graph
+    // (every partner fits), on a few blocks. At least 2^18 slots: the compact
+    // table of up to 65535 candidate classes takes half of the region.
     uint32_t max_ns = 0;
     for (auto &d : set.desc) max_ns = std::max(max_ns, d.n_s);
-    // at least 2^18 slots: the compact table of up to 65535 candidate classes
-    // takes half of the region
-    uint32_t H = 1u << 18;
-    int lg = 18;
-    while (H < 2ull * max_ns + 64 && lg < 24) { H <<= 1; lg++; }
-    if (!w.gtab.p || w.gH < H) {
-        uint64_t words = 2ull * H + 2ull * maxd + kmax + 64;
+    uint32_t HD = 1u << 18;
+    int lgd = 18;
+    while (HD < 2ull * max_ns + 64 && lgd < 25) { HD <<= 1; lgd++; }
+    const uint32_t HC = std::min(HD, 1u << 20);
+    const int lgc = std::min(lgd, 20);
+    if (!w.gtab.p || w.gH < HC) {
+        uint64_t words = 2ull * HC + 2ull * maxd + kmax + 64;
         uint32_t blocks = (uint32_t)std::max<uint64_t>(
-            1, std::min<uint64_t>(32, (1ull << 30) / (words * 4)));
+            1, std::min<uint64_t>(ctx->num_cus, (2ull << 30) / (words * 4)));
         w.gtab.ensure(al, words * 4 * blocks);
-        w.gH = H; w.glog2 = lg; w.gmaxd = maxd; w.gkmax = kmax;
+        w.gH = HC; w.glog2 = lgc; w.gmaxd = maxd; w.gkmax = kmax;
         w.gtab_words = words; w.gtab_blocks = blocks;
+    }
+    if (!w.dtab.p || w.dH < HD) {
+        uint64_t words = 2ull * HD + 2ull * maxd + kmax + 64;
+        uint32_t blocks = (uint32_t)std::max<uint64_t>(
+            1, std::min<uint64_t>(16, (1ull << 30) / (words * 4)));
+        w.dtab.ensure(al, words * 4 * blocks);
+        w.dH = HD; w.dlog2 = lgd;
+        w.dtab_words = words; w.dtab_blocks = blocks;
     }
 }
 
@@ -631,9 +681,12 @@ Workspace ws_view(Work &w, bool pv, bool pvo)
     ws.masks = w.masks.as<uint32_t>(); ws.cap_mask_words = w.cap_masks;
     ws.cands = w.cands.as<uint32_t>(); ws.cap_cands = w.cap_cands;
     ws.defer[0] = w.defer0.as<uint32_t>(); ws.defer[1] = w.defer1.as<uint32_t>();
+    ws.defer[2] = w.defer2.as<uint32_t>();
     ws.cap_defer = w.cap_defer;
     ws.gtab = w.gtab.as<uint32_t>(); ws.gtab_words_per_block = w.gtab_words;
     ws.gtab_blocks = w.gtab_blocks;
+    ws.dtab = w.dtab.as<uint32_t>(); ws.dtab_words_per_block = w.dtab_words;
+    ws.dtab_blocks = w.dtab_blocks;
     ws.bscr = w.bscr.as<uint32_t>(); ws.bscr_words_per_block = w.bscr_words;
     ws.ucnt = w.ucnt.as<uint32_t>(); ws.uoff = w.uoff.as<uint64_t>();
     ws.count = w.count.as<unsigned long long>();
@@ -670,9 +723,11 @@ LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
     L.P.a1 = set.desc[r.g1 - 1].s_base + set.desc[r.g1 - 1].n_s;
     L.P.chunk_base = std::min(shp.chunk_base, max_unit_chunk());
     L.P.gH = w.gH; L.P.glog2h = w.glog2; L.P.gmaxd = w.gmaxd; L.P.gkmax = w.gkmax;
+    L.P.dH = w.dH; L.P.dlog2h = w.dlog2;
     L.ls.grid_a = std::max(1u, ctx->num_cus * shp.grid_a_per_cu);
     L.ls.grid_b = std::max(1u, (uint32_t)ctx->num_cus);
     L.ls.grid_c = w.gtab_blocks;
+    L.ls.grid_d = w.dtab_blocks;
     L.ls.grid_t = std::max(1u, ctx->num_cus * shp.grid_t_per_cu);
     L.T.g = L.P.g;
     L.T.ws = ws;
@@ -743,6 +798,7 @@ bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set)
     ctx->stats.pair_words = c->pair_words;
     ctx->stats.deferred_b = c->n_list[0];
     ctx->stats.deferred_c = c->n_list[1];
+    ctx->stats.deferred_d = c->n_list[2];
     return true;
 }
 
@@ -766,14 +822,30 @@ void count_sync(bbc_ctx *ctx, Work &w, GraphSet &set, uint32_t g0, uint32_t g1, 
 {
     CountReq r{&set, g0, g1, mode};
     const bool timed = ctx->timing && s == ctx->stream && &w == &ctx->work;
+    const bool tune = set.tune_key && mode == 0 && s == ctx->stream && &w == &ctx->work;
+    if (tune && !ctx->tev[0]) {
+        HIP_OK(hipEventCreate(&ctx->tev[0]));
+        HIP_OK(hipEventCreate(&ctx->tev[1]));
+    }
     for (int attempt = 0; attempt < 8; attempt++) {
         ensure_work(ctx, w, set);
         if (mode == 1) w.pv.ensure(ctx->al.get(), std::max<uint64_t>(set.NS, 1) * 8);
         if (mode == 2) w.pv_o.ensure(ctx->al.get(), std::max<uint64_t>(set.NO, 1) * 8);
+        if (tune) HIP_OK(hipEventRecord(ctx->tev[0], s));
         enqueue_count(ctx, w, r, shp, s, timed);
+        if (tune) HIP_OK(hipEventRecord(ctx->tev[1], s));
         enqueue_readback(w, set, s);
         HIP_OK(hipStreamSynchronize(s));
         if (check_counters(ctx, w, set)) {
+            if (tune) {
+                float ms = 0;
+                HIP_OK(hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[1]));
+                std::lock_guard<std::mutex> lk(ctx->tune_mu);
+                auto &st = ctx->side_tune[set.tune_key];
+                const uint32_t sd = set.tune_side;
+                st.ms[sd] = st.tried[sd] ? std::min(st.ms[sd], ms) : ms;
+                st.tried[sd] = true;
+            }
             if (&w == &ctx->work) ctx->stats.attempts = attempt + 1;
             if (timed) {
                 HIP_OK(hipEventElapsedTime(&ctx->stats.ms_pair, ctx->ev[0], ctx->ev[1]));
@@ -876,6 +948,7 @@ void count_set_batched(bbc_ctx *ctx, Work &w, GraphSet &set, hipStream_t s, int6
 // ---------------------------------------------------------------- serving
 constexpr int kServeStreams = 4;
 constexpr size_t kServeBatchMax = 4096;
+constexpr uint64_t kServeBatchEdges = 64ull << 20;   // bounds the time of one launch
 
 uint64_t footprint_estimate(uint64_t m, uint64_t nu, uint64_t nv)
 {
@@ -896,10 +969,13 @@ void serve_worker(bbc_ctx *ctx, int slot)
             if (ctx->stopping && ctx->queue.empty()) return;
             // admission in arrival order while the footprint fits under the cap
             const uint64_t cap = ctx->al->cap();
+            uint64_t batch_edges = 0;
             while (!ctx->queue.empty() && batch.size() < kServeBatchMax) {
                 auto &r = ctx->queue.front();
                 bool fits = !cap || ctx->admitted_bytes + r->footprint <= cap || ctx->admitted_bytes == 0;
                 if (!fits) break;
+                if (!batch.empty() && batch_edges + r->m > kServeBatchEdges) break;
+                batch_edges += r->m;
                 ctx->admitted_bytes += r->footprint;
                 batch_bytes += r->footprint;
                 batch.push_back(r);
@@ -938,14 +1014,19 @@ void serve_worker(bbc_ctx *ctx, int slot)
                     off[i + 1] = off[i] + rs[i]->m;
                 }
                 const uint64_t M = off.back();
-                std::vector<uint32_t> eu(M), ev(M);
-                std::vector<uint8_t> sg(sign_bytes(M, flags));
+                const uint64_t sbytes = sign_bytes(M, flags);
+                // concatenate into pinned memory: the uploads are then true DMA copies
+                w.coo.ensure(8 * std::max<uint64_t>(M, 1) + sbytes + 64);
+                uint32_t *eu = w.coo.as<uint32_t>();
+                uint32_t *ev = eu + M;
+                uint8_t *sg = (uint8_t *)(ev + M);
+                memset(sg, 0, sbytes);
                 bool packed = flags & BBC_SIGNS_2BIT_PACKED;
                 for (size_t i = 0; i < rs.size(); i++) {
-                    std::copy(rs[i]->eu.begin(), rs[i]->eu.end(), eu.begin() + off[i]);
-                    std::copy(rs[i]->ev.begin(), rs[i]->ev.end(), ev.begin() + off[i]);
+                    memcpy(eu + off[i], rs[i]->eu.data(), rs[i]->m * 4);
+                    memcpy(ev + off[i], rs[i]->ev.data(), rs[i]->m * 4);
                     if (!packed) {
-                        std::copy(rs[i]->sign.begin(), rs[i]->sign.end(), sg.begin() + off[i]);
+                        memcpy(sg + off[i], rs[i]->sign.data(), rs[i]->m);
                     } else {
                         for (uint64_t e = 0; e < rs[i]->m; e++) {
                             uint32_t code = (rs[i]->sign[e >> 2] >> (2 * (e & 3))) & 3u;
@@ -954,11 +1035,11 @@ void serve_worker(bbc_ctx *ctx, int slot)
                         }
                     }
                 }
-                CooIn in{(uint32_t)rs.size(), nu.data(), nv.data(), off.data(), eu.data(), ev.data(),
-                         sg.data(), flags & ~BBC_IN_DEVICE_PTRS};
+                CooIn in{(uint32_t)rs.size(), nu.data(), nv.data(), off.data(), eu, ev,
+                         sg, flags & ~BBC_IN_DEVICE_PTRS};
                 std::vector<int64_t> res(rs.size());
                 bbc_status st = guard(nullptr, [&] {
-                    auto set = build_set(ctx, in, s);
+                    auto set = build_set(ctx, in, s, w.bhost);
                     count_sync(ctx, w, *set, 0, set->G, 0, default_shape(), s, res.data());
                 });
                 if (st != BBC_OK && rs.size() > 1) {
@@ -969,7 +1050,7 @@ void serve_worker(bbc_ctx *ctx, int slot)
                                   rs[i]->sign.data(), flags & ~BBC_IN_DEVICE_PTRS};
                         int64_t v = 0;
                         bbc_status st1 = guard(nullptr, [&] {
-                            auto set = build_set(ctx, one, s);
+                            auto set = build_set(ctx, one, s, w.bhost);
                             count_sync(ctx, w, *set, 0, 1, 0, default_shape(), s, &v);
                         });
                         finish(rs[i], st1, v);
@@ -1092,6 +1173,8 @@ void bbc_ctx_destroy(bbc_ctx *ctx)
     if (ctx->work.exec) { (void)hipGraphExecDestroy(ctx->work.exec); ctx->work.exec = nullptr; }
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->tev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -1106,7 +1189,7 @@ bbc_status bbc_build_csr(bbc_ctx *ctx, uint32_t n_u, uint32_t n_v, uint64_t n_ed
         (void)hipSetDevice(ctx->device);
         uint64_t off[2] = {0, n_edges};
         CooIn in{1, &n_u, &n_v, off, eu, ev, sign, flags};
-        auto set = build_set(ctx, in, ctx->stream);
+        auto set = build_set(ctx, in, ctx->stream, ctx->work.bhost);
         *out = new bbc_graph{set, 0};
     });
 }
@@ -1122,7 +1205,7 @@ bbc_status bbc_build_csr_batch(bbc_ctx *ctx, uint32_t n_graphs, const uint32_t *
         if (n_graphs == 0) fail(BBC_E_INVAL, "n_graphs is 0");
         (void)hipSetDevice(ctx->device);
         CooIn in{n_graphs, n_u, n_v, edge_offsets, eu, ev, sign, flags};
-        auto set = build_set(ctx, in, ctx->stream);
+        auto set = build_set(ctx, in, ctx->stream, ctx->work.bhost);
         std::vector<bbc_graph *> hs(n_graphs, nullptr);
         for (uint32_t i = 0; i < n_graphs; i++) hs[i] = new bbc_graph{set, i};
         std::copy(hs.begin(), hs.end(), out_graphs);
