@@ -297,7 +297,8 @@ def main():
         "kernel_ms": kern_avg,
         "last_count_stats": {k: st[k] for k in ("active_anchors", "virtual_candidates",
                                                  "pair_units", "candidate_pairs", "pair_words",
-                                                 "wedges", "attempts", "deferred_b", "deferred_c")},
+                                                 "wedges", "attempts", "deferred_a", "deferred_b",
+                                                 "deferred_c", "deferred_d")},
         "roofline": roof,
     }
 

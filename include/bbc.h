@@ -163,9 +163,11 @@ typedef struct {
     float ms_plan;              /* unit planning */
     float ms_triplet;           /* triplet kernel */
     uint32_t attempts;          /* launches of the count sequence (1 unless buffers grew) */
-    uint32_t deferred_b;        /* anchors handed from the 4096-slot to the 16384-slot tier */
+    uint32_t deferred_b;        /* anchors handed from the 8192-slot to the 16384-slot LDS tier */
     uint32_t deferred_c;        /* anchors handed to the bounded global-memory tier */
     uint32_t deferred_d;        /* anchors handed to the full-size global-memory tier */
+    uint32_t deferred_a;        /* anchors handed from the per-wave tier to the workgroup tiers
+                                   (degree above 32, or more partners than a wave's table) */
 } bbc_count_stats;
 bbc_status bbc_get_last_stats(bbc_ctx *ctx, bbc_count_stats *out);
 /* Enable (1) or disable (0) per-phase event timing on this context. */

@@ -59,7 +59,7 @@ class CountStats(ctypes.Structure):
                 ("ms_pair", ctypes.c_float), ("ms_plan", ctypes.c_float),
                 ("ms_triplet", ctypes.c_float), ("attempts", ctypes.c_uint32),
                 ("deferred_b", ctypes.c_uint32), ("deferred_c", ctypes.c_uint32),
-                ("deferred_d", ctypes.c_uint32)]
+                ("deferred_d", ctypes.c_uint32), ("deferred_a", ctypes.c_uint32)]
 
 
 _vp = ctypes.c_void_p

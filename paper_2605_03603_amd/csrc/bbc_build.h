@@ -41,7 +41,8 @@ struct BuildArgs {
     uint32_t *rank_of;             // [NS] slot -> global rank
     // CSR outputs
     uint64_t *s_off, *o_off;
-    uint32_t *s_adj, *o_adj, *s_rev, *s_graph, *s_vert;
+    uint32_t *s_adj, *o_adj, *s_graph, *s_vert;
+    uint2 *s_suf;
     uint32_t *o_ent;               // [M] scratch: O-side entry per S position
     void *tmp;
     size_t tmp_bytes;

@@ -8,14 +8,15 @@ namespace bbc {
 struct PairArgs {
     CsrView g;
     Workspace ws;
-    uint32_t a0, a1;        // anchor range (global ranks) of the first tier
-    int tier;               // 0, 1: LDS tables; 2: bounded global tables; 3: full-size global tables
+    uint32_t a0, a1;        // anchor range (global ranks) scanned by the per-wave tier
+    int tier;               // 0: per-wave LDS tables; 1, 2: per-workgroup LDS tables;
+                            // 3: bounded global tables; 4: full-size global tables
     uint32_t chunk_base;    // triplet unit width in columns for 1-word masks (<= 2048)
     uint32_t gH;            // tier-2 table slots (power of two)
     int glog2h;
     uint32_t dH;            // tier-3 table slots
     int dlog2h;
-    uint32_t gmaxd, gkmax;  // degree and candidate limits of tiers 1 and 2
+    uint32_t gmaxd, gkmax;  // degree and candidate limits of tiers 2, 3 and 4
 };
 
 struct TriArgs {
@@ -24,7 +25,7 @@ struct TriArgs {
 };
 
 struct LaunchShape {
-    uint32_t grid_a, grid_b, grid_c, grid_d, grid_t;
+    uint32_t grid_w, grid_a, grid_b, grid_c, grid_d, grid_t;
 };
 
 hipError_t count_pairs(const PairArgs &P, const LaunchShape &sh, hipStream_t s);
@@ -34,6 +35,9 @@ hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_
 // mode 0: totals only; 1: also per vertex of the anchor side; 2: per vertex of
 // the opposite side
 hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t s);
+// workgroups (and waves) of the per-wave tier that fit on one compute unit
+uint32_t wave_tier_blocks_per_cu();
+uint32_t wave_tier_waves_per_cu();
 uint32_t tier_c_max_degree();
 uint32_t tier_c_max_k();
 uint32_t max_unit_chunk();

@@ -22,9 +22,11 @@ constexpr int kWave = 64;
 //                          entry = (global O index << 1) | (sign < 0)
 //   o_off[NO+1], o_adj[M]: neighbours of O vertex v, sorted by rank;
 //                          entry = (global rank << 1) | (sign < 0)
-//   s_rev[M]               for S position t (edge (r, v)), the position of the
-//                          same edge in o_adj: the neighbours of v ranked above
-//                          r are o_adj[s_rev[t]+1 .. o_off[v+1])
+//   s_suf[M]               for S position t (edge (r, v)): x = first position
+//                          in o_adj of the neighbours of v ranked above r (they
+//                          end at o_off[v+1]); y = their number, 0 when below 2
+//                          (v then closes no triple anchored at r), with the
+//                          edge's sign bit (negative) in bit 31
 //   s_graph[NS]            graph of each global rank
 //   s_vert[NS]             the vertex's id inside its graph (input numbering)
 //   o_vert (implicit)      O index - o_base is the id inside the graph
@@ -45,7 +47,7 @@ struct CsrView {
     const uint32_t *s_adj;
     const uint64_t *o_off;
     const uint32_t *o_adj;
-    const uint32_t *s_rev;
+    const uint2 *s_suf;
     const uint32_t *s_graph;
     const uint32_t *s_vert;
     const GraphDesc *desc;
@@ -96,11 +98,11 @@ struct Counters {           // device-side cursors and flags, zeroed per count
     unsigned long long pair_words;
     uint32_t n_anchor;      // anchor records reserved (including unused slots)
     uint32_t over_cap;      // 1, 2: a workspace capacity was exceeded; 4: unsupported anchor
-    uint32_t n_list[3];     // anchors deferred to tiers B, C, D
+    uint32_t n_list[4];     // anchors handed to the workgroup tiers A, B, C, D
     uint32_t n_units;       // written by the plan kernel: all units
     uint32_t n_narrow;      // units of masks up to 16 words come first
     unsigned long long need_masks, need_cands, need_recs, need_units;   // exact demand
-    Cursor q_pair[4][kXcd]; // work-queue cursors of the pair tiers, one per XCD slice
+    Cursor q_pair[5][kXcd]; // work-queue cursors of the pair tiers, one per XCD slice
     Cursor q_tri[kXcd];
     Cursor q_tri_wide[kXcd];
 };
@@ -111,7 +113,7 @@ struct Workspace {
     Unit *units;         uint64_t cap_units;
     uint32_t *masks;     uint64_t cap_mask_words;
     uint32_t *cands;     uint64_t cap_cands;
-    uint32_t *defer[3];  uint64_t cap_defer;     // anchors for tiers B, C, D
+    uint32_t *defer[4];  uint64_t cap_defer;     // anchors for tiers A, B, C, D
     uint32_t *gtab;      uint64_t gtab_words_per_block; uint32_t gtab_blocks;  // tier C tables
     uint32_t *dtab;      uint64_t dtab_words_per_block; uint32_t dtab_blocks;  // tier D tables
     uint32_t *bscr;      uint64_t bscr_words_per_block;   // tier B per-block position lists

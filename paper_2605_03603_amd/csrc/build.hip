@@ -176,14 +176,19 @@ __global__ void __launch_bounds__(kT) k_s_finish(BuildArgs a)
 }
 
 // Sorted by O index (stably, so each O list is in rank order): emit o_adj
-// and, for every S position, the position of the same edge in o_adj.
+// and, for every S position, where the part of the O list ranked above the
+// S vertex starts and how long it is.
 __global__ void __launch_bounds__(kT) k_o_finish(BuildArgs a)
 {
     for (uint64_t t = (uint64_t)blockIdx.x * kT + threadIdx.x; t < a.M;
          t += (uint64_t)gridDim.x * kT) {
-        uint32_t ts = a.val1[t];
-        a.o_adj[t] = a.o_ent[ts];
-        a.s_rev[ts] = (uint32_t)t;
+        const uint32_t ts = a.val1[t];
+        const uint32_t ent = a.o_ent[ts];
+        a.o_adj[t] = ent;
+        const uint32_t v = (uint32_t)a.key1[t];
+        uint32_t len = (uint32_t)(a.o_off[v + 1] - t - 1);
+        if (len < 2) len = 0;
+        a.s_suf[ts] = make_uint2((uint32_t)t + 1, len | ((ent & 1u) << 31));
     }
 }
 

@@ -22,7 +22,7 @@
 //
 // k_pair (the signed pair table: Algorithm 2's cnt map split by sign class)
 //   one workgroup per anchor: walk the higher-priority part of each
-//   neighbour's list (found through s_rev, no search), count (same,
+//   neighbour's list (located by s_suf, no search), count (same,
 //   different) per partner in an LDS hash table, keep the classes with >= 3,
 //   walk again to set the mask bits, emit masks. Three tiers: 4096- and
 //   16384-slot LDS tables, then global-memory tables for anchors that
@@ -347,13 +347,14 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
     const uint32_t limit = HS - HS / 4;
     uint64_t my_wedges = 0;
 
+    // tier t (1..4) takes the anchors listed for it and hands the ones it
+    // cannot hold to tier t + 1
     const uint32_t n_items =
-        P.tier ? (uint32_t)min((uint64_t)__atomic_load_n(&C->n_list[P.tier - 1], __ATOMIC_RELAXED),
-                               P.ws.cap_defer)
-               : P.a1 - P.a0;
+        (uint32_t)min((uint64_t)__atomic_load_n(&C->n_list[P.tier - 1], __ATOMIC_RELAXED),
+                      P.ws.cap_defer);
     if (n_items == 0) return;
-    const uint32_t *list = P.tier ? P.ws.defer[P.tier - 1] : nullptr;
-    uint32_t *next_list = P.tier < 3 ? P.ws.defer[P.tier] : nullptr;
+    const uint32_t *list = P.ws.defer[P.tier - 1];
+    uint32_t *next_list = P.tier < 4 ? P.ws.defer[P.tier] : nullptr;
 
     auto clear_region = [&]() {
         if (PACKED) {
@@ -395,7 +396,7 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
         __syncthreads();
         const uint32_t item = sh.item;
         if (item >= n_items) break;
-        const uint32_t r = list ? list[item] : P.a0 + item;
+        const uint32_t r = list[item];
         const uint64_t s0 = g.s_off[r];
         const uint32_t d = (uint32_t)(g.s_off[r + 1] - s0);
         if (d < 3) continue;
@@ -406,13 +407,10 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
         // phase 0: the part of each neighbour's list ranked above the anchor,
         // and the position with the longest such suffix
         for (uint32_t p = tid; p < d; p += THREADS) {
-            const uint32_t e = g.s_adj[s0 + p];
-            const uint32_t st = g.s_rev[s0 + p] + 1;
-            const uint32_t hi = (uint32_t)g.o_off[(e >> 1) + 1];
-            uint32_t len = hi - st;
-            if (len < 2) len = 0;   // v needs 2 higher partners to lie in any T
-            m.pst[p] = st;
-            m.pln[p] = len | ((e & 1u) << 31);
+            const uint2 sf = g.s_suf[s0 + p];
+            const uint32_t len = sf.y & 0x7fffffffu;
+            m.pst[p] = sf.x;
+            m.pln[p] = sf.y;
             if (len) {
                 atomicAdd(&sh.wedges, len);
                 atomicMax(&sh.top1, ((unsigned long long)len << 32) | p);
@@ -664,7 +662,7 @@ template <bool PACKED>
 __global__ void __launch_bounds__(kGThreads) k_pair_global(PairArgs P)
 {
     __shared__ PairShared sh;
-    const bool d = P.tier == 3;
+    const bool d = P.tier == 4;
     uint32_t *base = (d ? P.ws.dtab : P.ws.gtab) +
                      (uint64_t)blockIdx.x * (d ? P.ws.dtab_words_per_block : P.ws.gtab_words_per_block);
     const uint32_t H = d ? P.dH : P.gH;
@@ -678,6 +676,375 @@ __global__ void __launch_bounds__(kGThreads) k_pair_global(PairArgs P)
     m.vc = m.pln + P.gmaxd;
     m.kmax = P.gkmax;
     pair_loop<kGThreads, PACKED>(P, m, sh);
+}
+
+// ----------------------------------------------------- per-wave tier
+// Anchors of degree <= 32 (masks of one word): one wave per anchor, each
+// wave with a table of its own in LDS that holds, per partner w, the key and
+// both class masks M_w^+ and M_w^- (bit p set by the wedge through position
+// p). The masks of the classes with >= 3 members are copied out as they
+// stand, so the wedges are walked once. Lane i takes the (j0 + i)-th wedge
+// of the concatenated suffix lists and finds its position by a binary
+// search over the lanes that hold the positions' prefix offsets. The two
+// longest suffixes only update partners found elsewhere, as in the
+// workgroup tiers; anchors of higher degree, or with more partners than the
+// table holds, are listed for tier A.
+constexpr uint32_t kWvMaxD = 32;
+constexpr int kWvUnroll = 8;              // loads in flight per lane, non-top positions
+constexpr int kWvTopUnroll = 16;          // and along the two longest suffixes
+constexpr uint64_t kWvMaskChunk = 4096;   // mask words reserved per wave at a time
+constexpr uint64_t kWvCandChunk = 4096;
+constexpr uint32_t kWvProbe = 64;
+constexpr uint32_t kWvGrab = 8;           // anchors taken from the queue at a time
+// non-top wedges (and so partners) of an anchor the per-wave tier takes, for
+// a table of S slots
+__host__ __device__ constexpr uint32_t wave_tier_limit(uint32_t S) { return S - S / 4; }
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t bcast32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t bcast64(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_max64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t w = __shfl_up(v, o, kWave);
+        if (lane >= (uint32_t)o) v += w;
+    }
+    return v;
+}
+
+template <int S, int NWV>
+__global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
+{
+    // per wave: S keys, 2S class masks and the list of occupied slots
+    constexpr uint32_t kLimit = wave_tier_limit(S);
+    __shared__ uint32_t tab_all[NWV][3 * S + kLimit];
+    constexpr int kLog2S = ilog2(S);
+    const uint32_t lane = __lane_id();
+    const uint32_t wv = threadIdx.x / kWave;
+    uint32_t *keys = tab_all[wv];
+    uint32_t *msk = tab_all[wv] + S;         // msk[2 slot + class]
+    uint32_t *used = tab_all[wv] + 3 * S;    // slots holding a key, in insertion order
+    const CsrView &g = P.g;
+    Counters *C = P.ws.ctr;
+    const uint32_t n_items = P.a1 - P.a0;
+
+    auto clear = [&]() {
+        for (uint32_t i = lane; i < 3u * S; i += kWave) tab_all[wv][i] = i < (uint32_t)S ? kEmpty : 0u;
+        wave_sync();
+    };
+    auto clear_used = [&](uint32_t n) {
+        for (uint32_t i = lane; i < n; i += kWave) {
+            const uint32_t sl = used[i];
+            keys[sl] = kEmpty; msk[2 * sl] = 0; msk[2 * sl + 1] = 0;
+        }
+        wave_sync();
+    };
+    auto to_tier_a = [&](bool mine, uint32_t r) {
+        const uint64_t b = ballot64(mine);
+        if (!b) return;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&C->n_list[0], (uint32_t)__popcll(b));
+        base = bcast32(base);
+        if (mine) {
+            const uint32_t t = base + (uint32_t)__popcll(b & lanemask_lt());
+            if (t < P.ws.cap_defer) P.ws.defer[0][t] = r; else atomicOr(&C->over_cap, 1u);
+        }
+    };
+    // continue a probe run after a first probe at slot h that met another key
+    auto insert_from = [&](uint32_t x, uint32_t h, bool &fresh) -> uint32_t {
+        for (uint32_t probe = 1; probe < kWvProbe; probe++) {
+            h = (h + 1) & (S - 1);
+            uint32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+            if (k == kEmpty) {
+                k = atomicCAS(&keys[h], kEmpty, x);
+                if (k == kEmpty) { fresh = true; return h; }
+            }
+            if (k == x) return h;
+        }
+        return kEmpty;
+    };
+    auto find_from = [&](uint32_t x, uint32_t h) -> uint32_t {
+        for (uint32_t probe = 1; probe < kWvProbe; probe++) {
+            h = (h + 1) & (S - 1);
+            const uint32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+            if (k == x) return h;
+            if (k == kEmpty) return kEmpty;
+        }
+        return kEmpty;
+    };
+
+    clear();
+    // wave-uniform reservation and demand state (as in the workgroup tiers)
+    uint64_t moff = 0, mres_end = 0, coff = 0, cres_end = 0;
+    uint32_t aidx = 0, arec_end = 0;
+    uint64_t need_m = 0, need_c = 0, need_r = 0, need_u = 0;
+    uint64_t vm = 0, vm_end = 0, vcn = 0, vc_end = 0;
+    uint64_t my_wedges = 0;
+    uint32_t slice = blockIdx.x % kXcd, tried = 0;
+
+    for (;;) {
+        uint32_t lo = 0, hi = 0, ok = 0;
+        if (lane == 0) ok = queue_take(C->q_pair[0], n_items, kWvGrab, &slice, &tried, &lo, &hi) ? 1u : 0u;
+        ok = bcast32(ok);
+        if (!ok) break;
+        lo = bcast32(lo); hi = bcast32(hi); slice = bcast32(slice); tried = bcast32(tried);
+        const uint32_t item = lo + lane;
+        const uint32_t rl = P.a0 + item;
+        uint32_t dl = 0;
+        uint64_t sl0 = 0;
+        if (item < hi) {
+            sl0 = g.s_off[rl];
+            dl = (uint32_t)(g.s_off[rl + 1] - sl0);
+        }
+        to_tier_a(item < hi && dl > kWvMaxD, rl);
+        uint64_t todo = ballot64(item < hi && dl >= 3 && dl <= kWvMaxD);
+        while (todo) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint32_t r = P.a0 + lo + l;
+            const uint64_t s0 = bcast64(__shfl(sl0, l, kWave));
+            const uint32_t d = bcast32(__shfl(dl, l, kWave));
+            // the part of each neighbour's list ranked above the anchor
+            uint32_t st = 0, len = 0, sg = 0;
+            if (lane < d) {
+                const uint2 sf = g.s_suf[s0 + lane];
+                st = sf.x;
+                len = sf.y & 0x7fffffffu;
+                sg = sf.y >> 31;
+            }
+            if (wave_sum<uint64_t>(len) < 6) continue;
+            const uint64_t key1 = len ? ((uint64_t)len << 6) | lane : 0;
+            const uint64_t k1 = wave_max64(key1);
+            const uint64_t k2 = wave_max64(lane == (uint32_t)(k1 & 63) ? 0 : key1);
+            const uint32_t t1 = (uint32_t)(k1 & 63), l1 = (uint32_t)(k1 >> 6);
+            const uint32_t t2 = (uint32_t)(k2 & 63), l2 = (uint32_t)(k2 >> 6);   // l2 = 0: no second
+            const uint32_t len1 = (lane == t1 || (l2 && lane == t2)) ? 0 : len;
+            // every non-top wedge inserts at most one partner: with T1 <= kLimit
+            // the table cannot fill up
+            const uint64_t T1 = wave_sum<uint64_t>(len1);
+            if (T1 > kLimit) {
+                to_tier_a(lane == 0, r);
+                continue;
+            }
+            const uint32_t incl = wave_incl_scan(len1);
+            const uint32_t pre = lane < d ? incl - len1 : 0xffffffffu;
+            const uint32_t info = (incl - len1) | (sg << 31);
+            // walk the other positions: insert partners, set mask bits
+            uint32_t nkeys = 0;
+            bool over = false;
+            // Lanes past the end repeat the last wedge: a repeated wedge sets a
+            // bit that is already set, so no lane needs a branch, and the
+            // searches, loads and first probes of all kWvUnroll wedges issue
+            // together.
+            for (uint32_t j0 = 0; j0 < (uint32_t)T1 && !over; j0 += kWave * kWvUnroll) {
+                uint32_t jj[kWvUnroll], p[kWvUnroll], e2[kWvUnroll], pp[kWvUnroll];
+#pragma unroll
+                for (int u = 0; u < kWvUnroll; u++) {
+                    jj[u] = min(j0 + u * kWave + lane, (uint32_t)T1 - 1);
+                    p[u] = 0;
+                }
+#pragma unroll
+                for (uint32_t step = 16; step; step >>= 1) {
+                    uint32_t v[kWvUnroll];
+#pragma unroll
+                    for (int u = 0; u < kWvUnroll; u++) v[u] = __shfl(pre, p[u] + step, kWave);
+#pragma unroll
+                    for (int u = 0; u < kWvUnroll; u++) p[u] += v[u] <= jj[u] ? step : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < kWvUnroll; u++) {
+                    const uint32_t stp = __shfl(st, p[u], kWave);
+                    const uint32_t inf = __shfl(info, p[u], kWave);
+                    e2[u] = g.o_adj[stp + (jj[u] - (inf & 0x7fffffffu))];
+                    pp[u] = p[u] | (inf & 0x80000000u);
+                }
+                // first probes of all partners at once (a CAS that returns the
+                // slot's key); the few longer probe runs follow one by one
+                uint32_t hs[kWvUnroll], old[kWvUnroll];
+#pragma unroll
+                for (int u = 0; u < kWvUnroll; u++) {
+                    hs[u] = hash_slot(e2[u] >> 1, kLog2S);
+                    old[u] = atomicCAS(&keys[hs[u]], kEmpty, e2[u] >> 1);
+                }
+                bool bad = false;
+#pragma unroll
+                for (int u = 0; u < kWvUnroll; u++) {
+                    const uint32_t x = e2[u] >> 1;
+                    const uint32_t cls = (e2[u] & 1u) ^ (pp[u] >> 31);
+                    bool fresh = old[u] == kEmpty;
+                    uint32_t h = hs[u];
+                    if (!fresh && old[u] != x) h = insert_from(x, h, fresh);
+                    if (h == kEmpty) bad = true;
+                    else atomicOr(&msk[2 * h + cls], 1u << (pp[u] & 31u));
+                    const uint64_t b = ballot64(fresh);
+                    if (fresh) used[nkeys + (uint32_t)__popcll(b & lanemask_lt())] = h;
+                    nkeys += (uint32_t)__popcll(b);
+                }
+                over = ballot64(bad) != 0;
+            }
+            if (over) {   // a probe run longer than kWvProbe
+                clear();
+                to_tier_a(lane == 0, r);
+                continue;
+            }
+            // the two longest suffixes: existing partners only
+            const uint32_t ltop = l1 + l2;
+            const uint32_t st1 = __shfl(st, t1, kWave), sg1 = __shfl(sg, t1, kWave);
+            const uint32_t st2 = __shfl(st, t2, kWave), sg2 = __shfl(sg, t2, kWave);
+            for (uint32_t j0 = 0; j0 < ltop; j0 += kWave * kWvTopUnroll) {
+                uint32_t e2[kWvTopUnroll], hs[kWvTopUnroll], kk[kWvTopUnroll];
+                bool first[kWvTopUnroll];
+#pragma unroll
+                for (int u = 0; u < kWvTopUnroll; u++) {
+                    const uint32_t j = min(j0 + u * kWave + lane, ltop - 1);   // repeats are harmless
+                    first[u] = j < l1;
+                    e2[u] = g.o_adj[first[u] ? st1 + j : st2 + (j - l1)];
+                }
+#pragma unroll
+                for (int u = 0; u < kWvTopUnroll; u++) {
+                    hs[u] = hash_slot(e2[u] >> 1, kLog2S);
+                    kk[u] = __atomic_load_n(&keys[hs[u]], __ATOMIC_RELAXED);
+                }
+#pragma unroll
+                for (int u = 0; u < kWvTopUnroll; u++) {
+                    if (kk[u] == kEmpty) continue;
+                    const uint32_t x = e2[u] >> 1;
+                    const uint32_t cls = (e2[u] & 1u) ^ (first[u] ? sg1 : sg2);
+                    const uint32_t h = kk[u] == x ? hs[u] : find_from(x, hs[u]);
+                    if (h != kEmpty) atomicOr(&msk[2 * h + cls], 1u << (first[u] ? t1 : t2));
+                }
+            }
+            wave_sync();
+            // classes with >= 3 members
+            uint32_t cnt = 0;
+            for (uint32_t i = lane; i < nkeys; i += kWave) {
+                const uint32_t sl = used[i];
+                cnt += (__popc(msk[2 * sl]) >= 3) + (__popc(msk[2 * sl + 1]) >= 3);
+            }
+            const uint32_t k = wave_sum<uint32_t>(cnt);
+            if (k < 2) {
+                clear_used(nkeys);
+                continue;
+            }
+            my_wedges += (uint64_t)T1 + ltop;
+            // reservations: wave-local bump allocation, large outputs apart;
+            // the demand counts what they consume with unlimited room
+            const bool big_m = k > kWvMaskChunk / 4, big_c = k > kWvCandChunk / 4;
+            if (big_m) {
+                need_m += k;
+            } else {
+                if (vm + k > vm_end) { need_m += kWvMaskChunk; vm = 0; vm_end = kWvMaskChunk; }
+                vm += k;
+            }
+            if (big_c) {
+                need_c += k;
+            } else {
+                if (vcn + k > vc_end) { need_c += kWvCandChunk; vcn = 0; vc_end = kWvCandChunk; }
+                vcn += k;
+            }
+            need_r += 1;
+            need_u += anchor_units(k, 1, P.chunk_base);
+            bool bad = false;
+            uint64_t mo = moff, co = coff;
+            {
+                if (big_m || moff + k > mres_end) {
+                    const uint64_t want = big_m ? k : kWvMaskChunk;
+                    uint64_t o = 0;
+                    if (lane == 0) o = atomicAdd(&C->mask_cursor, (unsigned long long)want);
+                    o = bcast64(o);
+                    mo = o;
+                    if (!big_m) { moff = o; mres_end = o + want; }
+                    if (o + want > P.ws.cap_mask_words) bad = true;
+                }
+                if (big_c || coff + k > cres_end) {
+                    const uint64_t want = big_c ? k : kWvCandChunk;
+                    uint64_t o = 0;
+                    if (lane == 0) o = atomicAdd(&C->cand_cursor, (unsigned long long)want);
+                    o = bcast64(o);
+                    co = o;
+                    if (!big_c) { coff = o; cres_end = o + want; }
+                    if (o + want > P.ws.cap_cands) bad = true;
+                }
+                if (aidx >= arec_end) {
+                    uint32_t o = 0;
+                    if (lane == 0) o = atomicAdd(&C->n_anchor, kRecChunk);
+                    o = bcast32(o);
+                    aidx = o; arec_end = o + kRecChunk;
+                    if ((uint64_t)o + kRecChunk > P.ws.cap_anchors) bad = true;
+                }
+            }
+            if (bad) {
+                if (lane == 0) atomicOr(&C->over_cap, 2u);
+                moff = mres_end = coff = cres_end = 0;
+                aidx = arec_end = 0;
+                clear_used(nkeys);
+                continue;
+            }
+            // copy out the selected classes and clear the table
+            uint32_t base = 0;
+            for (uint32_t i0 = 0; i0 < nkeys; i0 += kWave) {
+                const uint32_t i = i0 + lane;
+                const uint32_t sl = i < nkeys ? used[i] : 0u;
+                const uint32_t key = i < nkeys ? keys[sl] : kEmpty;
+                uint32_t m0 = 0, m1 = 0;
+                if (key != kEmpty) { m0 = msk[2 * sl]; m1 = msk[2 * sl + 1]; }
+                const bool a0 = __popc(m0) >= 3, a1 = __popc(m1) >= 3;
+                const uint64_t b0 = ballot64(a0), b1 = ballot64(a1);
+                const uint64_t lt = lanemask_lt();
+                uint32_t idx = base + (uint32_t)__popcll(b0 & lt) + (uint32_t)__popcll(b1 & lt);
+                if (a0) { P.ws.cands[co + idx] = key; P.ws.masks[mo + idx] = m0; idx++; }
+                if (a1) { P.ws.cands[co + idx] = key; P.ws.masks[mo + idx] = m1; }
+                base += (uint32_t)__popcll(b0) + (uint32_t)__popcll(b1);
+                if (i < nkeys) { keys[sl] = kEmpty; msk[2 * sl] = 0; msk[2 * sl + 1] = 0; }
+            }
+            wave_sync();
+            if (lane == 0) {
+                AnchorRec a;
+                a.rank = r; a.k = k; a.w32 = 1; a.graph = g.s_graph[r];
+                a.mask_off = mo; a.cand_off = co;
+                P.ws.anchors[aidx] = a;
+            }
+            if (!big_m) moff = mo + k;
+            if (!big_c) coff = co + k;
+            aidx++;
+        }
+    }
+    if (lane == 0) {
+        if (need_m) atomicAdd(&C->need_masks, (unsigned long long)need_m);
+        if (need_c) atomicAdd(&C->need_cands, (unsigned long long)need_c);
+        if (need_r) atomicAdd(&C->need_recs, (unsigned long long)need_r);
+        if (need_u) atomicAdd(&C->need_units, (unsigned long long)need_u);
+        if (my_wedges) atomicAdd(&C->wedges, (unsigned long long)my_wedges);
+    }
+    // unused reserved anchor records are marked empty
+    for (uint32_t i = aidx + lane; i < arec_end; i += kWave) {
+        AnchorRec a;
+        a.rank = 0; a.k = 0; a.w32 = 0; a.graph = 0; a.mask_off = 0; a.cand_off = 0;
+        P.ws.anchors[i] = a;
+    }
 }
 
 // ------------------------------------------------------------- planning
@@ -906,7 +1273,7 @@ constexpr uint32_t kMaxChunk = 2048;
 constexpr uint32_t kUnitGrab = 4;
 
 template <int MODE, bool WIDE>
-__global__ void __launch_bounds__(kTThreads, 5) k_triplet(TriArgs T)
+__global__ void __launch_bounds__(kTThreads, MODE == 1 ? 2 : 5) k_triplet(TriArgs T)
 {
     __shared__ uint32_t c3[kC3Max + 1];
     __shared__ unsigned long long colacc_all[MODE == 1 ? kTThreads / kWave : 1][MODE == 1 ? kMaxChunk : 1];
@@ -1008,6 +1375,14 @@ __global__ void __launch_bounds__(kTThreads, 5) k_triplet(TriArgs T)
 // tier B ~ 144 KiB).
 constexpr int kAThreads = 512, kAH = 8192, kAMaxD = 1024, kAKmax = 1984;
 constexpr int kBThreads = 1024, kBH = 16384, kBKmax = 4096;
+// per-wave tier: 2048 slots (30 KiB with the slot list) per wave
+constexpr int kWvSlots = 2048, kWvWaves = 1;
+
+uint32_t wave_tier_blocks_per_cu()
+{
+    return (160u * 1024u) / ((3u * kWvSlots + wave_tier_limit(kWvSlots)) * 4u * kWvWaves);
+}
+uint32_t wave_tier_waves_per_cu() { return wave_tier_blocks_per_cu() * kWvWaves; }
 
 uint32_t tier_c_max_degree() { return 65535; }
 uint32_t tier_c_max_k() { return 65535; }
@@ -1018,14 +1393,17 @@ static void launch_pairs(const PairArgs &base, const LaunchShape &sh, hipStream_
 {
     PairArgs P = base;
     P.tier = 0;
+    hipLaunchKernelGGL((k_pair_wave<kWvSlots, kWvWaves>), dim3(sh.grid_w), dim3(kWvWaves * kWave),
+                       0, s, P);
+    P.tier = 1;
     hipLaunchKernelGGL((k_pair_lds<kAThreads, kAH, kAMaxD, kAKmax, PACKED>), dim3(sh.grid_a),
                        dim3(kAThreads), 0, s, P);
-    P.tier = 1;
+    P.tier = 2;
     hipLaunchKernelGGL((k_pair_big<kBThreads, kBH, kBKmax, PACKED>), dim3(sh.grid_b),
                        dim3(kBThreads), 0, s, P);
-    P.tier = 2;
-    hipLaunchKernelGGL((k_pair_global<PACKED>), dim3(sh.grid_c), dim3(kGThreads), 0, s, P);
     P.tier = 3;
+    hipLaunchKernelGGL((k_pair_global<PACKED>), dim3(sh.grid_c), dim3(kGThreads), 0, s, P);
+    P.tier = 4;
     hipLaunchKernelGGL((k_pair_global<PACKED>), dim3(sh.grid_d), dim3(kGThreads), 0, s, P);
 }
 

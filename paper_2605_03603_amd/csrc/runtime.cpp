@@ -201,7 +201,7 @@ struct GraphSet {
     uint64_t M = 0;
     std::vector<GraphDesc> desc;
     DBuf d_desc, s_off, o_off, s_adj, o_adj, s_graph, s_vert;
-    DBuf s_rev;
+    DBuf s_suf;
     // sizing hints learnt by earlier counts
     uint64_t hint_masks = 0, hint_cands = 0, hint_units = 0;
     // anchor-side tuning of a single large graph: shape key and side used
@@ -210,7 +210,7 @@ struct GraphSet {
     uint64_t device_bytes() const
     {
         return d_desc.bytes + s_off.bytes + o_off.bytes + s_adj.bytes + o_adj.bytes +
-               s_rev.bytes + s_graph.bytes + s_vert.bytes;
+               s_suf.bytes + s_graph.bytes + s_vert.bytes;
     }
     CsrView view() const
     {
@@ -219,7 +219,7 @@ struct GraphSet {
         v.G = G; v.NS = NS; v.NO = NO; v.M = M;
         v.s_off = s_off.as<uint64_t>(); v.s_adj = s_adj.as<uint32_t>();
         v.o_off = o_off.as<uint64_t>(); v.o_adj = o_adj.as<uint32_t>();
-        v.s_rev = s_rev.as<uint32_t>();
+        v.s_suf = s_suf.as<uint2>();
         v.s_graph = s_graph.as<uint32_t>(); v.s_vert = s_vert.as<uint32_t>();
         v.desc = d_desc.as<GraphDesc>();
         return v;
@@ -235,7 +235,7 @@ namespace {
 
 // Count workspace (one per stream that counts).
 struct Work {
-    DBuf ctr, anchors, units, masks, cands, defer0, defer1, defer2, gtab, dtab, bscr, count,
+    DBuf ctr, anchors, units, masks, cands, defer0, defer1, defer2, defer3, gtab, dtab, bscr, count,
         carry, pv, pv_o;
     DBuf ucnt, uoff, ptmp;
     HBuf host;          // counters + counts + carries read back
@@ -562,7 +562,7 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
     set->o_off.ensure(al, (NO + 1) * 8);
     set->s_adj.ensure(al, std::max<uint64_t>(M, 1) * 4);
     set->o_adj.ensure(al, std::max<uint64_t>(M, 1) * 4);
-    set->s_rev.ensure(al, std::max<uint64_t>(M, 1) * 4);
+    set->s_suf.ensure(al, std::max<uint64_t>(M, 1) * 8);
     DBuf o_ent;
     o_ent.ensure(al, std::max<uint64_t>(M, 1) * 4);
     set->s_graph.ensure(al, std::max<uint64_t>(NS, 1) * 4);
@@ -583,7 +583,7 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
     a.rank_of = rank_of.as<uint32_t>();
     a.s_off = set->s_off.as<uint64_t>(); a.o_off = set->o_off.as<uint64_t>();
     a.s_adj = set->s_adj.as<uint32_t>(); a.o_adj = set->o_adj.as<uint32_t>();
-    a.s_rev = set->s_rev.as<uint32_t>(); a.o_ent = o_ent.as<uint32_t>();
+    a.s_suf = set->s_suf.as<uint2>(); a.o_ent = o_ent.as<uint32_t>();
     a.s_graph = set->s_graph.as<uint32_t>(); a.s_vert = set->s_vert.as<uint32_t>();
     a.tmp = tmp.p; a.tmp_bytes = tmp_bytes;
     HIP_OK(build_rank(a, s));
@@ -607,8 +607,10 @@ void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set)
 {
     Allocator *al = ctx->al.get();
     uint64_t M = std::max<uint64_t>(set.M, 1);
-    // records are reserved 16 at a time per workgroup
-    uint64_t want_anchors = std::max<uint64_t>(set.NS, 1) + 16ull * 4 * ctx->num_cus + 64;
+    // records are reserved 16 at a time per wave of the per-wave tier and per
+    // workgroup of the others
+    const uint64_t agents = (uint64_t)ctx->num_cus * (wave_tier_waves_per_cu() + 8) + 64;
+    uint64_t want_anchors = std::max<uint64_t>(set.NS, 1) + 16ull * agents;
     // first guesses; an overflowing count records its exact demand and reruns once
     uint64_t want_masks = std::max<uint64_t>({set.hint_masks, 2 * M, 1ull << 22});
     uint64_t want_cands = std::max<uint64_t>({set.hint_cands, M / 2, 1ull << 20});
@@ -628,7 +630,7 @@ void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set)
     if (w.cap_units < want_units) { w.units.ensure(al, want_units * sizeof(Unit)); w.cap_units = want_units; }
     if (w.cap_defer < set.NS + 1ull) {
         w.defer0.ensure(al, (set.NS + 1ull) * 4); w.defer1.ensure(al, (set.NS + 1ull) * 4);
-        w.defer2.ensure(al, (set.NS + 1ull) * 4);
+        w.defer2.ensure(al, (set.NS + 1ull) * 4); w.defer3.ensure(al, (set.NS + 1ull) * 4);
         w.cap_defer = set.NS + 1ull;
     }
     w.ctr.ensure(al, sizeof(Counters));
@@ -681,7 +683,7 @@ Workspace ws_view(Work &w, bool pv, bool pvo)
     ws.masks = w.masks.as<uint32_t>(); ws.cap_mask_words = w.cap_masks;
     ws.cands = w.cands.as<uint32_t>(); ws.cap_cands = w.cap_cands;
     ws.defer[0] = w.defer0.as<uint32_t>(); ws.defer[1] = w.defer1.as<uint32_t>();
-    ws.defer[2] = w.defer2.as<uint32_t>();
+    ws.defer[2] = w.defer2.as<uint32_t>(); ws.defer[3] = w.defer3.as<uint32_t>();
     ws.cap_defer = w.cap_defer;
     ws.gtab = w.gtab.as<uint32_t>(); ws.gtab_words_per_block = w.gtab_words;
     ws.gtab_blocks = w.gtab_blocks;
@@ -724,6 +726,7 @@ LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
     L.P.chunk_base = std::min(shp.chunk_base, max_unit_chunk());
     L.P.gH = w.gH; L.P.glog2h = w.glog2; L.P.gmaxd = w.gmaxd; L.P.gkmax = w.gkmax;
     L.P.dH = w.dH; L.P.dlog2h = w.dlog2;
+    L.ls.grid_w = std::max(1u, ctx->num_cus * wave_tier_blocks_per_cu());
     L.ls.grid_a = std::max(1u, ctx->num_cus * shp.grid_a_per_cu);
     L.ls.grid_b = std::max(1u, (uint32_t)ctx->num_cus);
     L.ls.grid_c = w.gtab_blocks;
@@ -780,8 +783,11 @@ bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set)
     if (c->over_cap & 4u)
         fail(BBC_E_UNSUPPORTED, "an anchor has degree above %u or more than %u candidate classes",
              tier_c_max_degree(), tier_c_max_k());
-    // demand plus room for the per-workgroup reservation chunks
-    const uint64_t slack_m = 4ull * ctx->num_cus * (1u << 16), slack_c = 4ull * ctx->num_cus * (1u << 13);
+    // demand plus room for the reservation chunks of the per-wave tier (4096
+    // words) and of the workgroup tiers
+    const uint64_t wv = (uint64_t)ctx->num_cus * wave_tier_waves_per_cu();
+    const uint64_t slack_m = 4ull * ctx->num_cus * (1u << 16) + wv * 4096;
+    const uint64_t slack_c = 4ull * ctx->num_cus * (1u << 13) + wv * 4096;
     set.hint_masks = std::max<uint64_t>(set.hint_masks, c->need_masks + c->need_masks / 16 + slack_m);
     set.hint_cands = std::max<uint64_t>(set.hint_cands, c->need_cands + c->need_cands / 16 + slack_c);
     if (c->over_cap & 3u) {
@@ -796,9 +802,10 @@ bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set)
     ctx->stats.mask_words = c->mask_cursor;
     ctx->stats.wedges = c->wedges;
     ctx->stats.pair_words = c->pair_words;
-    ctx->stats.deferred_b = c->n_list[0];
-    ctx->stats.deferred_c = c->n_list[1];
-    ctx->stats.deferred_d = c->n_list[2];
+    ctx->stats.deferred_a = c->n_list[0];
+    ctx->stats.deferred_b = c->n_list[1];
+    ctx->stats.deferred_c = c->n_list[2];
+    ctx->stats.deferred_d = c->n_list[3];
     return true;
 }
 
