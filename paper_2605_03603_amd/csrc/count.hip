@@ -73,6 +73,7 @@ constexpr uint32_t kEmpty = 0xffffffffu;
 constexpr uint32_t kC3Max = 512;       // C(n,3) table covers masks of up to 16 words
 constexpr uint32_t kRegW = 16;         // widest mask kept in registers per row
 constexpr uint32_t kWideCols = 32;     // unit width (columns) for wider masks
+constexpr uint32_t kMfmaMaxW = 16;     // widest mask counted on the matrix cores
 constexpr uint32_t kMaskChunk = 1u << 16;   // mask words reserved per workgroup at a time
 constexpr uint32_t kCandChunk = 1u << 13;
 constexpr uint32_t kRecChunk = 16;
@@ -125,7 +126,7 @@ __host__ __device__ __forceinline__ uint32_t unit_cols(uint32_t w32, uint32_t ba
     if (w32 > kRegW) return kWideCols;
     uint32_t c = base / w32;
     c = c < 32 ? 32 : c;
-    return (c + 7) & ~7u;
+    return (c + 15) & ~15u;   // whole 16-column matrix-core tiles
 }
 
 __device__ __forceinline__ uint32_t slice_lo(uint32_t n, uint32_t s)
@@ -1272,8 +1273,142 @@ constexpr int kTThreads = 256;
 constexpr uint32_t kMaxChunk = 2048;
 constexpr uint32_t kUnitGrab = 4;
 
+// ---------------------------------------------- matrix-core triplet path
+// The counts |M_x n M_y| of one unit form an integer matrix product of
+// 0/1 matrices (rows x mask bits times mask bits x columns), so they run on
+// the int8 matrix cores: v_mfma_i32_16x16x64_i8 multiplies a 16 x 64 by a
+// 64 x 16 int8 tile. Lane l supplies row (or column) l % 16, elements
+// 16 (l / 16) .. + 15, and receives rows 4 (l / 16) .. + 3 of column l % 16
+// of the product. Element e of a lane's slice is bit e of a 16-bit piece of
+// a mask word, spread to one byte per bit.
+//
+// With the accumulator started at -1 the product gives D = n - 1, and
+// n (n - 1) (n - 2) = D (D^2 - 1): two 24-bit multiply-adds per pair, zero
+// for n <= 2 (also for padding rows and columns, whose masks are zero, and
+// for masked pairs, set to D = -1). Each term is 6 C(n, 3), so a lane's sum
+// is divided by 6 once.
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+
+// a * b + c with a and b taken as 24-bit signed integers (full rate)
+__device__ __forceinline__ uint32_t mad_i24(int a, int b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ int mad_i24(int a, int b, int c)
+{
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ v4i32 spread16(uint32_t x)
+{
+    // 4 bits -> 4 bytes: the multiplier copies bit b of the nibble to bit 8b
+    v4i32 r;
+    r[0] = (int)(((x & 0xfu) * 0x00204081u) & 0x01010101u);
+    r[1] = (int)((((x >> 4) & 0xfu) * 0x00204081u) & 0x01010101u);
+    r[2] = (int)((((x >> 8) & 0xfu) * 0x00204081u) & 0x01010101u);
+    r[3] = (int)((((x >> 12) & 0xfu) * 0x00204081u) & 0x01010101u);
+    return r;
+}
+
+// The 16-bit pieces that lane group g feeds into the K-chunks of mask m:
+// chunk t takes word 2 t + (g >> 1), half g & 1 (zero past the mask width
+// or for an invalid row / column). The loads are unconditional (clamped to
+// valid words) so that all of them are in flight together.
+template <int W>
+__device__ __forceinline__ void mask_pieces(const uint32_t *m, bool valid, uint32_t g,
+                                            uint32_t (&pc)[(W + 1) / 2])
+{
+#pragma unroll
+    for (int t = 0; t < (W + 1) / 2; t++) {
+        const uint32_t w = 2 * t + (g >> 1);
+        const uint32_t v = m[w < (uint32_t)W ? w : (uint32_t)W - 1];
+        pc[t] = (valid && w < (uint32_t)W) ? (v >> (16 * (g & 1u))) & 0xffffu : 0u;
+    }
+}
+
+// Sum over the unit's pairs (j < i) of C(|M_i n M_j|, 3), masks of W words.
+// The 64 rows go in passes of SBP 16-row blocks, so that the spread row
+// operands (SBP x ceil(W/2) x 4 registers) stay in registers.
+template <int W>
+__device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
+                                  const uint32_t *__restrict__ masks)
+{
+    constexpr int NC = (W + 1) / 2;          // 64-bit K-chunks
+    constexpr int SBP = W <= 8 ? 4 : 2;      // 16-row blocks per pass
+    const uint32_t lane = __lane_id();
+    const uint32_t g = lane >> 4, r16 = lane & 15u;
+    const uint32_t *M = masks + a.mask_off;
+    const uint32_t rbase = un.rb * kWave;
+    auto col_pieces = [&](uint32_t j0, uint32_t (&pc)[NC]) {
+        const uint32_t j = j0 + r16;
+        const bool vj = j < un.c1;
+        mask_pieces<W>(M + (uint64_t)(vj ? j : un.c1 - 1) * W, vj, g, pc);
+    };
+    uint64_t sum = 0;
+#pragma unroll 1
+    for (int pass = 0; pass < 4 / SBP; pass++) {
+        const uint32_t pbase = rbase + 16 * SBP * pass;
+        if (pbase >= a.k) break;
+        v4i32 A[SBP][NC];
+#pragma unroll
+        for (int sb = 0; sb < SBP; sb++) {
+            const uint32_t i = pbase + 16 * sb + r16;
+            uint32_t pc[NC];
+            mask_pieces<W>(M + (uint64_t)(i < a.k ? i : a.k - 1) * W, i < a.k, g, pc);
+#pragma unroll
+            for (int t = 0; t < NC; t++) A[sb][t] = spread16(pc[t]);
+        }
+        // column pieces of the next 16-column tile are loaded one tile ahead
+        uint32_t cur[NC], nxt[NC];
+        col_pieces(un.c0, cur);
+        for (uint32_t j0 = un.c0; j0 < un.c1; j0 += 16) {
+            if (j0 + 16 < un.c1) col_pieces(j0 + 16, nxt);
+            v4i32 acc[SBP];
+#pragma unroll
+            for (int sb = 0; sb < SBP; sb++) acc[sb] = (v4i32){-1, -1, -1, -1};
+#pragma unroll
+            for (int t = 0; t < NC; t++) {
+                const v4i32 B = spread16(cur[t]);
+#pragma unroll
+                for (int sb = 0; sb < SBP; sb++)
+                    acc[sb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[sb][t], B, acc[sb], 0, 0, 0);
+            }
+            // lane holds rows pbase + 16 sb + 4 g + e of column j; only j < i
+            // counts. -1 <= D < 32 W <= 512: both products fit the 24-bit
+            // multiply-add, which the compiler cannot prove by itself.
+            const uint32_t j = j0 + r16;
+            uint32_t s32 = 0;
+            if (j0 + 16 <= pbase) {
+#pragma unroll
+                for (int sb = 0; sb < SBP; sb++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const int D = acc[sb][e];
+                        s32 = mad_i24(D, mad_i24(D, D, -1), s32);
+                    }
+            } else {
+#pragma unroll
+                for (int sb = 0; sb < SBP; sb++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const int D = j < pbase + 16 * sb + 4 * g + e ? acc[sb][e] : -1;
+                        s32 = mad_i24(D, mad_i24(D, D, -1), s32);
+                    }
+            }
+            sum += s32;
+#pragma unroll
+            for (int t = 0; t < NC; t++) cur[t] = nxt[t];
+        }
+    }
+    return sum / 6;
+}
+
 template <int MODE, bool WIDE>
-__global__ void __launch_bounds__(kTThreads, MODE == 1 ? 2 : 5) k_triplet(TriArgs T)
+__global__ void __launch_bounds__(kTThreads, MODE == 1 ? 2 : (MODE == 0 && !WIDE ? 3 : 5)) k_triplet(TriArgs T)
 {
     __shared__ uint32_t c3[kC3Max + 1];
     __shared__ unsigned long long colacc_all[MODE == 1 ? kTThreads / kWave : 1][MODE == 1 ? kMaxChunk : 1];
@@ -1330,12 +1465,22 @@ __global__ void __launch_bounds__(kTThreads, MODE == 1 ? 2 : 5) k_triplet(TriArg
         if (WIDE) {
             acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T);
         } else {
-            switch (a.w32) {
-#define BBC_W(n) case n: acc = tri_rows<n, MODE>(un, a, T.ws.masks, c3, colacc, T); break;
-                BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) BBC_W(5) BBC_W(6) BBC_W(7) BBC_W(8)
-                BBC_W(9) BBC_W(10) BBC_W(11) BBC_W(12) BBC_W(13) BBC_W(14) BBC_W(15) BBC_W(16)
+            if (MODE == 0 && a.w32 <= kMfmaMaxW) {
+                switch (a.w32) {
+#define BBC_W(n) case n: acc = tri_rows_mfma<n>(un, a, T.ws.masks); break;
+                    BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) BBC_W(5) BBC_W(6) BBC_W(7) BBC_W(8)
+                    BBC_W(9) BBC_W(10) BBC_W(11) BBC_W(12) BBC_W(13) BBC_W(14) BBC_W(15) BBC_W(16)
 #undef BBC_W
-                default: break;
+                    default: break;
+                }
+            } else {
+                switch (a.w32) {
+#define BBC_W(n) case n: acc = tri_rows<n, MODE>(un, a, T.ws.masks, c3, colacc, T); break;
+                    BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) BBC_W(5) BBC_W(6) BBC_W(7) BBC_W(8)
+                    BBC_W(9) BBC_W(10) BBC_W(11) BBC_W(12) BBC_W(13) BBC_W(14) BBC_W(15) BBC_W(16)
+#undef BBC_W
+                    default: break;
+                }
             }
         }
         const uint32_t i = un.rb * kWave + lane;

@@ -23,7 +23,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/bbc.h"
+#include "bbc.h"
 #include "bbc_build.h"
 #include "bbc_count.h"
 
@@ -257,7 +257,7 @@ struct Work {
 };
 
 struct Shape {
-    uint32_t chunk_base = 512;
+    uint32_t chunk_base = 2048;
     uint32_t grid_a_per_cu = 2;
     uint32_t grid_t_per_cu = 6;
 };
@@ -723,7 +723,8 @@ LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
     L.P.ws = ws;
     L.P.a0 = set.desc[r.g0].s_base;
     L.P.a1 = set.desc[r.g1 - 1].s_base + set.desc[r.g1 - 1].n_s;
-    L.P.chunk_base = std::min(shp.chunk_base, max_unit_chunk());
+    // per-vertex counts keep one LDS sum per unit column: their units stay narrower
+    L.P.chunk_base = std::min(shp.chunk_base, r.mode == 1 ? max_unit_chunk() : 16384u);
     L.P.gH = w.gH; L.P.glog2h = w.glog2; L.P.gmaxd = w.gmaxd; L.P.gkmax = w.gkmax;
     L.P.dH = w.dH; L.P.dlog2h = w.dlog2;
     L.ls.grid_w = std::max(1u, ctx->num_cus * wave_tier_blocks_per_cu());
@@ -880,7 +881,7 @@ Shape tune_shape(bbc_ctx *ctx, Work &w, GraphSet &set, hipStream_t s)
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) return it->second;
     std::vector<Shape> cands;
-    for (uint32_t cb : {256u, 512u, 1024u})
+    for (uint32_t cb : {512u, 2048u, 4096u})
         for (uint32_t gt : {4u, 8u}) {
             Shape sh;
             sh.chunk_base = cb;
