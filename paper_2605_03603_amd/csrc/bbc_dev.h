@@ -142,6 +142,16 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+__device__ __forceinline__ uint64_t wave_max64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
 __host__ __device__ __forceinline__ uint64_t choose2(uint64_t n) { return n < 2 ? 0 : n * (n - 1) / 2; }
 __host__ __device__ __forceinline__ uint64_t choose3(uint64_t n)
 {

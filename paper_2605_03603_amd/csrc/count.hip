@@ -281,12 +281,14 @@ __device__ __forceinline__ uint32_t compact_find(const uint32_t *ckeys, const ui
 template <int THREADS, typename F>
 __device__ __forceinline__ void walk_positions(const CsrView &g, const PairMem &m, uint32_t d,
                                                uint32_t t1, uint32_t t2, bool ordinary,
-                                               bool top, F &&f)
+                                               bool top, F &&f, uint32_t p0 = 0,
+                                               uint32_t p1 = 0xffffffffu)
 {
     constexpr int NW = THREADS / kWave;
     const int tid = threadIdx.x, lane = __lane_id(), wv = tid / kWave;
+    if (p1 > d) p1 = d;
     if (ordinary) {
-        for (uint32_t p = wv; p < d; p += NW) {
+        for (uint32_t p = p0 + wv; p < p1; p += NW) {
             if (p == t1 || p == t2) continue;
             const uint32_t ln = m.pln[p];
             const uint32_t len = ln & 0x7fffffffu;
@@ -306,8 +308,8 @@ __device__ __forceinline__ void walk_positions(const CsrView &g, const PairMem &
         }
     }
     if (top) {
-        const uint32_t l1 = t1 < d ? (m.pln[t1] & 0x7fffffffu) : 0;
-        const uint32_t l2 = t2 < d ? (m.pln[t2] & 0x7fffffffu) : 0;
+        const uint32_t l1 = (t1 >= p0 && t1 < p1) ? (m.pln[t1] & 0x7fffffffu) : 0;
+        const uint32_t l2 = (t2 >= p0 && t2 < p1) ? (m.pln[t2] & 0x7fffffffu) : 0;
         const uint32_t tot = l1 + l2;
         for (uint32_t j0 = 0; j0 < tot; j0 += THREADS * kUnroll) {
             uint32_t e2[kUnroll], pp[kUnroll];
@@ -407,22 +409,38 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
         }
         // phase 0: the part of each neighbour's list ranked above the anchor,
         // and the position with the longest such suffix
-        for (uint32_t p = tid; p < d; p += THREADS) {
-            const uint2 sf = g.s_suf[s0 + p];
-            const uint32_t len = sf.y & 0x7fffffffu;
-            m.pst[p] = sf.x;
-            m.pln[p] = sf.y;
-            if (len) {
-                atomicAdd(&sh.wedges, len);
-                atomicMax(&sh.top1, ((unsigned long long)len << 32) | p);
+        {
+            // per-wave sum and maximum, then one LDS atomic per wave
+            uint32_t wsum = 0;
+            uint64_t wtop = 0;
+            for (uint32_t p = tid; p < d; p += THREADS) {
+                const uint2 sf = g.s_suf[s0 + p];
+                const uint32_t len = sf.y & 0x7fffffffu;
+                m.pst[p] = sf.x;
+                m.pln[p] = sf.y;
+                wsum += len;
+                const uint64_t key = len ? ((uint64_t)len << 32) | p : 0;
+                wtop = key > wtop ? key : wtop;
+            }
+            wsum = wave_sum<uint32_t>(wsum);
+            wtop = wave_max64(wtop);
+            if (lane == 0 && wsum) {
+                atomicAdd(&sh.wedges, wsum);
+                atomicMax(&sh.top1, (unsigned long long)wtop);
             }
         }
         __syncthreads();
         if (sh.wedges < 6) continue;   // fewer than 2 classes of 3 are impossible
         const uint32_t t1 = sh.top1 ? (uint32_t)sh.top1 : kEmpty;
-        for (uint32_t p = tid; p < d; p += THREADS) {
-            const uint32_t len = m.pln[p] & 0x7fffffffu;
-            if (len && p != t1) atomicMax(&sh.top2, ((unsigned long long)len << 32) | p);
+        {
+            uint64_t wtop = 0;
+            for (uint32_t p = tid; p < d; p += THREADS) {
+                const uint32_t len = m.pln[p] & 0x7fffffffu;
+                const uint64_t key = (len && p != t1) ? ((uint64_t)len << 32) | p : 0;
+                wtop = key > wtop ? key : wtop;
+            }
+            wtop = wave_max64(wtop);
+            if (lane == 0 && wtop) atomicMax(&sh.top2, (unsigned long long)wtop);
         }
         __syncthreads();
         const uint32_t t2 = sh.top2 ? (uint32_t)sh.top2 : kEmpty;
@@ -460,22 +478,8 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
                                     });
             __syncthreads();
             // phase 2: classes with >= 3 members become virtual candidates
-            for (uint32_t slot = tid; slot < HS; slot += THREADS) {
-                uint32_t k;
-                bool same3, diff3;
-                if (PACKED) {
-                    const uint32_t v = m.region[slot];
-                    if (v == kEmpty) continue;
-                    k = v & kKeyMask;
-                    same3 = (v >> 26) & 1u;
-                    diff3 = (v >> 29) & 1u;
-                } else {
-                    k = keys[slot];
-                    if (k == kEmpty) continue;
-                    const uint32_t v = vals[slot];
-                    same3 = (v & 0xffffu) >= 3;
-                    diff3 = (v >> 16) >= 3;
-                }
+            // (packed slots are read four at a time)
+            auto select = [&](uint32_t k, bool same3, bool diff3) {
                 if (same3) {
                     const uint32_t t = atomicAdd(&sh.nv, 1u);
                     if (t < m.kmax) m.vc[t] = k;
@@ -484,6 +488,29 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
                     const uint32_t t = atomicAdd(&sh.nv, 1u);
                     if (t < m.kmax) m.vc[t] = k | 0x80000000u;
                 }
+            };
+            if (PACKED) {
+                const uint4 *R4 = reinterpret_cast<const uint4 *>(m.region);
+                for (uint32_t q = tid; q < HS / 4; q += THREADS) {
+                    const uint4 v4 = R4[q];
+                    const uint32_t vv[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        if (vv[e] != kEmpty && (vv[e] & (0x24u << 24)))
+                            select(vv[e] & kKeyMask, (vv[e] >> 26) & 1u, (vv[e] >> 29) & 1u);
+                }
+            }
+            for (uint32_t slot = tid; !PACKED && slot < HS; slot += THREADS) {
+                uint32_t k;
+                bool same3, diff3;
+                {
+                    k = keys[slot];
+                    if (k == kEmpty) continue;
+                    const uint32_t v = vals[slot];
+                    same3 = (v & 0xffffu) >= 3;
+                    diff3 = (v >> 16) >= 3;
+                }
+                select(k, same3, diff3);
             }
             __syncthreads();
             defer = sh.nv > m.kmax;
@@ -572,23 +599,37 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
             clear_region();
             continue;
         }
-        const bool staged = words <= m.maskw;
         const uint64_t moff = sh.big_m ? sh.bm : sh.moff, coff = sh.big_c ? sh.bc : sh.coff;
         const uint32_t aidx = sh.aidx;
-        uint32_t *mp = staged ? mstage : P.ws.masks + moff;
-        for (uint64_t i = tid; i < words; i += THREADS) mp[i] = 0;
-        if (!staged) __threadfence();
-        __syncthreads();
-        // phase 3: bit p of M_(w,c) for every higher-priority wedge through position p
-        walk_positions<THREADS>(g, m, d, t1, t2, true, true,
-                                [&](uint32_t e2, uint32_t p, uint32_t sg) {
-                                    const uint32_t v = compact_find(ckeys, cidx, m.HC, m.log2hc, e2 >> 1);
-                                    const uint32_t idx = ((e2 & 1u) ^ sg) ? (v >> 16) : (v & 0xffffu);
-                                    if (idx) atomicOr(&mp[(uint64_t)(idx - 1) * W + (p >> 5)], 1u << (p & 31));
-                                });
-        __syncthreads();
-        if (staged)
-            for (uint64_t i = tid; i < words; i += THREADS) P.ws.masks[moff + i] = mstage[i];
+        // phase 3: bit p of M_(w,c) for every higher-priority wedge through
+        // position p, built in the staging area in slabs of whole mask words
+        // (k x sw words each); a slab walks only the positions of its words,
+        // so every wedge is visited once and every mask word written once.
+        const uint32_t sw = min(W, max(1u, m.maskw / k));
+        for (uint32_t w0 = 0; w0 < W; w0 += sw) {
+            const uint32_t nw = min(sw, W - w0);
+            const uint32_t slab = k * nw;
+            for (uint32_t i = tid; i < slab; i += THREADS) mstage[i] = 0;
+            __syncthreads();
+            walk_positions<THREADS>(g, m, d, t1, t2, true, true,
+                                    [&](uint32_t e2, uint32_t p, uint32_t sg) {
+                                        const uint32_t v = compact_find(ckeys, cidx, m.HC, m.log2hc, e2 >> 1);
+                                        const uint32_t idx = ((e2 & 1u) ^ sg) ? (v >> 16) : (v & 0xffffu);
+                                        if (idx)
+                                            atomicOr(&mstage[(idx - 1) * nw + (p >> 5) - w0], 1u << (p & 31));
+                                    },
+                                    32 * w0, 32 * (w0 + nw));
+            __syncthreads();
+            if (nw == W) {
+                for (uint32_t i = tid; i < slab; i += THREADS) P.ws.masks[moff + i] = mstage[i];
+            } else {
+                for (uint32_t i = tid; i < slab; i += THREADS) {
+                    const uint32_t c = i / nw;
+                    P.ws.masks[moff + (uint64_t)c * W + w0 + (i - c * nw)] = mstage[i];
+                }
+            }
+            __syncthreads();
+        }
         for (uint32_t i = tid; i < k; i += THREADS) P.ws.cands[coff + i] = m.vc[i] & 0x7fffffffu;
         if (tid == 0) {
             AnchorRec a;
@@ -629,7 +670,8 @@ __host__ __device__ constexpr uint32_t compact_slots(uint32_t kmax, uint32_t H)
 template <int THREADS, int H, int MAXD, int KMAX, bool PACKED>
 __global__ void __launch_bounds__(THREADS) k_pair_lds(PairArgs P)
 {
-    __shared__ uint32_t region[2 * H], pst[MAXD], pln[MAXD], vc[KMAX];
+    __shared__ __align__(16) uint32_t region[2 * H];
+    __shared__ uint32_t pst[MAXD], pln[MAXD], vc[KMAX];
     __shared__ PairShared sh;
     constexpr uint32_t HC = compact_slots(KMAX, H);
     PairMem m;
@@ -643,7 +685,8 @@ __global__ void __launch_bounds__(THREADS) k_pair_lds(PairArgs P)
 template <int THREADS, int H, int KMAX, bool PACKED>
 __global__ void __launch_bounds__(THREADS) k_pair_big(PairArgs P)
 {
-    __shared__ uint32_t region[2 * H], vc[KMAX];
+    __shared__ __align__(16) uint32_t region[2 * H];
+    __shared__ uint32_t vc[KMAX];
     __shared__ PairShared sh;
     constexpr uint32_t HC = compact_slots(KMAX, H);
     PairMem m;
@@ -715,15 +758,6 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t x)
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint64_t wave_max64(uint64_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint64_t w = __shfl_xor(v, o, kWave);
-        v = w > v ? w : v;
-    }
-    return v;
-}
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {

@@ -656,7 +656,8 @@ void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set)
     const uint32_t HC = std::min(HD, 1u << 20);
     const int lgc = std::min(lgd, 20);
     if (!w.gtab.p || w.gH < HC) {
-        uint64_t words = 2ull * HC + 2ull * maxd + kmax + 64;
+        // per-block regions start 16-byte aligned (the table is read 4 slots at a time)
+        uint64_t words = (2ull * HC + 2ull * maxd + kmax + 64 + 3) & ~3ull;
         uint32_t blocks = (uint32_t)std::max<uint64_t>(
             1, std::min<uint64_t>(ctx->num_cus, (2ull << 30) / (words * 4)));
         w.gtab.ensure(al, words * 4 * blocks);
@@ -664,7 +665,7 @@ void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set)
         w.gtab_words = words; w.gtab_blocks = blocks;
     }
     if (!w.dtab.p || w.dH < HD) {
-        uint64_t words = 2ull * HD + 2ull * maxd + kmax + 64;
+        uint64_t words = (2ull * HD + 2ull * maxd + kmax + 64 + 3) & ~3ull;
         uint32_t blocks = (uint32_t)std::max<uint64_t>(
             1, std::min<uint64_t>(16, (1ull << 30) / (words * 4)));
         w.dtab.ensure(al, words * 4 * blocks);
