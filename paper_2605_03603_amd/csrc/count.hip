@@ -108,18 +108,6 @@ __device__ __forceinline__ bool hash_add(uint32_t *keys, uint32_t *vals, uint32_
     return false;
 }
 
-// Slot of a key known to be present; H if absent (never expected).
-__device__ __forceinline__ uint32_t hash_find(const uint32_t *keys, uint32_t H, int log2h,
-                                              uint32_t x)
-{
-    uint32_t h = hash_slot(x, log2h);
-    for (uint32_t probe = 0; probe < H; probe++) {
-        if (keys[h] == x) return h;
-        h = (h + 1) & (H - 1);
-    }
-    return H;
-}
-
 // Columns per work unit for masks of w32 words.
 __host__ __device__ __forceinline__ uint32_t unit_cols(uint32_t w32, uint32_t base)
 {
@@ -219,65 +207,12 @@ __device__ __forceinline__ void hash_inc(const uint32_t *keys, uint32_t *vals, u
 // of the (key, count) layout in the same memory.
 constexpr uint32_t kKeyMask = 0xffffffu;
 
-__device__ __forceinline__ void therm_inc(uint32_t *slot, uint32_t b0)
-{
-    const uint32_t old = atomicOr(slot, b0);
-    if (old & b0) {
-        const uint32_t old1 = atomicOr(slot, b0 << 1);
-        if (old1 & (b0 << 1)) atomicOr(slot, b0 << 2);
-    }
-}
-
-__device__ __forceinline__ bool phash_add(uint32_t *slots, uint32_t H, int log2h, uint32_t x,
-                                          uint32_t cls, volatile uint32_t *over)
-{
-    const uint32_t b0 = 1u << (24 + 3 * cls);
-    uint32_t h = hash_slot(x, log2h);
-    const uint32_t max_probe = H < 256 ? H : 256;
-    for (uint32_t probe = 0; probe < max_probe; probe++) {
-        uint32_t v = __atomic_load_n(&slots[h], __ATOMIC_RELAXED);
-        if (v == kEmpty) {
-            const uint32_t old = atomicCAS(&slots[h], kEmpty, x | b0);
-            if (old == kEmpty) return true;
-            v = old;
-        }
-        if ((v & kKeyMask) == x) { therm_inc(&slots[h], b0); return false; }
-        h = (h + 1) & (H - 1);
-    }
-    *over = 1;
-    return false;
-}
-
-__device__ __forceinline__ void phash_inc(uint32_t *slots, uint32_t H, int log2h, uint32_t x,
-                                          uint32_t cls)
-{
-    uint32_t h = hash_slot(x, log2h);
-    for (uint32_t probe = 0; probe < H; probe++) {
-        const uint32_t v = slots[h];
-        if (v == kEmpty) return;
-        if ((v & kKeyMask) == x) { therm_inc(&slots[h], 1u << (24 + 3 * cls)); return; }
-        h = (h + 1) & (H - 1);
-    }
-}
-
-// Packed candidate indices of a partner in the compact table (0 if absent).
-__device__ __forceinline__ uint32_t compact_find(const uint32_t *ckeys, const uint32_t *cidx,
-                                                 uint32_t HC, int log2hc, uint32_t x)
-{
-    uint32_t h = hash_slot(x, log2hc);
-    for (uint32_t probe = 0; probe < HC; probe++) {
-        const uint32_t k = ckeys[h];
-        if (k == x) return cidx[h];
-        if (k == kEmpty) return 0;
-        h = (h + 1) & (HC - 1);
-    }
-    return 0;
-}
-
-// Visit the wedges of the anchor's positions: the ordinary positions one
-// wave per position, the two longest suffixes spread over the whole
-// workgroup. f(entry, position, sign of (anchor, v)) is called per wedge;
-// every lane keeps kUnroll independent loads in flight.
+// Visit the wedges of the anchor's positions in [p0, p1): the ordinary
+// positions one wave per position, the two longest suffixes spread over the
+// whole workgroup. f(e2, pos, sg) receives kUnroll wedges per lane at once
+// (entry, position, sign of (anchor, v); entry kEmpty for an idle slot), so
+// that it can issue their first hash probes together. The loads are clamped
+// to valid entries and all in flight together.
 template <int THREADS, typename F>
 __device__ __forceinline__ void walk_positions(const CsrView &g, const PairMem &m, uint32_t d,
                                                uint32_t t1, uint32_t t2, bool ordinary,
@@ -287,23 +222,24 @@ __device__ __forceinline__ void walk_positions(const CsrView &g, const PairMem &
     constexpr int NW = THREADS / kWave;
     const int tid = threadIdx.x, lane = __lane_id(), wv = tid / kWave;
     if (p1 > d) p1 = d;
+    uint32_t e2[kUnroll], pp[kUnroll], sg[kUnroll];
     if (ordinary) {
         for (uint32_t p = p0 + wv; p < p1; p += NW) {
             if (p == t1 || p == t2) continue;
             const uint32_t ln = m.pln[p];
             const uint32_t len = ln & 0x7fffffffu;
             if (!len) continue;
-            const uint32_t st = m.pst[p], sg = ln >> 31;
+            const uint32_t st = m.pst[p];
             for (uint32_t j0 = 0; j0 < len; j0 += kWave * kUnroll) {
-                uint32_t e2[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; u++) {
                     const uint32_t j = j0 + u * kWave + lane;
-                    e2[u] = j < len ? g.o_adj[st + j] : kEmpty;
+                    const uint32_t e = g.o_adj[st + min(j, len - 1)];
+                    e2[u] = j < len ? e : kEmpty;
+                    pp[u] = p;
+                    sg[u] = ln >> 31;
                 }
-#pragma unroll
-                for (int u = 0; u < kUnroll; u++)
-                    if (e2[u] != kEmpty) f(e2[u], p, sg);
+                f(e2, pp, sg);
             }
         }
     }
@@ -311,25 +247,79 @@ __device__ __forceinline__ void walk_positions(const CsrView &g, const PairMem &
         const uint32_t l1 = (t1 >= p0 && t1 < p1) ? (m.pln[t1] & 0x7fffffffu) : 0;
         const uint32_t l2 = (t2 >= p0 && t2 < p1) ? (m.pln[t2] & 0x7fffffffu) : 0;
         const uint32_t tot = l1 + l2;
+        const uint32_t s1 = l1 ? m.pst[t1] : 0, s2 = l2 ? m.pst[t2] : 0;
+        const uint32_t g1 = l1 ? m.pln[t1] >> 31 : 0, g2 = l2 ? m.pln[t2] >> 31 : 0;
         for (uint32_t j0 = 0; j0 < tot; j0 += THREADS * kUnroll) {
-            uint32_t e2[kUnroll], pp[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; u++) {
                 const uint32_t j = j0 + u * THREADS + tid;
-                e2[u] = kEmpty;
-                pp[u] = 0;
-                if (j < tot) {
-                    const uint32_t p = j < l1 ? t1 : t2;
-                    const uint32_t jj = j < l1 ? j : j - l1;
-                    e2[u] = g.o_adj[m.pst[p] + jj];
-                    pp[u] = p;
-                }
+                const uint32_t jc = min(j, tot - 1);
+                const bool first = jc < l1;
+                const uint32_t e = g.o_adj[first ? s1 + jc : s2 + (jc - l1)];
+                e2[u] = j < tot ? e : kEmpty;
+                pp[u] = first ? t1 : t2;
+                sg[u] = first ? g1 : g2;
             }
-#pragma unroll
-            for (int u = 0; u < kUnroll; u++)
-                if (e2[u] != kEmpty) f(e2[u], pp[u], m.pln[pp[u]] >> 31);
+            f(e2, pp, sg);
         }
     }
+}
+
+// Thermometer update of one class in a packed slot whose value was seen as
+// `cur`: set the lowest bit of the class not yet set (a concurrent hit that
+// took it moves this one to the next bit). b0 is the class's first bit.
+__device__ __forceinline__ void therm_from(uint32_t *slot, uint32_t cur, uint32_t b0)
+{
+    uint32_t bit = b0;
+#pragma unroll
+    for (int i = 0; i < 3; i++, bit <<= 1) {
+        if (cur & bit) continue;
+        const uint32_t o2 = atomicOr(slot, bit);
+        if (!(o2 & bit)) return;
+        cur = o2;
+    }
+}
+
+// Probe runs continued after a first probe at slot h that met another key.
+__device__ __forceinline__ bool phash_add_from(uint32_t *slots, uint32_t H, uint32_t h, uint32_t x,
+                                               uint32_t b0, volatile uint32_t *over)
+{
+    const uint32_t max_probe = H < 256 ? H : 256;
+    for (uint32_t probe = 1; probe < max_probe; probe++) {
+        h = (h + 1) & (H - 1);
+        uint32_t v = __atomic_load_n(&slots[h], __ATOMIC_RELAXED);
+        if (v == kEmpty) {
+            const uint32_t old = atomicCAS(&slots[h], kEmpty, x | b0);
+            if (old == kEmpty) return true;
+            v = old;
+        }
+        if ((v & kKeyMask) == x) { therm_from(&slots[h], v, b0); return false; }
+    }
+    *over = 1;
+    return false;
+}
+
+__device__ __forceinline__ void phash_inc_from(uint32_t *slots, uint32_t H, uint32_t h, uint32_t x,
+                                               uint32_t b0)
+{
+    for (uint32_t probe = 1; probe < H; probe++) {
+        h = (h + 1) & (H - 1);
+        const uint32_t v = __atomic_load_n(&slots[h], __ATOMIC_RELAXED);
+        if (v == kEmpty) return;
+        if ((v & kKeyMask) == x) { therm_from(&slots[h], v, b0); return; }
+    }
+}
+
+__device__ __forceinline__ uint32_t compact_find_from(const uint32_t *ckeys, const uint32_t *cidx,
+                                                      uint32_t HC, uint32_t h, uint32_t x)
+{
+    for (uint32_t probe = 1; probe < HC; probe++) {
+        h = (h + 1) & (HC - 1);
+        const uint32_t k = ckeys[h];
+        if (k == x) return cidx[h];
+        if (k == kEmpty) return 0;
+    }
+    return 0;
 }
 
 // The per-anchor procedure shared by all tiers (LDS storage for tiers A and
@@ -451,14 +441,40 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
         {
             uint32_t fresh = 0;
             walk_positions<THREADS>(g, m, d, t1, t2, true, false,
-                                    [&](uint32_t e2, uint32_t, uint32_t sg) {
-                                        my_wedges++;
-                                        const uint32_t cls = (e2 & 1u) ^ sg;
-                                        if (PACKED)
-                                            fresh += phash_add(m.region, HS, log2hs, e2 >> 1, cls, &sh.over);
-                                        else
-                                            fresh += hash_add(keys, vals, H, m.log2h, e2 >> 1,
-                                                              cls ? 0x10000u : 1u, &sh.over);
+                                    [&](const uint32_t (&e2)[kUnroll], const uint32_t (&)[kUnroll],
+                                        const uint32_t (&sg)[kUnroll]) {
+                                        if (PACKED) {
+                                            // first probes together: a CAS that inserts or
+                                            // returns the slot's value
+                                            uint32_t hs[kUnroll], old[kUnroll];
+#pragma unroll
+                                            for (int u = 0; u < kUnroll; u++) {
+                                                const uint32_t b0 = 1u << (24 + 3 * ((e2[u] & 1u) ^ sg[u]));
+                                                hs[u] = hash_slot(e2[u] >> 1, log2hs);
+                                                old[u] = e2[u] != kEmpty
+                                                             ? atomicCAS(&m.region[hs[u]], kEmpty, (e2[u] >> 1) | b0)
+                                                             : 0u;
+                                            }
+#pragma unroll
+                                            for (int u = 0; u < kUnroll; u++) {
+                                                if (e2[u] == kEmpty) continue;
+                                                my_wedges++;
+                                                const uint32_t x = e2[u] >> 1;
+                                                const uint32_t b0 = 1u << (24 + 3 * ((e2[u] & 1u) ^ sg[u]));
+                                                if (old[u] == kEmpty) fresh++;
+                                                else if ((old[u] & kKeyMask) == x) therm_from(&m.region[hs[u]], old[u], b0);
+                                                else fresh += phash_add_from(m.region, HS, hs[u], x, b0, &sh.over);
+                                            }
+                                        } else {
+#pragma unroll
+                                            for (int u = 0; u < kUnroll; u++) {
+                                                if (e2[u] == kEmpty) continue;
+                                                my_wedges++;
+                                                const uint32_t cls = (e2[u] & 1u) ^ sg[u];
+                                                fresh += hash_add(keys, vals, H, m.log2h, e2[u] >> 1,
+                                                                  cls ? 0x10000u : 1u, &sh.over);
+                                            }
+                                        }
                                     });
             const uint32_t nf = wave_sum<uint32_t>(fresh);
             if (lane == 0 && nf && atomicAdd(&sh.used, nf) + nf > limit) sh.over = 1;
@@ -467,14 +483,35 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
         bool defer = sh.over != 0;
         if (!defer) {
             walk_positions<THREADS>(g, m, d, t1, t2, false, true,
-                                    [&](uint32_t e2, uint32_t, uint32_t sg) {
-                                        my_wedges++;
-                                        const uint32_t cls = (e2 & 1u) ^ sg;
-                                        if (PACKED)
-                                            phash_inc(m.region, HS, log2hs, e2 >> 1, cls);
-                                        else
-                                            hash_inc(keys, vals, H, m.log2h, e2 >> 1,
-                                                     cls ? 0x10000u : 1u);
+                                    [&](const uint32_t (&e2)[kUnroll], const uint32_t (&)[kUnroll],
+                                        const uint32_t (&sg)[kUnroll]) {
+                                        if (PACKED) {
+                                            uint32_t hs[kUnroll], v[kUnroll];
+#pragma unroll
+                                            for (int u = 0; u < kUnroll; u++) {
+                                                hs[u] = hash_slot(e2[u] >> 1, log2hs);
+                                                v[u] = e2[u] != kEmpty ? __atomic_load_n(&m.region[hs[u]], __ATOMIC_RELAXED)
+                                                                       : kEmpty;
+                                            }
+#pragma unroll
+                                            for (int u = 0; u < kUnroll; u++) {
+                                                if (e2[u] == kEmpty) continue;
+                                                my_wedges++;
+                                                if (v[u] == kEmpty) continue;
+                                                const uint32_t x = e2[u] >> 1;
+                                                const uint32_t b0 = 1u << (24 + 3 * ((e2[u] & 1u) ^ sg[u]));
+                                                if ((v[u] & kKeyMask) == x) therm_from(&m.region[hs[u]], v[u], b0);
+                                                else phash_inc_from(m.region, HS, hs[u], x, b0);
+                                            }
+                                        } else {
+#pragma unroll
+                                            for (int u = 0; u < kUnroll; u++) {
+                                                if (e2[u] == kEmpty) continue;
+                                                my_wedges++;
+                                                const uint32_t cls = (e2[u] & 1u) ^ sg[u];
+                                                hash_inc(keys, vals, H, m.log2h, e2[u] >> 1, cls ? 0x10000u : 1u);
+                                            }
+                                        }
                                     });
             __syncthreads();
             // phase 2: classes with >= 3 members become virtual candidates
@@ -612,11 +649,26 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
             for (uint32_t i = tid; i < slab; i += THREADS) mstage[i] = 0;
             __syncthreads();
             walk_positions<THREADS>(g, m, d, t1, t2, true, true,
-                                    [&](uint32_t e2, uint32_t p, uint32_t sg) {
-                                        const uint32_t v = compact_find(ckeys, cidx, m.HC, m.log2hc, e2 >> 1);
-                                        const uint32_t idx = ((e2 & 1u) ^ sg) ? (v >> 16) : (v & 0xffffu);
-                                        if (idx)
-                                            atomicOr(&mstage[(idx - 1) * nw + (p >> 5) - w0], 1u << (p & 31));
+                                    [&](const uint32_t (&e2)[kUnroll], const uint32_t (&pp)[kUnroll],
+                                        const uint32_t (&sg)[kUnroll]) {
+                                        uint32_t hc[kUnroll], kk[kUnroll], ci[kUnroll];
+#pragma unroll
+                                        for (int u = 0; u < kUnroll; u++) {
+                                            hc[u] = hash_slot(e2[u] >> 1, m.log2hc);
+                                            kk[u] = ckeys[hc[u]];
+                                            ci[u] = cidx[hc[u]];
+                                        }
+#pragma unroll
+                                        for (int u = 0; u < kUnroll; u++) {
+                                            if (e2[u] == kEmpty || kk[u] == kEmpty) continue;
+                                            const uint32_t x = e2[u] >> 1;
+                                            const uint32_t v = kk[u] == x ? ci[u]
+                                                                          : compact_find_from(ckeys, cidx, m.HC, hc[u], x);
+                                            const uint32_t idx = ((e2[u] & 1u) ^ sg[u]) ? (v >> 16) : (v & 0xffffu);
+                                            const uint32_t p = pp[u];
+                                            if (idx)
+                                                atomicOr(&mstage[(idx - 1) * nw + (p >> 5) - w0], 1u << (p & 31));
+                                        }
                                     },
                                     32 * w0, 32 * (w0 + nw));
             __syncthreads();
@@ -757,7 +809,6 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t x)
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
     return ((uint64_t)hi << 32) | lo;
 }
-
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
