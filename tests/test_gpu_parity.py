@@ -331,3 +331,28 @@ def test_config2_full(ctx):
     assert hashlib.sha256(pv.astype("<i8").tobytes()).hexdigest() == gold["per_v_sha256"]
     for flags in (1 << 4, 1 << 5):
         assert ctx.count_global(build(ctx, g, flags)) == gold["total"]
+
+
+def test_config3_full(ctx):
+    """Config 3 at full size (2M x 500k, 40M edges): per-vertex values of both
+    sides on sampled vertices against the oracle's, each side anchored on
+    itself; U- and V-anchored totals equal; per-vertex sums are 3 x total."""
+    gold = golden("cfg3_seed1_sample.json")
+    say("config3 full: generate")
+    g = G.config3(1)
+    assert g.m == gold["m"]
+    say("config3 full: U anchored")
+    hu = build(ctx, g, 1 << 4)
+    pu, tu = ctx.count_per_vertex(hu, 0)
+    for k, v in gold["per_u_sample"].items():
+        assert int(pu[int(k)]) == v, k
+    assert int(pu.sum()) == 3 * tu
+    assert ctx.count_global(hu) == tu
+    hu.free()
+    say("config3 full: V anchored")
+    hv = build(ctx, g, 1 << 5)
+    pv, tv = ctx.count_per_vertex(hv, 1)
+    assert tv == tu
+    for k, v in gold["per_v_sample"].items():
+        assert int(pv[int(k)]) == v, k
+    assert int(pv.sum()) == 3 * tu
