@@ -1399,25 +1399,35 @@ __device__ __forceinline__ v4i32 spread16(uint32_t x)
     return r;
 }
 
-// The 16-bit pieces that lane group g feeds into the K-chunks of mask m:
-// chunk t takes word 2 t + (g >> 1), half g & 1 (zero past the mask width
-// or for an invalid row / column). The loads are unconditional (clamped to
-// valid words) so that all of them are in flight together.
+// Lane group g feeds K-chunk t the 16-bit piece of mask word 2 t + (g >> 1),
+// half g & 1 (zero past the mask width or for an invalid row / column).
+// The raw words are loaded unconditionally (clamped to valid words) and
+// reduced to pieces only where they are used, so that a prefetch stays in
+// flight until then.
 template <int W>
-__device__ __forceinline__ void mask_pieces(const uint32_t *m, bool valid, uint32_t g,
-                                            uint32_t (&pc)[(W + 1) / 2])
+__device__ __forceinline__ void mask_words(const uint32_t *m, uint32_t g, uint32_t (&raw)[(W + 1) / 2])
 {
 #pragma unroll
     for (int t = 0; t < (W + 1) / 2; t++) {
         const uint32_t w = 2 * t + (g >> 1);
-        const uint32_t v = m[w < (uint32_t)W ? w : (uint32_t)W - 1];
-        pc[t] = (valid && w < (uint32_t)W) ? (v >> (16 * (g & 1u))) & 0xffffu : 0u;
+        raw[t] = m[w < (uint32_t)W ? w : (uint32_t)W - 1];
     }
+}
+
+template <int W>
+__device__ __forceinline__ uint32_t mask_piece(uint32_t raw, int t, uint32_t g, bool valid)
+{
+    const uint32_t w = 2 * t + (g >> 1);
+    const uint32_t keep = (valid && w < (uint32_t)W) ? 0xffffu : 0u;
+    return (raw >> (16 * (g & 1u))) & keep;
 }
 
 // Sum over the unit's pairs (j < i) of C(|M_i n M_j|, 3), masks of W words.
 // The 64 rows go in passes of SBP 16-row blocks, so that the spread row
-// operands (SBP x ceil(W/2) x 4 registers) stay in registers.
+// operands (SBP x ceil(W/2) x 4 registers) stay in registers. The column
+// tiles are software-pipelined: the products of tile t + 1 are issued before
+// the epilogue of tile t reads its accumulators (no waiting on the matrix
+// cores), and column words are loaded two tiles ahead.
 template <int W>
 __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
                                   const uint32_t *__restrict__ masks)
@@ -1428,10 +1438,9 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
     const uint32_t g = lane >> 4, r16 = lane & 15u;
     const uint32_t *M = masks + a.mask_off;
     const uint32_t rbase = un.rb * kWave;
-    auto col_pieces = [&](uint32_t j0, uint32_t (&pc)[NC]) {
+    auto col_words = [&](uint32_t j0, uint32_t (&raw)[NC]) {
         const uint32_t j = j0 + r16;
-        const bool vj = j < un.c1;
-        mask_pieces<W>(M + (uint64_t)(vj ? j : un.c1 - 1) * W, vj, g, pc);
+        mask_words<W>(M + (uint64_t)(j < un.c1 ? j : un.c1 - 1) * W, g, raw);
     };
     uint64_t sum = 0;
 #pragma unroll 1
@@ -1442,29 +1451,27 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
 #pragma unroll
         for (int sb = 0; sb < SBP; sb++) {
             const uint32_t i = pbase + 16 * sb + r16;
-            uint32_t pc[NC];
-            mask_pieces<W>(M + (uint64_t)(i < a.k ? i : a.k - 1) * W, i < a.k, g, pc);
+            uint32_t raw[NC];
+            mask_words<W>(M + (uint64_t)(i < a.k ? i : a.k - 1) * W, g, raw);
 #pragma unroll
-            for (int t = 0; t < NC; t++) A[sb][t] = spread16(pc[t]);
+            for (int t = 0; t < NC; t++) A[sb][t] = spread16(mask_piece<W>(raw[t], t, g, i < a.k));
         }
-        // column pieces of the next 16-column tile are loaded one tile ahead
-        uint32_t cur[NC], nxt[NC];
-        col_pieces(un.c0, cur);
-        for (uint32_t j0 = un.c0; j0 < un.c1; j0 += 16) {
-            if (j0 + 16 < un.c1) col_pieces(j0 + 16, nxt);
-            v4i32 acc[SBP];
+        auto products = [&](const uint32_t (&raw)[NC], uint32_t j0, v4i32 (&acc)[SBP]) {
+            const bool vj = j0 + r16 < un.c1;
 #pragma unroll
             for (int sb = 0; sb < SBP; sb++) acc[sb] = (v4i32){-1, -1, -1, -1};
 #pragma unroll
             for (int t = 0; t < NC; t++) {
-                const v4i32 B = spread16(cur[t]);
+                const v4i32 B = spread16(mask_piece<W>(raw[t], t, g, vj));
 #pragma unroll
                 for (int sb = 0; sb < SBP; sb++)
                     acc[sb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[sb][t], B, acc[sb], 0, 0, 0);
             }
-            // lane holds rows pbase + 16 sb + 4 g + e of column j; only j < i
-            // counts. -1 <= D < 32 W <= 512: both products fit the 24-bit
-            // multiply-add, which the compiler cannot prove by itself.
+        };
+        // lane holds rows pbase + 16 sb + 4 g + e of column j0 + r16; only
+        // j < i counts. -1 <= D < 32 W <= 512: both products fit the 24-bit
+        // multiply-add, which the compiler cannot prove by itself.
+        auto epilogue = [&](const v4i32 (&acc)[SBP], uint32_t j0) -> uint32_t {
             const uint32_t j = j0 + r16;
             uint32_t s32 = 0;
             if (j0 + 16 <= pbase) {
@@ -1484,16 +1491,40 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
                         s32 = mad_i24(D, mad_i24(D, D, -1), s32);
                     }
             }
-            sum += s32;
-#pragma unroll
-            for (int t = 0; t < NC; t++) cur[t] = nxt[t];
+            return s32;
+        };
+        uint32_t w0[NC], w1[NC];
+        v4i32 acc0[SBP], acc1[SBP];
+        uint32_t j0 = un.c0;
+        col_words(j0, w0);
+        if (j0 + 16 < un.c1) col_words(j0 + 16, w1);
+        products(w0, j0, acc0);
+        for (;;) {
+            // acc0: tile j0; w1: words of tile j0 + 16
+            bool more = j0 + 16 < un.c1;
+            if (more) {
+                if (j0 + 32 < un.c1) col_words(j0 + 32, w0);
+                products(w1, j0 + 16, acc1);
+            }
+            sum += epilogue(acc0, j0);
+            if (!more) break;
+            j0 += 16;
+            // acc1: tile j0; w0: words of tile j0 + 16
+            more = j0 + 16 < un.c1;
+            if (more) {
+                if (j0 + 32 < un.c1) col_words(j0 + 32, w1);
+                products(w0, j0 + 16, acc0);
+            }
+            sum += epilogue(acc1, j0);
+            if (!more) break;
+            j0 += 16;
         }
     }
     return sum / 6;
 }
 
 template <int MODE, bool WIDE>
-__global__ void __launch_bounds__(kTThreads, MODE == 1 ? 2 : (MODE == 0 && !WIDE ? 3 : 5)) k_triplet(TriArgs T)
+__global__ void __launch_bounds__(kTThreads, MODE == 1 || (MODE == 0 && !WIDE) ? 2 : 5) k_triplet(TriArgs T)
 {
     __shared__ uint32_t c3[kC3Max + 1];
     __shared__ unsigned long long colacc_all[MODE == 1 ? kTThreads / kWave : 1][MODE == 1 ? kMaxChunk : 1];
