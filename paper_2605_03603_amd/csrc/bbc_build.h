@@ -33,7 +33,7 @@ struct BuildArgs {
     uint32_t *max_deg_u, *max_deg_v;
     // ranking
     uint32_t max_deg_s;            // max degree over S slots (key radix)
-    int rank_bits, s_bits, o_bits, obits;
+    int rank_bits, s_bits, o_bits;
     uint64_t *key0, *key1;
     uint32_t *val0, *val1;
     uint32_t *deg_o;               // [NO]

@@ -18,7 +18,7 @@ constexpr int kWave = 64;
 // rank means a higher priority; all graphs' S vertices are concatenated
 // (graph g owns global ranks [s_base, s_base + n_s)) and so are O vertices.
 //
-//   s_off[NS+1], s_adj[M]: neighbours of S vertex r, sorted by O index;
+//   s_off[NS+1], s_adj[M]: neighbours of S vertex r (in input order);
 //                          entry = (global O index << 1) | (sign < 0)
 //   o_off[NO+1], o_adj[M]: neighbours of O vertex v, sorted by rank;
 //                          entry = (global rank << 1) | (sign < 0)

@@ -151,24 +151,21 @@ __global__ void __launch_bounds__(kT) k_edge_keys(BuildArgs a)
         const GraphDesc &d = a.desc[g];
         uint32_t u = a.eu[e], v = a.ev[e];
         uint32_t s_loc = d.side ? v : u, o_loc = d.side ? u : v;
-        uint32_t r = a.rank_of[d.s_base + s_loc];
-        a.key0[e] = ((uint64_t)r << a.obits) | o_loc;
+        a.key0[e] = a.rank_of[d.s_base + s_loc];
         a.val0[e] = ((d.o_base + o_loc) << 1) | neg;
     }
 }
 
-// Sorted by (rank, O id): emit s_adj, flag repeated pairs, and prepare the
-// (O index -> S position) keys whose stable sort yields the O-side lists in
-// rank order. o_ent[t] is the O-side entry of S position t.
+// Sorted by rank (stably: a list keeps the input order): emit s_adj and
+// prepare the (O index -> S position) keys whose stable sort yields the
+// O-side lists in rank order. o_ent[t] is the O-side entry of S position t.
 __global__ void __launch_bounds__(kT) k_s_finish(BuildArgs a)
 {
     for (uint64_t t = (uint64_t)blockIdx.x * kT + threadIdx.x; t < a.M;
          t += (uint64_t)gridDim.x * kT) {
-        uint64_t key = a.key0[t];
-        uint32_t val = a.val0[t];
+        const uint32_t r = (uint32_t)a.key0[t];
+        const uint32_t val = a.val0[t];
         a.s_adj[t] = val;
-        if (t > 0 && a.key0[t - 1] == key) atomicOr(a.err, kErrDup);
-        uint32_t r = (uint32_t)(key >> a.obits);
         a.key1[t] = val >> 1;
         a.val1[t] = (uint32_t)t;
         a.o_ent[t] = (r << 1) | (val & 1);
@@ -186,6 +183,9 @@ __global__ void __launch_bounds__(kT) k_o_finish(BuildArgs a)
         const uint32_t ent = a.o_ent[ts];
         a.o_adj[t] = ent;
         const uint32_t v = (uint32_t)a.key1[t];
+        // a repeated (u, v) pair: equal neighbours in one O list are adjacent
+        if (t > 0 && (uint32_t)a.key1[t - 1] == v && (a.o_ent[a.val1[t - 1]] >> 1) == (ent >> 1))
+            atomicOr(a.err, kErrDup);
         uint32_t len = (uint32_t)(a.o_off[v + 1] - t - 1);
         if (len < 2) len = 0;
         a.s_suf[ts] = make_uint2((uint32_t)t + 1, len | ((ent & 1u) << 31));

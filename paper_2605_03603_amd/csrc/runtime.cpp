@@ -506,7 +506,6 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
 
     // side choice and S/O numbering
     uint64_t ns = 0, no = 0;
-    uint32_t max_no = 0;
     std::vector<uint32_t> sbase(G), obase(G);
     bool any_u = false, any_v = false;
     const bool auto_side = !(in.flags & (BBC_ANCHOR_U | BBC_ANCHOR_V | BBC_ANCHOR_SMALLER));
@@ -530,7 +529,6 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
         d.s_base = (uint32_t)ns; d.o_base = (uint32_t)no;
         sbase[g] = d.s_base; obase[g] = d.o_base;
         ns += d.n_s; no += d.n_o;
-        max_no = std::max(max_no, d.n_o);
         (d.side ? any_v : any_u) = true;
     }
     set->NS = (uint32_t)ns;
@@ -574,8 +572,9 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
     a.NS = (uint32_t)NS; a.NO = (uint32_t)NO;
     a.max_deg_s = max_deg_s;
     a.rank_bits = bit_width((uint64_t)G * (max_deg_s + 1ull) - 1);
-    a.obits = max_no > 1 ? bit_width(max_no - 1) : 0;
-    a.s_bits = (NS > 1 ? bit_width(NS - 1) : 0) + a.obits;
+    // S lists are sorted by rank only (order within a list does not matter);
+    // the stable sort by O index that follows puts every O list in rank order
+    a.s_bits = NS > 1 ? bit_width(NS - 1) : 0;
     a.o_bits = NO > 1 ? bit_width(NO - 1) : 0;
     a.key0 = key0.as<uint64_t>(); a.key1 = key1.as<uint64_t>();
     a.val0 = val0.as<uint32_t>(); a.val1 = val1.as<uint32_t>();
