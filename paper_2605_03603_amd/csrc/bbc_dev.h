@@ -142,6 +142,17 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t w = __shfl_up(v, o, kWave);
+        if (lane >= (uint32_t)o) v += w;
+    }
+    return v;
+}
+
 __device__ __forceinline__ uint64_t wave_max64(uint64_t v)
 {
 #pragma unroll

@@ -224,23 +224,45 @@ __device__ __forceinline__ void walk_positions(const CsrView &g, const PairMem &
     if (p1 > d) p1 = d;
     uint32_t e2[kUnroll], pp[kUnroll], sg[kUnroll];
     if (ordinary) {
-        for (uint32_t p = p0 + wv; p < p1; p += NW) {
-            if (p == t1 || p == t2) continue;
-            const uint32_t ln = m.pln[p];
-            const uint32_t len = ln & 0x7fffffffu;
-            if (!len) continue;
-            const uint32_t st = m.pst[p];
-            for (uint32_t j0 = 0; j0 < len; j0 += kWave * kUnroll) {
-#pragma unroll
-                for (int u = 0; u < kUnroll; u++) {
-                    const uint32_t j = j0 + u * kWave + lane;
-                    const uint32_t e = g.o_adj[st + min(j, len - 1)];
-                    e2[u] = j < len ? e : kEmpty;
-                    pp[u] = p;
-                    sg[u] = ln >> 31;
-                }
-                f(e2, pp, sg);
+        // The suffixes are cut into pieces of kPiece wedges, dealt round-robin
+        // to the waves by their global index; each wave finds its pieces from
+        // a prefix sum of piece counts over 64 positions at a time.
+        constexpr uint32_t kPiece = kWave * kUnroll;
+        uint32_t cum_base = 0;
+        for (uint32_t c0 = p0; c0 < p1; c0 += kWave) {
+            const uint32_t p = c0 + lane;
+            uint32_t len = 0, st = 0, ln = 0;
+            if (p < p1 && p != t1 && p != t2) {
+                ln = m.pln[p];
+                len = ln & 0x7fffffffu;
+                st = m.pst[p];
             }
+            const uint32_t np = (len + kPiece - 1) / kPiece;
+            const uint32_t incl = wave_incl_scan(np);
+            const uint32_t cum = cum_base + incl - np;          // first piece of position p
+            const uint32_t first = cum + (uint32_t)((wv + NW - (int)(cum % NW)) % NW);
+            uint64_t todo = ballot64(first < cum + np);
+            while (todo) {
+                const uint32_t l = (uint32_t)__builtin_ctzll(todo);
+                todo &= todo - 1;
+                const uint32_t pl = c0 + l;
+                const uint32_t stl = __shfl(st, l, kWave), lenl = __shfl(len, l, kWave);
+                const uint32_t sgl = __shfl(ln, l, kWave) >> 31;
+                const uint32_t cuml = __shfl(cum, l, kWave), endl = cuml + __shfl(np, l, kWave);
+                for (uint32_t q = __shfl(first, l, kWave); q < endl; q += NW) {
+                    const uint32_t j0 = (q - cuml) * kPiece;
+#pragma unroll
+                    for (int u = 0; u < kUnroll; u++) {
+                        const uint32_t j = j0 + u * kWave + lane;
+                        const uint32_t e = g.o_adj[stl + min(j, lenl - 1)];
+                        e2[u] = j < lenl ? e : kEmpty;
+                        pp[u] = pl;
+                        sg[u] = sgl;
+                    }
+                    f(e2, pp, sg);
+                }
+            }
+            cum_base += __shfl(incl, kWave - 1, kWave);
         }
     }
     if (top) {
@@ -527,14 +549,31 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
                 }
             };
             if (PACKED) {
+                // count this thread's classes, reserve once per wave, then
+                // read the same slots again and write them out
                 const uint4 *R4 = reinterpret_cast<const uint4 *>(m.region);
+                uint32_t cnt = 0;
                 for (uint32_t q = tid; q < HS / 4; q += THREADS) {
                     const uint4 v4 = R4[q];
                     const uint32_t vv[4] = {v4.x, v4.y, v4.z, v4.w};
 #pragma unroll
                     for (int e = 0; e < 4; e++)
-                        if (vv[e] != kEmpty && (vv[e] & (0x24u << 24)))
-                            select(vv[e] & kKeyMask, (vv[e] >> 26) & 1u, (vv[e] >> 29) & 1u);
+                        if (vv[e] != kEmpty) cnt += ((vv[e] >> 26) & 1u) + ((vv[e] >> 29) & 1u);
+                }
+                const uint32_t incl = wave_incl_scan(cnt);
+                uint32_t base = 0;
+                if (lane == kWave - 1 && incl) base = atomicAdd(&sh.nv, incl);
+                uint32_t t = __shfl(base, kWave - 1, kWave) + incl - cnt;
+                for (uint32_t q = tid; cnt && q < HS / 4; q += THREADS) {
+                    const uint4 v4 = R4[q];
+                    const uint32_t vv[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        if (vv[e] == kEmpty) continue;
+                        const uint32_t k = vv[e] & kKeyMask;
+                        if ((vv[e] >> 26) & 1u) { if (t < m.kmax) m.vc[t] = k; t++; }
+                        if ((vv[e] >> 29) & 1u) { if (t < m.kmax) m.vc[t] = k | 0x80000000u; t++; }
+                    }
                 }
             }
             for (uint32_t slot = tid; !PACKED && slot < HS; slot += THREADS) {
@@ -720,7 +759,7 @@ __host__ __device__ constexpr uint32_t compact_slots(uint32_t kmax, uint32_t H)
 }
 
 template <int THREADS, int H, int MAXD, int KMAX, bool PACKED>
-__global__ void __launch_bounds__(THREADS) k_pair_lds(PairArgs P)
+__global__ void __launch_bounds__(THREADS, 2048 / THREADS) k_pair_lds(PairArgs P)
 {
     __shared__ __align__(16) uint32_t region[2 * H];
     __shared__ uint32_t pst[MAXD], pln[MAXD], vc[KMAX];
@@ -810,16 +849,6 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t x)
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
-{
-    const uint32_t lane = __lane_id();
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t w = __shfl_up(v, o, kWave);
-        if (lane >= (uint32_t)o) v += w;
-    }
-    return v;
-}
 
 template <int S, int NWV>
 __global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
