@@ -1462,7 +1462,7 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
                                   const uint32_t *__restrict__ masks)
 {
     constexpr int NC = (W + 1) / 2;          // 64-bit K-chunks
-    constexpr int SBP = W <= 8 ? 4 : 2;      // 16-row blocks per pass
+    constexpr int SBP = W <= 10 ? 4 : 2;     // 16-row blocks per pass
     const uint32_t lane = __lane_id();
     const uint32_t g = lane >> 4, r16 = lane & 15u;
     const uint32_t *M = masks + a.mask_off;
