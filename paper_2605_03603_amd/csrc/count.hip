@@ -72,7 +72,7 @@ __device__ __forceinline__ AnchorRec load_anchor(const AnchorRec *p)
 constexpr uint32_t kEmpty = 0xffffffffu;
 constexpr uint32_t kC3Max = 512;       // C(n,3) table covers masks of up to 16 words
 constexpr uint32_t kRegW = 16;         // widest mask kept in registers per row
-constexpr uint32_t kWideCols = 32;     // unit width (columns) for wider masks
+constexpr uint32_t kWideCols = 64;     // unit width (columns) for wider masks
 constexpr uint32_t kMfmaMaxW = 16;     // widest mask counted on the matrix cores
 constexpr uint32_t kMaskChunk = 1u << 16;   // mask words reserved per workgroup at a time
 constexpr uint32_t kCandChunk = 1u << 13;
@@ -1552,8 +1552,79 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
     return sum / 6;
 }
 
+// Masks wider than 16 words (totals): 64 rows x up to 64 columns per unit.
+// The products of all four column tiles stay in accumulators while the mask
+// words go by in K-blocks of 8 words (4 chunks): a row piece is spread once
+// per K-block and unit, a column piece once per unit. n can reach 32 W here,
+// so the epilogue is 64-bit: n (n - 1) (n - 2) = n ((n^2 + 2) - 3 n), which
+// is 0 for n = 0, 1, 2 with unsigned wrap-around.
+__device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
+                                       const uint32_t *__restrict__ masks)
+{
+    constexpr int KB = 4;                    // chunks per K-block
+    const uint32_t lane = __lane_id();
+    const uint32_t g = lane >> 4, r16 = lane & 15u;
+    const uint32_t W = a.w32;
+    const uint32_t NC = (W + 1) / 2;
+    const uint32_t *M = masks + a.mask_off;
+    const uint32_t rbase = un.rb * kWave;
+    const uint32_t nt = (un.c1 - un.c0 + 15) / 16;   // column tiles (<= 4)
+    const uint32_t half = 16 * (g & 1u);
+    v4i32 acc[4][4];
+#pragma unroll
+    for (int tt = 0; tt < 4; tt++)
+#pragma unroll
+        for (int sb = 0; sb < 4; sb++) acc[tt][sb] = (v4i32){0, 0, 0, 0};
+    for (uint32_t kc = 0; kc < NC; kc += KB) {
+        v4i32 Ab[4][KB];
+#pragma unroll
+        for (int sb = 0; sb < 4; sb++) {
+            const uint32_t i = rbase + 16 * sb + r16;
+            const bool vi = i < a.k;
+            const uint32_t *mr = M + (uint64_t)(vi ? i : a.k - 1) * W;
+#pragma unroll
+            for (int t = 0; t < KB; t++) {
+                const uint32_t w = 2 * (kc + t) + (g >> 1);
+                const uint32_t raw = mr[w < W ? w : W - 1];
+                Ab[sb][t] = spread16((vi && w < W) ? (raw >> half) & 0xffffu : 0u);
+            }
+        }
+#pragma unroll
+        for (int tt = 0; tt < 4; tt++) {
+            if ((uint32_t)tt >= nt) break;
+            const uint32_t j = un.c0 + 16 * tt + r16;
+            const bool vj = j < un.c1;
+            const uint32_t *mc = M + (uint64_t)(vj ? j : un.c1 - 1) * W;
+#pragma unroll
+            for (int t = 0; t < KB; t++) {
+                const uint32_t w = 2 * (kc + t) + (g >> 1);
+                const uint32_t raw = mc[w < W ? w : W - 1];
+                const v4i32 B = spread16((vj && w < W) ? (raw >> half) & 0xffffu : 0u);
+#pragma unroll
+                for (int sb = 0; sb < 4; sb++)
+                    acc[tt][sb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Ab[sb][t], B, acc[tt][sb], 0, 0, 0);
+            }
+        }
+    }
+    uint64_t sum = 0;
+#pragma unroll
+    for (int tt = 0; tt < 4; tt++) {
+        if ((uint32_t)tt >= nt) break;
+        const uint32_t j = un.c0 + 16 * tt + r16;
+#pragma unroll
+        for (int sb = 0; sb < 4; sb++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint32_t n = j < rbase + 16 * sb + 4 * g + e ? (uint32_t)acc[tt][sb][e] : 0u;
+                const uint32_t t2 = n * n + 2u - 3u * n;   // (n - 1)(n - 2) mod 2^32, n < 2^16
+                sum += (uint64_t)n * t2;
+            }
+    }
+    return sum / 6;
+}
+
 template <int MODE, bool WIDE>
-__global__ void __launch_bounds__(kTThreads, MODE == 1 || (MODE == 0 && !WIDE) ? 2 : 5) k_triplet(TriArgs T)
+__global__ void __launch_bounds__(kTThreads, MODE == 1 || MODE == 0 ? 2 : 5) k_triplet(TriArgs T)
 {
     __shared__ uint32_t c3[kC3Max + 1];
     __shared__ unsigned long long colacc_all[MODE == 1 ? kTThreads / kWave : 1][MODE == 1 ? kMaxChunk : 1];
@@ -1608,7 +1679,8 @@ __global__ void __launch_bounds__(kTThreads, MODE == 1 || (MODE == 0 && !WIDE) ?
         }
         uint64_t acc = 0;
         if (WIDE) {
-            acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T);
+            if (MODE == 0) acc = tri_rows_mfma_wide(un, a, T.ws.masks);
+            else acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T);
         } else {
             if (MODE == 0 && a.w32 <= kMfmaMaxW) {
                 switch (a.w32) {
