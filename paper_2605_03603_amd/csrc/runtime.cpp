@@ -294,6 +294,11 @@ struct bbc_ctx {
     std::map<uint64_t, Shape> tuned;   // autotuner cache by size class
     struct SideTime { float ms[2] = {0, 0}; bool tried[2] = {false, false}; };
     std::map<uint64_t, SideTime> side_tune;   // anchor side by graph shape
+    // workspace sizes a count of a graph shape needed (size class and side):
+    // a later graph of the same shape starts from them instead of from the
+    // edge-count guess, which saves a rerun on graphs with heavy anchors
+    struct WsHint { uint64_t masks = 0, cands = 0, units = 0; };
+    std::map<uint64_t, WsHint> ws_hint;
     std::mutex tune_mu;
     hipEvent_t tev[2] = {nullptr, nullptr};
     // serving
@@ -602,10 +607,26 @@ struct CountReq {
     int mode;               // 0 totals, 1 per vertex of S, 2 per vertex of O
 };
 
-void ensure_work(bbc_ctx *ctx, Work &w, const GraphSet &set)
+uint64_t hint_key(const GraphSet &set)
+{
+    const uint64_t side = set.G == 1 ? set.desc[0].side : 2;
+    return ((uint64_t)bit_width(set.NS) << 40) | ((uint64_t)bit_width(set.NO) << 32) |
+           ((uint64_t)bit_width(set.M) << 24) | ((uint64_t)std::min(set.G, 0xffffu) << 2) | side;
+}
+
+void ensure_work(bbc_ctx *ctx, Work &w, GraphSet &set)
 {
     Allocator *al = ctx->al.get();
     uint64_t M = std::max<uint64_t>(set.M, 1);
+    {
+        std::lock_guard<std::mutex> lk(ctx->tune_mu);
+        auto it = ctx->ws_hint.find(hint_key(set));
+        if (it != ctx->ws_hint.end()) {
+            set.hint_masks = std::max(set.hint_masks, it->second.masks);
+            set.hint_cands = std::max(set.hint_cands, it->second.cands);
+            set.hint_units = std::max(set.hint_units, it->second.units);
+        }
+    }
     // records are reserved 16 at a time per wave of the per-wave tier and per
     // workgroup of the others
     const uint64_t agents = (uint64_t)ctx->num_cus * (wave_tier_waves_per_cu() + 8) + 64;
@@ -796,6 +817,13 @@ bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set)
         return false;
     }
     set.hint_units = std::max<uint64_t>(set.hint_units, (uint64_t)c->n_units + c->n_units / 8);
+    {
+        std::lock_guard<std::mutex> lk(ctx->tune_mu);
+        auto &h = ctx->ws_hint[hint_key(set)];
+        h.masks = std::max(h.masks, set.hint_masks);
+        h.cands = std::max(h.cands, set.hint_cands);
+        h.units = std::max(h.units, set.hint_units);
+    }
     ctx->stats.active_anchors = c->n_anchor;
     ctx->stats.virtual_candidates = c->cand_cursor;
     ctx->stats.pair_units = c->n_units;
