@@ -830,7 +830,7 @@ constexpr int kWvTopUnroll = 16;          // and along the two longest suffixes
 constexpr uint64_t kWvMaskChunk = 4096;   // mask words reserved per wave at a time
 constexpr uint64_t kWvCandChunk = 4096;
 constexpr uint32_t kWvProbe = 64;
-constexpr uint32_t kWvGrab = 8;           // anchors taken from the queue at a time
+constexpr uint32_t kWvGrab = 2;           // anchors taken from the queue at a time
 // non-top wedges (and so partners) of an anchor the per-wave tier takes, for
 // a table of S slots
 __host__ __device__ constexpr uint32_t wave_tier_limit(uint32_t S) { return S - S / 4; }
@@ -1670,7 +1670,9 @@ __global__ void __launch_bounds__(kTThreads, MODE == 1 || MODE == 0 ? 2 : 5) k_t
             slice = __builtin_amdgcn_readfirstlane(slice);
             tried = __builtin_amdgcn_readfirstlane(tried);
         }
-        const uint32_t u = u_base + qlo++;
+        // from the end of the list: the records of the later pair tiers (the
+        // widest masks, the heaviest units) start first
+        const uint32_t u = u_base + (n_units - 1 - qlo++);
         const Unit un = load_unit(T.ws.units + u);
         const AnchorRec a = load_anchor(T.ws.anchors + un.anchor);
         if (a.graph != cur_graph) {
