@@ -1417,6 +1417,60 @@ __device__ __forceinline__ int mad_i24(int a, int b, int c)
     return r;
 }
 
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// For -1 <= D < 256 the sum of D (D^2 - 1) runs in 16-bit halves: converted
+// to 16 bits (truncated or clamped), -1 (2^32 - 1 unsigned) becomes 0xffff,
+// whose square minus one wraps to 0, and D^2 - 1 < 2^16 for the others, so
+// one packed multiply-add and one two-term dot product serve two pairs.
+// Sum of D (D^2 - 1) over N accumulators, D = n - 1 with n <= 32 W: packed
+// for W <= 8 (n <= 256), 24-bit multiply-adds above (-1 <= D < 512: both
+// products fit, which the compiler cannot prove). Every accumulator has a
+// partial sum of its own, and in the packed form all squares are formed
+// before the first product that reads one, so that consecutive instructions
+// do not depend on each other.
+// With MASKED set, element k of accumulator n (row i0 + 16 n + k, column j)
+// counts only for j < i0 + 16 n + k, the others are taken as D = -1.
+template <int W, int N, bool MASKED>
+__device__ __forceinline__ uint32_t cubic_sum(const v4i32 (&acc)[N], uint32_t j, uint32_t i0)
+{
+    auto D = [&](int n, int k) -> int {
+        return !MASKED || j < i0 + 16 * n + k ? acc[n][k] : -1;
+    };
+    uint32_t s[N];
+    if constexpr (W <= 8) {
+        u16x2 p[N][2], e[N][2];
+#pragma unroll
+        for (int n = 0; n < N; n++)
+#pragma unroll
+            for (int h = 0; h < 2; h++)
+                p[n][h] = __builtin_bit_cast(
+                    u16x2, __builtin_amdgcn_cvt_pk_u16((uint32_t)D(n, 2 * h), (uint32_t)D(n, 2 * h + 1)));
+#pragma unroll
+        for (int n = 0; n < N; n++)
+#pragma unroll
+            for (int h = 0; h < 2; h++) e[n][h] = p[n][h] * p[n][h] + (u16x2){0xffff, 0xffff};
+#pragma unroll
+        for (int n = 0; n < N; n++) s[n] = __builtin_amdgcn_udot2(p[n][0], e[n][0], 0u, false);
+#pragma unroll
+        for (int n = 0; n < N; n++) s[n] = __builtin_amdgcn_udot2(p[n][1], e[n][1], s[n], false);
+    } else {
+#pragma unroll
+        for (int n = 0; n < N; n++) s[n] = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+            for (int n = 0; n < N; n++) {
+                const int d = D(n, k);
+                s[n] = mad_i24(d, mad_i24(d, d, -1), s[n]);
+            }
+    }
+    uint32_t t = 0;
+#pragma unroll
+    for (int n = 0; n < N; n++) t += s[n];
+    return t;
+}
+
 __device__ __forceinline__ v4i32 spread16(uint32_t x)
 {
     // 4 bits -> 4 bytes: the multiplier copies bit b of the nibble to bit 8b
@@ -1498,29 +1552,11 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
             }
         };
         // lane holds rows pbase + 16 sb + 4 g + e of column j0 + r16; only
-        // j < i counts. -1 <= D < 32 W <= 512: both products fit the 24-bit
-        // multiply-add, which the compiler cannot prove by itself.
+        // j < i counts. One partial sum per row block keeps the dependency
+        // chains short.
         auto epilogue = [&](const v4i32 (&acc)[SBP], uint32_t j0) -> uint32_t {
-            const uint32_t j = j0 + r16;
-            uint32_t s32 = 0;
-            if (j0 + 16 <= pbase) {
-#pragma unroll
-                for (int sb = 0; sb < SBP; sb++)
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const int D = acc[sb][e];
-                        s32 = mad_i24(D, mad_i24(D, D, -1), s32);
-                    }
-            } else {
-#pragma unroll
-                for (int sb = 0; sb < SBP; sb++)
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const int D = j < pbase + 16 * sb + 4 * g + e ? acc[sb][e] : -1;
-                        s32 = mad_i24(D, mad_i24(D, D, -1), s32);
-                    }
-            }
-            return s32;
+            if (j0 + 16 <= pbase) return cubic_sum<W, SBP, false>(acc, 0, 0);
+            return cubic_sum<W, SBP, true>(acc, j0 + r16, pbase + 4 * g);
         };
         uint32_t w0[NC], w1[NC];
         v4i32 acc0[SBP], acc1[SBP];
