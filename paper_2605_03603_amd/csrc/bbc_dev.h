@@ -75,11 +75,12 @@ struct AnchorRec {
     uint64_t cand_off;  // first candidate id (global rank of its partner)
 };
 
-// A triplet work unit: rows [64*rb, 64*rb+64) x columns [c0, c1) of the
-// lower triangle of one anchor's candidate-pair matrix.
+// A triplet work unit: rows [R*rb, R*rb+R) x columns [c0, c1) of the lower
+// triangle of one anchor's candidate-pair matrix (R = 64, or 128 for the
+// matrix-core units of narrow masks when only totals are counted).
 struct Unit {
     uint32_t anchor;    // index into AnchorRec[]
-    uint32_t rb;
+    uint32_t rb;        // row block of R rows
     uint32_t c0, c1;
 };
 

@@ -144,14 +144,27 @@ __device__ __forceinline__ bool queue_take(Cursor *cur, uint32_t n, uint32_t chu
     return false;
 }
 
-__device__ __forceinline__ uint32_t anchor_units(uint32_t k, uint32_t w32, uint32_t base)
+// Rows of a triplet unit. Matrix-core units of masks up to kTallMaxW words
+// (totals only) take 128 rows when the anchor has more than 64 candidates,
+// so that each spread column tile serves twice as many rows (wider masks
+// would need more registers for the row operands than a wave has).
+constexpr uint32_t kTallMaxW = 2;
+__host__ __device__ __forceinline__ uint32_t unit_rows(uint32_t k, uint32_t w32, bool tall)
+{
+    return tall && w32 <= kTallMaxW && k > kWave ? 2 * kWave : kWave;
+}
+
+// Units of one anchor record: row blocks of `rows` rows, each cut into
+// column ranges of unit_cols() columns of the lower triangle.
+__device__ __forceinline__ uint32_t anchor_units(uint32_t k, uint32_t w32, uint32_t base,
+                                                 uint32_t rows = kWave)
 {
     if (k < 2) return 0;
     const uint32_t CH = unit_cols(w32, base);
-    const uint32_t nb = (k + kWave - 1) / kWave;
+    const uint32_t nb = (k + rows - 1) / rows;
     uint32_t tot = 0;
     for (uint32_t b = 0; b < nb; b++) {
-        const uint32_t ncols = min(kWave * (b + 1), k) - 1;
+        const uint32_t ncols = min(rows * (b + 1), k) - 1;
         tot += (ncols + CH - 1) / CH;
     }
     return tot;
@@ -1165,7 +1178,7 @@ __global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
 // ------------------------------------------------------------- planning
 // Units per anchor record; units of masks wider than kRegW words are
 // counted in the second half so that they follow all the others.
-__global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk_base)
+__global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk_base, bool tall)
 {
     // after a capacity overflow the records are incomplete: plan nothing
     const uint32_t n_rec = ws.ctr->over_cap ? 0u
@@ -1175,7 +1188,7 @@ __global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk
         uint32_t c = 0, wide = 0;
         if (a < n_rec) {
             const AnchorRec &r = ws.anchors[a];
-            if (r.k <= 65535u) c = anchor_units(r.k, r.w32, chunk_base);
+            if (r.k <= 65535u) c = anchor_units(r.k, r.w32, chunk_base, unit_rows(r.k, r.w32, tall));
             wide = r.w32 > kRegW;
         }
         ws.ucnt[a] = wide ? 0 : c;
@@ -1184,7 +1197,7 @@ __global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk
 }
 
 // One wave per anchor record writes its units.
-__global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk_base)
+__global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk_base, bool tall)
 {
     Counters *C = ws.ctr;
     const uint32_t n_rec = C->over_cap ? 0u : (uint32_t)min((uint64_t)C->n_anchor, ws.cap_anchors);
@@ -1202,10 +1215,11 @@ __global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk
         if (r.k < 2 || r.k > 65535u) continue;
         const uint64_t base = ws.uoff[(r.w32 > kRegW ? ws.cap_anchors : 0) + a];
         const uint32_t CH = unit_cols(r.w32, chunk_base);
-        const uint32_t nb = (r.k + kWave - 1) / kWave;
+        const uint32_t rows = unit_rows(r.k, r.w32, tall);
+        const uint32_t nb = (r.k + rows - 1) / rows;
         uint32_t u0 = 0;
         for (uint32_t b = 0; b < nb; b++) {
-            const uint32_t ncols = min(kWave * (b + 1), r.k) - 1;
+            const uint32_t ncols = min(rows * (b + 1), r.k) - 1;
             const uint32_t nu = (ncols + CH - 1) / CH;
             for (uint32_t c = lane; c < nu; c += kWave) {
                 const uint64_t idx = base + u0 + c;
@@ -1393,14 +1407,13 @@ constexpr uint32_t kUnitGrab = 4;
 // the int8 matrix cores: v_mfma_i32_16x16x64_i8 multiplies a 16 x 64 by a
 // 64 x 16 int8 tile. Lane l supplies row (or column) l % 16, elements
 // 16 (l / 16) .. + 15, and receives rows 4 (l / 16) .. + 3 of column l % 16
-// of the product. Element e of a lane's slice is bit e of a 16-bit piece of
-// a mask word, spread to one byte per bit.
+// of the product. A lane's 16 elements are 16 bits of one mask word, one
+// byte per bit (spread_word).
 //
 // With the accumulator started at -1 the product gives D = n - 1, and
-// n (n - 1) (n - 2) = D (D^2 - 1): two 24-bit multiply-adds per pair, zero
-// for n <= 2 (also for padding rows and columns, whose masks are zero, and
-// for masked pairs, set to D = -1). Each term is 6 C(n, 3), so a lane's sum
-// is divided by 6 once.
+// n (n - 1) (n - 2) = D (D^2 - 1), zero for n <= 2 (also for padding rows
+// and columns, whose masks are zero, and for masked pairs, set to D = -1).
+// Each term is 6 C(n, 3), so a lane's sum is divided by 6 once.
 typedef int v4i32 __attribute__((ext_vector_type(4)));
 
 // a * b + c with a and b taken as 24-bit signed integers (full rate)
@@ -1471,22 +1484,29 @@ __device__ __forceinline__ uint32_t cubic_sum(const v4i32 (&acc)[N], uint32_t j,
     return t;
 }
 
-__device__ __forceinline__ v4i32 spread16(uint32_t x)
+// Lane group g feeds K-chunk t from mask word w = 2 t + (g >> 1): byte b of
+// its element register q is bit 8 b + q + 4 (g & 1) of the word, so the two
+// lane groups of a word take the low and the high nibble of each of its
+// bytes. Any one-to-one placement of the mask bits on the K positions gives
+// the same products as long as rows and columns share it; this one costs a
+// shift and a mask per register. `keep` is false past the mask width and for
+// an invalid row or column (all zero); it becomes a register mask at once, so
+// that no lane-mask register pair stays live until the bits are used.
+__device__ __forceinline__ v4i32 spread_word(uint32_t raw, uint32_t h4, bool keep)
 {
-    // 4 bits -> 4 bytes: the multiplier copies bit b of the nibble to bit 8b
+    const uint32_t m = keep ? 0x01010101u : 0u;
+    const uint32_t x = raw >> h4;
     v4i32 r;
-    r[0] = (int)(((x & 0xfu) * 0x00204081u) & 0x01010101u);
-    r[1] = (int)((((x >> 4) & 0xfu) * 0x00204081u) & 0x01010101u);
-    r[2] = (int)((((x >> 8) & 0xfu) * 0x00204081u) & 0x01010101u);
-    r[3] = (int)((((x >> 12) & 0xfu) * 0x00204081u) & 0x01010101u);
+    r[0] = (int)(x & m);
+    r[1] = (int)((x >> 1) & m);
+    r[2] = (int)((x >> 2) & m);
+    r[3] = (int)((x >> 3) & m);
     return r;
 }
 
-// Lane group g feeds K-chunk t the 16-bit piece of mask word 2 t + (g >> 1),
-// half g & 1 (zero past the mask width or for an invalid row / column).
-// The raw words are loaded unconditionally (clamped to valid words) and
-// reduced to pieces only where they are used, so that a prefetch stays in
-// flight until then.
+// The raw words of one row or column (word 2 t + (g >> 1) for chunk t) are
+// loaded unconditionally (clamped to valid words) and spread only where they
+// are used, so that a prefetch stays in flight until then.
 template <int W>
 __device__ __forceinline__ void mask_words(const uint32_t *m, uint32_t g, uint32_t (&raw)[(W + 1) / 2])
 {
@@ -1497,37 +1517,43 @@ __device__ __forceinline__ void mask_words(const uint32_t *m, uint32_t g, uint32
     }
 }
 
+// chunk t of a row or column of W-word masks
 template <int W>
-__device__ __forceinline__ uint32_t mask_piece(uint32_t raw, int t, uint32_t g, bool valid)
+__device__ __forceinline__ v4i32 mask_piece(uint32_t raw, int t, uint32_t g, bool valid)
 {
     const uint32_t w = 2 * t + (g >> 1);
-    const uint32_t keep = (valid && w < (uint32_t)W) ? 0xffffu : 0u;
-    return (raw >> (16 * (g & 1u))) & keep;
+    return spread_word(raw, 4 * (g & 1u), valid && w < (uint32_t)W);
 }
 
-// Sum over the unit's pairs (j < i) of C(|M_i n M_j|, 3), masks of W words.
-// The 64 rows go in passes of SBP 16-row blocks, so that the spread row
-// operands (SBP x ceil(W/2) x 4 registers) stay in registers. The column
-// tiles are software-pipelined: the products of tile t + 1 are issued before
-// the epilogue of tile t reads its accumulators (no waiting on the matrix
-// cores), and column words are loaded two tiles ahead.
-template <int W>
+// Sum over the unit's pairs (j < i) of C(|M_i n M_j|, 3), masks of W words,
+// ROWS (64 or 128) rows per unit. The rows go in passes of SBP 16-row
+// blocks, so that the spread row operands (SBP x ceil(W/2) x 4 registers)
+// stay in registers and each spread column tile serves SBP blocks. The
+// column tiles are software-pipelined: the products of tile t + 1 are issued
+// before the epilogue of tile t reads its accumulators (no waiting on the
+// matrix cores), and column words are loaded two tiles ahead. Every block
+// of a pass takes part in every tile (rows past the last candidate have zero
+// masks; the epilogue drops pairs with j >= i): branches around single
+// products would keep the scheduler from interleaving them with the
+// epilogue of the previous tile.
+template <int W, int ROWS>
 __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
                                   const uint32_t *__restrict__ masks)
 {
     constexpr int NC = (W + 1) / 2;          // 64-bit K-chunks
-    constexpr int SBP = W <= 10 ? 4 : 2;     // 16-row blocks per pass
+    constexpr int SBP = ROWS == 128 ? 8 : (W <= 10 ? 4 : 2);   // 16-row blocks per pass
+    static_assert(ROWS == 64 || W <= (int)kTallMaxW, "128-row units hold narrow masks only");
     const uint32_t lane = __lane_id();
     const uint32_t g = lane >> 4, r16 = lane & 15u;
     const uint32_t *M = masks + a.mask_off;
-    const uint32_t rbase = un.rb * kWave;
+    const uint32_t rbase = un.rb * ROWS;
     auto col_words = [&](uint32_t j0, uint32_t (&raw)[NC]) {
         const uint32_t j = j0 + r16;
         mask_words<W>(M + (uint64_t)(j < un.c1 ? j : un.c1 - 1) * W, g, raw);
     };
     uint64_t sum = 0;
 #pragma unroll 1
-    for (int pass = 0; pass < 4 / SBP; pass++) {
+    for (int pass = 0; pass < ROWS / (16 * SBP); pass++) {
         const uint32_t pbase = rbase + 16 * SBP * pass;
         if (pbase >= a.k) break;
         v4i32 A[SBP][NC];
@@ -1537,7 +1563,7 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
             uint32_t raw[NC];
             mask_words<W>(M + (uint64_t)(i < a.k ? i : a.k - 1) * W, g, raw);
 #pragma unroll
-            for (int t = 0; t < NC; t++) A[sb][t] = spread16(mask_piece<W>(raw[t], t, g, i < a.k));
+            for (int t = 0; t < NC; t++) A[sb][t] = mask_piece<W>(raw[t], t, g, i < a.k);
         }
         auto products = [&](const uint32_t (&raw)[NC], uint32_t j0, v4i32 (&acc)[SBP]) {
             const bool vj = j0 + r16 < un.c1;
@@ -1545,15 +1571,14 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
             for (int sb = 0; sb < SBP; sb++) acc[sb] = (v4i32){-1, -1, -1, -1};
 #pragma unroll
             for (int t = 0; t < NC; t++) {
-                const v4i32 B = spread16(mask_piece<W>(raw[t], t, g, vj));
+                const v4i32 B = mask_piece<W>(raw[t], t, g, vj);
 #pragma unroll
                 for (int sb = 0; sb < SBP; sb++)
                     acc[sb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[sb][t], B, acc[sb], 0, 0, 0);
             }
         };
         // lane holds rows pbase + 16 sb + 4 g + e of column j0 + r16; only
-        // j < i counts. One partial sum per row block keeps the dependency
-        // chains short.
+        // j < i counts.
         auto epilogue = [&](const v4i32 (&acc)[SBP], uint32_t j0) -> uint32_t {
             if (j0 + 16 <= pbase) return cubic_sum<W, SBP, false>(acc, 0, 0);
             return cubic_sum<W, SBP, true>(acc, j0 + r16, pbase + 4 * g);
@@ -1588,6 +1613,17 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
     return sum / 6;
 }
 
+// the unit height chosen by unit_rows() for totals
+template <int W>
+__device__ __forceinline__ uint64_t tri_rows_mfma_any(const Unit &un, const AnchorRec &a,
+                                                      const uint32_t *__restrict__ masks)
+{
+    if constexpr (W <= (int)kTallMaxW) {
+        if (unit_rows(a.k, W, true) == 2 * kWave) return tri_rows_mfma<W, 2 * kWave>(un, a, masks);
+    }
+    return tri_rows_mfma<W, kWave>(un, a, masks);
+}
+
 // Masks wider than 16 words (totals): 64 rows x up to 64 columns per unit.
 // The products of all four column tiles stay in accumulators while the mask
 // words go by in K-blocks of 8 words (4 chunks): a row piece is spread once
@@ -1605,7 +1641,7 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
     const uint32_t *M = masks + a.mask_off;
     const uint32_t rbase = un.rb * kWave;
     const uint32_t nt = (un.c1 - un.c0 + 15) / 16;   // column tiles (<= 4)
-    const uint32_t half = 16 * (g & 1u);
+    const uint32_t h4 = 4 * (g & 1u);
     v4i32 acc[4][4];
 #pragma unroll
     for (int tt = 0; tt < 4; tt++)
@@ -1622,7 +1658,7 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
             for (int t = 0; t < KB; t++) {
                 const uint32_t w = 2 * (kc + t) + (g >> 1);
                 const uint32_t raw = mr[w < W ? w : W - 1];
-                Ab[sb][t] = spread16((vi && w < W) ? (raw >> half) & 0xffffu : 0u);
+                Ab[sb][t] = spread_word(raw, h4, vi && w < W);
             }
         }
 #pragma unroll
@@ -1635,7 +1671,7 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
             for (int t = 0; t < KB; t++) {
                 const uint32_t w = 2 * (kc + t) + (g >> 1);
                 const uint32_t raw = mc[w < W ? w : W - 1];
-                const v4i32 B = spread16((vj && w < W) ? (raw >> half) & 0xffffu : 0u);
+                const v4i32 B = spread_word(raw, h4, vj && w < W);
 #pragma unroll
                 for (int sb = 0; sb < 4; sb++)
                     acc[tt][sb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Ab[sb][t], B, acc[tt][sb], 0, 0, 0);
@@ -1722,7 +1758,7 @@ __global__ void __launch_bounds__(kTThreads, MODE == 1 || MODE == 0 ? 2 : 5) k_t
         } else {
             if (MODE == 0 && a.w32 <= kMfmaMaxW) {
                 switch (a.w32) {
-#define BBC_W(n) case n: acc = tri_rows_mfma<n>(un, a, T.ws.masks); break;
+#define BBC_W(n) case n: acc = tri_rows_mfma_any<n>(un, a, T.ws.masks); break;
                     BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) BBC_W(5) BBC_W(6) BBC_W(7) BBC_W(8)
                     BBC_W(9) BBC_W(10) BBC_W(11) BBC_W(12) BBC_W(13) BBC_W(14) BBC_W(15) BBC_W(16)
 #undef BBC_W
@@ -1738,15 +1774,19 @@ __global__ void __launch_bounds__(kTThreads, MODE == 1 || MODE == 0 ? 2 : 5) k_t
                 }
             }
         }
-        const uint32_t i = un.rb * kWave + lane;
-        if (i < a.k && i > un.c0) {
-            const uint32_t ex = min(i, un.c1) - un.c0;
-            examined += ex;
-            exwords += (uint64_t)ex * a.w32;
+        const uint32_t rows = WIDE ? kWave : unit_rows(a.k, a.w32, MODE == 0);
+        for (uint32_t i = un.rb * rows + lane; i < (un.rb + 1) * rows; i += kWave) {
+            if (i < a.k && i > un.c0) {
+                const uint32_t ex = min(i, un.c1) - un.c0;
+                examined += ex;
+                exwords += (uint64_t)ex * a.w32;
+            }
         }
         total += acc;
         if (MODE == 1) {
-            // this lane's row total, the anchor's total, and the column totals
+            // this lane's row total (units of 64 rows here), the anchor's
+            // total, and the column totals
+            const uint32_t i = un.rb * kWave + lane;
             if (i < a.k && acc)
                 atomicAdd(&T.ws.pv[T.ws.cands[a.cand_off + i]], (unsigned long long)acc);
             const uint64_t tot = wave_sum<uint64_t>(acc);
@@ -1815,14 +1855,14 @@ hipError_t count_pairs(const PairArgs &base, const LaunchShape &sh, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_t tmp_bytes,
-                      hipStream_t s)
+hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, bool tall, void *tmp,
+                      size_t tmp_bytes, hipStream_t s)
 {
     uint32_t grid = (uint32_t)std::min<uint64_t>((ws.cap_anchors + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_plan_count, dim3(grid), dim3(256), 0, s, ws, chunk_base);
+    hipLaunchKernelGGL(k_plan_count, dim3(grid), dim3(256), 0, s, ws, chunk_base, tall);
     hipError_t e = scan_u32_to_u64(ws.ucnt, ws.uoff, 2 * ws.cap_anchors, tmp, tmp_bytes, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_write, dim3(1024), dim3(256), 0, s, ws, chunk_base);
+    hipLaunchKernelGGL(k_plan_write, dim3(1024), dim3(256), 0, s, ws, chunk_base, tall);
     return hipGetLastError();
 }
 

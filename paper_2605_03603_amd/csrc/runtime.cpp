@@ -774,7 +774,7 @@ void enqueue_args(bbc_ctx *ctx, const LaunchArgs &L, hipStream_t s, bool timed)
     if (timed) HIP_OK(hipEventRecord(ctx->ev[0], s));
     HIP_OK(count_pairs(L.P, L.ls, s));
     if (timed) HIP_OK(hipEventRecord(ctx->ev[1], s));
-    HIP_OK(count_plan(ws, L.P.chunk_base, L.ptmp, L.ptmp_bytes, s));
+    HIP_OK(count_plan(ws, L.P.chunk_base, L.mode == 0, L.ptmp, L.ptmp_bytes, s));
     if (timed) HIP_OK(hipEventRecord(ctx->ev[2], s));
     HIP_OK(count_triplets(L.T, L.mode, L.ls.grid_t, s));
     if (timed) HIP_OK(hipEventRecord(ctx->ev[3], s));
