@@ -27,6 +27,8 @@ struct BuildArgs {
     // ingest outputs
     uint32_t *eg;                  // [M] (graph << 1) | negative
     uint32_t *deg_u, *deg_v;       // [NU], [NV]
+    uint32_t *deg_x;               // [kXcd][NU + NV] zeroed per-XCD degree copies, or null
+                                   // (then the increments go to deg_u, deg_v directly)
     uint32_t *err;
     unsigned long long *first_bad;
     unsigned long long *stat_c2_u, *stat_c2_v, *stat_d2_u, *stat_d2_v;   // [G]

@@ -11,6 +11,7 @@ namespace bbc {
 namespace {
 
 constexpr int kT = 256;
+constexpr uint32_t kSideBlocks = 256;   // workgroups of k_side_stats (one update each per graph)
 
 __device__ __forceinline__ uint32_t find_graph(const uint64_t *__restrict__ off, uint32_t G,
                                                uint64_t x)
@@ -49,8 +50,17 @@ __device__ __forceinline__ void seg_atomic_add(unsigned long long *dst, uint32_t
     }
 }
 
+// Degrees are counted with atomics. A hub takes one increment per edge, from
+// every part of the edge list; with per-XCD copies of the counters (the
+// workgroups of one XCD share a copy) each counter is updated from one XCD
+// only, which keeps the increments of a hub in that XCD's L2.
 __global__ void __launch_bounds__(kT) k_ingest(BuildArgs a)
 {
+    uint32_t *du = a.deg_u, *dv = a.deg_v;
+    if (a.deg_x) {
+        du = a.deg_x + (uint64_t)(blockIdx.x % kXcd) * ((uint64_t)a.NU + a.NV);
+        dv = du + a.NU;
+    }
     for (uint64_t e = (uint64_t)blockIdx.x * kT + threadIdx.x; e < a.M;
          e += (uint64_t)gridDim.x * kT) {
         uint32_t g = a.G == 1 ? 0 : find_graph(a.edge_off, a.G, e);
@@ -72,35 +82,100 @@ __global__ void __launch_bounds__(kT) k_ingest(BuildArgs a)
         if (!ok_sign) { atomicOr(a.err, kErrSign); atomicMin(a.first_bad, (unsigned long long)e); }
         a.eg[e] = (g << 1) | (uint32_t)neg;
         if (ok_range) {
-            atomicAdd(&a.deg_u[d.u_base + u], 1u);
-            atomicAdd(&a.deg_v[d.v_base + v], 1u);
+            atomicAdd(&du[d.u_base + u], 1u);
+            atomicAdd(&dv[d.v_base + v], 1u);
         }
     }
 }
 
-// Per-graph degree statistics of one side (side 0: U slots, 1: V slots).
+// deg_u, deg_v = the sums of the per-XCD copies
+__global__ void __launch_bounds__(kT) k_deg_sum(BuildArgs a)
+{
+    const uint64_t n = (uint64_t)a.NU + a.NV;
+    for (uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kT) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int x = 0; x < kXcd; x++) t += a.deg_x[x * n + i];
+        if (i < a.NU) a.deg_u[i] = t;
+        else a.deg_v[i - a.NU] = t;
+    }
+}
+
+// Per-graph degree statistics of one side (side 0: U slots, 1: V slots):
+// sum of C(d, 2), sum of d^2 and the largest degree. Each workgroup takes a
+// contiguous range of slots, and each thread adds up its slots until the
+// graph changes, so that a set of a few large graphs updates each graph's
+// sums once per workgroup (updates of one address serialise).
 __global__ void __launch_bounds__(kT) k_side_stats(BuildArgs a, int side, uint32_t n_slots)
 {
+    constexpr uint32_t kNone = 0xffffffffu;
+    constexpr int NW = kT / kWave;
+    __shared__ uint32_t s_g[NW], s_max[NW];
+    __shared__ unsigned long long s_c2[NW], s_d2[NW];
     const uint32_t *deg = side ? a.deg_v : a.deg_u;
     const uint32_t *base = side ? a.v_base_arr : a.u_base_arr;
-    unsigned long long *c2 = side ? a.stat_c2_v : a.stat_c2_u;
-    unsigned long long *d2 = side ? a.stat_d2_v : a.stat_d2_u;
-    uint32_t local_max = 0;
-    uint32_t n_iter = (n_slots + gridDim.x * kT - 1) / (gridDim.x * kT);
-    for (uint32_t it = 0; it < n_iter; it++) {
-        uint32_t i = (it * gridDim.x + blockIdx.x) * kT + threadIdx.x;
-        bool act = i < n_slots;
-        uint32_t g = 0, dg = 0;
-        if (act) {
-            g = a.G == 1 ? 0 : find_graph32(base, a.G, i);
-            dg = deg[i];
-            local_max = max(local_max, dg);
+    unsigned long long *c2p = side ? a.stat_c2_v : a.stat_c2_u;
+    unsigned long long *d2p = side ? a.stat_d2_v : a.stat_d2_u;
+    const uint32_t per = (uint32_t)(((uint64_t)n_slots + gridDim.x - 1) / gridDim.x);
+    const uint32_t lo = (uint32_t)min((uint64_t)blockIdx.x * per, (uint64_t)n_slots);
+    const uint32_t hi = (uint32_t)min((uint64_t)lo + per, (uint64_t)n_slots);
+    uint32_t g_cur = kNone, mx = 0;
+    uint64_t c2 = 0, d2 = 0;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kT) {
+        const uint32_t g = a.G == 1 ? 0 : find_graph32(base, a.G, i);
+        const uint32_t dg = deg[i];
+        mx = max(mx, dg);
+        if (g != g_cur) {
+            if (c2) atomicAdd(c2p + g_cur, (unsigned long long)c2);
+            if (d2) atomicAdd(d2p + g_cur, (unsigned long long)d2);
+            g_cur = g; c2 = 0; d2 = 0;
         }
-        seg_atomic_add(c2, g, choose2(dg), act);
-        seg_atomic_add(d2, g, (uint64_t)dg * dg, act);
+        c2 += choose2(dg);
+        d2 += (uint64_t)dg * dg;
     }
-    for (int o = 32; o > 0; o >>= 1) local_max = max(local_max, (uint32_t)__shfl_xor(local_max, o, kWave));
-    if (__lane_id() == 0) atomicMax(side ? a.max_deg_v : a.max_deg_u, local_max);
+    // what is left: one update per workgroup where all threads end in one graph
+    const uint32_t key = (c2 | d2) ? g_cur : kNone;
+    uint32_t kmin = key, kmax = key == kNone ? 0u : key;
+    for (int o = 32; o > 0; o >>= 1) {
+        kmin = min(kmin, (uint32_t)__shfl_xor(kmin, o, kWave));
+        kmax = max(kmax, (uint32_t)__shfl_xor(kmax, o, kWave));
+        mx = max(mx, (uint32_t)__shfl_xor(mx, o, kWave));
+    }
+    const uint32_t w = threadIdx.x / kWave;
+    if (kmin != kNone && kmin != kmax) {   // several graphs in this wave
+        if (key != kNone) {
+            atomicAdd(c2p + key, (unsigned long long)c2);
+            atomicAdd(d2p + key, (unsigned long long)d2);
+        }
+        kmin = kNone;
+        c2 = d2 = 0;
+    }
+    c2 = wave_sum<uint64_t>(c2);
+    d2 = wave_sum<uint64_t>(d2);
+    if (__lane_id() == 0) { s_g[w] = kmin; s_max[w] = mx; s_c2[w] = c2; s_d2[w] = d2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t g = kNone, m = 0;
+        uint64_t t2 = 0, q2 = 0;
+        for (int x = 0; x < NW; x++) {
+            m = max(m, s_max[x]);
+            if (s_g[x] == kNone) continue;
+            if (s_g[x] != g) {
+                if (g != kNone) {
+                    atomicAdd(c2p + g, (unsigned long long)t2);
+                    atomicAdd(d2p + g, (unsigned long long)q2);
+                }
+                g = s_g[x]; t2 = 0; q2 = 0;
+            }
+            t2 += s_c2[x];
+            q2 += s_d2[x];
+        }
+        if (g != kNone) {
+            atomicAdd(c2p + g, (unsigned long long)t2);
+            atomicAdd(d2p + g, (unsigned long long)q2);
+        }
+        if (m) atomicMax(side ? a.max_deg_v : a.max_deg_u, m);
+    }
 }
 
 // One thread per global S slot / O slot: degree in the chosen orientation
@@ -234,8 +309,10 @@ hipError_t fill_u64(void *p, uint64_t v, uint64_t n, hipStream_t s)
 hipError_t build_ingest(const BuildArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_ingest, dim3(grid_for(a.M)), dim3(kT), 0, s, a);
-    hipLaunchKernelGGL(k_side_stats, dim3(grid_for(a.NU, 2048)), dim3(kT), 0, s, a, 0, a.NU);
-    hipLaunchKernelGGL(k_side_stats, dim3(grid_for(a.NV, 2048)), dim3(kT), 0, s, a, 1, a.NV);
+    if (a.deg_x)
+        hipLaunchKernelGGL(k_deg_sum, dim3(grid_for((uint64_t)a.NU + a.NV)), dim3(kT), 0, s, a);
+    hipLaunchKernelGGL(k_side_stats, dim3(grid_for(a.NU, kSideBlocks)), dim3(kT), 0, s, a, 0, a.NU);
+    hipLaunchKernelGGL(k_side_stats, dim3(grid_for(a.NV, kSideBlocks)), dim3(kT), 0, s, a, 1, a.NV);
     return hipGetLastError();
 }
 

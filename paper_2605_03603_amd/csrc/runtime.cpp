@@ -385,6 +385,9 @@ uint32_t choose_side(uint32_t flags, uint32_t n_u, uint32_t n_v, uint64_t m, uin
 }
 
 constexpr uint64_t kSideTuneMinEdges = 1u << 18;
+// vertex slots (|U| + |V| over the set) up to which the ingest counts degrees
+// in per-XCD copies (8 words per slot)
+constexpr uint64_t kDegCopyMaxSlots = 1u << 22;
 
 // Graphs with the same size classes and degree-statistic ratio share a key.
 uint64_t side_key(uint32_t n_u, uint32_t n_v, uint64_t m, uint64_t c2_u, uint64_t c2_v,
@@ -472,12 +475,19 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
         HIP_OK(hipMemcpyAsync(d_small.p, hp, (G + 1) * 8 + G * sizeof(GraphDesc) + 2 * G * 4,
                               hipMemcpyHostToDevice, s));
     }
-    DBuf eg, deg_u, deg_v;
+    DBuf eg, deg_u, deg_v, deg_x;
     eg.ensure(al, std::max<uint64_t>(M, 1) * 4);
     deg_u.ensure(al, std::max<uint64_t>(NU, 1) * 4);
     deg_v.ensure(al, std::max<uint64_t>(NV, 1) * 4);
-    HIP_OK(fill_u32(deg_u.as<uint32_t>(), 0, NU, s));
-    HIP_OK(fill_u32(deg_v.as<uint32_t>(), 0, NV, s));
+    // per-XCD degree copies (k_ingest) while they stay small
+    const bool xcd_copies = NU + NV <= kDegCopyMaxSlots;
+    if (xcd_copies) {
+        deg_x.ensure(al, (uint64_t)kXcd * (NU + NV) * 4);
+        HIP_OK(fill_u32(deg_x.as<uint32_t>(), 0, (uint64_t)kXcd * (NU + NV), s));
+    } else {
+        HIP_OK(fill_u32(deg_u.as<uint32_t>(), 0, NU, s));
+        HIP_OK(fill_u32(deg_v.as<uint32_t>(), 0, NV, s));
+    }
     HIP_OK(fill_u64(d_stats, 0, 4ull * G, s));
     HIP_OK(fill_u32(d_flags, 0, 4, s));
     HIP_OK(fill_u64(d_flags + 4, ~0ull, 1, s));
@@ -488,6 +498,7 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
     a.edge_off = d_eoff; a.desc = d_desc_tmp; a.u_base_arr = d_ub; a.v_base_arr = d_vb;
     a.NU = (uint32_t)NU; a.NV = (uint32_t)NV;
     a.eg = eg.as<uint32_t>(); a.deg_u = deg_u.as<uint32_t>(); a.deg_v = deg_v.as<uint32_t>();
+    a.deg_x = xcd_copies ? deg_x.as<uint32_t>() : nullptr;
     a.err = d_flags; a.max_deg_u = d_flags + 1; a.max_deg_v = d_flags + 2;
     a.first_bad = (unsigned long long *)(d_flags + 4);
     a.stat_c2_u = d_stats; a.stat_c2_v = d_stats + G; a.stat_d2_u = d_stats + 2 * G;

@@ -356,3 +356,37 @@ def test_config3_full(ctx):
     for k, v in gold["per_v_sample"].items():
         assert int(pv[int(k)]) == v, k
     assert int(pv.sum()) == 3 * tu
+
+
+# ------------------------------------------------- side from degree sums
+def _side_rule(g):
+    """The documented default of the anchor side: sum_o C(d_o, 2) wedges,
+    weighted by 1 + (edge-weighted mean degree of the anchor side) / 32."""
+    du = np.bincount(np.asarray(g.eu, np.int64), minlength=g.n_u).astype(np.int64)
+    dv = np.bincount(np.asarray(g.ev, np.int64), minlength=g.n_v).astype(np.int64)
+    m = int(du.sum())
+    if m == 0:
+        return 0
+    c2u, c2v = int((du * (du - 1) // 2).sum()), int((dv * (dv - 1) // 2).sum())
+    d2u, d2v = int((du * du).sum()), int((dv * dv).sum())
+    cost_u = float(c2v) * (1.0 + (d2u / m) / 32.0)
+    cost_v = float(c2u) * (1.0 + (d2v / m) / 32.0)
+    return 1 if cost_v < cost_u else 0
+
+
+def test_side_stats_batch(ctx):
+    """The per-graph degree sums behind the side choice, for a batch mixing
+    many small graphs (several per workgroup and per wave) with graphs that
+    span many workgroups, in both orientations."""
+    say("side statistics")
+    rng = np.random.default_rng(99)
+    gs = G.config4(5, n_graphs=300)
+    gs.insert(120, G.config2(3, scale=0.2))
+    gs.insert(7, G.config2(4, scale=0.1).transpose())
+    gs += [G.tiny_random(rng, 9, 9) for _ in range(200)]
+    want = [_side_rule(g) for g in gs]
+    assert 0 < sum(want) < len(want)          # both sides occur
+    nu, nv, off, eu, ev, sg = G.concat(gs)
+    hs = ctx.build_csr_batch(nu, nv, off, eu, ev, sg)
+    got = [h.info().anchor_side for h in hs]
+    assert got == want
