@@ -36,20 +36,6 @@ __device__ __forceinline__ uint32_t find_graph32(const uint32_t *__restrict__ ba
     return lo;
 }
 
-// Sum over a wave when every lane belongs to the same graph, else per lane.
-__device__ __forceinline__ void seg_atomic_add(unsigned long long *dst, uint32_t g, uint64_t v,
-                                               bool active)
-{
-    uint32_t g0 = __shfl(g, 0, kWave);
-    bool same = __all(!active || g == g0) && __any(active);
-    if (same) {
-        uint64_t s = wave_sum<uint64_t>(active ? v : 0);
-        if (__lane_id() == 0 && s) atomicAdd(dst + g0, (unsigned long long)s);
-    } else if (active && v) {
-        atomicAdd(dst + g, (unsigned long long)v);
-    }
-}
-
 // Degrees are counted with atomics. A hub takes one increment per edge, from
 // every part of the edge list; with per-XCD copies of the counters (the
 // workgroups of one XCD share a copy) each counter is updated from one XCD
