@@ -29,10 +29,9 @@ struct LaunchShape {
 };
 
 hipError_t count_pairs(const PairArgs &P, const LaunchShape &sh, hipStream_t s);
-// cut the anchors' pair matrices into triplet work units; `tall` (totals
-// only) lets matrix-core units of narrow masks take 128 rows
-hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, bool tall, void *tmp,
-                      size_t tmp_bytes, hipStream_t s);
+// cut the anchors' pair matrices into triplet work units
+hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_t tmp_bytes,
+                      hipStream_t s);
 // mode 0: totals only; 1: also per vertex of the anchor side; 2: per vertex of
 // the opposite side
 hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t s);

@@ -75,12 +75,11 @@ struct AnchorRec {
     uint64_t cand_off;  // first candidate id (global rank of its partner)
 };
 
-// A triplet work unit: rows [R*rb, R*rb+R) x columns [c0, c1) of the lower
-// triangle of one anchor's candidate-pair matrix (R = 64, or 128 for the
-// matrix-core units of narrow masks when only totals are counted).
+// A triplet work unit: rows [64*rb, 64*rb+64) x columns [c0, c1) of the
+// lower triangle of one anchor's candidate-pair matrix.
 struct Unit {
     uint32_t anchor;    // index into AnchorRec[]
-    uint32_t rb;        // row block of R rows
+    uint32_t rb;
     uint32_t c0, c1;
 };
 
@@ -101,11 +100,11 @@ struct Counters {           // device-side cursors and flags, zeroed per count
     uint32_t over_cap;      // 1, 2: a workspace capacity was exceeded; 4: unsupported anchor
     uint32_t n_list[4];     // anchors handed to the workgroup tiers A, B, C, D
     uint32_t n_units;       // written by the plan kernel: all units
-    uint32_t n_narrow;      // units of masks up to 16 words come first
+    uint32_t n_cls_end[2];  // units of class 0 (masks <= 4 words) come first, then
+                            // class 1 (up to 16 words), then class 2 (wider)
     unsigned long long need_masks, need_cands, need_recs, need_units;   // exact demand
     Cursor q_pair[5][kXcd]; // work-queue cursors of the pair tiers, one per XCD slice
-    Cursor q_tri[kXcd];
-    Cursor q_tri_wide[kXcd];
+    Cursor q_tri[3][kXcd];  // one queue per unit class
 };
 
 struct Workspace {
@@ -118,8 +117,8 @@ struct Workspace {
     uint32_t *gtab;      uint64_t gtab_words_per_block; uint32_t gtab_blocks;  // tier C tables
     uint32_t *dtab;      uint64_t dtab_words_per_block; uint32_t dtab_blocks;  // tier D tables
     uint32_t *bscr;      uint64_t bscr_words_per_block;   // tier B per-block position lists
-    uint32_t *ucnt;      // [2 cap_anchors] units per anchor record: narrow masks, then wide
-    uint64_t *uoff;      // [2 cap_anchors + 1] exclusive prefix of ucnt
+    uint32_t *ucnt;      // [3 cap_anchors] units per anchor record, one slice per unit class
+    uint64_t *uoff;      // [3 cap_anchors + 1] exclusive prefix of ucnt
     unsigned long long *count;   // [G] totals
     uint32_t *carry;             // [G] carries out of 64 bits
     unsigned long long *pv;      // [NS] per-vertex (by global rank) or null

@@ -144,27 +144,16 @@ __device__ __forceinline__ bool queue_take(Cursor *cur, uint32_t n, uint32_t chu
     return false;
 }
 
-// Rows of a triplet unit. Matrix-core units of masks up to kTallMaxW words
-// (totals only) take 128 rows when the anchor has more than 64 candidates,
-// so that each spread column tile serves twice as many rows (wider masks
-// would need more registers for the row operands than a wave has).
-constexpr uint32_t kTallMaxW = 2;
-__host__ __device__ __forceinline__ uint32_t unit_rows(uint32_t k, uint32_t w32, bool tall)
-{
-    return tall && w32 <= kTallMaxW && k > kWave ? 2 * kWave : kWave;
-}
-
-// Units of one anchor record: row blocks of `rows` rows, each cut into
-// column ranges of unit_cols() columns of the lower triangle.
-__device__ __forceinline__ uint32_t anchor_units(uint32_t k, uint32_t w32, uint32_t base,
-                                                 uint32_t rows = kWave)
+// Units of one anchor record: row blocks of 64 rows, each cut into column
+// ranges of unit_cols() columns of the lower triangle.
+__device__ __forceinline__ uint32_t anchor_units(uint32_t k, uint32_t w32, uint32_t base)
 {
     if (k < 2) return 0;
     const uint32_t CH = unit_cols(w32, base);
-    const uint32_t nb = (k + rows - 1) / rows;
+    const uint32_t nb = (k + kWave - 1) / kWave;
     uint32_t tot = 0;
     for (uint32_t b = 0; b < nb; b++) {
-        const uint32_t ncols = min(rows * (b + 1), k) - 1;
+        const uint32_t ncols = min(kWave * (b + 1), k) - 1;
         tot += (ncols + CH - 1) / CH;
     }
     return tot;
@@ -1176,35 +1165,44 @@ __global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
 }
 
 // ------------------------------------------------------------- planning
-// Units per anchor record; units of masks wider than kRegW words are
-// counted in the second half so that they follow all the others.
-__global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk_base, bool tall)
+// Unit classes, each counted by a kernel of its own so that the register
+// needs of wide masks do not lower the occupancy for narrow ones: 0 = masks
+// of up to kSmallW words, 1 = up to kRegW words, 2 = wider.
+constexpr uint32_t kSmallW = 4;
+__device__ __forceinline__ uint32_t unit_class(uint32_t w32)
+{
+    return w32 > kRegW ? 2u : (w32 > kSmallW ? 1u : 0u);
+}
+
+// Units per anchor record, in the slice of its class.
+__global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk_base)
 {
     // after a capacity overflow the records are incomplete: plan nothing
     const uint32_t n_rec = ws.ctr->over_cap ? 0u
                                             : (uint32_t)min((uint64_t)ws.ctr->n_anchor, ws.cap_anchors);
     for (uint64_t a = (uint64_t)blockIdx.x * 256 + threadIdx.x; a < ws.cap_anchors;
          a += (uint64_t)gridDim.x * 256) {
-        uint32_t c = 0, wide = 0;
+        uint32_t c = 0, cls = 0;
         if (a < n_rec) {
             const AnchorRec &r = ws.anchors[a];
-            if (r.k <= 65535u) c = anchor_units(r.k, r.w32, chunk_base, unit_rows(r.k, r.w32, tall));
-            wide = r.w32 > kRegW;
+            if (r.k <= 65535u) c = anchor_units(r.k, r.w32, chunk_base);
+            cls = unit_class(r.w32);
         }
-        ws.ucnt[a] = wide ? 0 : c;
-        ws.ucnt[ws.cap_anchors + a] = wide ? c : 0;
+#pragma unroll
+        for (uint32_t x = 0; x < 3; x++) ws.ucnt[x * ws.cap_anchors + a] = x == cls ? c : 0u;
     }
 }
 
 // One wave per anchor record writes its units.
-__global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk_base, bool tall)
+__global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk_base)
 {
     Counters *C = ws.ctr;
     const uint32_t n_rec = C->over_cap ? 0u : (uint32_t)min((uint64_t)C->n_anchor, ws.cap_anchors);
-    const uint64_t total = ws.uoff[2 * ws.cap_anchors];
+    const uint64_t total = ws.uoff[3 * ws.cap_anchors];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         C->n_units = (uint32_t)min(total, ws.cap_units);
-        C->n_narrow = (uint32_t)min(ws.uoff[ws.cap_anchors], ws.cap_units);
+        C->n_cls_end[0] = (uint32_t)min(ws.uoff[ws.cap_anchors], ws.cap_units);
+        C->n_cls_end[1] = (uint32_t)min(ws.uoff[2 * ws.cap_anchors], ws.cap_units);
         if (total > ws.cap_units) atomicOr(&C->over_cap, 2u);
     }
     const uint32_t lane = __lane_id();
@@ -1213,13 +1211,12 @@ __global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk
     for (uint32_t a = wave; a < n_rec; a += nwaves) {
         const AnchorRec r = ws.anchors[a];
         if (r.k < 2 || r.k > 65535u) continue;
-        const uint64_t base = ws.uoff[(r.w32 > kRegW ? ws.cap_anchors : 0) + a];
+        const uint64_t base = ws.uoff[unit_class(r.w32) * ws.cap_anchors + a];
         const uint32_t CH = unit_cols(r.w32, chunk_base);
-        const uint32_t rows = unit_rows(r.k, r.w32, tall);
-        const uint32_t nb = (r.k + rows - 1) / rows;
+        const uint32_t nb = (r.k + kWave - 1) / kWave;
         uint32_t u0 = 0;
         for (uint32_t b = 0; b < nb; b++) {
-            const uint32_t ncols = min(rows * (b + 1), r.k) - 1;
+            const uint32_t ncols = min(kWave * (b + 1), r.k) - 1;
             const uint32_t nu = (ncols + CH - 1) / CH;
             for (uint32_t c = lane; c < nu; c += kWave) {
                 const uint64_t idx = base + u0 + c;
@@ -1525,35 +1522,33 @@ __device__ __forceinline__ v4i32 mask_piece(uint32_t raw, int t, uint32_t g, boo
     return spread_word(raw, 4 * (g & 1u), valid && w < (uint32_t)W);
 }
 
-// Sum over the unit's pairs (j < i) of C(|M_i n M_j|, 3), masks of W words,
-// ROWS (64 or 128) rows per unit. The rows go in passes of SBP 16-row
-// blocks, so that the spread row operands (SBP x ceil(W/2) x 4 registers)
-// stay in registers and each spread column tile serves SBP blocks. The
-// column tiles are software-pipelined: the products of tile t + 1 are issued
+// Sum over the unit's pairs (j < i) of C(|M_i n M_j|, 3), masks of W words.
+// The 64 rows go in passes of SBP 16-row blocks, so that the spread row
+// operands (SBP x ceil(W/2) x 4 registers) stay in registers and each spread
+// column tile serves SBP blocks. The column tiles are software-pipelined: the products of tile t + 1 are issued
 // before the epilogue of tile t reads its accumulators (no waiting on the
 // matrix cores), and column words are loaded two tiles ahead. Every block
 // of a pass takes part in every tile (rows past the last candidate have zero
 // masks; the epilogue drops pairs with j >= i): branches around single
 // products would keep the scheduler from interleaving them with the
 // epilogue of the previous tile.
-template <int W, int ROWS>
+template <int W>
 __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
                                   const uint32_t *__restrict__ masks)
 {
     constexpr int NC = (W + 1) / 2;          // 64-bit K-chunks
-    constexpr int SBP = ROWS == 128 ? 8 : (W <= 10 ? 4 : 2);   // 16-row blocks per pass
-    static_assert(ROWS == 64 || W <= (int)kTallMaxW, "128-row units hold narrow masks only");
+    constexpr int SBP = W <= 10 ? 4 : 2;     // 16-row blocks per pass
     const uint32_t lane = __lane_id();
     const uint32_t g = lane >> 4, r16 = lane & 15u;
     const uint32_t *M = masks + a.mask_off;
-    const uint32_t rbase = un.rb * ROWS;
+    const uint32_t rbase = un.rb * kWave;
     auto col_words = [&](uint32_t j0, uint32_t (&raw)[NC]) {
         const uint32_t j = j0 + r16;
         mask_words<W>(M + (uint64_t)(j < un.c1 ? j : un.c1 - 1) * W, g, raw);
     };
     uint64_t sum = 0;
 #pragma unroll 1
-    for (int pass = 0; pass < ROWS / (16 * SBP); pass++) {
+    for (int pass = 0; pass < kWave / (16 * SBP); pass++) {
         const uint32_t pbase = rbase + 16 * SBP * pass;
         if (pbase >= a.k) break;
         v4i32 A[SBP][NC];
@@ -1611,17 +1606,6 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
         }
     }
     return sum / 6;
-}
-
-// the unit height chosen by unit_rows() for totals
-template <int W>
-__device__ __forceinline__ uint64_t tri_rows_mfma_any(const Unit &un, const AnchorRec &a,
-                                                      const uint32_t *__restrict__ masks)
-{
-    if constexpr (W <= (int)kTallMaxW) {
-        if (unit_rows(a.k, W, true) == 2 * kWave) return tri_rows_mfma<W, 2 * kWave>(un, a, masks);
-    }
-    return tri_rows_mfma<W, kWave>(un, a, masks);
 }
 
 // Masks wider than 16 words (totals): 64 rows x up to 64 columns per unit.
@@ -1695,9 +1679,17 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
     return sum / 6;
 }
 
-template <int MODE, bool WIDE>
-__global__ void __launch_bounds__(kTThreads, MODE == 1 || MODE == 0 ? 2 : 5) k_triplet(TriArgs T)
+// Waves per SIMD: totals of masks up to kSmallW words 3, other totals and
+// per-vertex counts of the anchor side 2, per-vertex counts of the other side 5.
+__host__ __device__ constexpr int tri_waves(int mode, int cls)
 {
+    return mode == 0 ? (cls == 0 ? 3 : 2) : (mode == 1 ? 2 : 5);
+}
+
+template <int MODE, int CLS>
+__global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(TriArgs T)
+{
+    constexpr bool WIDE = CLS == 2;
     __shared__ uint32_t c3[kC3Max + 1];
     __shared__ unsigned long long colacc_all[MODE == 1 ? kTThreads / kWave : 1][MODE == 1 ? kMaxChunk : 1];
     for (uint32_t i = threadIdx.x; i <= kC3Max; i += kTThreads) c3[i] = (uint32_t)choose3(i);
@@ -1707,11 +1699,12 @@ __global__ void __launch_bounds__(kTThreads, MODE == 1 || MODE == 0 ? 2 : 5) k_t
     __syncthreads();
     Counters *C = T.ws.ctr;
     if (__atomic_load_n(&C->over_cap, __ATOMIC_RELAXED)) return;
-    // narrow units are [0, n_narrow), wide ones [n_narrow, n_units)
-    const uint32_t n_narrow = __atomic_load_n(&C->n_narrow, __ATOMIC_RELAXED);
-    const uint32_t u_base = WIDE ? n_narrow : 0;
-    const uint32_t n_units = WIDE ? __atomic_load_n(&C->n_units, __ATOMIC_RELAXED) - n_narrow : n_narrow;
-    Cursor *queue = WIDE ? C->q_tri_wide : C->q_tri;
+    // the units of class CLS
+    const uint32_t u_base = CLS == 0 ? 0u : __atomic_load_n(&C->n_cls_end[CLS - 1], __ATOMIC_RELAXED);
+    const uint32_t u_end = CLS == 2 ? __atomic_load_n(&C->n_units, __ATOMIC_RELAXED)
+                                    : __atomic_load_n(&C->n_cls_end[CLS], __ATOMIC_RELAXED);
+    const uint32_t n_units = u_end - u_base;
+    Cursor *queue = C->q_tri[CLS];
     const uint32_t lane = __lane_id();
     uint64_t *colacc = (uint64_t *)colacc_all[MODE == 1 ? threadIdx.x / kWave : 0];
     uint64_t examined = 0, exwords = 0;
@@ -1756,37 +1749,42 @@ __global__ void __launch_bounds__(kTThreads, MODE == 1 || MODE == 0 ? 2 : 5) k_t
             if (MODE == 0) acc = tri_rows_mfma_wide(un, a, T.ws.masks);
             else acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T);
         } else {
+            // only the widths of this kernel's class are instantiated
             if (MODE == 0 && a.w32 <= kMfmaMaxW) {
-                switch (a.w32) {
-#define BBC_W(n) case n: acc = tri_rows_mfma_any<n>(un, a, T.ws.masks); break;
-                    BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) BBC_W(5) BBC_W(6) BBC_W(7) BBC_W(8)
-                    BBC_W(9) BBC_W(10) BBC_W(11) BBC_W(12) BBC_W(13) BBC_W(14) BBC_W(15) BBC_W(16)
-#undef BBC_W
-                    default: break;
+#define BBC_W(n) case n: acc = tri_rows_mfma<n>(un, a, T.ws.masks); break;
+                if constexpr (CLS == 0) {
+                    switch (a.w32) { BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) default: break; }
+                } else {
+                    switch (a.w32) {
+                        BBC_W(5) BBC_W(6) BBC_W(7) BBC_W(8) BBC_W(9) BBC_W(10) BBC_W(11) BBC_W(12)
+                        BBC_W(13) BBC_W(14) BBC_W(15) BBC_W(16)
+                        default: break;
+                    }
                 }
+#undef BBC_W
             } else {
-                switch (a.w32) {
 #define BBC_W(n) case n: acc = tri_rows<n, MODE>(un, a, T.ws.masks, c3, colacc, T); break;
-                    BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) BBC_W(5) BBC_W(6) BBC_W(7) BBC_W(8)
-                    BBC_W(9) BBC_W(10) BBC_W(11) BBC_W(12) BBC_W(13) BBC_W(14) BBC_W(15) BBC_W(16)
-#undef BBC_W
-                    default: break;
+                if constexpr (CLS == 0) {
+                    switch (a.w32) { BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) default: break; }
+                } else {
+                    switch (a.w32) {
+                        BBC_W(5) BBC_W(6) BBC_W(7) BBC_W(8) BBC_W(9) BBC_W(10) BBC_W(11) BBC_W(12)
+                        BBC_W(13) BBC_W(14) BBC_W(15) BBC_W(16)
+                        default: break;
+                    }
                 }
+#undef BBC_W
             }
         }
-        const uint32_t rows = WIDE ? kWave : unit_rows(a.k, a.w32, MODE == 0);
-        for (uint32_t i = un.rb * rows + lane; i < (un.rb + 1) * rows; i += kWave) {
-            if (i < a.k && i > un.c0) {
-                const uint32_t ex = min(i, un.c1) - un.c0;
-                examined += ex;
-                exwords += (uint64_t)ex * a.w32;
-            }
+        const uint32_t i = un.rb * kWave + lane;
+        if (i < a.k && i > un.c0) {
+            const uint32_t ex = min(i, un.c1) - un.c0;
+            examined += ex;
+            exwords += (uint64_t)ex * a.w32;
         }
         total += acc;
         if (MODE == 1) {
-            // this lane's row total (units of 64 rows here), the anchor's
-            // total, and the column totals
-            const uint32_t i = un.rb * kWave + lane;
+            // this lane's row total, the anchor's total, and the column totals
             if (i < a.k && acc)
                 atomicAdd(&T.ws.pv[T.ws.cands[a.cand_off + i]], (unsigned long long)acc);
             const uint64_t tot = wave_sum<uint64_t>(acc);
@@ -1855,31 +1853,32 @@ hipError_t count_pairs(const PairArgs &base, const LaunchShape &sh, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, bool tall, void *tmp,
-                      size_t tmp_bytes, hipStream_t s)
+hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_t tmp_bytes,
+                      hipStream_t s)
 {
     uint32_t grid = (uint32_t)std::min<uint64_t>((ws.cap_anchors + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_plan_count, dim3(grid), dim3(256), 0, s, ws, chunk_base, tall);
-    hipError_t e = scan_u32_to_u64(ws.ucnt, ws.uoff, 2 * ws.cap_anchors, tmp, tmp_bytes, s);
+    hipLaunchKernelGGL(k_plan_count, dim3(grid), dim3(256), 0, s, ws, chunk_base);
+    hipError_t e = scan_u32_to_u64(ws.ucnt, ws.uoff, 3 * ws.cap_anchors, tmp, tmp_bytes, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_write, dim3(1024), dim3(256), 0, s, ws, chunk_base, tall);
+    hipLaunchKernelGGL(k_plan_write, dim3(1024), dim3(256), 0, s, ws, chunk_base);
     return hipGetLastError();
 }
 
 hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t s)
 {
-    // masks of up to 16 words, then the wider ones (a kernel of their own:
-    // its register use would otherwise lower the occupancy of the first)
-    const uint32_t grid_w = grid;
+    // one kernel per unit class (masks of up to 4, up to 16, and more words)
     if (mode == 0) {
-        hipLaunchKernelGGL((k_triplet<0, false>), dim3(grid), dim3(kTThreads), 0, s, T);
-        hipLaunchKernelGGL((k_triplet<0, true>), dim3(grid_w), dim3(kTThreads), 0, s, T);
+        hipLaunchKernelGGL((k_triplet<0, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
+        hipLaunchKernelGGL((k_triplet<0, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
+        hipLaunchKernelGGL((k_triplet<0, 2>), dim3(grid), dim3(kTThreads), 0, s, T);
     } else if (mode == 1) {
-        hipLaunchKernelGGL((k_triplet<1, false>), dim3(grid), dim3(kTThreads), 0, s, T);
-        hipLaunchKernelGGL((k_triplet<1, true>), dim3(grid_w), dim3(kTThreads), 0, s, T);
+        hipLaunchKernelGGL((k_triplet<1, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
+        hipLaunchKernelGGL((k_triplet<1, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
+        hipLaunchKernelGGL((k_triplet<1, 2>), dim3(grid), dim3(kTThreads), 0, s, T);
     } else {
-        hipLaunchKernelGGL((k_triplet<2, false>), dim3(grid), dim3(kTThreads), 0, s, T);
-        hipLaunchKernelGGL((k_triplet<2, true>), dim3(grid_w), dim3(kTThreads), 0, s, T);
+        hipLaunchKernelGGL((k_triplet<2, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
+        hipLaunchKernelGGL((k_triplet<2, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
+        hipLaunchKernelGGL((k_triplet<2, 2>), dim3(grid), dim3(kTThreads), 0, s, T);
     }
     return hipGetLastError();
 }

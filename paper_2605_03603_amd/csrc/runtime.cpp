@@ -648,9 +648,9 @@ void ensure_work(bbc_ctx *ctx, Work &w, GraphSet &set)
     uint64_t want_units = std::max<uint64_t>({set.hint_units, M / 16, 1ull << 16});
     if (w.cap_anchors < want_anchors) {
         w.anchors.ensure(al, want_anchors * sizeof(AnchorRec));
-        w.ucnt.ensure(al, 2 * want_anchors * 4);
-        w.uoff.ensure(al, (2 * want_anchors + 1) * 8);
-        w.ptmp_bytes = scan_tmp_bytes(2 * want_anchors + 1) + 256;
+        w.ucnt.ensure(al, 3 * want_anchors * 4);
+        w.uoff.ensure(al, (3 * want_anchors + 1) * 8);
+        w.ptmp_bytes = scan_tmp_bytes(3 * want_anchors + 1) + 256;
         w.ptmp.ensure(al, w.ptmp_bytes);
         w.cap_anchors = want_anchors;
     }
@@ -785,7 +785,7 @@ void enqueue_args(bbc_ctx *ctx, const LaunchArgs &L, hipStream_t s, bool timed)
     if (timed) HIP_OK(hipEventRecord(ctx->ev[0], s));
     HIP_OK(count_pairs(L.P, L.ls, s));
     if (timed) HIP_OK(hipEventRecord(ctx->ev[1], s));
-    HIP_OK(count_plan(ws, L.P.chunk_base, L.mode == 0, L.ptmp, L.ptmp_bytes, s));
+    HIP_OK(count_plan(ws, L.P.chunk_base, L.ptmp, L.ptmp_bytes, s));
     if (timed) HIP_OK(hipEventRecord(ctx->ev[2], s));
     HIP_OK(count_triplets(L.T, L.mode, L.ls.grid_t, s));
     if (timed) HIP_OK(hipEventRecord(ctx->ev[3], s));
