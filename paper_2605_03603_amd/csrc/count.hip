@@ -816,11 +816,13 @@ __global__ void __launch_bounds__(kGThreads) k_pair_global(PairArgs P)
 }
 
 // ----------------------------------------------------- per-wave tier
-// Anchors of degree <= 32 (masks of one word): one wave per anchor, each
-// wave with a table of its own in LDS that holds, per partner w, the key and
-// both class masks M_w^+ and M_w^- (bit p set by the wedge through position
-// p). The masks of the classes with >= 3 members are copied out as they
-// stand, so the wedges are walked once. Lane i takes the (j0 + i)-th wedge
+// Anchors of degree <= 32 (masks of one word): the kWvWaves waves of a
+// workgroup take one anchor at a time together, with a table in LDS that
+// holds, per partner w, the key and both class masks M_w^+ and M_w^- (bit p
+// set by the wedge through position p). The masks of the classes with >= 3
+// members are copied out as they stand, so the wedges are walked once. A
+// table per workgroup rather than per wave lets twice the waves share the
+// LDS; the waves take alternate wedge chunks. Lane i takes the (j0 + i)-th wedge
 // of the concatenated suffix lists and finds its position by a binary
 // search over the lanes that hold the positions' prefix offsets. The two
 // longest suffixes only update partners found elsewhere, as in the
@@ -829,7 +831,7 @@ __global__ void __launch_bounds__(kGThreads) k_pair_global(PairArgs P)
 constexpr uint32_t kWvMaxD = 32;
 constexpr int kWvUnroll = 8;              // loads in flight per lane, non-top positions
 constexpr int kWvTopUnroll = 16;          // and along the two longest suffixes
-constexpr uint64_t kWvMaskChunk = 4096;   // mask words reserved per wave at a time
+constexpr uint64_t kWvMaskChunk = 4096;   // mask words reserved per workgroup at a time
 constexpr uint64_t kWvCandChunk = 4096;
 constexpr uint32_t kWvProbe = 64;
 constexpr uint32_t kWvGrab = 2;           // anchors taken from the queue at a time
@@ -852,33 +854,38 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t x)
 }
 
 
-template <int S, int NWV>
-__global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
+template <int S, int NWC>
+__global__ void __launch_bounds__(NWC * kWave) k_pair_wave(PairArgs P)
 {
-    // per wave: S keys, 2S class masks and the list of occupied slots
+    // per workgroup: S keys, 2S class masks and the list of occupied slots,
+    // shared by its NWC waves, which take each anchor together
     constexpr uint32_t kLimit = wave_tier_limit(S);
-    __shared__ uint32_t tab_all[NWV][3 * S + kLimit];
+    constexpr uint32_t NT = NWC * kWave;
+    __shared__ uint32_t tab[3 * S + kLimit];
+    __shared__ uint32_t sh_ok, sh_lo, sh_hi, sh_nkeys, sh_over, sh_k, sh_wpos, sh_bad, sh_aidx;
+    __shared__ unsigned long long sh_mo, sh_co;
     constexpr int kLog2S = ilog2(S);
+    const uint32_t tid = threadIdx.x;
     const uint32_t lane = __lane_id();
-    const uint32_t wv = threadIdx.x / kWave;
-    uint32_t *keys = tab_all[wv];
-    uint32_t *msk = tab_all[wv] + S;         // msk[2 slot + class]
-    uint32_t *used = tab_all[wv] + 3 * S;    // slots holding a key, in insertion order
+    const uint32_t wv = tid / kWave;
+    uint32_t *keys = tab;
+    uint32_t *msk = tab + S;         // msk[2 slot + class]
+    uint32_t *used = tab + 3 * S;    // slots holding a key, in insertion order
     const CsrView &g = P.g;
     Counters *C = P.ws.ctr;
     const uint32_t n_items = P.a1 - P.a0;
 
     auto clear = [&]() {
-        for (uint32_t i = lane; i < 3u * S; i += kWave) tab_all[wv][i] = i < (uint32_t)S ? kEmpty : 0u;
-        wave_sync();
+        for (uint32_t i = tid; i < 3u * S; i += NT) tab[i] = i < (uint32_t)S ? kEmpty : 0u;
+        __syncthreads();
     };
     auto clear_used = [&](uint32_t n) {
-        for (uint32_t i = lane; i < n; i += kWave) {
+        for (uint32_t i = tid; i < n; i += NT) {
             const uint32_t sl = used[i];
             keys[sl] = kEmpty; msk[2 * sl] = 0; msk[2 * sl + 1] = 0;
         }
-        wave_sync();
     };
+    // called by wave 0 only, so that every anchor is listed once
     auto to_tier_a = [&](bool mine, uint32_t r) {
         const uint64_t b = ballot64(mine);
         if (!b) return;
@@ -912,22 +919,34 @@ __global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
         }
         return kEmpty;
     };
+    // the end of one anchor: table and shared counters back to idle
+    auto finish_anchor = [&](uint32_t nkeys) {
+        clear_used(nkeys);
+        __syncthreads();
+        if (tid == 0) { sh_nkeys = 0; sh_k = 0; sh_wpos = 0; sh_over = 0; }
+        __syncthreads();
+    };
 
+    if (tid == 0) { sh_nkeys = 0; sh_k = 0; sh_wpos = 0; sh_over = 0; }
     clear();
-    // wave-uniform reservation and demand state (as in the workgroup tiers)
+    // reservation and demand state, kept by wave 0 (wave-uniform)
     uint64_t moff = 0, mres_end = 0, coff = 0, cres_end = 0;
     uint32_t aidx = 0, arec_end = 0;
     uint64_t need_m = 0, need_c = 0, need_r = 0, need_u = 0;
     uint64_t vm = 0, vm_end = 0, vcn = 0, vc_end = 0;
     uint64_t my_wedges = 0;
-    uint32_t slice = blockIdx.x % kXcd, tried = 0;
+    uint32_t slice = blockIdx.x % kXcd, tried = 0;   // queue state of thread 0
 
     for (;;) {
-        uint32_t lo = 0, hi = 0, ok = 0;
-        if (lane == 0) ok = queue_take(C->q_pair[0], n_items, kWvGrab, &slice, &tried, &lo, &hi) ? 1u : 0u;
-        ok = bcast32(ok);
+        if (tid == 0) {
+            uint32_t lo = 0, hi = 0;
+            sh_ok = queue_take(C->q_pair[0], n_items, kWvGrab, &slice, &tried, &lo, &hi) ? 1u : 0u;
+            sh_lo = lo; sh_hi = hi;
+        }
+        __syncthreads();
+        const uint32_t ok = bcast32(sh_ok), lo = bcast32(sh_lo), hi = bcast32(sh_hi);
+        __syncthreads();
         if (!ok) break;
-        lo = bcast32(lo); hi = bcast32(hi); slice = bcast32(slice); tried = bcast32(tried);
         const uint32_t item = lo + lane;
         const uint32_t rl = P.a0 + item;
         uint32_t dl = 0;
@@ -936,7 +955,7 @@ __global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
             sl0 = g.s_off[rl];
             dl = (uint32_t)(g.s_off[rl + 1] - sl0);
         }
-        to_tier_a(item < hi && dl > kWvMaxD, rl);
+        if (wv == 0) to_tier_a(item < hi && dl > kWvMaxD, rl);
         uint64_t todo = ballot64(item < hi && dl >= 3 && dl <= kWvMaxD);
         while (todo) {
             const uint32_t l = (uint32_t)__builtin_ctzll(todo);
@@ -944,7 +963,8 @@ __global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
             const uint32_t r = P.a0 + lo + l;
             const uint64_t s0 = bcast64(__shfl(sl0, l, kWave));
             const uint32_t d = bcast32(__shfl(dl, l, kWave));
-            // the part of each neighbour's list ranked above the anchor
+            // the part of each neighbour's list ranked above the anchor (every
+            // wave reads it, so that all take the same decisions below)
             uint32_t st = 0, len = 0, sg = 0;
             if (lane < d) {
                 const uint2 sf = g.s_suf[s0 + lane];
@@ -963,20 +983,20 @@ __global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
             // the table cannot fill up
             const uint64_t T1 = wave_sum<uint64_t>(len1);
             if (T1 > kLimit) {
-                to_tier_a(lane == 0, r);
+                if (wv == 0) to_tier_a(lane == 0, r);
                 continue;
             }
             const uint32_t incl = wave_incl_scan(len1);
             const uint32_t pre = lane < d ? incl - len1 : 0xffffffffu;
             const uint32_t info = (incl - len1) | (sg << 31);
-            // walk the other positions: insert partners, set mask bits
-            uint32_t nkeys = 0;
+            // walk the other positions: insert partners, set mask bits. The
+            // waves take alternate chunks of kWave * kWvUnroll wedges.
             bool over = false;
             // Lanes past the end repeat the last wedge: a repeated wedge sets a
             // bit that is already set, so no lane needs a branch, and the
             // searches, loads and first probes of all kWvUnroll wedges issue
             // together.
-            for (uint32_t j0 = 0; j0 < (uint32_t)T1 && !over; j0 += kWave * kWvUnroll) {
+            for (uint32_t j0 = wv * kWave * kWvUnroll; j0 < (uint32_t)T1 && !over; j0 += NT * kWvUnroll) {
                 uint32_t jj[kWvUnroll], p[kWvUnroll], e2[kWvUnroll], pp[kWvUnroll];
 #pragma unroll
                 for (int u = 0; u < kWvUnroll; u++) {
@@ -1017,21 +1037,29 @@ __global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
                     if (h == kEmpty) bad = true;
                     else atomicOr(&msk[2 * h + cls], 1u << (pp[u] & 31u));
                     const uint64_t b = ballot64(fresh);
-                    if (fresh) used[nkeys + (uint32_t)__popcll(b & lanemask_lt())] = h;
-                    nkeys += (uint32_t)__popcll(b);
+                    if (b) {
+                        uint32_t base = 0;
+                        if (lane == 0) base = atomicAdd(&sh_nkeys, (uint32_t)__popcll(b));
+                        base = bcast32(base);
+                        if (fresh) used[base + (uint32_t)__popcll(b & lanemask_lt())] = h;
+                    }
                 }
                 over = ballot64(bad) != 0;
             }
-            if (over) {   // a probe run longer than kWvProbe
+            if (over && lane == 0) sh_over = 1;
+            __syncthreads();
+            if (sh_over) {   // a probe run longer than kWvProbe
+                __syncthreads();
+                if (tid == 0) { sh_nkeys = 0; sh_k = 0; sh_wpos = 0; sh_over = 0; }
                 clear();
-                to_tier_a(lane == 0, r);
+                if (wv == 0) to_tier_a(lane == 0, r);
                 continue;
             }
             // the two longest suffixes: existing partners only
             const uint32_t ltop = l1 + l2;
             const uint32_t st1 = __shfl(st, t1, kWave), sg1 = __shfl(sg, t1, kWave);
             const uint32_t st2 = __shfl(st, t2, kWave), sg2 = __shfl(sg, t2, kWave);
-            for (uint32_t j0 = 0; j0 < ltop; j0 += kWave * kWvTopUnroll) {
+            for (uint32_t j0 = wv * kWave * kWvTopUnroll; j0 < ltop; j0 += NT * kWvTopUnroll) {
                 uint32_t e2[kWvTopUnroll], hs[kWvTopUnroll], kk[kWvTopUnroll];
                 bool first[kWvTopUnroll];
 #pragma unroll
@@ -1054,39 +1082,43 @@ __global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
                     if (h != kEmpty) atomicOr(&msk[2 * h + cls], 1u << (first[u] ? t1 : t2));
                 }
             }
-            wave_sync();
+            __syncthreads();
+            const uint32_t nkeys = sh_nkeys;
             // classes with >= 3 members
             uint32_t cnt = 0;
-            for (uint32_t i = lane; i < nkeys; i += kWave) {
+            for (uint32_t i = tid; i < nkeys; i += NT) {
                 const uint32_t sl = used[i];
                 cnt += (__popc(msk[2 * sl]) >= 3) + (__popc(msk[2 * sl + 1]) >= 3);
             }
-            const uint32_t k = wave_sum<uint32_t>(cnt);
+            cnt = wave_sum<uint32_t>(cnt);
+            if (lane == 0 && cnt) atomicAdd(&sh_k, cnt);
+            __syncthreads();
+            const uint32_t k = sh_k;
             if (k < 2) {
-                clear_used(nkeys);
+                finish_anchor(nkeys);
                 continue;
             }
-            my_wedges += (uint64_t)T1 + ltop;
-            // reservations: wave-local bump allocation, large outputs apart;
-            // the demand counts what they consume with unlimited room
-            const bool big_m = k > kWvMaskChunk / 4, big_c = k > kWvCandChunk / 4;
-            if (big_m) {
-                need_m += k;
-            } else {
-                if (vm + k > vm_end) { need_m += kWvMaskChunk; vm = 0; vm_end = kWvMaskChunk; }
-                vm += k;
-            }
-            if (big_c) {
-                need_c += k;
-            } else {
-                if (vcn + k > vc_end) { need_c += kWvCandChunk; vcn = 0; vc_end = kWvCandChunk; }
-                vcn += k;
-            }
-            need_r += 1;
-            need_u += anchor_units(k, 1, P.chunk_base);
-            bool bad = false;
-            uint64_t mo = moff, co = coff;
-            {
+            if (wv == 0) {
+                my_wedges += (uint64_t)T1 + ltop;
+                // reservations: wave-local bump allocation, large outputs apart;
+                // the demand counts what they consume with unlimited room
+                const bool big_m = k > kWvMaskChunk / 4, big_c = k > kWvCandChunk / 4;
+                if (big_m) {
+                    need_m += k;
+                } else {
+                    if (vm + k > vm_end) { need_m += kWvMaskChunk; vm = 0; vm_end = kWvMaskChunk; }
+                    vm += k;
+                }
+                if (big_c) {
+                    need_c += k;
+                } else {
+                    if (vcn + k > vc_end) { need_c += kWvCandChunk; vcn = 0; vc_end = kWvCandChunk; }
+                    vcn += k;
+                }
+                need_r += 1;
+                need_u += anchor_units(k, 1, P.chunk_base);
+                bool bad = false;
+                uint64_t mo = moff, co = coff;
                 if (big_m || moff + k > mres_end) {
                     const uint64_t want = big_m ? k : kWvMaskChunk;
                     uint64_t o = 0;
@@ -1112,17 +1144,26 @@ __global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
                     aidx = o; arec_end = o + kRecChunk;
                     if ((uint64_t)o + kRecChunk > P.ws.cap_anchors) bad = true;
                 }
+                if (bad) {
+                    if (lane == 0) atomicOr(&C->over_cap, 2u);
+                    moff = mres_end = coff = cres_end = 0;
+                    aidx = arec_end = 0;
+                } else {
+                    if (!big_m) moff = mo + k;
+                    if (!big_c) coff = co + k;
+                }
+                if (lane == 0) { sh_bad = bad; sh_mo = mo; sh_co = co; sh_aidx = aidx; }
+                if (!bad) aidx++;
             }
-            if (bad) {
-                if (lane == 0) atomicOr(&C->over_cap, 2u);
-                moff = mres_end = coff = cres_end = 0;
-                aidx = arec_end = 0;
-                clear_used(nkeys);
+            __syncthreads();
+            if (sh_bad) {
+                finish_anchor(nkeys);
                 continue;
             }
-            // copy out the selected classes and clear the table
-            uint32_t base = 0;
-            for (uint32_t i0 = 0; i0 < nkeys; i0 += kWave) {
+            const uint64_t mo = sh_mo, co = sh_co;
+            // copy out the selected classes and clear the table; the waves take
+            // alternate groups of 64 occupied slots
+            for (uint32_t i0 = wv * kWave; i0 < nkeys; i0 += NT) {
                 const uint32_t i = i0 + lane;
                 const uint32_t sl = i < nkeys ? used[i] : 0u;
                 const uint32_t key = i < nkeys ? keys[sl] : kEmpty;
@@ -1130,26 +1171,28 @@ __global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
                 if (key != kEmpty) { m0 = msk[2 * sl]; m1 = msk[2 * sl + 1]; }
                 const bool a0 = __popc(m0) >= 3, a1 = __popc(m1) >= 3;
                 const uint64_t b0 = ballot64(a0), b1 = ballot64(a1);
+                const uint32_t n01 = (uint32_t)__popcll(b0) + (uint32_t)__popcll(b1);
+                uint32_t base = 0;
+                if (n01) {
+                    if (lane == 0) base = atomicAdd(&sh_wpos, n01);
+                    base = bcast32(base);
+                }
                 const uint64_t lt = lanemask_lt();
                 uint32_t idx = base + (uint32_t)__popcll(b0 & lt) + (uint32_t)__popcll(b1 & lt);
                 if (a0) { P.ws.cands[co + idx] = key; P.ws.masks[mo + idx] = m0; idx++; }
                 if (a1) { P.ws.cands[co + idx] = key; P.ws.masks[mo + idx] = m1; }
-                base += (uint32_t)__popcll(b0) + (uint32_t)__popcll(b1);
-                if (i < nkeys) { keys[sl] = kEmpty; msk[2 * sl] = 0; msk[2 * sl + 1] = 0; }
             }
-            wave_sync();
-            if (lane == 0) {
+            if (tid == 0) {
                 AnchorRec a;
                 a.rank = r; a.k = k; a.w32 = 1; a.graph = g.s_graph[r];
                 a.mask_off = mo; a.cand_off = co;
-                P.ws.anchors[aidx] = a;
+                P.ws.anchors[sh_aidx] = a;
             }
-            if (!big_m) moff = mo + k;
-            if (!big_c) coff = co + k;
-            aidx++;
+            __syncthreads();
+            finish_anchor(nkeys);
         }
     }
-    if (lane == 0) {
+    if (wv == 0 && lane == 0) {
         if (need_m) atomicAdd(&C->need_masks, (unsigned long long)need_m);
         if (need_c) atomicAdd(&C->need_cands, (unsigned long long)need_c);
         if (need_r) atomicAdd(&C->need_recs, (unsigned long long)need_r);
@@ -1157,10 +1200,12 @@ __global__ void __launch_bounds__(NWV * kWave) k_pair_wave(PairArgs P)
         if (my_wedges) atomicAdd(&C->wedges, (unsigned long long)my_wedges);
     }
     // unused reserved anchor records are marked empty
-    for (uint32_t i = aidx + lane; i < arec_end; i += kWave) {
-        AnchorRec a;
-        a.rank = 0; a.k = 0; a.w32 = 0; a.graph = 0; a.mask_off = 0; a.cand_off = 0;
-        P.ws.anchors[i] = a;
+    if (wv == 0) {
+        for (uint32_t i = aidx + lane; i < arec_end; i += kWave) {
+            AnchorRec a;
+            a.rank = 0; a.k = 0; a.w32 = 0; a.graph = 0; a.mask_off = 0; a.cand_off = 0;
+            P.ws.anchors[i] = a;
+        }
     }
 }
 
@@ -1814,11 +1859,11 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
 constexpr int kAThreads = 512, kAH = 8192, kAMaxD = 1024, kAKmax = 1984;
 constexpr int kBThreads = 1024, kBH = 16384, kBKmax = 4096;
 // per-wave tier: 2048 slots (30 KiB with the slot list) per wave
-constexpr int kWvSlots = 2048, kWvWaves = 1;
+constexpr int kWvSlots = 2048, kWvWaves = 2;   // waves of a workgroup share its table
 
 uint32_t wave_tier_blocks_per_cu()
 {
-    return (160u * 1024u) / ((3u * kWvSlots + wave_tier_limit(kWvSlots)) * 4u * kWvWaves);
+    return (160u * 1024u) / ((3u * kWvSlots + wave_tier_limit(kWvSlots)) * 4u + 64u);
 }
 uint32_t wave_tier_waves_per_cu() { return wave_tier_blocks_per_cu() * kWvWaves; }
 
