@@ -104,7 +104,7 @@ struct Counters {           // device-side cursors and flags, zeroed per count
                             // class 1 (up to 16 words), then class 2 (wider)
     unsigned long long need_masks, need_cands, need_recs, need_units;   // exact demand
     Cursor q_pair[5][kXcd]; // work-queue cursors of the pair tiers, one per XCD slice
-    Cursor q_tri[3][kXcd];  // one queue per unit class
+    Cursor q_tri[2][kXcd];  // queues of the two triplet kernels
 };
 
 struct Workspace {

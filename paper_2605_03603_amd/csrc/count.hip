@@ -1724,8 +1724,11 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
     return sum / 6;
 }
 
-// Waves per SIMD: totals of masks up to kSmallW words 3, other totals and
-// per-vertex counts of the anchor side 2, per-vertex counts of the other side 5.
+// Two kernels per mode: CLS 0 takes the units of class 0, CLS 1 those of
+// classes 1 and 2 (both need about the whole register file, so one kernel
+// for the two costs no occupancy and saves a tail). Waves per SIMD: totals
+// of masks up to kSmallW words 3, other totals and per-vertex counts of the
+// anchor side 2, per-vertex counts of the other side 5.
 __host__ __device__ constexpr int tri_waves(int mode, int cls)
 {
     return mode == 0 ? (cls == 0 ? 3 : 2) : (mode == 1 ? 2 : 5);
@@ -1734,7 +1737,6 @@ __host__ __device__ constexpr int tri_waves(int mode, int cls)
 template <int MODE, int CLS>
 __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(TriArgs T)
 {
-    constexpr bool WIDE = CLS == 2;
     __shared__ uint32_t c3[kC3Max + 1];
     __shared__ unsigned long long colacc_all[MODE == 1 ? kTThreads / kWave : 1][MODE == 1 ? kMaxChunk : 1];
     for (uint32_t i = threadIdx.x; i <= kC3Max; i += kTThreads) c3[i] = (uint32_t)choose3(i);
@@ -1744,10 +1746,10 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
     __syncthreads();
     Counters *C = T.ws.ctr;
     if (__atomic_load_n(&C->over_cap, __ATOMIC_RELAXED)) return;
-    // the units of class CLS
-    const uint32_t u_base = CLS == 0 ? 0u : __atomic_load_n(&C->n_cls_end[CLS - 1], __ATOMIC_RELAXED);
-    const uint32_t u_end = CLS == 2 ? __atomic_load_n(&C->n_units, __ATOMIC_RELAXED)
-                                    : __atomic_load_n(&C->n_cls_end[CLS], __ATOMIC_RELAXED);
+    // class 0, or classes 1 and 2
+    const uint32_t u_base = CLS == 0 ? 0u : __atomic_load_n(&C->n_cls_end[0], __ATOMIC_RELAXED);
+    const uint32_t u_end = CLS == 0 ? __atomic_load_n(&C->n_cls_end[0], __ATOMIC_RELAXED)
+                                    : __atomic_load_n(&C->n_units, __ATOMIC_RELAXED);
     const uint32_t n_units = u_end - u_base;
     Cursor *queue = C->q_tri[CLS];
     const uint32_t lane = __lane_id();
@@ -1790,9 +1792,12 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
             cur_graph = a.graph;
         }
         uint64_t acc = 0;
-        if (WIDE) {
-            if (MODE == 0) acc = tri_rows_mfma_wide(un, a, T.ws.masks);
-            else acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T);
+        const bool wide = CLS != 0 && a.w32 > kRegW;
+        if (wide) {
+            if constexpr (CLS != 0) {
+                if (MODE == 0) acc = tri_rows_mfma_wide(un, a, T.ws.masks);
+                else acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T);
+            }
         } else {
             // only the widths of this kernel's class are instantiated
             if (MODE == 0 && a.w32 <= kMfmaMaxW) {
@@ -1911,19 +1916,16 @@ hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_
 
 hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t s)
 {
-    // one kernel per unit class (masks of up to 4, up to 16, and more words)
+    // masks of up to 4 words, then the wider ones
     if (mode == 0) {
         hipLaunchKernelGGL((k_triplet<0, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
         hipLaunchKernelGGL((k_triplet<0, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
-        hipLaunchKernelGGL((k_triplet<0, 2>), dim3(grid), dim3(kTThreads), 0, s, T);
     } else if (mode == 1) {
         hipLaunchKernelGGL((k_triplet<1, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
         hipLaunchKernelGGL((k_triplet<1, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
-        hipLaunchKernelGGL((k_triplet<1, 2>), dim3(grid), dim3(kTThreads), 0, s, T);
     } else {
         hipLaunchKernelGGL((k_triplet<2, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
         hipLaunchKernelGGL((k_triplet<2, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
-        hipLaunchKernelGGL((k_triplet<2, 2>), dim3(grid), dim3(kTThreads), 0, s, T);
     }
     return hipGetLastError();
 }
