@@ -7,9 +7,10 @@
  * must fail loudly when its own extension is missing.
  *
  * Paper: "Counting Small Balanced (p,q)-bicliques in Signed Bipartite Graphs"
- * (arXiv 2605.03603). Everything here is for p = q = 3, in exact integer
- * arithmetic (128-bit accumulators), written as plain loops so that it can be
- * checked against the paper by eye.
+ * (arXiv 2605.03603). Everything here is for p = q = 3 unless a function says
+ * otherwise (the _q and _pq variants take a general q, or p and q), in exact
+ * integer arithmetic (128-bit accumulators), written as plain loops so that
+ * it can be checked against the paper by eye.
  *
  *   orc_butterfly_balanced   Section 1 (Fig. 2): a butterfly is balanced iff it
  *                            has an even number of negative edges.
@@ -28,6 +29,12 @@
  *   orc_vertex_count         the same per-anchor steps without the priority
  *                            filter: the number of balanced (3,3)-bicliques
  *                            that contain one given vertex.
+ *   orc_count_bbvp_q         Algorithm 2 with p = 3 on the anchor side and a
+ *                            general q (3..7) on the other: prune cnt >= q,
+ *                            skip |T| < q, add C(x[kappa], q).
+ *   orc_count_bruteforce_pq  the definitions for general (p, q): every p x q
+ *                            vertex subset, all edges present, every butterfly
+ *                            balanced (totals only).
  *
  * Readings of points the paper leaves open:
  *   - vertex priority (Definition 4.1): higher degree first, equal degree
@@ -87,6 +94,16 @@ static uint64_t choose3(uint64_t n)
 
 uint64_t orc_choose3(uint64_t n) { return choose3(n); }
 
+/* C(n, k) exactly: after step i, c = C(n, i + 1), and c * (n - i) is always
+ * divisible by i + 1. */
+static i128 choose_k(uint64_t n, int k)
+{
+    if ((uint64_t)k > n) return 0;
+    i128 c = 1;
+    for (int i = 0; i < k; i++) c = c * (i128)(n - (uint64_t)i) / (i + 1);
+    return c;
+}
+
 /* ----------------------------------------------------- O1: the definition */
 
 /* Count balanced (3,3)-bicliques of a tiny graph straight from the
@@ -135,6 +152,59 @@ int orc_count_bruteforce(int n_u, int n_v, int64_t m, const uint32_t *eu, const 
                 if (per_v) { per_v[x]++; per_v[y]++; per_v[z]++; }
             }
         }
+    }
+    *out_total = total;
+    return 0;
+}
+
+/* The definitions for general (p, q), totals only: every p-subset L of U and
+ * q-subset R of V (in lexicographic order) counts when all p*q edges exist and
+ * every butterfly of L x R is balanced. Tiny graphs only (sides up to 24, p
+ * and q up to 8). Returns -1 on bad input. */
+int orc_count_bruteforce_pq(int n_u, int n_v, int64_t m, const uint32_t *eu, const uint32_t *ev,
+                            const int8_t *sign, int p, int q, uint64_t *out_total)
+{
+    if (n_u < 0 || n_v < 0 || n_u > 24 || n_v > 24 || p < 1 || q < 1 || p > 8 || q > 8) return -1;
+    int8_t s[24][24];
+    memset(s, 0, sizeof(s));
+    for (int64_t e = 0; e < m; e++) {
+        if (eu[e] >= (uint32_t)n_u || ev[e] >= (uint32_t)n_v) return -1;
+        if (s[eu[e]][ev[e]] != 0) return -1;
+        s[eu[e]][ev[e]] = sign[e];
+    }
+    uint64_t total = 0;
+    *out_total = 0;
+    if (p > n_u || q > n_v) return 0;
+    int L[8], R[8];
+    for (int i = 0; i < p; i++) L[i] = i;
+    for (;;) {
+        for (int j = 0; j < q; j++) R[j] = j;
+        for (;;) {
+            int ok = 1;
+            for (int i = 0; i < p && ok; i++)
+                for (int j = 0; j < q && ok; j++)
+                    if (s[L[i]][R[j]] == 0) ok = 0;                 /* cohesiveness */
+            for (int i = 0; i < p && ok; i++)
+            for (int i2 = i + 1; i2 < p && ok; i2++)
+            for (int j = 0; j < q && ok; j++)
+            for (int j2 = j + 1; j2 < q && ok; j2++)
+                if (!orc_butterfly_balanced(s[L[i]][R[j]], s[L[i]][R[j2]],
+                                            s[L[i2]][R[j]], s[L[i2]][R[j2]]))
+                    ok = 0;                                         /* balance */
+            total += (uint64_t)ok;
+            /* next q-subset of V */
+            int j = q - 1;
+            while (j >= 0 && R[j] == n_v - q + j) j--;
+            if (j < 0) break;
+            R[j]++;
+            for (int j2 = j + 1; j2 < q; j2++) R[j2] = R[j2 - 1] + 1;
+        }
+        /* next p-subset of U */
+        int i = p - 1;
+        while (i >= 0 && L[i] == n_u - p + i) i--;
+        if (i < 0) break;
+        L[i]++;
+        for (int i2 = i + 1; i2 < p; i2++) L[i2] = L[i2 - 1] + 1;
     }
     *out_total = total;
     return 0;
@@ -284,11 +354,10 @@ static void scratch_free(scratch_t *w)
  * every balanced biclique containing u exactly once. per_s (optional) gets
  * each counted biclique's contribution added to u, w1 and w2. */
 static void bbvp_anchor(const graph_t *g, uint32_t u, int oriented, scratch_t *w, tally_t *t,
-                        i128 *per_s, trace_t *tr)
+                        i128 *per_s, trace_t *tr, int q)
 {
-    const int q = 3;
 #if ORC_MUTANT == 4
-    const int q_prune = 4;
+    const int q_prune = q + 1;
 #else
     const int q_prune = q;
 #endif
@@ -381,13 +450,13 @@ static void bbvp_anchor(const graph_t *g, uint32_t u, int oriented, scratch_t *w
             }
             if (size_t_ < (uint64_t)q) continue;   /* |T| < q */
             t->feasible++;
-            uint64_t add = 0;
+            i128 add = 0;
 #if ORC_MUTANT == 5
-            for (int k = 0; k < 3; k++) add += choose3(x[k]);
+            for (int k = 0; k < 3; k++) add += q == 3 ? (i128)choose3(x[k]) : choose_k(x[k], q);
 #else
-            for (int k = 0; k < 4; k++) add += choose3(x[k]);
+            for (int k = 0; k < 4; k++) add += q == 3 ? (i128)choose3(x[k]) : choose_k(x[k], q);
 #endif
-            t->total += (i128)add;
+            t->total += add;
             if (per_s && add) {
                 per_s[u] += add;
                 per_s[w->cand[i]] += add;
@@ -407,6 +476,7 @@ typedef struct {
     pthread_mutex_t lock;
     int64_t stride;          /* process anchors whose index is a multiple of stride */
     int want_per_vertex;
+    int q;
     tally_t tally;
     i128 *per_s;             /* shared per-vertex, merged under the lock */
 } job_t;
@@ -429,7 +499,7 @@ static void *worker(void *arg)
         if (begin >= g->n_s) break;
         int64_t end = begin + chunk < g->n_s ? begin + chunk : g->n_s;
         for (int64_t u = begin; u < end; u++)
-            if (u % jb->stride == 0) bbvp_anchor(g, (uint32_t)u, 1, &w, &t, per, NULL);
+            if (u % jb->stride == 0) bbvp_anchor(g, (uint32_t)u, 1, &w, &t, per, NULL, jb->q);
     }
     pthread_mutex_lock(&jb->lock);
     jb->tally.total += t.total;
@@ -442,7 +512,10 @@ static void *worker(void *arg)
     return NULL;
 }
 
-/* Algorithm 2 (BBVP) for p = q = 3.
+/* Algorithm 2 (BBVP) with p = 3 on the anchor side and q (3..7) on the other
+ * (orc_count_bbvp: q = 3). A balanced (p, 3)-biclique of G is a balanced
+ * (3, p)-biclique of G with the sides exchanged, so side = 1 with q = p counts
+ * (p, 3).
  *   side: 0 anchors on U, 1 on V, -1 on the smaller partition (the paper's
  *         choice; U when equal).
  *   n_threads: worker threads over anchors (dynamic chunks of 64).
@@ -451,11 +524,13 @@ static void *worker(void *arg)
  *   out_total: the count as a 128-bit integer, little-endian words lo, hi.
  *   out_stats: [feasible triples (|T| >= 3), candidate pairs of C, side used].
  *   per_vertex: optional int64 per vertex of the side used.
- * Returns 0, -1 on a bad edge list, -2 if a per-vertex value exceeds int64. */
-int orc_count_bbvp(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu, const uint32_t *ev,
-                   const int8_t *sign, int side, int n_threads, int64_t anchor_stride,
-                   uint64_t *out_total, uint64_t *out_stats, int64_t *per_vertex)
+ * Returns 0, -1 on a bad edge list or q, -2 if a per-vertex value exceeds int64. */
+int orc_count_bbvp_q(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
+                     const uint32_t *ev, const int8_t *sign, int side, int n_threads,
+                     int64_t anchor_stride, int q, uint64_t *out_total, uint64_t *out_stats,
+                     int64_t *per_vertex)
 {
+    if (q < 3 || q > 7) return -1;
     if (side < 0) side = (n_v < n_u) ? 1 : 0;
     graph_t g;
     if (build_graph(&g, n_u, n_v, m, eu, ev, sign, side) != 0) { free_graph(&g); return -1; }
@@ -466,6 +541,7 @@ int orc_count_bbvp(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu, cons
     jb.g = &g;
     jb.stride = anchor_stride;
     jb.want_per_vertex = per_vertex != NULL;
+    jb.q = q;
     pthread_mutex_init(&jb.lock, NULL);
     if (per_vertex) jb.per_s = calloc(g.n_s + 1, sizeof(i128));
     pthread_t *th = malloc(sizeof(pthread_t) * n_threads);
@@ -492,6 +568,14 @@ int orc_count_bbvp(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu, cons
     return rc;
 }
 
+int orc_count_bbvp(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu, const uint32_t *ev,
+                   const int8_t *sign, int side, int n_threads, int64_t anchor_stride,
+                   uint64_t *out_total, uint64_t *out_stats, int64_t *per_vertex)
+{
+    return orc_count_bbvp_q(n_u, n_v, m, eu, ev, sign, side, n_threads, anchor_stride, 3,
+                            out_total, out_stats, per_vertex);
+}
+
 /* Number of balanced (3,3)-bicliques that contain vertex x of the given side
  * (0 = U, 1 = V): the per-anchor steps of Algorithm 2 with every other vertex
  * of the side as a partner. out_count gets lo, hi words of the 128-bit value.
@@ -508,7 +592,7 @@ int orc_vertex_counts(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu, c
     for (int64_t i = 0; i < n_x; i++) {
         if ((int64_t)xs[i] >= g.n_s) { rc = -1; break; }
         tally_t t = {0, 0, 0};
-        bbvp_anchor(&g, xs[i], 0, &w, &t, NULL, NULL);
+        bbvp_anchor(&g, xs[i], 0, &w, &t, NULL, NULL, 3);
         out_counts[2 * i] = (uint64_t)t.total;
         out_counts[2 * i + 1] = (uint64_t)(t.total >> 64);
     }
@@ -534,7 +618,7 @@ int orc_anchor_detail(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu, c
     scratch_init(&w, &g);
     trace_t tr = {cap_c, 0, cand, cap_pairs, 0, pairs};
     tally_t t = {0, 0, 0};
-    bbvp_anchor(&g, u, oriented, &w, &t, NULL, &tr);
+    bbvp_anchor(&g, u, oriented, &w, &t, NULL, &tr, 3);
     *n_cand = tr.n_c;
     *n_pairs = tr.n_pairs;
     out_total[0] = (uint64_t)t.total;

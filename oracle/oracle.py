@@ -67,6 +67,13 @@ def _bind(L):
                                  _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _u64p, _u64p,
                                  _i64p]
     L.orc_count_bbvp.restype = ctypes.c_int
+    L.orc_count_bbvp_q.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _u32p, _u32p,
+                                   _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                   _u64p, _u64p, _i64p]
+    L.orc_count_bbvp_q.restype = ctypes.c_int
+    L.orc_count_bruteforce_pq.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _u32p,
+                                          _u32p, _i8p, ctypes.c_int, ctypes.c_int, _u64p]
+    L.orc_count_bruteforce_pq.restype = ctypes.c_int
     L.orc_vertex_counts.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _u32p, _u32p,
                                     _i8p, ctypes.c_int, ctypes.c_int64, _u32p, _u64p]
     L.orc_vertex_counts.restype = ctypes.c_int
@@ -141,6 +148,35 @@ def count_bbvp(g, side: int = 0, threads: int = 1, anchor_stride: int = 1,
             raise OverflowError("per-vertex count exceeds int64")
         res["per_vertex"] = pv[:n_side].copy()
     return res
+
+
+def count_bbvp_q(g, q: int, side: int = 0, threads: int = 1, anchor_stride: int = 1) -> dict:
+    """Algorithm 2 with p = 3 on the anchor side and q (3..7) on the other:
+    side 0 counts balanced (3, q)-bicliques, side 1 balanced (q, 3)-bicliques.
+
+    Returns dict(total, feasible, candidates, side)."""
+    eu, ev, sg = _arrs(g)
+    out = np.zeros(2, np.uint64)
+    st = np.zeros(3, np.uint64)
+    rc = lib().orc_count_bbvp_q(g.n_u, g.n_v, eu.size, _p(eu, _u32p), _p(ev, _u32p),
+                                _p(sg, _i8p), side, threads, anchor_stride, q, _p(out, _u64p),
+                                _p(st, _u64p), None)
+    if rc != 0:
+        raise ValueError(f"orc_count_bbvp_q failed ({rc})")
+    total = int(out[0]) | (int(out[1]) << 64)
+    return {"total": total, "feasible": int(st[0]), "candidates": int(st[1]), "side": int(st[2])}
+
+
+def count_bruteforce_pq(g, p: int, q: int) -> int:
+    """Definition-level count of balanced (p, q)-bicliques (|L| = p in U,
+    |R| = q in V); tiny graphs only (n_u, n_v <= 24)."""
+    eu, ev, sg = _arrs(g)
+    out = np.zeros(1, np.uint64)
+    rc = lib().orc_count_bruteforce_pq(g.n_u, g.n_v, eu.size, _p(eu, _u32p), _p(ev, _u32p),
+                                       _p(sg, _i8p), p, q, _p(out, _u64p))
+    if rc != 0:
+        raise ValueError(f"orc_count_bruteforce_pq failed ({rc})")
+    return int(out[0])
 
 
 def vertex_counts(g, side: int, xs: Sequence[int]) -> list:

@@ -267,3 +267,64 @@ def test_bad_edges_rejected(oracle):
     assert oracle.count_bbvp(g)["total"] == 0
     empty = G._finish(0, 0, np.zeros(0), np.zeros(0), np.zeros(0, np.int8))
     assert oracle.count_bbvp(empty)["total"] == 0
+
+
+# ------------------------------------------ general q (p = 3 on one side)
+# Section 3 defines balanced (p, q)-bicliques for any p, q; Algorithm 2 takes
+# (p - 1)-subsets of the candidate set and sums C(x, q). The oracle's _q
+# variant keeps p = 3 on the anchor side; anchored on V it counts (q, 3).
+
+@pytest.mark.parametrize("n,m", [(5, 8), (7, 7), (8, 6)])
+def test_general_q_complete_all_positive(oracle, n, m):
+    """All-positive K_{n,m}: every (p,q) vertex choice is a balanced
+    biclique, C(n,p) C(m,q)."""
+    g = complete(n, m, lambda i, j: 1)
+    for p, q in [(3, 4), (3, 5), (4, 3), (3, 7), (5, 3), (4, 4), (2, 6)]:
+        assert oracle.count_bruteforce_pq(g, p, q) == math.comb(n, p) * math.comb(m, q), (p, q)
+    for q in range(3, 8):
+        assert oracle.count_bbvp_q(g, q, 0)["total"] == C3(n) * math.comb(m, q), q
+        assert oracle.count_bbvp_q(g, q, 1)["total"] == math.comb(n, q) * C3(m), q
+
+
+@pytest.mark.parametrize("n1,n2,m1,m2", [(3, 4, 4, 3), (2, 5, 5, 4), (4, 4, 6, 2), (1, 6, 7, 1)])
+def test_general_q_two_block_closed_form(oracle, n1, n2, m1, m2):
+    """The two-block sign pattern (sign -1 exactly on U2 x V2) for (3, q): a
+    triple inside U1 or U2 has equal rows, any q columns; a mixed triple needs
+    its q columns all in V1 or all in V2. For (p, 3) the same holds with the
+    sides exchanged (the pattern is its own transpose up to relabelling)."""
+    n, m = n1 + n2, m1 + m2
+    g = complete(n, m, lambda i, j: -1 if (i >= n1 and j >= m1) else 1)
+    pure = C3(n1) + C3(n2)
+    pure_t = C3(m1) + C3(m2)
+    for q in range(3, 8):
+        want = pure * math.comb(m, q) + (C3(n) - pure) * (math.comb(m1, q) + math.comb(m2, q))
+        assert oracle.count_bbvp_q(g, q, 0)["total"] == want, q
+        assert oracle.count_bruteforce_pq(g, 3, q) == want, q
+        want_t = pure_t * math.comb(n, q) + (C3(m) - pure_t) * (math.comb(n1, q) + math.comb(n2, q))
+        assert oracle.count_bbvp_q(g, q, 1)["total"] == want_t, q
+        assert oracle.count_bruteforce_pq(g, q, 3) == want_t, q
+
+
+def test_general_q_bruteforce_equals_bbvp_tiny(oracle):
+    """O1 for (3, q) and (q, 3) = Algorithm 2 with that q on U and on V, on
+    random tiny graphs (dense enough that q >= 4 common neighbours occur)."""
+    rng = np.random.default_rng(515)
+    nonzero = {q: 0 for q in (4, 5)}
+    for it in range(400):
+        g = G.tiny_random(rng, 9, 9, density=float(rng.choice([0.6, 0.8, 1.0])))
+        for q in (4, 5):
+            b = oracle.count_bruteforce_pq(g, 3, q)
+            assert oracle.count_bbvp_q(g, q, 0)["total"] == b, (it, q)
+            assert oracle.count_bbvp_q(g, q, 1)["total"] == oracle.count_bruteforce_pq(g, q, 3), (it, q)
+            nonzero[q] += b > 0
+    assert min(nonzero.values()) > 40
+
+
+def test_general_q_three_is_the_default(oracle):
+    g = G.config1(2)
+    for side in (0, 1):
+        assert oracle.count_bbvp_q(g, 3, side)["total"] == oracle.count_bbvp(g, side)["total"]
+    rng = np.random.default_rng(3)
+    for it in range(50):
+        t = G.tiny_random(rng, 8, 8, density=0.9)
+        assert oracle.count_bruteforce_pq(t, 3, 3) == oracle.count_bruteforce(t), it
