@@ -108,16 +108,23 @@ typedef struct {
 } bbc_graph_info;
 bbc_status bbc_get_graph_info(bbc_ctx *ctx, const bbc_graph *g, bbc_graph_info *out);
 
-/* Number of balanced (p,q)-bicliques of g (Problem statement, Section 3),
- * for p = q = 3. out_count: host int64. Errors: BBC_E_UNSUPPORTED,
- * BBC_E_OVERFLOW, BBC_E_NOMEM, BBC_E_HIP. */
+/* Number of balanced (p,q)-bicliques of g (Problem statement, Section 3):
+ * |L| = p vertices of U, |R| = q of V. Supported: (3, 3) on any graph;
+ * (3, q) for q = 4..7 on a graph built with BBC_ANCHOR_U, and (p, 3) for
+ * p = 4..7 on one built with BBC_ANCHOR_V (Algorithm 2 with triples on the
+ * anchor side and C(n, q) for the other; (p, 3) is (3, p) with the sides
+ * exchanged). out_count: host int64. Errors: BBC_E_UNSUPPORTED (other (p, q),
+ * or the graph anchored on the other side), BBC_E_OVERFLOW (the count, or a
+ * single C(n, q) term, does not fit 64 bits), BBC_E_NOMEM, BBC_E_HIP. */
 bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int64_t *out_count);
 
 /* Per-vertex counts: out_per_vertex[x] (caller-owned, n_u or n_v int64
  * entries, host memory) = number of balanced (3,3)-bicliques that contain
  * vertex x of the requested side (0 = U, 1 = V); their sum is 3 * count.
- * out_count (optional) receives the global count. The triples are anchored
- * on the requested side for this call. */
+ * out_count (optional) receives the global count. Only (p, q) = (3, 3).
+ * Either side works whichever side the graph is anchored on: the triples stay
+ * on the anchor side, and a vertex of the other side gets C(n - 1, 2) from
+ * every counted pair whose common class of size n holds it. */
 bbc_status bbc_count_per_vertex(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int side,
                                 int64_t *out_per_vertex, int64_t *out_count);
 

@@ -22,6 +22,7 @@ struct PairArgs {
 struct TriArgs {
     CsrView g;
     Workspace ws;
+    uint32_t q;             // mode 3: size of the vertex subsets of the opposite side
 };
 
 struct LaunchShape {
@@ -33,7 +34,7 @@ hipError_t count_pairs(const PairArgs &P, const LaunchShape &sh, hipStream_t s);
 hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_t tmp_bytes,
                       hipStream_t s);
 // mode 0: totals only; 1: also per vertex of the anchor side; 2: per vertex of
-// the opposite side
+// the opposite side; 3: totals with q (T.q, 4..7) vertices on the opposite side
 hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t s);
 // workgroups (and waves) of the per-wave tier that fit on one compute unit
 uint32_t wave_tier_blocks_per_cu();

@@ -1277,13 +1277,31 @@ __global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk
 }
 
 // ------------------------------------------------------------ triplets
+// C(n, q) for the general-q totals. After step i, c = C(n, i + 1), computed
+// as (c div d) (n - i) + (c mod d) (n - i) / d with d = i + 1, which is exact
+// because d divides c (n - i); `ovf` is set when C(n, q) needs more than 64
+// bits.
+__host__ __device__ __forceinline__ uint64_t choose_q(uint32_t n, uint32_t q, bool &ovf)
+{
+    if (n < q) return 0;
+    uint64_t c = 1;
+    for (uint32_t i = 0; i < q; i++) {
+        const uint64_t d = i + 1, f = n - i;
+        uint64_t hi;
+        if (__builtin_mul_overflow(c / d, f, &hi)) { ovf = true; return 0; }
+        const uint64_t lo = (c % d) * f / d;
+        if (__builtin_add_overflow(hi, lo, &c)) { ovf = true; return 0; }
+    }
+    return c;
+}
+
 // Rows in lanes, masks of W <= 16 words in registers; columns through
 // scalar loads, 8 at a time.
 template <int W, int MODE>
 __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
                                              const uint32_t *__restrict__ masks,
-                                             const uint32_t *c3, uint64_t *colacc,
-                                             const TriArgs &T)
+                                             const uint32_t *c3, const uint64_t *cq,
+                                             uint64_t *colacc, const TriArgs &T)
 {
     const uint32_t lane = __lane_id();
     const uint32_t i = un.rb * kWave + lane;
@@ -1296,6 +1314,17 @@ __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
     const bool diag = un.c1 > un.rb * kWave;
     uint64_t acc = 0;
     uint32_t j = un.c0;
+    if (MODE == 3) {
+        // totals with C(n, q) from the 64-bit table cq
+        for (; j < un.c1; j++) {
+            const BBC_CONST uint32_t *cp = MS + (uint64_t)j * W;
+            uint32_t n = 0;
+#pragma unroll
+            for (int w = 0; w < W; w++) n += __popc(row[w] & cp[w]);
+            acc += (!diag || j < i) ? cq[n] : 0ull;
+        }
+        return acc;
+    }
     if (MODE == 0) {
         // 8 columns = 8*W consecutive words: one pointer, immediate offsets.
         // Only units that reach the diagonal need the j < i test.
@@ -1414,9 +1443,18 @@ __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
 #pragma unroll
         for (int c = 0; c < 8; c++) {
             const uint32_t j = un.c0 + cg + c;
-            const uint64_t t = (cg + c < ncol && j < i) ? choose3(n[c]) : 0;
+            uint64_t t = 0;
+            if (cg + c < ncol && j < i) {
+                if (MODE == 3) {
+                    bool ovf = false;
+                    t = choose_q(n[c], T.q, ovf);
+                    if (ovf) atomicOr(&T.ws.ctr->over_cap, 16u);
+                } else {
+                    t = choose3(n[c]);
+                }
+            }
             acc += t;
-            if (MODE != 0 && t) {
+            if ((MODE == 1 || MODE == 2) && t) {
                 if (MODE == 1) {
                     atomicAdd((unsigned long long *)&colacc[cg + c], (unsigned long long)t);
                 } else {
@@ -1728,18 +1766,23 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
 // classes 1 and 2 (both need about the whole register file, so one kernel
 // for the two costs no occupancy and saves a tail). Waves per SIMD: totals
 // of masks up to kSmallW words 3, other totals and per-vertex counts of the
-// anchor side 2, per-vertex counts of the other side 5.
+// anchor side 2, per-vertex counts of the other side and totals for q > 3 5.
 __host__ __device__ constexpr int tri_waves(int mode, int cls)
 {
-    return mode == 0 ? (cls == 0 ? 3 : 2) : (mode == 1 ? 2 : 5);
+    return mode == 0 ? (cls == 0 ? 3 : 2) : (mode == 1 ? 2 : 5);   // mode 3 as mode 2
 }
 
 template <int MODE, int CLS>
 __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(TriArgs T)
 {
     __shared__ uint32_t c3[kC3Max + 1];
+    __shared__ uint64_t cq[MODE == 3 ? kC3Max + 1 : 1];   // C(n, q), n <= 32 kRegW
     __shared__ unsigned long long colacc_all[MODE == 1 ? kTThreads / kWave : 1][MODE == 1 ? kMaxChunk : 1];
     for (uint32_t i = threadIdx.x; i <= kC3Max; i += kTThreads) c3[i] = (uint32_t)choose3(i);
+    if (MODE == 3) {
+        bool ovf = false;   // C(512, 7) < 2^51
+        for (uint32_t i = threadIdx.x; i <= kC3Max; i += kTThreads) cq[i] = choose_q(i, T.q, ovf);
+    }
     if (MODE == 1)
         for (uint32_t i = threadIdx.x; i < (kTThreads / kWave) * kMaxChunk; i += kTThreads)
             (&colacc_all[0][0])[i] = 0;
@@ -1813,7 +1856,7 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
                 }
 #undef BBC_W
             } else {
-#define BBC_W(n) case n: acc = tri_rows<n, MODE>(un, a, T.ws.masks, c3, colacc, T); break;
+#define BBC_W(n) case n: acc = tri_rows<n, MODE>(un, a, T.ws.masks, c3, cq, colacc, T); break;
                 if constexpr (CLS == 0) {
                     switch (a.w32) { BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) default: break; }
                 } else {
@@ -1917,15 +1960,23 @@ hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_
 hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t s)
 {
     // masks of up to 4 words, then the wider ones
-    if (mode == 0) {
-        hipLaunchKernelGGL((k_triplet<0, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
-        hipLaunchKernelGGL((k_triplet<0, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
-    } else if (mode == 1) {
-        hipLaunchKernelGGL((k_triplet<1, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
-        hipLaunchKernelGGL((k_triplet<1, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
-    } else {
-        hipLaunchKernelGGL((k_triplet<2, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
-        hipLaunchKernelGGL((k_triplet<2, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
+    switch (mode) {
+        case 0:
+            hipLaunchKernelGGL((k_triplet<0, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
+            hipLaunchKernelGGL((k_triplet<0, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_triplet<1, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
+            hipLaunchKernelGGL((k_triplet<1, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_triplet<2, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
+            hipLaunchKernelGGL((k_triplet<2, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
+            break;
+        default:
+            hipLaunchKernelGGL((k_triplet<3, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
+            hipLaunchKernelGGL((k_triplet<3, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
+            break;
     }
     return hipGetLastError();
 }

@@ -615,7 +615,8 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
 struct CountReq {
     const GraphSet *set;
     uint32_t g0, g1;        // graph range
-    int mode;               // 0 totals, 1 per vertex of S, 2 per vertex of O
+    int mode;               // 0 totals, 1 per vertex of S, 2 per vertex of O, 3 totals for q > 3
+    uint32_t q;             // mode 3: vertices taken on the opposite side
 };
 
 uint64_t hint_key(const GraphSet &set)
@@ -767,6 +768,7 @@ LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
     L.ls.grid_t = std::max(1u, ctx->num_cus * shp.grid_t_per_cu);
     L.T.g = L.P.g;
     L.T.ws = ws;
+    L.T.q = r.mode == 3 ? r.q : 3u;
     L.mode = r.mode;
     L.G = set.G; L.NS = set.NS; L.NO = set.NO;
     L.ptmp = w.ptmp.p;
@@ -813,6 +815,7 @@ bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set)
 {
     const Counters *c = w.host.as<Counters>();
     if (c->over_cap & 8u) fail(BBC_E_HIP, "internal error: pair table lookup failed");
+    if (c->over_cap & 16u) fail(BBC_E_OVERFLOW, "a term C(n, q) of the count needs more than 64 bits");
     if (c->over_cap & 4u)
         fail(BBC_E_UNSUPPORTED, "an anchor has degree above %u or more than %u candidate classes",
              tier_c_max_degree(), tier_c_max_k());
@@ -865,9 +868,9 @@ Shape default_shape() { return Shape(); }
 
 // One synchronous count of a graph range; grows buffers and retries as needed.
 void count_sync(bbc_ctx *ctx, Work &w, GraphSet &set, uint32_t g0, uint32_t g1, int mode,
-                const Shape &shp, hipStream_t s, int64_t *out)
+                const Shape &shp, hipStream_t s, int64_t *out, uint32_t q = 3)
 {
-    CountReq r{&set, g0, g1, mode};
+    CountReq r{&set, g0, g1, mode, q};
     const bool timed = ctx->timing && s == ctx->stream && &w == &ctx->work;
     const bool tune = set.tune_key && mode == 0 && s == ctx->stream && &w == &ctx->work;
     if (tune && !ctx->tev[0]) {
@@ -1160,7 +1163,7 @@ const char *bbc_status_string(bbc_status s)
         case BBC_E_DUP_EDGE: return "duplicate edge";
         case BBC_E_NOMEM: return "out of device memory or over the memory cap";
         case BBC_E_OVERFLOW: return "count does not fit in int64";
-        case BBC_E_UNSUPPORTED: return "unsupported (only p = q = 3)";
+        case BBC_E_UNSUPPORTED: return "unsupported (p, q) or input";
         case BBC_E_NOT_READY: return "request not finished";
         case BBC_E_UNKNOWN_TICKET: return "unknown ticket";
         case BBC_E_HIP: return "HIP runtime error";
@@ -1285,10 +1288,25 @@ bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int6
     if (!ctx) return BBC_E_INVAL;
     return guard(ctx, [&] {
         if (!g || !out_count) fail(BBC_E_INVAL, "null argument");
-        if (p != 3 || q != 3) fail(BBC_E_UNSUPPORTED, "only (p, q) = (3, 3) is supported");
+        // (3, q) anchors triples on U, (p, 3) on V (the same count with the
+        // sides exchanged); (3, 3) runs on whichever side the graph was built
+        const uint32_t side = g->set->desc[g->idx].side;
+        uint32_t qq = 3;
+        if (p == 3 && q == 3) {
+            qq = 3;
+        } else if (p == 3 && q >= 4 && q <= 7) {
+            if (side != 0) fail(BBC_E_UNSUPPORTED, "(3, %d) needs a graph built with BBC_ANCHOR_U", q);
+            qq = (uint32_t)q;
+        } else if (q == 3 && p >= 4 && p <= 7) {
+            if (side != 1) fail(BBC_E_UNSUPPORTED, "(%d, 3) needs a graph built with BBC_ANCHOR_V", p);
+            qq = (uint32_t)p;
+        } else {
+            fail(BBC_E_UNSUPPORTED, "(p, q) = (%d, %d): supported are (3, 3..7) and (3..7, 3)", p, q);
+        }
         (void)hipSetDevice(ctx->device);
         int64_t v = 0;
-        count_sync(ctx, ctx->work, *g->set, g->idx, g->idx + 1, 0, default_shape(), ctx->stream, &v);
+        count_sync(ctx, ctx->work, *g->set, g->idx, g->idx + 1, qq == 3 ? 0 : 3, default_shape(),
+                   ctx->stream, &v, qq);
         *out_count = v;
     });
 }

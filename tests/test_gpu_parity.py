@@ -185,7 +185,7 @@ def test_invalid_inputs(ctx, B):
     assert ei.value.name == "BBC_E_SIGN"
     h = build(ctx, G.config1(1))
     with pytest.raises(B.BBCError) as ei:
-        ctx.count_global(h, 4, 3)
+        ctx.count_global(h, 4, 4)
     assert ei.value.name == "BBC_E_UNSUPPORTED"
     # the context is still usable after errors
     assert ctx.count_global(h) > 0
@@ -390,3 +390,72 @@ def test_side_stats_batch(ctx):
     hs = ctx.build_csr_batch(nu, nv, off, eu, ev, sg)
     got = [h.info().anchor_side for h in hs]
     assert got == want
+
+
+
+# ------------------------------------------- general q (p = 3 on one side)
+def _complete_rows(n, m, neg):
+    return ["".join("-" if neg(i, j) else "+" for j in range(m)) for i in range(n)]
+
+
+def test_general_q_closed_forms(ctx):
+    """All-positive K_{n,m}: C(n,p) C(m,q); the two-block pattern (sign -1
+    on U2 x V2): pure C(m,q) + mixed (C(m1,q) + C(m2,q)) for (3, q), and the
+    same with the sides exchanged for (q, 3)."""
+    say("general q closed forms")
+    comb = math.comb
+    for n, m in [(6, 9), (9, 7)]:
+        g = G.from_rows(_complete_rows(n, m, lambda i, j: False))
+        hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
+        for q in range(3, 8):
+            assert ctx.count_global(hu, 3, q) == C3(n) * comb(m, q), (n, m, q)
+            assert ctx.count_global(hv, q, 3) == comb(n, q) * C3(m), (n, m, q)
+    for n1, n2, m1, m2 in [(3, 4, 6, 3), (5, 4, 4, 5), (2, 7, 8, 1)]:
+        n, m = n1 + n2, m1 + m2
+        g = G.from_rows(_complete_rows(n, m, lambda i, j: i >= n1 and j >= m1))
+        hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
+        pure, pure_t = C3(n1) + C3(n2), C3(m1) + C3(m2)
+        for q in range(3, 8):
+            want = pure * comb(m, q) + (C3(n) - pure) * (comb(m1, q) + comb(m2, q))
+            want_t = pure_t * comb(n, q) + (C3(m) - pure_t) * (comb(n1, q) + comb(n2, q))
+            assert ctx.count_global(hu, 3, q) == want, (n1, n2, m1, m2, q)
+            assert ctx.count_global(hv, q, 3) == want_t, (n1, n2, m1, m2, q)
+
+
+def test_general_q_vs_oracle(ctx, oracle):
+    """(3, q) on U and (q, 3) on V against Algorithm 2 with that q, on the
+    small configurations (planted balanced blocks make q >= 4 counts large),
+    and against the definition on dense tiny graphs."""
+    say("general q vs oracle")
+    for g in [G.config1(1), G.config1(4), G.config2(5, scale=0.04)]:
+        hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
+        for q in (4, 5, 6, 7):
+            want_u = oracle.count_bbvp_q(g, q, 0, threads=8)["total"]
+            want_v = oracle.count_bbvp_q(g, q, 1, threads=8)["total"]
+            assert ctx.count_global(hu, 3, q) == want_u, (g.n_u, q)
+            assert ctx.count_global(hv, q, 3) == want_v, (g.n_u, q)
+        # q = 3 through the same call equals the (3,3) count on either side
+        assert ctx.count_global(hu, 3, 3) == ctx.count_global(hv, 3, 3)
+    rng = np.random.default_rng(808)
+    nonzero = 0
+    for it in range(120):
+        g = G.tiny_random(rng, 9, 9, density=float(rng.choice([0.7, 0.9, 1.0])))
+        hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
+        for q in (4, 5):
+            b = oracle.count_bruteforce_pq(g, 3, q)
+            assert ctx.count_global(hu, 3, q) == b, (it, q)
+            assert ctx.count_global(hv, q, 3) == oracle.count_bruteforce_pq(g, q, 3), (it, q)
+            nonzero += b > 0
+        hu.free(); hv.free()
+    assert nonzero > 20
+
+
+def test_general_q_rejected(ctx, B):
+    say("general q rejected")
+    g = G.config1(2)
+    hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
+    for h, p, q in [(hv, 3, 4), (hu, 4, 3), (hu, 3, 8), (hu, 4, 4), (hu, 2, 3), (hv, 3, 2)]:
+        with pytest.raises(B.BBCError) as ei:
+            ctx.count_global(h, p, q)
+        assert ei.value.name == "BBC_E_UNSUPPORTED", (p, q)
+    assert ctx.count_global(hu, 3, 5) >= 0
