@@ -193,6 +193,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-general-q", action="store_true",
+                    help="skip the timing of the (3, q) and (q, 3) counts, q = 4..7")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (5 times), the reference for "
                          "the HBM byte counters")
@@ -277,7 +279,7 @@ def main():
         # the int8 matrix cores; the wider ones on the vector ALUs)
         ops = 64.0 * st["pair_words"]
         achieved = ops / (kern_avg["ms_triplet"] / 1e3) / 1e12
-        roof = {"kernel": "triplet phase: k_triplet<0,narrow> + k_triplet<0,wide>", "bound": "mfma",
+        roof = {"kernel": "triplet phase: k_triplet<0,0> + k_triplet<0,1>", "bound": "mfma",
                 "achieved": round(achieved, 3), "peak": MFMA_I8_PEAK_TOPS, "unit": "TOP/s",
                 "frac": round(achieved / MFMA_I8_PEAK_TOPS, 4),
                 "algorithmic_ops_per_launch": ops,
@@ -320,6 +322,25 @@ def main():
                                                  "deferred_c", "deferred_d")},
         "roofline": roof,
     }
+
+    if not args.no_general_q:
+        # balanced (3, q) on a U-anchored build and (q, 3) on a V-anchored one,
+        # same workload; exactness against the oracle is in the GPU tests
+        log("general q")
+        gq = {"(3,q)": {}, "(q,3)": {}}
+        for flags, key in ((1 << 4, "(3,q)"), (1 << 5, "(q,3)")):
+            h = ctx.build_csr(g.n_u, g.n_v, d_eu, d_ev, d_sg, flags)
+            for q in range(4, 8):
+                pq = (3, q) if key == "(3,q)" else (q, 3)
+                ts = []
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t = time.time()
+                    c = ctx.count_global(h, *pq)
+                    ts.append(1e3 * (time.time() - t))
+                gq[key][str(q)] = {"count": c, "ms": round(sorted(ts)[1], 3)}
+            h.free()
+        out["general_q"] = gq
 
     if not args.no_cpu:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)

@@ -2,7 +2,7 @@
 
 Calls only the CPU oracle (oracle/) on the seeded generators; nothing here
 touches the HIP library. Run from the repository root:
-    python tests/golden/make_golden.py [cfg2] [cfg3]
+    python tests/golden/make_golden.py [cfg2] [cfg3] [cfg2q]
 """
 import hashlib
 import json
@@ -85,8 +85,29 @@ def cfg3():
     print("cfg3 sample", out["oracle_seconds"])
 
 
+def cfg2q():
+    """Balanced (3, q) and (q, 3) counts of config 2 for q = 4, 5: Algorithm 2
+    with that q, anchored on U and on V respectively."""
+    g = G.config2(1)
+    t = time.time()
+    counts = {}
+    for q in (4, 5):
+        counts[f"3,{q}"] = O.count_bbvp_q(g, q, 0, threads=THREADS)["total"]
+        counts[f"{q},3"] = O.count_bbvp_q(g, q, 1, threads=THREADS)["total"]
+    out = {
+        "workload": "config2 seed 1 (as cfg2_seed1.json)",
+        "source": "oracle/ Algorithm 2 with p = 3 on the anchor side and q on the other "
+                  "(orc_count_bbvp_q; (q, 3) anchored on V) (tests/golden/make_golden.py)",
+        "m": g.m, "counts": counts,
+        "oracle_seconds": round(time.time() - t, 1), "oracle_threads": THREADS,
+    }
+    with open(os.path.join(HERE, "cfg2_seed1_general_q.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("cfg2q", counts, out["oracle_seconds"])
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["cfg2", "cfg3"]
+    which = sys.argv[1:] or ["cfg2", "cfg3", "cfg2q"]
     O.build()
     for w in which:
         globals()[w]()

@@ -459,3 +459,18 @@ def test_general_q_rejected(ctx, B):
             ctx.count_global(h, p, q)
         assert ei.value.name == "BBC_E_UNSUPPORTED", (p, q)
     assert ctx.count_global(hu, 3, 5) >= 0
+
+
+def test_general_q_config2_full(ctx):
+    """Config 2 at full size: (3, 4), (3, 5) anchored on U and (4, 3), (5, 3)
+    anchored on V against the oracle's values (cfg2_seed1_general_q.json,
+    written by tests/golden/make_golden.py from oracle/ only)."""
+    say("general q config2 full")
+    gold = golden("cfg2_seed1_general_q.json")
+    g = G.config2(1)
+    assert g.m == gold["m"]
+    hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
+    for key, want in gold["counts"].items():
+        p, q = (int(x) for x in key.split(","))
+        got = ctx.count_global(hu if p == 3 else hv, p, q)
+        assert got == want, key
