@@ -238,14 +238,26 @@ __global__ void __launch_bounds__(kT) k_s_finish(BuildArgs a)
 // S vertex starts and how long it is.
 __global__ void __launch_bounds__(kT) k_o_finish(BuildArgs a)
 {
-    for (uint64_t t = (uint64_t)blockIdx.x * kT + threadIdx.x; t < a.M;
-         t += (uint64_t)gridDim.x * kT) {
-        const uint32_t ts = a.val1[t];
-        const uint32_t ent = a.o_ent[ts];
+    // every thread of the grid runs the same number of rounds, so that whole
+    // waves take part in the shuffles below
+    const uint64_t stride = (uint64_t)gridDim.x * kT;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * kT; t0 < a.M; t0 += stride) {
+        const uint64_t t = t0 + threadIdx.x;
+        const bool in = t < a.M;
+        const uint32_t ts = in ? a.val1[t] : 0u;
+        const uint32_t ent = in ? a.o_ent[ts] : 0u;
+        const uint32_t v = in ? (uint32_t)a.key1[t] : 0u;
+        // the previous position's entry and O vertex: from the lane below, or
+        // loaded by the first lane of the wave
+        uint32_t ent_p = __shfl_up(ent, 1, kWave), v_p = __shfl_up(v, 1, kWave);
+        if (__lane_id() == 0 && in && t > 0) {
+            ent_p = a.o_ent[a.val1[t - 1]];
+            v_p = (uint32_t)a.key1[t - 1];
+        }
+        if (!in) continue;
         a.o_adj[t] = ent;
-        const uint32_t v = (uint32_t)a.key1[t];
         // a repeated (u, v) pair: equal neighbours in one O list are adjacent
-        if (t > 0 && (uint32_t)a.key1[t - 1] == v && (a.o_ent[a.val1[t - 1]] >> 1) == (ent >> 1))
+        if (t > 0 && v_p == v && (ent_p >> 1) == (ent >> 1))
             atomicOr(a.err, kErrDup);
         uint32_t len = (uint32_t)(a.o_off[v + 1] - t - 1);
         if (len < 2) len = 0;
