@@ -73,7 +73,8 @@ constexpr uint32_t kEmpty = 0xffffffffu;
 constexpr uint32_t kC3Max = 512;       // C(n,3) table covers masks of up to 16 words
 constexpr uint32_t kRegW = 16;         // widest mask kept in registers per row
 constexpr uint32_t kWideCols = 64;     // unit width (columns) for wider masks
-constexpr uint32_t kMfmaMaxW = 16;     // widest mask counted on the matrix cores
+constexpr uint32_t kMfmaMaxW = 16;     // widest mask counted with the rows held in registers
+constexpr int kFp4MinW = 3;            // narrowest mask counted on the fp4 matrix cores
 constexpr uint32_t kMaskChunk = 1u << 16;   // mask words reserved per workgroup at a time
 constexpr uint32_t kCandChunk = 1u << 13;
 constexpr uint32_t kRecChunk = 16;
@@ -1605,6 +1606,36 @@ __device__ __forceinline__ v4i32 mask_piece(uint32_t raw, int t, uint32_t g, boo
     return spread_word(raw, 4 * (g & 1u), valid && w < (uint32_t)W);
 }
 
+// fp4 operands: v_mfma_scale_f32_16x16x128_f8f6f4 with both operands in e2m1
+// (and unit scales) multiplies 16 x 128 by 128 x 16; lane l supplies row (or
+// column) l % 16, elements 32 (l / 16) .. + 31, eight per register. A mask
+// bit becomes the element 1.0 (code 0b0010) or 0, so every product is 0 or 1
+// and the fp32 sums are exact integers (n <= 32 W < 2^24). One 32-bit mask
+// word fills a lane's four registers: element i of register q is bit 4 i + q
+// (spread_fp4), half the VALU work per bit of the int8 form, and each
+// instruction covers twice its K.
+typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef int v8i32 __attribute__((ext_vector_type(8)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+constexpr int kFp4 = 4;       // operand format code of e2m1 (A and B)
+constexpr int kScale1 = 127;  // e8m0 scale 2^0
+
+__device__ __forceinline__ v8i32 spread_fp4(uint32_t x, bool keep)
+{
+    const uint32_t m = keep ? 0x22222222u : 0u;
+    v8i32 r = {0, 0, 0, 0, 0, 0, 0, 0};
+    r[0] = (int)((x << 1) & m);
+    r[1] = (int)(x & m);
+    r[2] = (int)((x >> 1) & m);
+    r[3] = (int)((x >> 2) & m);
+    return r;
+}
+
+__device__ __forceinline__ v4f32 mfma_fp4(const v8i32 &a, const v8i32 &b, const v4f32 &c)
+{
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, kFp4, kFp4, 0, kScale1, 0, kScale1);
+}
+
 // Sum over the unit's pairs (j < i) of C(|M_i n M_j|, 3), masks of W words.
 // The 64 rows go in passes of SBP 16-row blocks, so that the spread row
 // operands (SBP x ceil(W/2) x 4 registers) stay in registers and each spread
@@ -1691,58 +1722,179 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
     return sum / 6;
 }
 
-// Masks wider than 16 words (totals): 64 rows x up to 64 columns per unit.
-// The products of all four column tiles stay in accumulators while the mask
-// words go by in K-blocks of 8 words (4 chunks): a row piece is spread once
-// per K-block and unit, a column piece once per unit. n can reach 32 W here,
-// so the epilogue is 64-bit: n (n - 1) (n - 2) = n ((n^2 + 2) - 3 n), which
-// is 0 for n = 0, 1, 2 with unsigned wrap-around.
+// The same sum on the fp4 matrix cores. Lane group g holds words
+// NC g .. NC g + NC - 1 of its row or column (NC = ceil(W / 4), one load of
+// NC consecutive words, at most NC - 1 of them past the row) and chunk t takes
+// word NC g + t, the same placement for rows and columns; words past the mask
+// width are dropped by the spread. The rows of all four blocks stay in
+// registers (4 NC x 4), so every unit is one pass; accumulators start at -1
+// and the epilogue converts D = n - 1 to integers.
+template <int W>
+__device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
+                                 const uint32_t *__restrict__ masks)
+{
+    constexpr int NC = (W + 3) / 4;          // 128-bit K-chunks
+    constexpr int SB = 4;
+    const uint32_t lane = __lane_id();
+    const uint32_t g = lane >> 4, r16 = lane & 15u;
+    const uint32_t *M = masks + a.mask_off;
+    const uint32_t rbase = un.rb * kWave;
+    const uint32_t wf = g * NC;                           // first word of the lane's piece
+    const uint32_t ws = wf < (uint32_t)W ? wf : (uint32_t)W - 1;
+    auto words = [&](uint32_t row, uint32_t (&raw)[NC]) {
+        const uint32_t *p = M + (row * (uint32_t)W + ws);
+        if constexpr (NC == 4) {
+            const u32x4a4 v = *reinterpret_cast<const u32x4a4 *>(p);
+            raw[0] = v.x; raw[1] = v.y; raw[2] = v.z; raw[3] = v.w;
+        } else {
+#pragma unroll
+            for (int t = 0; t < NC; t++) raw[t] = p[t];
+        }
+    };
+    auto piece = [&](uint32_t raw, int t, bool valid) {
+        return spread_fp4(raw, valid && wf + t < (uint32_t)W);
+    };
+    v8i32 A[SB][NC];
+#pragma unroll
+    for (int sb = 0; sb < SB; sb++) {
+        const uint32_t i = rbase + 16 * sb + r16;
+        uint32_t raw[NC];
+        words(i < a.k ? i : a.k - 1, raw);
+#pragma unroll
+        for (int t = 0; t < NC; t++) A[sb][t] = piece(raw[t], t, i < a.k);
+    }
+    auto col_words = [&](uint32_t j0, uint32_t (&raw)[NC]) {
+        const uint32_t j = j0 + r16;
+        words(j < un.c1 ? j : un.c1 - 1, raw);
+    };
+    auto products = [&](const uint32_t (&raw)[NC], uint32_t j0, v4f32 (&acc)[SB]) {
+        const bool vj = j0 + r16 < un.c1;
+#pragma unroll
+        for (int sb = 0; sb < SB; sb++) acc[sb] = (v4f32){-1.f, -1.f, -1.f, -1.f};
+#pragma unroll
+        for (int t = 0; t < NC; t++) {
+            const v8i32 B = piece(raw[t], t, vj);
+#pragma unroll
+            for (int sb = 0; sb < SB; sb++) acc[sb] = mfma_fp4(A[sb][t], B, acc[sb]);
+        }
+    };
+    auto epilogue = [&](const v4f32 (&acc)[SB], uint32_t j0) -> uint32_t {
+        v4i32 d[SB];
+#pragma unroll
+        for (int sb = 0; sb < SB; sb++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) d[sb][e] = (int)acc[sb][e];
+        if (j0 + 16 <= rbase) return cubic_sum<W, SB, false>(d, 0, 0);
+        return cubic_sum<W, SB, true>(d, j0 + r16, rbase + 4 * g);
+    };
+    uint64_t sum = 0;
+    uint32_t w0[NC], w1[NC];
+    v4f32 acc0[SB], acc1[SB];
+    uint32_t j0 = un.c0;
+    col_words(j0, w0);
+    if (j0 + 16 < un.c1) col_words(j0 + 16, w1);
+    products(w0, j0, acc0);
+    for (;;) {
+        bool more = j0 + 16 < un.c1;
+        if (more) {
+            if (j0 + 32 < un.c1) col_words(j0 + 32, w0);
+            products(w1, j0 + 16, acc1);
+        }
+        sum += epilogue(acc0, j0);
+        if (!more) break;
+        j0 += 16;
+        more = j0 + 16 < un.c1;
+        if (more) {
+            if (j0 + 32 < un.c1) col_words(j0 + 32, w1);
+            products(w0, j0 + 16, acc0);
+        }
+        sum += epilogue(acc1, j0);
+        if (!more) break;
+        j0 += 16;
+    }
+    return sum / 6;
+}
+
+// Masks wider than 16 words (totals): 64 rows x up to 64 columns per unit,
+// on the fp4 matrix cores. The products of all four column tiles stay in
+// accumulators while the mask words go by in K-blocks of 16 words: lane
+// group g holds words 4 g .. 4 g + 3 of its row or column (one 16-byte load)
+// and chunk t takes word 4 g + t, the same placement for rows and columns.
+// The last W mod 16 words go by chunks of four consecutive words (chunk t,
+// group g: word 4 t + g), so that no chunk past the mask is issued and no
+// word past a row is read. n can reach 32 W, so the epilogue is 64-bit:
+// n (n - 1) (n - 2) = n ((n^2 + 2) - 3 n), which is 0 for n = 0, 1, 2 with
+// unsigned wrap-around.
 __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
                                        const uint32_t *__restrict__ masks)
 {
-    constexpr int KB = 4;                    // chunks per K-block
+    constexpr uint32_t KW = 16;              // words per K-block
     const uint32_t lane = __lane_id();
     const uint32_t g = lane >> 4, r16 = lane & 15u;
     const uint32_t W = a.w32;
-    const uint32_t NC = (W + 1) / 2;
     const uint32_t *M = masks + a.mask_off;
     const uint32_t rbase = un.rb * kWave;
     const uint32_t nt = (un.c1 - un.c0 + 15) / 16;   // column tiles (<= 4)
-    const uint32_t h4 = 4 * (g & 1u);
-    v4i32 acc[4][4];
+    // word offsets of the lane's rows and columns (k W < 2^32), clamped to
+    // valid candidates
+    uint32_t ro[4], co[4];
+    bool rv[4], cv[4];
+#pragma unroll
+    for (int sb = 0; sb < 4; sb++) {
+        const uint32_t i = rbase + 16 * sb + r16;
+        rv[sb] = i < a.k;
+        ro[sb] = (rv[sb] ? i : a.k - 1) * W;
+        const uint32_t j = un.c0 + 16 * sb + r16;
+        cv[sb] = j < un.c1;
+        co[sb] = (cv[sb] ? j : un.c1 - 1) * W;
+    }
+    v4f32 acc[4][4];
 #pragma unroll
     for (int tt = 0; tt < 4; tt++)
 #pragma unroll
-        for (int sb = 0; sb < 4; sb++) acc[tt][sb] = (v4i32){0, 0, 0, 0};
-    for (uint32_t kc = 0; kc < NC; kc += KB) {
-        v4i32 Ab[4][KB];
+        for (int sb = 0; sb < 4; sb++) acc[tt][sb] = (v4f32){0.f, 0.f, 0.f, 0.f};
+    const uint32_t Wf = W & ~(KW - 1);
+    for (uint32_t w0 = 0; w0 < Wf; w0 += KW) {
+        const uint32_t wl = w0 + 4 * g;
+        uint32_t ra[4][4], rc[4][4];
 #pragma unroll
         for (int sb = 0; sb < 4; sb++) {
-            const uint32_t i = rbase + 16 * sb + r16;
-            const bool vi = i < a.k;
-            const uint32_t *mr = M + (uint64_t)(vi ? i : a.k - 1) * W;
-#pragma unroll
-            for (int t = 0; t < KB; t++) {
-                const uint32_t w = 2 * (kc + t) + (g >> 1);
-                const uint32_t raw = mr[w < W ? w : W - 1];
-                Ab[sb][t] = spread_word(raw, h4, vi && w < W);
-            }
+            const u32x4a4 v = *reinterpret_cast<const u32x4a4 *>(M + (ro[sb] + wl));
+            ra[sb][0] = v.x; ra[sb][1] = v.y; ra[sb][2] = v.z; ra[sb][3] = v.w;
         }
 #pragma unroll
         for (int tt = 0; tt < 4; tt++) {
             if ((uint32_t)tt >= nt) break;
-            const uint32_t j = un.c0 + 16 * tt + r16;
-            const bool vj = j < un.c1;
-            const uint32_t *mc = M + (uint64_t)(vj ? j : un.c1 - 1) * W;
+            const u32x4a4 v = *reinterpret_cast<const u32x4a4 *>(M + (co[tt] + wl));
+            rc[tt][0] = v.x; rc[tt][1] = v.y; rc[tt][2] = v.z; rc[tt][3] = v.w;
+        }
 #pragma unroll
-            for (int t = 0; t < KB; t++) {
-                const uint32_t w = 2 * (kc + t) + (g >> 1);
-                const uint32_t raw = mc[w < W ? w : W - 1];
-                const v4i32 B = spread_word(raw, h4, vj && w < W);
+        for (int t = 0; t < 4; t++) {
+            v8i32 A[4];
 #pragma unroll
-                for (int sb = 0; sb < 4; sb++)
-                    acc[tt][sb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Ab[sb][t], B, acc[tt][sb], 0, 0, 0);
+            for (int sb = 0; sb < 4; sb++) A[sb] = spread_fp4(ra[sb][t], rv[sb]);
+#pragma unroll
+            for (int tt = 0; tt < 4; tt++) {
+                if ((uint32_t)tt >= nt) break;
+                const v8i32 B = spread_fp4(rc[tt][t], cv[tt]);
+#pragma unroll
+                for (int sb = 0; sb < 4; sb++) acc[tt][sb] = mfma_fp4(A[sb], B, acc[tt][sb]);
             }
+        }
+    }
+    for (uint32_t w = Wf; w < W; w += 4) {
+        const uint32_t wg = w + g;
+        const bool kw = wg < W;
+        const uint32_t wa = kw ? wg : W - 1;
+        v8i32 A[4];
+#pragma unroll
+        for (int sb = 0; sb < 4; sb++) A[sb] = spread_fp4(M[ro[sb] + wa], rv[sb] && kw);
+#pragma unroll
+        for (int tt = 0; tt < 4; tt++) {
+            if ((uint32_t)tt >= nt) break;
+            const v8i32 B = spread_fp4(M[co[tt] + wa], cv[tt] && kw);
+#pragma unroll
+            for (int sb = 0; sb < 4; sb++) acc[tt][sb] = mfma_fp4(A[sb], B, acc[tt][sb]);
         }
     }
     uint64_t sum = 0;
@@ -1763,13 +1915,14 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
 }
 
 // Two kernels per mode: CLS 0 takes the units of class 0, CLS 1 those of
-// classes 1 and 2 (both need about the whole register file, so one kernel
-// for the two costs no occupancy and saves a tail). Waves per SIMD: totals
-// of masks up to kSmallW words 3, other totals and per-vertex counts of the
-// anchor side 2, per-vertex counts of the other side and totals for q > 3 5.
+// classes 1 and 2 (one kernel for the two saves a tail). Waves per SIMD:
+// totals of masks up to kSmallW words 4, other totals 3 (both measured
+// faster than 3 and 2 in spite of a few spilled registers, reloaded once per
+// column tile), per-vertex counts of the anchor side 2, per-vertex counts of
+// the other side and totals for q > 3 5.
 __host__ __device__ constexpr int tri_waves(int mode, int cls)
 {
-    return mode == 0 ? (cls == 0 ? 3 : 2) : (mode == 1 ? 2 : 5);   // mode 3 as mode 2
+    return mode == 0 ? (cls == 0 ? 4 : 3) : (mode == 1 ? 2 : 5);   // mode 3 as mode 2
 }
 
 template <int MODE, int CLS>
@@ -1844,7 +1997,7 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
         } else {
             // only the widths of this kernel's class are instantiated
             if (MODE == 0 && a.w32 <= kMfmaMaxW) {
-#define BBC_W(n) case n: acc = tri_rows_mfma<n>(un, a, T.ws.masks); break;
+#define BBC_W(n) case n: acc = n >= kFp4MinW ? tri_rows_fp4<n>(un, a, T.ws.masks) : tri_rows_mfma<n>(un, a, T.ws.masks); break;
                 if constexpr (CLS == 0) {
                     switch (a.w32) { BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) default: break; }
                 } else {
