@@ -73,6 +73,32 @@ def test_two_block_closed_form(ctx):
             assert ctx.count_global(build(ctx, g, flags)) == want
 
 
+def _complete_signed(n, m, n1, m1):
+    """K_{n,m} with sign -1 exactly on rows >= n1 x columns >= m1, as COO."""
+    u, v = np.divmod(np.arange(n * m, dtype=np.int64), m)
+    s = np.where((u >= n1) & (v >= m1), -1, 1).astype(np.int8)
+    return G._finish(n, m, u, v, s)
+
+
+@pytest.mark.parametrize("w", [1, 2, 3, 4, 5, 8, 9, 16, 17, 32, 33, 64])
+def test_full_masks_every_width(ctx, w):
+    """Anchored on U, every mask of K_{67, 32 w} has all 32 w bits set, so
+    each candidate pair has the largest intersection its width allows (the
+    top of each width class of the triplet kernels); 67 rows leave a ragged
+    second row block. The two-block sign pattern splits each anchor's
+    candidates into two classes of different sizes."""
+    n, m = 67, 32 * w
+    say("full masks", w)
+    g = _complete_signed(n, m, n, m)
+    assert ctx.count_global(build(ctx, g, 1 << 4)) == C3(n) * C3(m)
+    n1, m1 = 40, m - m // 3
+    n2, m2 = n - n1, m - m1
+    g = _complete_signed(n, m, n1, m1)
+    pure = C3(n1) + C3(n2)
+    want = pure * C3(m) + (C3(n) - pure) * (C3(m1) + C3(m2))
+    assert ctx.count_global(build(ctx, g, 1 << 4)) == want
+
+
 # --------------------------------------------------------- random tiny
 def test_tiny_random_batch_vs_bruteforce(ctx, oracle):
     say("tiny batch")
