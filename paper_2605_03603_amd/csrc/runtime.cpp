@@ -204,6 +204,9 @@ struct GraphSet {
     DBuf s_suf;
     // sizing hints learnt by earlier counts
     uint64_t hint_masks = 0, hint_cands = 0, hint_units = 0;
+    // oriented wedges through the opposite sides, sum over graphs of
+    // sum_o C(d_o, 2) (the first workspace guess of a single graph)
+    uint64_t wedges_o = 0;
     // anchor-side tuning of a single large graph: shape key and side used
     uint64_t tune_key = 0;
     uint32_t tune_side = 0;
@@ -542,6 +545,7 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
         }
         d.n_s = d.side ? d.n_v : d.n_u;
         d.n_o = d.side ? d.n_u : d.n_v;
+        set->wedges_o += d.side ? h_stats[g] : h_stats[G + g];
         d.s_base = (uint32_t)ns; d.o_base = (uint32_t)no;
         sbase[g] = d.s_base; obase[g] = d.o_base;
         ns += d.n_s; no += d.n_o;
@@ -647,6 +651,29 @@ void ensure_work(bbc_ctx *ctx, Work &w, GraphSet &set)
     uint64_t want_masks = std::max<uint64_t>({set.hint_masks, 2 * M, 1ull << 22});
     uint64_t want_cands = std::max<uint64_t>({set.hint_cands, M / 2, 1ull << 20});
     uint64_t want_units = std::max<uint64_t>({set.hint_units, M / 16, 1ull << 16});
+    if (set.G == 1 && set.hint_masks == 0 && set.wedges_o > 0) {
+        // no count of this shape yet: the Chung-Lu workloads need 0.23 W2
+        // (100k x 50k) to 0.42 W2 (2M x 500k, wider masks) mask words, under
+        // 0.07 W2 candidates and under W2 / 60 units (W2 = the oriented
+        // wedges); with some margin these are taken if they fit a quarter of
+        // the free device memory and a third of the room left under the
+        // context's cap
+        const uint64_t W2 = set.wedges_o;
+        const uint64_t gm = W2 / 20 * 9, gc = W2 / 10, gu = W2 / 40;
+        const uint64_t bytes = 4 * (gm + gc) + sizeof(Unit) * gu;
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            (void)hipGetLastError();
+            fr = 0;
+        }
+        uint64_t room = fr / 4;
+        if (al->cap()) room = std::min<uint64_t>(room, al->cap() > al->used() ? (al->cap() - al->used()) / 3 : 0);
+        if (bytes <= room) {
+            want_masks = std::max(want_masks, gm);
+            want_cands = std::max(want_cands, gc);
+            want_units = std::max(want_units, gu);
+        }
+    }
     if (w.cap_anchors < want_anchors) {
         w.anchors.ensure(al, want_anchors * sizeof(AnchorRec));
         w.ucnt.ensure(al, 3 * want_anchors * 4);
