@@ -1728,10 +1728,12 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
 // word NC g + t, the same placement for rows and columns; words past the mask
 // width are dropped by the spread. The rows of all four blocks stay in
 // registers (4 NC x 4), so every unit is one pass; accumulators start at -1
-// and the epilogue converts D = n - 1 to integers.
-template <int W>
+// and the epilogue converts D = n - 1 to integers. MODE 0 sums C(n, 3) (the
+// cubic, divided by 6 once); MODE 3 sums C(n, q) from the workgroup's table
+// cq (n <= 32 W <= 512).
+template <int W, int MODE>
 __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
-                                 const uint32_t *__restrict__ masks)
+                                 const uint32_t *__restrict__ masks, const uint64_t *cq)
 {
     constexpr int NC = (W + 3) / 4;          // 128-bit K-chunks
     constexpr int SB = 4;
@@ -1778,14 +1780,29 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
             for (int sb = 0; sb < SB; sb++) acc[sb] = mfma_fp4(A[sb][t], B, acc[sb]);
         }
     };
-    auto epilogue = [&](const v4f32 (&acc)[SB], uint32_t j0) -> uint32_t {
-        v4i32 d[SB];
+    auto epilogue = [&](const v4f32 (&acc)[SB], uint32_t j0) -> uint64_t {
+        if constexpr (MODE == 3) {
+            // element e of block sb: row rbase + 16 sb + 4 g + e, column j0 + r16
+            const bool diag = j0 + 16 > rbase;
+            const uint32_t j = j0 + r16, i0 = rbase + 4 * g;
+            uint64_t t = 0;
 #pragma unroll
-        for (int sb = 0; sb < SB; sb++)
+            for (int sb = 0; sb < SB; sb++)
 #pragma unroll
-            for (int e = 0; e < 4; e++) d[sb][e] = (int)acc[sb][e];
-        if (j0 + 16 <= rbase) return cubic_sum<W, SB, false>(d, 0, 0);
-        return cubic_sum<W, SB, true>(d, j0 + r16, rbase + 4 * g);
+                for (int e = 0; e < 4; e++) {
+                    const uint32_t n = (uint32_t)((int)acc[sb][e] + 1);
+                    if (!diag || j < i0 + 16 * sb + e) t += cq[n];
+                }
+            return t;
+        } else {
+            v4i32 d[SB];
+#pragma unroll
+            for (int sb = 0; sb < SB; sb++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) d[sb][e] = (int)acc[sb][e];
+            if (j0 + 16 <= rbase) return cubic_sum<W, SB, false>(d, 0, 0);
+            return cubic_sum<W, SB, true>(d, j0 + r16, rbase + 4 * g);
+        }
     };
     uint64_t sum = 0;
     uint32_t w0[NC], w1[NC];
@@ -1812,7 +1829,7 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
         if (!more) break;
         j0 += 16;
     }
-    return sum / 6;
+    return MODE == 3 ? sum : sum / 6;
 }
 
 // Masks wider than 16 words (totals): 64 rows x up to 64 columns per unit,
@@ -1918,11 +1935,11 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
 // classes 1 and 2 (one kernel for the two saves a tail). Waves per SIMD:
 // totals of masks up to kSmallW words 4, other totals 3 (both measured
 // faster than 3 and 2 in spite of a few spilled registers, reloaded once per
-// column tile), per-vertex counts of the anchor side 2, per-vertex counts of
-// the other side and totals for q > 3 5.
+// column tile; the same for totals with q > 3), per-vertex counts of the
+// anchor side 2, per-vertex counts of the other side 5.
 __host__ __device__ constexpr int tri_waves(int mode, int cls)
 {
-    return mode == 0 ? (cls == 0 ? 4 : 3) : (mode == 1 ? 2 : 5);   // mode 3 as mode 2
+    return (mode == 0 || mode == 3) ? (cls == 0 ? 4 : 3) : (mode == 1 ? 2 : 5);
 }
 
 template <int MODE, int CLS>
@@ -1996,8 +2013,16 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
             }
         } else {
             // only the widths of this kernel's class are instantiated
-            if (MODE == 0 && a.w32 <= kMfmaMaxW) {
-#define BBC_W(n) case n: acc = n >= kFp4MinW ? tri_rows_fp4<n>(un, a, T.ws.masks) : tri_rows_mfma<n>(un, a, T.ws.masks); break;
+            // totals: the matrix cores (fp4 from kFp4MinW words; below it int8
+            // for C(n, 3), the VALU path for C(n, q))
+            constexpr bool mc = MODE == 0 || MODE == 3;
+            if (mc && a.w32 <= kMfmaMaxW) {
+#define BBC_W(n)                                                                                       \
+    case n:                                                                                            \
+        if constexpr (mc && n >= kFp4MinW) acc = tri_rows_fp4<n, MODE>(un, a, T.ws.masks, cq);         \
+        else if constexpr (MODE == 0) acc = tri_rows_mfma<n>(un, a, T.ws.masks);                       \
+        else acc = tri_rows<n, MODE>(un, a, T.ws.masks, c3, cq, colacc, T);                            \
+        break;
                 if constexpr (CLS == 0) {
                     switch (a.w32) { BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) default: break; }
                 } else {
