@@ -122,6 +122,7 @@ struct Workspace {
     unsigned long long *count;   // [G] totals
     uint32_t *carry;             // [G] carries out of 64 bits
     unsigned long long *pv;      // [NS] per-vertex (by global rank) or null
+    unsigned long long *pv_slot; // [cap_cands] per candidate slot, anchor-side per-vertex counts
     unsigned long long *pv_o;    // [NO] per-vertex of the opposite side or null
 };
 

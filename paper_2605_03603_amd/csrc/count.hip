@@ -1730,10 +1730,16 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
 // registers (4 NC x 4), so every unit is one pass; accumulators start at -1
 // and the epilogue converts D = n - 1 to integers. MODE 0 sums C(n, 3) (the
 // cubic, divided by 6 once); MODE 3 sums C(n, q) from the workgroup's table
-// cq (n <= 32 W <= 512).
+// cq (n <= 32 W <= 512). MODE 1 (per vertex of the anchor side) takes C(n, 3)
+// per pair from the table c3, adds each column's total to the wave's colacc
+// (one lane per column) and keeps 16 row totals per lane, which are summed
+// over the lane group at the end of the unit and handed out so that lane L
+// returns the total of row 64 rb + L (a row total is at most C(512, 3) x 128
+// < 2^32 for W <= 16, as the unit has at most 2048 / W columns).
 template <int W, int MODE>
 __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
-                                 const uint32_t *__restrict__ masks, const uint64_t *cq)
+                                 const uint32_t *__restrict__ masks, const uint64_t *cq,
+                                 const uint32_t *c3, uint64_t *colacc)
 {
     constexpr int NC = (W + 3) / 4;          // 128-bit K-chunks
     constexpr int SB = 4;
@@ -1780,8 +1786,30 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
             for (int sb = 0; sb < SB; sb++) acc[sb] = mfma_fp4(A[sb][t], B, acc[sb]);
         }
     };
+    uint32_t rs[SB][4];   // MODE 1: row totals of the lane's 16 rows over its columns
+#pragma unroll
+    for (int sb = 0; sb < SB; sb++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) rs[sb][e] = 0;
     auto epilogue = [&](const v4f32 (&acc)[SB], uint32_t j0) -> uint64_t {
-        if constexpr (MODE == 3) {
+        if constexpr (MODE == 1) {
+            const bool diag = j0 + 16 > rbase;
+            const uint32_t j = j0 + r16, i0 = rbase + 4 * g;
+            uint32_t cs = 0;
+#pragma unroll
+            for (int sb = 0; sb < SB; sb++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const uint32_t n = (uint32_t)((int)acc[sb][e] + 1);
+                    const uint32_t t = (!diag || j < i0 + 16 * sb + e) ? c3[n] : 0u;
+                    rs[sb][e] += t;
+                    cs += t;
+                }
+            cs += __shfl_xor(cs, 16, kWave);
+            cs += __shfl_xor(cs, 32, kWave);
+            if (g == 0 && j < un.c1 && cs) colacc[j - un.c0] += cs;
+            return 0;
+        } else if constexpr (MODE == 3) {
             // element e of block sb: row rbase + 16 sb + 4 g + e, column j0 + r16
             const bool diag = j0 + 16 > rbase;
             const uint32_t j = j0 + r16, i0 = rbase + 4 * g;
@@ -1828,6 +1856,26 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
         sum += epilogue(acc1, j0);
         if (!more) break;
         j0 += 16;
+    }
+    if constexpr (MODE == 1) {
+        // row totals over the 16 lanes of the group (their columns), then lane
+        // L takes row 64 rb + L: block L / 16, group (L / 4) % 4, element L % 4
+#pragma unroll
+        for (int sb = 0; sb < SB; sb++)
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) rs[sb][e] += __shfl_xor(rs[sb][e], o, kWave);
+        const uint32_t src = 16 * ((lane >> 2) & 3u), want = 4 * (lane >> 4) + (lane & 3u);
+        uint32_t mine = 0;
+#pragma unroll
+        for (int sb = 0; sb < SB; sb++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint32_t v = __shfl(rs[sb][e], src, kWave);
+                mine = (uint32_t)(4 * sb + e) == want ? v : mine;
+            }
+        return mine;
     }
     return MODE == 3 ? sum : sum / 6;
 }
@@ -2013,15 +2061,17 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
             }
         } else {
             // only the widths of this kernel's class are instantiated
-            // totals: the matrix cores (fp4 from kFp4MinW words; below it int8
-            // for C(n, 3), the VALU path for C(n, q))
-            constexpr bool mc = MODE == 0 || MODE == 3;
+            // the matrix cores for all but the per-vertex counts of the other
+            // side (C(n, 3) totals: fp4 from kFp4MinW words, int8 below; C(n, q)
+            // totals and anchor-side per-vertex counts: fp4 at every width)
+            constexpr bool mc = MODE != 2;
             if (mc && a.w32 <= kMfmaMaxW) {
 #define BBC_W(n)                                                                                       \
     case n:                                                                                            \
-        if constexpr (mc && n >= kFp4MinW) acc = tri_rows_fp4<n, MODE>(un, a, T.ws.masks, cq);         \
-        else if constexpr (MODE == 0) acc = tri_rows_mfma<n>(un, a, T.ws.masks);                       \
-        else acc = tri_rows<n, MODE>(un, a, T.ws.masks, c3, cq, colacc, T);                            \
+        if constexpr (MODE != 0 || n >= kFp4MinW)                                                      \
+            acc = tri_rows_fp4<n, MODE>(un, a, T.ws.masks, cq, c3, colacc);                            \
+        else                                                                                           \
+            acc = tri_rows_mfma<n>(un, a, T.ws.masks);                                                 \
         break;
                 if constexpr (CLS == 0) {
                     switch (a.w32) { BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) default: break; }
@@ -2055,15 +2105,16 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
         }
         total += acc;
         if (MODE == 1) {
-            // this lane's row total, the anchor's total, and the column totals
-            if (i < a.k && acc)
-                atomicAdd(&T.ws.pv[T.ws.cands[a.cand_off + i]], (unsigned long long)acc);
+            // this lane's row total, the anchor's total, and the column totals;
+            // candidates are summed in their own slots (only the units of one
+            // anchor meet there) and scattered to their vertices once at the end
+            if (i < a.k && acc) atomicAdd(&T.ws.pv_slot[a.cand_off + i], (unsigned long long)acc);
             const uint64_t tot = wave_sum<uint64_t>(acc);
             if (lane == 0 && tot) atomicAdd(&T.ws.pv[a.rank], (unsigned long long)tot);
             for (uint32_t c = lane; c < un.c1 - un.c0; c += kWave) {
                 const uint64_t v = colacc[c];
                 if (v) {
-                    atomicAdd(&T.ws.pv[T.ws.cands[a.cand_off + un.c0 + c]], (unsigned long long)v);
+                    atomicAdd(&T.ws.pv_slot[a.cand_off + un.c0 + c], (unsigned long long)v);
                     colacc[c] = 0;
                 }
             }
@@ -2075,6 +2126,28 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
     if (lane == 0 && examined) {
         atomicAdd(&C->pairs_examined, (unsigned long long)examined);
         atomicAdd(&C->pair_words, (unsigned long long)exwords);
+    }
+}
+
+// Anchor-side per-vertex counts: the candidate slots in use (the cursor of
+// the pair tables) are cleared before the triplet kernels and scattered to
+// their vertices after them, one atomic per slot. A vertex that is a
+// candidate of many anchors then takes one update per anchor and class
+// instead of one per unit row and column.
+__global__ void __launch_bounds__(256) k_pv_slot_clear(Workspace ws)
+{
+    const uint64_t n = min((uint64_t)__atomic_load_n(&ws.ctr->cand_cursor, __ATOMIC_RELAXED), ws.cap_cands);
+    for (uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (uint64_t)gridDim.x * 256)
+        ws.pv_slot[t] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_pv_slot_scatter(Workspace ws)
+{
+    if (__atomic_load_n(&ws.ctr->over_cap, __ATOMIC_RELAXED)) return;
+    const uint64_t n = min((uint64_t)__atomic_load_n(&ws.ctr->cand_cursor, __ATOMIC_RELAXED), ws.cap_cands);
+    for (uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (uint64_t)gridDim.x * 256) {
+        const unsigned long long v = ws.pv_slot[t];
+        if (v) atomicAdd(&ws.pv[ws.cands[t]], v);
     }
 }
 
@@ -2144,8 +2217,10 @@ hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t
             hipLaunchKernelGGL((k_triplet<0, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
             break;
         case 1:
+            hipLaunchKernelGGL(k_pv_slot_clear, dim3(grid), dim3(256), 0, s, T.ws);
             hipLaunchKernelGGL((k_triplet<1, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
             hipLaunchKernelGGL((k_triplet<1, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
+            hipLaunchKernelGGL(k_pv_slot_scatter, dim3(grid), dim3(256), 0, s, T.ws);
             break;
         case 2:
             hipLaunchKernelGGL((k_triplet<2, 0>), dim3(grid), dim3(kTThreads), 0, s, T);

@@ -239,7 +239,7 @@ namespace {
 // Count workspace (one per stream that counts).
 struct Work {
     DBuf ctr, anchors, units, masks, cands, defer0, defer1, defer2, defer3, gtab, dtab, bscr, count,
-        carry, pv, pv_o;
+        carry, pv, pv_o, pv_slot;
     DBuf ucnt, uoff, ptmp;
     HBuf host;          // counters + counts + carries read back
     HBuf bhost;         // small staging of the CSR builder
@@ -754,6 +754,7 @@ Workspace ws_view(Work &w, bool pv, bool pvo)
     ws.count = w.count.as<unsigned long long>();
     ws.carry = w.carry.as<uint32_t>();
     ws.pv = pv ? w.pv.as<unsigned long long>() : nullptr;
+    ws.pv_slot = pv ? w.pv_slot.as<unsigned long long>() : nullptr;
     ws.pv_o = pvo ? w.pv_o.as<unsigned long long>() : nullptr;
     return ws;
 }
@@ -906,7 +907,10 @@ void count_sync(bbc_ctx *ctx, Work &w, GraphSet &set, uint32_t g0, uint32_t g1, 
     }
     for (int attempt = 0; attempt < 8; attempt++) {
         ensure_work(ctx, w, set);
-        if (mode == 1) w.pv.ensure(ctx->al.get(), std::max<uint64_t>(set.NS, 1) * 8);
+        if (mode == 1) {
+            w.pv.ensure(ctx->al.get(), std::max<uint64_t>(set.NS, 1) * 8);
+            w.pv_slot.ensure(ctx->al.get(), std::max<uint64_t>(w.cap_cands, 1) * 8);
+        }
         if (mode == 2) w.pv_o.ensure(ctx->al.get(), std::max<uint64_t>(set.NO, 1) * 8);
         if (tune) HIP_OK(hipEventRecord(ctx->tev[0], s));
         enqueue_count(ctx, w, r, shp, s, timed);
