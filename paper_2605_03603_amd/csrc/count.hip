@@ -1384,17 +1384,17 @@ __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
             if (MODE == 1) {
                 atomicAdd((unsigned long long *)&colacc[j - un.c0], (unsigned long long)t);
             } else {
-                // every member of the common class lies in C(n-1, 2) of these bicliques
+                // every member of the common class lies in C(n-1, 2) of these
+                // bicliques: summed per anchor position in the wave's LDS array
+                // (colacc here), scattered to the vertices once per unit
                 const uint64_t each = choose2(n - 1);
-                const uint64_t s0 = T.g.s_off[a.rank];
 #pragma unroll
                 for (int w = 0; w < W; w++) {
                     uint32_t m = row[w] & cw[w];
                     while (m) {
                         const uint32_t b = __ffs(m) - 1;
                         m &= m - 1;
-                        const uint32_t o = T.g.s_adj[s0 + w * 32 + b] >> 1;
-                        atomicAdd(&T.ws.pv_o[o], (unsigned long long)each);
+                        atomicAdd((unsigned long long *)&colacc[w * 32 + b], (unsigned long long)each);
                     }
                 }
             }
@@ -1995,14 +1995,17 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
 {
     __shared__ uint32_t c3[kC3Max + 1];
     __shared__ uint64_t cq[MODE == 3 ? kC3Max + 1 : 1];   // C(n, q), n <= 32 kRegW
-    __shared__ unsigned long long colacc_all[MODE == 1 ? kTThreads / kWave : 1][MODE == 1 ? kMaxChunk : 1];
+    // per wave: column totals of a unit (MODE 1) or totals per anchor position,
+    // masks up to kRegW words (MODE 2)
+    constexpr uint32_t kLacc = MODE == 1 ? kMaxChunk : (MODE == 2 ? 32 * kRegW : 1);
+    __shared__ unsigned long long colacc_all[MODE == 1 || MODE == 2 ? kTThreads / kWave : 1][kLacc];
     for (uint32_t i = threadIdx.x; i <= kC3Max; i += kTThreads) c3[i] = (uint32_t)choose3(i);
     if (MODE == 3) {
         bool ovf = false;   // C(512, 7) < 2^51
         for (uint32_t i = threadIdx.x; i <= kC3Max; i += kTThreads) cq[i] = choose_q(i, T.q, ovf);
     }
-    if (MODE == 1)
-        for (uint32_t i = threadIdx.x; i < (kTThreads / kWave) * kMaxChunk; i += kTThreads)
+    if (MODE == 1 || MODE == 2)
+        for (uint32_t i = threadIdx.x; i < (kTThreads / kWave) * kLacc; i += kTThreads)
             (&colacc_all[0][0])[i] = 0;
     __syncthreads();
     Counters *C = T.ws.ctr;
@@ -2014,7 +2017,7 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
     const uint32_t n_units = u_end - u_base;
     Cursor *queue = C->q_tri[CLS];
     const uint32_t lane = __lane_id();
-    uint64_t *colacc = (uint64_t *)colacc_all[MODE == 1 ? threadIdx.x / kWave : 0];
+    uint64_t *colacc = (uint64_t *)colacc_all[MODE == 1 || MODE == 2 ? threadIdx.x / kWave : 0];
     uint64_t examined = 0, exwords = 0;
     uint64_t total = 0;
     uint32_t cur_graph = 0xffffffffu;
@@ -2104,6 +2107,18 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
             exwords += (uint64_t)ex * a.w32;
         }
         total += acc;
+        if (MODE == 2 && !wide) {
+            // the unit's totals per anchor position to the opposite vertices
+            const uint64_t s0 = T.g.s_off[a.rank];
+            const uint32_t d = (uint32_t)(T.g.s_off[a.rank + 1] - s0);
+            for (uint32_t p = lane; p < d; p += kWave) {
+                const uint64_t v = colacc[p];
+                if (v) {
+                    atomicAdd(&T.ws.pv_o[T.g.s_adj[s0 + p] >> 1], (unsigned long long)v);
+                    colacc[p] = 0;
+                }
+            }
+        }
         if (MODE == 1) {
             // this lane's row total, the anchor's total, and the column totals;
             // candidates are summed in their own slots (only the units of one
