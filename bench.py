@@ -191,6 +191,7 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=8192)
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-edges", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-general-q", action="store_true",
@@ -342,6 +343,28 @@ def main():
                 gq[key][str(q)] = {"count": c, "ms": round(sorted(ts)[1], 3)}
             h.free()
         out["general_q"] = gq
+
+    if not args.no_edges:
+        # edge queries (balanced bicliques through an edge: the change of the
+        # count on inserting, deleting or re-signing it), 200 existing edges
+        # with their own sign and 200 new pairs, one after the other;
+        # exactness against the oracle is in the GPU tests
+        log("edge queries")
+        rng = np.random.default_rng(7)
+        h = ctx.build_csr(g.n_u, g.n_v, d_eu, d_ev, d_sg, 1 << 4)
+        idx = rng.choice(g.m, size=200, replace=False)
+        qu = np.concatenate([g.eu[idx], rng.integers(0, g.n_u, 200)]).astype(np.uint32)
+        qv = np.concatenate([g.ev[idx], rng.integers(0, g.n_v, 200)]).astype(np.uint32)
+        qs = np.concatenate([g.sign[idx], np.ones(200, np.int8)]).astype(np.int8)
+        ctx.count_through_edges(h, qu[:8], qv[:8], qs[:8])
+        torch.cuda.synchronize()
+        t = time.time()
+        through = ctx.count_through_edges(h, qu, qv, qs)
+        ms = 1e3 * (time.time() - t)
+        h.free()
+        out["edge_queries"] = {"queries": int(qu.size), "ms_per_query": round(ms / qu.size, 4),
+                               "existing_edges_sum": int(through[:200].sum()),
+                               "new_pairs_sum": int(through[200:].sum())}
 
     if not args.no_cpu:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)

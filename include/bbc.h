@@ -118,6 +118,22 @@ bbc_status bbc_get_graph_info(bbc_ctx *ctx, const bbc_graph *g, bbc_graph_info *
  * single C(n, q) term, does not fit 64 bits), BBC_E_NOMEM, BBC_E_HIP. */
 bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int64_t *out_count);
 
+/* Edge queries for dynamic graphs (Section 6 names dynamic signed bipartite
+ * graphs as the next direction). For query i, out[i] = number of balanced
+ * (3,3)-bicliques that contain the edge (eu[i], ev[i]) (ids of U and V) in g
+ * with that edge present with sign es[i] (+1 / -1): added if g lacks it,
+ * re-signed if g has it with the other sign. This is the change of the
+ * global count when the edge is inserted with sign es[i]; deleting an edge
+ * of sign s changes the count by minus the query with s, and flipping it by
+ * the query with -s minus the query with s. Every other edge is as in g.
+ * All arrays are host memory of n_queries entries (out caller-owned); the
+ * queries run one after the other on the context's stream. Errors:
+ * BBC_E_RANGE (an id outside the graph), BBC_E_SIGN (a sign other than
+ * +1 / -1), BBC_E_OVERFLOW, BBC_E_NOMEM, BBC_E_HIP; out is then unspecified. */
+bbc_status bbc_count_through_edges(bbc_ctx *ctx, const bbc_graph *g, uint64_t n_queries,
+                                   const uint32_t *eu, const uint32_t *ev, const int8_t *es,
+                                   int64_t *out);
+
 /* Per-vertex counts: out_per_vertex[x] (caller-owned, n_u or n_v int64
  * entries, host memory) = number of balanced (3,3)-bicliques that contain
  * vertex x of the requested side (0 = U, 1 = V); their sum is 3 * count.

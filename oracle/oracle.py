@@ -209,3 +209,34 @@ def anchor_detail(g, side: int, u: int, oriented: bool = True, cap: int = 4096):
     return {"candidates": [int(c) for c in cand[:int(nc[0])]],
             "pairs": [tuple(int(x) for x in pairs[7 * i:7 * i + 7]) for i in range(n)],
             "total": int(tot[0]) | (int(tot[1]) << 64)}
+
+
+class _Edges:
+    """A graph with an edge list of its own (the attributes the counts read)."""
+
+    def __init__(self, n_u, n_v, eu, ev, sign):
+        self.n_u, self.n_v = n_u, n_v
+        self.eu = np.ascontiguousarray(eu, np.uint32)
+        self.ev = np.ascontiguousarray(ev, np.uint32)
+        self.sign = np.ascontiguousarray(sign, np.int8)
+
+
+def count_through_edge(g, u: int, v: int, s: int, brute: bool = False, threads: int = 1) -> int:
+    """Balanced (3,3)-bicliques that contain the edge (u, v) of sign s in g
+    with that edge set to s (added or re-signed): by definition the count of
+    that graph minus the count of g without the edge, both from the counts
+    above (the definition itself with brute=True, else Algorithm 2). This is
+    the change of the count when the edge is inserted with sign s, the
+    quantity behind dynamic updates, which Section 6 names as the next
+    direction. No arithmetic of its own: it rests on the two (pinned) counts
+    it subtracts."""
+    eu = np.asarray(g.eu, np.int64)
+    ev = np.asarray(g.ev, np.int64)
+    sg = np.asarray(g.sign, np.int8)
+    keep = ~((eu == u) & (ev == v))
+    without = _Edges(g.n_u, g.n_v, eu[keep], ev[keep], sg[keep])
+    with_e = _Edges(g.n_u, g.n_v, np.append(eu[keep], u), np.append(ev[keep], v),
+                    np.append(sg[keep], np.int8(s)))
+    if brute:
+        return count_bruteforce(with_e) - count_bruteforce(without)
+    return count_bbvp(with_e, 0, threads=threads)["total"] - count_bbvp(without, 0, threads=threads)["total"]

@@ -35,6 +35,7 @@ BBC_ANCHOR_SMALLER = 1 << 6
 
 EXPORTED = ["bbc_ctx_create", "bbc_ctx_destroy", "bbc_build_csr", "bbc_build_csr_batch",
             "bbc_graph_free", "bbc_get_graph_info", "bbc_count_global", "bbc_count_per_vertex",
+            "bbc_count_through_edges",
             "bbc_count_batch", "bbc_submit", "bbc_submit_coo", "bbc_poll", "bbc_wait",
             "bbc_get_last_stats", "bbc_set_timing", "bbc_status_string", "bbc_last_error"]
 
@@ -87,6 +88,7 @@ def _load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.bbc_count_global.argtypes = [_vp, _vp, _i32, _i32, ctypes.POINTER(ctypes.c_int64)]
     L.bbc_count_per_vertex.argtypes = [_vp, _vp, _i32, _i32, _i32, _vp,
                                        ctypes.POINTER(ctypes.c_int64)]
+    L.bbc_count_through_edges.argtypes = [_vp, _vp, _u64, _vp, _vp, _vp, _vp]
     L.bbc_count_batch.argtypes = [_vp, _vp, _u32, _vp]
     L.bbc_submit.argtypes = [_vp, _vp, ctypes.POINTER(_u64)]
     L.bbc_submit_coo.argtypes = [_vp, _u32, _u32, _u64, _vp, _vp, _vp, _u32, ctypes.POINTER(_u64)]
@@ -208,6 +210,23 @@ class Context:
         out = ctypes.c_int64()
         self._check(lib.bbc_count_global(self.handle, g.handle, p, q, ctypes.byref(out)))
         return out.value
+
+    def count_through_edges(self, g: Graph, eu, ev, es) -> np.ndarray:
+        """Balanced (3,3)-bicliques through each queried edge (eu[i], ev[i])
+        taken with sign es[i] (+1 / -1): the change of the count when the edge
+        is inserted with that sign (bbc_count_through_edges)."""
+        eu = np.ascontiguousarray(eu, dtype=np.uint32)
+        ev = np.ascontiguousarray(ev, dtype=np.uint32)
+        es = np.ascontiguousarray(es, dtype=np.int8)
+        if not (eu.shape == ev.shape == es.shape) or eu.ndim != 1:
+            raise ValueError("eu, ev, es must be 1-D arrays of one length")
+        out = np.zeros(eu.shape[0], dtype=np.int64)
+        self._check(lib.bbc_count_through_edges(self.handle, g.handle, eu.shape[0],
+                                                eu.ctypes.data_as(ctypes.c_void_p),
+                                                ev.ctypes.data_as(ctypes.c_void_p),
+                                                es.ctypes.data_as(ctypes.c_void_p),
+                                                out.ctypes.data_as(ctypes.c_void_p)))
+        return out
 
     def count_per_vertex(self, g: Graph, side: int, p: int = 3, q: int = 3) -> Tuple[np.ndarray, int]:
         info = g.info()

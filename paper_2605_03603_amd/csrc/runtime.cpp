@@ -26,6 +26,7 @@
 #include "bbc.h"
 #include "bbc_build.h"
 #include "bbc_count.h"
+#include "bbc_edge.h"
 
 using namespace bbc;
 
@@ -207,6 +208,7 @@ struct GraphSet {
     // oriented wedges through the opposite sides, sum over graphs of
     // sum_o C(d_o, 2) (the first workspace guess of a single graph)
     uint64_t wedges_o = 0;
+    uint32_t max_deg = 0;   // largest vertex degree of the set, either side
     // anchor-side tuning of a single large graph: shape key and side used
     uint64_t tune_key = 0;
     uint32_t tune_side = 0;
@@ -522,6 +524,7 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
     if (err & kErrRange) fail(BBC_E_RANGE, "edge %llu has an endpoint out of range", (unsigned long long)first_bad);
     if (err & kErrSign) fail(BBC_E_SIGN, "edge %llu has an invalid sign", (unsigned long long)first_bad);
     const uint32_t maxdu = h_flags[1], maxdv = h_flags[2];
+    set->max_deg = std::max(maxdu, maxdv);
 
     // side choice and S/O numbering
     uint64_t ns = 0, no = 0;
@@ -1339,6 +1342,65 @@ bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int6
         count_sync(ctx, ctx->work, *g->set, g->idx, g->idx + 1, qq == 3 ? 0 : 3, default_shape(),
                    ctx->stream, &v, qq);
         *out_count = v;
+    });
+}
+
+bbc_status bbc_count_through_edges(bbc_ctx *ctx, const bbc_graph *g, uint64_t n_queries,
+                                   const uint32_t *eu, const uint32_t *ev, const int8_t *es,
+                                   int64_t *out)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return guard(ctx, [&] {
+        if (!g) fail(BBC_E_INVAL, "null graph");
+        if (n_queries == 0) return;
+        if (!eu || !ev || !es || !out) fail(BBC_E_INVAL, "null argument");
+        const GraphSet &set = *g->set;
+        const GraphDesc &d = set.desc[g->idx];
+        for (uint64_t i = 0; i < n_queries; i++) {
+            if (eu[i] >= d.n_u || ev[i] >= d.n_v)
+                fail(BBC_E_RANGE, "query %llu: edge (%u, %u) outside %u x %u", (unsigned long long)i,
+                     eu[i], ev[i], d.n_u, d.n_v);
+            if (es[i] != 1 && es[i] != -1)
+                fail(BBC_E_SIGN, "query %llu: sign %d is not +1 or -1", (unsigned long long)i, (int)es[i]);
+        }
+        (void)hipSetDevice(ctx->device);
+        Allocator *al = ctx->al.get();
+        hipStream_t s = ctx->stream;
+        // scratch for the largest degree D of the set
+        const uint64_t D = set.max_deg;
+        uint32_t lg = 6;
+        while ((1ull << lg) < 2 * (D + 1)) lg++;
+        const uint64_t H = 1ull << lg;
+        const uint64_t mask_words = (D + 1) * (D / 32 + 1);
+        DBuf ctl, res, hk, hv, part, masks;
+        ctl.ensure(al, 8 * 4);
+        res.ensure(al, 8);
+        hk.ensure(al, H * 4);
+        hv.ensure(al, H * 4);
+        part.ensure(al, (D + 1) * 4);
+        masks.ensure(al, mask_words * 4);
+        EdgeScratch x;
+        x.ctl = ctl.as<uint32_t>();
+        x.result = res.as<unsigned long long>();
+        x.hkey = hk.as<uint32_t>();
+        x.hval = hv.as<uint32_t>();
+        x.lg = lg;
+        x.part = part.as<uint32_t>();
+        x.masks = masks.as<uint32_t>();
+        const CsrView view = set.view();
+        const uint32_t grid = std::max(1u, (uint32_t)ctx->num_cus * 4);
+        for (uint64_t i = 0; i < n_queries; i++) {
+            // a on the anchor side S, b on the other
+            const uint32_t a = d.side ? ev[i] : eu[i];
+            const uint32_t b = d.side ? eu[i] : ev[i];
+            HIP_OK(edge_through(view, d.s_base, d.n_s, a, d.o_base + b, es[i] < 0 ? 1u : 0u, x, grid, s));
+            unsigned long long v = 0;
+            HIP_OK(hipMemcpyAsync(&v, x.result, 8, hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            if (v > (unsigned long long)INT64_MAX) fail(BBC_E_OVERFLOW, "query %llu: count needs more than 63 bits",
+                                                        (unsigned long long)i);
+            out[i] = (int64_t)v;
+        }
     });
 }
 

@@ -328,3 +328,33 @@ def test_general_q_three_is_the_default(oracle):
     for it in range(50):
         t = G.tiny_random(rng, 8, 8, density=0.9)
         assert oracle.count_bruteforce_pq(t, 3, 3) == oracle.count_bruteforce(t), it
+
+
+# ------------------------------------------------------- edges (dynamic graphs)
+def test_through_edge_closed_forms(oracle):
+    """All-positive K_{n,m}: every edge lies in C(n-1, 2) C(m-1, 2) balanced
+    (3,3)-bicliques; with its sign flipped, in none (each butterfly through it
+    then has one negative edge); a missing edge inserted with + closes the
+    complete graph again."""
+    for n, m in [(3, 3), (4, 5), (6, 4)]:
+        g = G.from_rows(["+" * m] * n)
+        want = math.comb(n - 1, 2) * math.comb(m - 1, 2)
+        assert oracle.count_through_edge(g, 1, 2, 1, brute=True) == want
+        assert oracle.count_through_edge(g, 1, 2, -1, brute=True) == 0
+        rows = ["+" * m] * n
+        rows[0] = "." + "+" * (m - 1)
+        assert oracle.count_through_edge(G.from_rows(rows), 0, 0, 1, brute=True) == want
+
+
+def test_through_edge_sums_to_nine_times_count(oracle):
+    """Every balanced (3,3)-biclique has 9 edges, so the queries of all edges
+    with their own signs sum to 9 B (brute force on tiny random graphs)."""
+    rng = np.random.default_rng(41)
+    for _ in range(25):
+        n_u, n_v = int(rng.integers(3, 8)), int(rng.integers(3, 8))
+        dense = rng.random((n_u, n_v)) < rng.uniform(0.5, 1.0)
+        u, v = np.nonzero(dense)
+        s = np.where(rng.random(u.size) < rng.uniform(0.3, 1.0), 1, -1).astype(np.int8)
+        g = G._finish(n_u, n_v, u, v, s)
+        tot = sum(oracle.count_through_edge(g, int(a), int(b), int(c), brute=True) for a, b, c in zip(u, v, s))
+        assert tot == 9 * oracle.count_bruteforce(g)
