@@ -470,13 +470,97 @@ static void bbvp_anchor(const graph_t *g, uint32_t u, int oriented, scratch_t *w
     }
 }
 
+/* One anchor u of Algorithm 2 with p = 4 on the anchor side: the candidate
+ * set C and the lists L[w] as for p = 3, then every 3-subset A = {w1, w2, w3}
+ * of C (the (p - 1)-subsets of the algorithm): T = L[w1] n L[w2] n L[w3], and
+ * each v in T falls in one of the 2^3 classes given by the three products
+ * s(u, v) s(wi, v) (the wedge types of the pairs (u, wi) at v); the subset adds
+ * C(x_c, q) over the classes. Oriented (partners of higher priority) only. */
+static void bbvp_anchor_p4(const graph_t *g, uint32_t u, scratch_t *w, tally_t *t, int q)
+{
+    int64_t n_touched = 0;
+    for (int64_t a = g->off_s[u]; a < g->off_s[u + 1]; a++) {
+        uint32_t v = g->adj_s[a];
+        for (int64_t b = g->off_o[v]; b < g->off_o[v + 1]; b++) {
+            uint32_t x = g->adj_o[b];
+            if (x == u || !higher_priority(g, x, u)) continue;
+            if (w->cnt[x] == 0) w->touched[n_touched++] = x;
+            w->cnt[x]++;
+        }
+    }
+    int64_t n_c = 0;
+    for (int64_t i = 0; i < n_touched; i++)
+        if (w->cnt[w->touched[i]] >= q) w->cand[n_c++] = w->touched[i];
+    for (int64_t i = 0; i < n_touched; i++) w->cnt[w->touched[i]] = 0;
+    if (n_c < 3) return;      /* |C| < p - 1 */
+    int64_t need = 0;
+    for (int64_t i = 0; i < n_c; i++) {
+        int64_t du = g->off_s[u + 1] - g->off_s[u];
+        int64_t dw = g->off_s[w->cand[i] + 1] - g->off_s[w->cand[i]];
+        need += du < dw ? du : dw;
+    }
+    if (need > w->l_cap) {
+        w->l_cap = need;
+        w->l_pos = realloc(w->l_pos, sizeof(int32_t) * need);
+        w->l_su = realloc(w->l_su, need);
+        w->l_sw = realloc(w->l_sw, need);
+    }
+    int64_t fill = 0;
+    for (int64_t i = 0; i < n_c; i++) {
+        uint32_t x = w->cand[i];
+        w->l_off[i] = fill;
+        int64_t a = g->off_s[u], ae = g->off_s[u + 1];
+        int64_t b = g->off_s[x], be = g->off_s[x + 1];
+        while (a < ae && b < be) {
+            if (g->adj_s[a] < g->adj_s[b]) a++;
+            else if (g->adj_s[a] > g->adj_s[b]) b++;
+            else {
+                w->l_pos[fill] = (int32_t)(a - g->off_s[u]);
+                w->l_su[fill] = g->sg_s[a];
+                w->l_sw[fill] = g->sg_s[b];
+                fill++; a++; b++;
+            }
+        }
+    }
+    w->l_off[n_c] = fill;
+    for (int64_t i = 0; i < n_c; i++)
+        for (int64_t j = i + 1; j < n_c; j++)
+            for (int64_t k = j + 1; k < n_c; k++) {
+                t->candidates++;
+                uint64_t x[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                uint64_t size_t_ = 0;
+                int64_t a = w->l_off[i], ae = w->l_off[i + 1];
+                int64_t b = w->l_off[j], be = w->l_off[j + 1];
+                int64_t c = w->l_off[k], ce = w->l_off[k + 1];
+                while (a < ae && b < be && c < ce) {
+                    const int32_t pa = w->l_pos[a], pb = w->l_pos[b], pc = w->l_pos[c];
+                    if (pa == pb && pb == pc) {
+                        const int su = w->l_su[a];
+                        const int cls = (su * w->l_sw[a] < 0) | ((su * w->l_sw[b] < 0) << 1) |
+                                        ((su * w->l_sw[c] < 0) << 2);
+                        x[cls]++;
+                        size_t_++;
+                        a++; b++; c++;
+                    } else {
+                        const int32_t mx = pa > pb ? (pa > pc ? pa : pc) : (pb > pc ? pb : pc);
+                        if (pa < mx) a++;
+                        if (pb < mx) b++;
+                        if (pc < mx) c++;
+                    }
+                }
+                if (size_t_ < (uint64_t)q) continue;   /* |T| < q */
+                t->feasible++;
+                for (int cl = 0; cl < 8; cl++) t->total += choose_k(x[cl], q);
+            }
+}
+
 typedef struct {
     const graph_t *g;
     int64_t next;            /* shared anchor cursor (dynamic chunks) */
     pthread_mutex_t lock;
     int64_t stride;          /* process anchors whose index is a multiple of stride */
     int want_per_vertex;
-    int q;
+    int p, q;
     tally_t tally;
     i128 *per_s;             /* shared per-vertex, merged under the lock */
 } job_t;
@@ -498,8 +582,11 @@ static void *worker(void *arg)
         pthread_mutex_unlock(&jb->lock);
         if (begin >= g->n_s) break;
         int64_t end = begin + chunk < g->n_s ? begin + chunk : g->n_s;
-        for (int64_t u = begin; u < end; u++)
-            if (u % jb->stride == 0) bbvp_anchor(g, (uint32_t)u, 1, &w, &t, per, NULL, jb->q);
+        for (int64_t u = begin; u < end; u++) {
+            if (u % jb->stride != 0) continue;
+            if (jb->p == 4) bbvp_anchor_p4(g, (uint32_t)u, &w, &t, jb->q);
+            else bbvp_anchor(g, (uint32_t)u, 1, &w, &t, per, NULL, jb->q);
+        }
     }
     pthread_mutex_lock(&jb->lock);
     jb->tally.total += t.total;
@@ -541,6 +628,7 @@ int orc_count_bbvp_q(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
     jb.g = &g;
     jb.stride = anchor_stride;
     jb.want_per_vertex = per_vertex != NULL;
+    jb.p = 3;
     jb.q = q;
     pthread_mutex_init(&jb.lock, NULL);
     if (per_vertex) jb.per_s = calloc(g.n_s + 1, sizeof(i128));
@@ -566,6 +654,41 @@ int orc_count_bbvp_q(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
     }
     free_graph(&g);
     return rc;
+}
+
+/* Algorithm 2 with p = 4 on the anchor side and q (3..7) on the other
+ * (side 0: balanced (4, q)-bicliques, anchored on U; side 1: balanced
+ * (q, 4)-bicliques, anchored on V). out_total: 128-bit count, words lo, hi;
+ * out_stats: [subsets with |T| >= q, 3-subsets of C enumerated].
+ * Returns 0, or -1 on a bad edge list, p or q. */
+int orc_count_bbvp_p4(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
+                      const uint32_t *ev, const int8_t *sign, int side, int n_threads, int q,
+                      uint64_t *out_total, uint64_t *out_stats)
+{
+    if (q < 3 || q > 7 || (side != 0 && side != 1)) return -1;
+    graph_t g;
+    if (build_graph(&g, n_u, n_v, m, eu, ev, sign, side) != 0) { free_graph(&g); return -1; }
+    if (n_threads < 1) n_threads = 1;
+    job_t jb;
+    memset(&jb, 0, sizeof(jb));
+    jb.g = &g;
+    jb.stride = 1;
+    jb.p = 4;
+    jb.q = q;
+    pthread_mutex_init(&jb.lock, NULL);
+    pthread_t *th = malloc(sizeof(pthread_t) * n_threads);
+    for (int i = 0; i < n_threads; i++) pthread_create(&th[i], NULL, worker, &jb);
+    for (int i = 0; i < n_threads; i++) pthread_join(th[i], NULL);
+    free(th);
+    pthread_mutex_destroy(&jb.lock);
+    out_total[0] = (uint64_t)jb.tally.total;
+    out_total[1] = (uint64_t)(jb.tally.total >> 64);
+    if (out_stats) {
+        out_stats[0] = jb.tally.feasible;
+        out_stats[1] = jb.tally.candidates;
+    }
+    free_graph(&g);
+    return 0;
 }
 
 int orc_count_bbvp(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu, const uint32_t *ev,

@@ -71,6 +71,9 @@ def _bind(L):
                                    _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                    _u64p, _u64p, _i64p]
     L.orc_count_bbvp_q.restype = ctypes.c_int
+    L.orc_count_bbvp_p4.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _u32p, _u32p,
+                                    _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p, _u64p]
+    L.orc_count_bbvp_p4.restype = ctypes.c_int
     L.orc_count_bruteforce_pq.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _u32p,
                                           _u32p, _i8p, ctypes.c_int, ctypes.c_int, _u64p]
     L.orc_count_bruteforce_pq.restype = ctypes.c_int
@@ -165,6 +168,23 @@ def count_bbvp_q(g, q: int, side: int = 0, threads: int = 1, anchor_stride: int 
         raise ValueError(f"orc_count_bbvp_q failed ({rc})")
     total = int(out[0]) | (int(out[1]) << 64)
     return {"total": total, "feasible": int(st[0]), "candidates": int(st[1]), "side": int(st[2])}
+
+
+def count_bbvp_p4(g, q: int, side: int = 0, threads: int = 1) -> dict:
+    """Algorithm 2 with p = 4 on the anchor side (3-subsets of the candidate
+    set, 2^3 wedge-type classes) and q (3..7) on the other: side 0 counts
+    balanced (4, q)-bicliques, side 1 balanced (q, 4)-bicliques.
+
+    Returns dict(total, feasible, candidates)."""
+    eu, ev, sg = _arrs(g)
+    out = np.zeros(2, np.uint64)
+    st = np.zeros(2, np.uint64)
+    rc = lib().orc_count_bbvp_p4(g.n_u, g.n_v, eu.size, _p(eu, _u32p), _p(ev, _u32p),
+                                 _p(sg, _i8p), side, threads, q, _p(out, _u64p), _p(st, _u64p))
+    if rc != 0:
+        raise ValueError(f"orc_count_bbvp_p4 failed ({rc})")
+    total = int(out[0]) | (int(out[1]) << 64)
+    return {"total": total, "feasible": int(st[0]), "candidates": int(st[1])}
 
 
 def count_bruteforce_pq(g, p: int, q: int) -> int:

@@ -358,3 +358,41 @@ def test_through_edge_sums_to_nine_times_count(oracle):
         g = G._finish(n_u, n_v, u, v, s)
         tot = sum(oracle.count_through_edge(g, int(a), int(b), int(c), brute=True) for a, b, c in zip(u, v, s))
         assert tot == 9 * oracle.count_bruteforce(g)
+
+
+# ------------------------------------------------- p = 4 on the anchor side
+def test_p4_closed_forms(oracle):
+    """All-positive K_{n,m}: C(n,4) C(m,q); the two-block sign pattern (sign -1
+    exactly on U2 x V2): [C(n1,4) + C(n2,4)] C(m,q) + [C(n,4) - C(n1,4) -
+    C(n2,4)] [C(m1,q) + C(m2,q)]; and the transposes on the other side."""
+    C = math.comb
+    for n, m, q in [(5, 6, 3), (6, 7, 4), (7, 5, 5), (4, 8, 7)]:
+        g = G.from_rows(["+" * m] * n)
+        assert oracle.count_bbvp_p4(g, q, 0)["total"] == C(n, 4) * C(m, q)
+        gt = G.from_rows(["+" * n] * m)
+        assert oracle.count_bbvp_p4(gt, q, 1)["total"] == C(n, 4) * C(m, q)
+    for (n1, n2, m1, m2, q) in [(3, 4, 4, 3, 3), (4, 5, 5, 3, 4), (2, 6, 3, 6, 5)]:
+        n, m = n1 + n2, m1 + m2
+        rows = ["".join("-" if (i >= n1 and j >= m1) else "+" for j in range(m)) for i in range(n)]
+        pure = C(n1, 4) + C(n2, 4)
+        want = pure * C(m, q) + (C(n, 4) - pure) * (C(m1, q) + C(m2, q))
+        assert oracle.count_bbvp_p4(G.from_rows(rows), q, 0)["total"] == want
+
+
+def test_p4_equals_definition_tiny(oracle):
+    """Algorithm 2 with p = 4 equals the definition (brute force over all
+    (4, q) and (q, 4) pairs of vertex sets) on dense tiny random graphs."""
+    rng = np.random.default_rng(77)
+    nonzero = 0
+    for _ in range(120):
+        n_u, n_v = int(rng.integers(4, 9)), int(rng.integers(4, 9))
+        dense = rng.random((n_u, n_v)) < rng.uniform(0.5, 1.0)
+        u, v = np.nonzero(dense)
+        s = np.where(rng.random(u.size) < rng.uniform(0.3, 1.0), 1, -1).astype(np.int8)
+        g = G._finish(n_u, n_v, u, v, s)
+        for q in (3, 4, 5):
+            want = oracle.count_bruteforce_pq(g, 4, q)
+            assert oracle.count_bbvp_p4(g, q, 0)["total"] == want
+            assert oracle.count_bbvp_p4(g, q, 1)["total"] == oracle.count_bruteforce_pq(g, q, 4)
+            nonzero += want > 0
+    assert nonzero > 40
