@@ -342,6 +342,15 @@ def main():
                     ts.append(1e3 * (time.time() - t))
                 gq[key][str(q)] = {"count": c, "ms": round(sorted(ts)[1], 3)}
             h.free()
+        # 4 vertices on the anchor side (triples of candidates), one count each
+        for pq in ((4, 3), (4, 4)):
+            h = ctx.build_csr(g.n_u, g.n_v, d_eu, d_ev, d_sg, 1 << 4)
+            ctx.count_global(h, *pq)                 # sizes the workspace
+            torch.cuda.synchronize()
+            t = time.time()
+            c = ctx.count_global(h, *pq)
+            gq["%d,%d" % pq] = {"count": c, "ms": round(1e3 * (time.time() - t), 1)}
+            h.free()
         out["general_q"] = gq
 
     if not args.no_edges:

@@ -109,13 +109,14 @@ typedef struct {
 bbc_status bbc_get_graph_info(bbc_ctx *ctx, const bbc_graph *g, bbc_graph_info *out);
 
 /* Number of balanced (p,q)-bicliques of g (Problem statement, Section 3):
- * |L| = p vertices of U, |R| = q of V. Supported: (3, 3) on any graph;
- * (3, q) for q = 4..7 on a graph built with BBC_ANCHOR_U, and (p, 3) for
- * p = 4..7 on one built with BBC_ANCHOR_V (Algorithm 2 with triples on the
- * anchor side and C(n, q) for the other; (p, 3) is (3, p) with the sides
- * exchanged). out_count: host int64. Errors: BBC_E_UNSUPPORTED (other (p, q),
- * or the graph anchored on the other side), BBC_E_OVERFLOW (the count, or a
- * single C(n, q) term, does not fit 64 bits), BBC_E_NOMEM, BBC_E_HIP. */
+ * |L| = p vertices of U, |R| = q of V. Algorithm 2 enumerates the vertices
+ * of the graph's anchor side (U with BBC_ANCHOR_U, V with BBC_ANCHOR_V, else
+ * the side the build chose) and takes C(n, .) on the other: supported are 3
+ * or 4 vertices on the anchor side and 3..7 on the other, e.g. (3, 3) on any
+ * graph, (3, q) and (4, q) anchored on U, (p, 3) and (p, 4) anchored on V.
+ * out_count: host int64. Errors: BBC_E_UNSUPPORTED (other (p, q) for the
+ * graph's anchor side), BBC_E_OVERFLOW (the count, or a single C(n, q) term,
+ * does not fit 64 bits), BBC_E_NOMEM, BBC_E_HIP. */
 bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int64_t *out_count);
 
 /* Edge queries for dynamic graphs (Section 6 names dynamic signed bipartite

@@ -30,11 +30,13 @@ struct LaunchShape {
 };
 
 hipError_t count_pairs(const PairArgs &P, const LaunchShape &sh, hipStream_t s);
-// cut the anchors' pair matrices into triplet work units
+// cut the anchors' pair matrices into triplet work units (p4: the pair
+// triangles after every candidate, for 4 vertices on the anchor side)
 hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_t tmp_bytes,
-                      hipStream_t s);
+                      bool p4, hipStream_t s);
 // mode 0: totals only; 1: also per vertex of the anchor side; 2: per vertex of
-// the opposite side; 3: totals with q (T.q, 4..7) vertices on the opposite side
+// the opposite side; 3: totals with q (T.q, 4..7) vertices on the opposite side;
+// 4: totals with 4 vertices on the anchor side and q (T.q, 3..7) on the other
 hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t s);
 // workgroups (and waves) of the per-wave tier that fit on one compute unit
 uint32_t wave_tier_blocks_per_cu();

@@ -1221,7 +1221,10 @@ __device__ __forceinline__ uint32_t unit_class(uint32_t w32)
 }
 
 // Units per anchor record, in the slice of its class.
-__global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk_base)
+// With p4 set (p = 4 on the anchor side) every candidate x of a record
+// opens the triangle of the candidates after it: units of all those
+// triangles, with x + 1 in the upper half of Unit::rb.
+__global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk_base, uint32_t p4)
 {
     // after a capacity overflow the records are incomplete: plan nothing
     const uint32_t n_rec = ws.ctr->over_cap ? 0u
@@ -1231,7 +1234,13 @@ __global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk
         uint32_t c = 0, cls = 0;
         if (a < n_rec) {
             const AnchorRec &r = ws.anchors[a];
-            if (r.k <= 65535u) c = anchor_units(r.k, r.w32, chunk_base);
+            if (r.k <= 65535u) {
+                if (p4) {
+                    for (uint32_t x = 0; x + 2 < r.k; x++) c += anchor_units(r.k - x - 1, r.w32, chunk_base);
+                } else {
+                    c = anchor_units(r.k, r.w32, chunk_base);
+                }
+            }
             cls = unit_class(r.w32);
         }
 #pragma unroll
@@ -1240,7 +1249,7 @@ __global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk
 }
 
 // One wave per anchor record writes its units.
-__global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk_base)
+__global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk_base, uint32_t p4)
 {
     Counters *C = ws.ctr;
     const uint32_t n_rec = C->over_cap ? 0u : (uint32_t)min((uint64_t)C->n_anchor, ws.cap_anchors);
@@ -1249,7 +1258,10 @@ __global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk
         C->n_units = (uint32_t)min(total, ws.cap_units);
         C->n_cls_end[0] = (uint32_t)min(ws.uoff[ws.cap_anchors], ws.cap_units);
         C->n_cls_end[1] = (uint32_t)min(ws.uoff[2 * ws.cap_anchors], ws.cap_units);
-        if (total > ws.cap_units) atomicOr(&C->over_cap, 2u);
+        if (total > ws.cap_units) {
+            atomicOr(&C->over_cap, 2u);
+            if (total > C->need_units) C->need_units = total;   // the exact demand
+        }
     }
     const uint32_t lane = __lane_id();
     const uint32_t wave = (blockIdx.x * 256 + threadIdx.x) / kWave;
@@ -1259,20 +1271,26 @@ __global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk
         if (r.k < 2 || r.k > 65535u) continue;
         const uint64_t base = ws.uoff[unit_class(r.w32) * ws.cap_anchors + a];
         const uint32_t CH = unit_cols(r.w32, chunk_base);
-        const uint32_t nb = (r.k + kWave - 1) / kWave;
         uint32_t u0 = 0;
-        for (uint32_t b = 0; b < nb; b++) {
-            const uint32_t ncols = min(kWave * (b + 1), r.k) - 1;
-            const uint32_t nu = (ncols + CH - 1) / CH;
-            for (uint32_t c = lane; c < nu; c += kWave) {
-                const uint64_t idx = base + u0 + c;
-                if (idx < ws.cap_units) {
-                    Unit un;
-                    un.anchor = a; un.rb = b; un.c0 = c * CH; un.c1 = min(un.c0 + CH, ncols);
-                    ws.units[idx] = un;
+        // p = 3: one triangle; p = 4: the triangle after every candidate x
+        const uint32_t nx = p4 ? (r.k >= 3 ? r.k - 2 : 0) : 1;
+        for (uint32_t x = 0; x < nx; x++) {
+            const uint32_t kk = p4 ? r.k - x - 1 : r.k;
+            const uint32_t tag = p4 ? (x + 1) << 16 : 0u;
+            const uint32_t nb = (kk + kWave - 1) / kWave;
+            for (uint32_t b = 0; b < nb; b++) {
+                const uint32_t ncols = min(kWave * (b + 1), kk) - 1;
+                const uint32_t nu = (ncols + CH - 1) / CH;
+                for (uint32_t c = lane; c < nu; c += kWave) {
+                    const uint64_t idx = base + u0 + c;
+                    if (idx < ws.cap_units) {
+                        Unit un;
+                        un.anchor = a; un.rb = b | tag; un.c0 = c * CH; un.c1 = min(un.c0 + CH, ncols);
+                        ws.units[idx] = un;
+                    }
                 }
+                u0 += nu;
             }
-            u0 += nu;
         }
     }
 }
@@ -1409,7 +1427,7 @@ __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
 template <int MODE>
 __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
                                   const uint32_t *__restrict__ masks, uint64_t *colacc,
-                                  const TriArgs &T)
+                                  const TriArgs &T, const uint32_t *xm = nullptr)
 {
     const uint32_t lane = __lane_id();
     const uint32_t i = un.rb * kWave + lane;
@@ -1427,8 +1445,10 @@ __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
             const uint32_t wn = min(kRegW, W - w0);
             uint32_t row[kRegW];
 #pragma unroll
-            for (int w = 0; w < (int)kRegW; w++)
+            for (int w = 0; w < (int)kRegW; w++) {
                 row[w] = (vi && (uint32_t)w < wn) ? M[(uint64_t)i * W + w0 + w] : 0u;
+                if (MODE == 4 && (uint32_t)w < wn) row[w] &= xm[w0 + w];   // rows meet the first candidate
+            }
 #pragma unroll
             for (int c = 0; c < 8; c++) {
                 if (cg + c < ncol) {
@@ -1446,7 +1466,7 @@ __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
             const uint32_t j = un.c0 + cg + c;
             uint64_t t = 0;
             if (cg + c < ncol && j < i) {
-                if (MODE == 3) {
+                if (MODE == 3 || MODE == 4) {
                     bool ovf = false;
                     t = choose_q(n[c], T.q, ovf);
                     if (ovf) atomicOr(&T.ws.ctr->over_cap, 16u);
@@ -1739,7 +1759,7 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
 template <int W, int MODE>
 __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
                                  const uint32_t *__restrict__ masks, const uint64_t *cq,
-                                 const uint32_t *c3, uint64_t *colacc)
+                                 const uint32_t *c3, uint64_t *colacc, const uint32_t *xm)
 {
     constexpr int NC = (W + 3) / 4;          // 128-bit K-chunks
     constexpr int SB = 4;
@@ -1762,6 +1782,10 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
     auto piece = [&](uint32_t raw, int t, bool valid) {
         return spread_fp4(raw, valid && wf + t < (uint32_t)W);
     };
+    // MODE 4: the rows meet the first candidate's mask xm (same word layout)
+    uint32_t xw[NC];
+#pragma unroll
+    for (int t = 0; t < NC; t++) xw[t] = MODE == 4 ? xm[ws + t] : ~0u;
     v8i32 A[SB][NC];
 #pragma unroll
     for (int sb = 0; sb < SB; sb++) {
@@ -1769,7 +1793,7 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
         uint32_t raw[NC];
         words(i < a.k ? i : a.k - 1, raw);
 #pragma unroll
-        for (int t = 0; t < NC; t++) A[sb][t] = piece(raw[t], t, i < a.k);
+        for (int t = 0; t < NC; t++) A[sb][t] = piece(raw[t] & xw[t], t, i < a.k);
     }
     auto col_words = [&](uint32_t j0, uint32_t (&raw)[NC]) {
         const uint32_t j = j0 + r16;
@@ -1809,7 +1833,7 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
             cs += __shfl_xor(cs, 32, kWave);
             if (g == 0 && j < un.c1 && cs) colacc[j - un.c0] += cs;
             return 0;
-        } else if constexpr (MODE == 3) {
+        } else if constexpr (MODE == 3 || MODE == 4) {
             // element e of block sb: row rbase + 16 sb + 4 g + e, column j0 + r16
             const bool diag = j0 + 16 > rbase;
             const uint32_t j = j0 + r16, i0 = rbase + 4 * g;
@@ -1877,7 +1901,7 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
             }
         return mine;
     }
-    return MODE == 3 ? sum : sum / 6;
+    return (MODE == 3 || MODE == 4) ? sum : sum / 6;
 }
 
 // Masks wider than 16 words (totals): 64 rows x up to 64 columns per unit,
@@ -1987,20 +2011,20 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
 // anchor side 2, per-vertex counts of the other side 5.
 __host__ __device__ constexpr int tri_waves(int mode, int cls)
 {
-    return (mode == 0 || mode == 3) ? (cls == 0 ? 4 : 3) : (mode == 1 ? 2 : 5);
+    return (mode == 0 || mode >= 3) ? (cls == 0 ? 4 : 3) : (mode == 1 ? 2 : 5);
 }
 
 template <int MODE, int CLS>
 __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(TriArgs T)
 {
     __shared__ uint32_t c3[kC3Max + 1];
-    __shared__ uint64_t cq[MODE == 3 ? kC3Max + 1 : 1];   // C(n, q), n <= 32 kRegW
+    __shared__ uint64_t cq[MODE == 3 || MODE == 4 ? kC3Max + 1 : 1];   // C(n, q), n <= 32 kRegW
     // per wave: column totals of a unit (MODE 1) or totals per anchor position,
     // masks up to kRegW words (MODE 2)
     constexpr uint32_t kLacc = MODE == 1 ? kMaxChunk : (MODE == 2 ? 32 * kRegW : 1);
     __shared__ unsigned long long colacc_all[MODE == 1 || MODE == 2 ? kTThreads / kWave : 1][kLacc];
     for (uint32_t i = threadIdx.x; i <= kC3Max; i += kTThreads) c3[i] = (uint32_t)choose3(i);
-    if (MODE == 3) {
+    if (MODE == 3 || MODE == 4) {
         bool ovf = false;   // C(512, 7) < 2^51
         for (uint32_t i = threadIdx.x; i <= kC3Max; i += kTThreads) cq[i] = choose_q(i, T.q, ovf);
     }
@@ -2049,8 +2073,18 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
         // from the end of the list: the records of the later pair tiers (the
         // widest masks, the heaviest units) start first
         const uint32_t u = u_base + (n_units - 1 - qlo++);
-        const Unit un = load_unit(T.ws.units + u);
-        const AnchorRec a = load_anchor(T.ws.anchors + un.anchor);
+        Unit un = load_unit(T.ws.units + u);
+        AnchorRec a = load_anchor(T.ws.anchors + un.anchor);
+        const uint32_t *xm = nullptr;
+        if constexpr (MODE == 4) {
+            // the triangle of the candidates after x = base - 1, whose mask
+            // every row meets: a record of k - base candidates from base on
+            const uint32_t base = un.rb >> 16;
+            un.rb &= 0xffffu;
+            xm = T.ws.masks + a.mask_off + (uint64_t)(base - 1) * a.w32;
+            a.k -= base;
+            a.mask_off += (uint64_t)base * a.w32;
+        }
         if (a.graph != cur_graph) {
             if (cur_graph != 0xffffffffu) flush();
             cur_graph = a.graph;
@@ -2060,7 +2094,7 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
         if (wide) {
             if constexpr (CLS != 0) {
                 if (MODE == 0) acc = tri_rows_mfma_wide(un, a, T.ws.masks);
-                else acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T);
+                else acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T, xm);
             }
         } else {
             // only the widths of this kernel's class are instantiated
@@ -2072,7 +2106,7 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
 #define BBC_W(n)                                                                                       \
     case n:                                                                                            \
         if constexpr (MODE != 0 || n >= kFp4MinW)                                                      \
-            acc = tri_rows_fp4<n, MODE>(un, a, T.ws.masks, cq, c3, colacc);                            \
+            acc = tri_rows_fp4<n, MODE>(un, a, T.ws.masks, cq, c3, colacc, xm);                        \
         else                                                                                           \
             acc = tri_rows_mfma<n>(un, a, T.ws.masks);                                                 \
         break;
@@ -2213,13 +2247,13 @@ hipError_t count_pairs(const PairArgs &base, const LaunchShape &sh, hipStream_t 
 }
 
 hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_t tmp_bytes,
-                      hipStream_t s)
+                      bool p4, hipStream_t s)
 {
     uint32_t grid = (uint32_t)std::min<uint64_t>((ws.cap_anchors + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_plan_count, dim3(grid), dim3(256), 0, s, ws, chunk_base);
+    hipLaunchKernelGGL(k_plan_count, dim3(grid), dim3(256), 0, s, ws, chunk_base, p4 ? 1u : 0u);
     hipError_t e = scan_u32_to_u64(ws.ucnt, ws.uoff, 3 * ws.cap_anchors, tmp, tmp_bytes, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_write, dim3(1024), dim3(256), 0, s, ws, chunk_base);
+    hipLaunchKernelGGL(k_plan_write, dim3(1024), dim3(256), 0, s, ws, chunk_base, p4 ? 1u : 0u);
     return hipGetLastError();
 }
 
@@ -2241,9 +2275,13 @@ hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t
             hipLaunchKernelGGL((k_triplet<2, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
             hipLaunchKernelGGL((k_triplet<2, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
             break;
-        default:
+        case 3:
             hipLaunchKernelGGL((k_triplet<3, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
             hipLaunchKernelGGL((k_triplet<3, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
+            break;
+        default:
+            hipLaunchKernelGGL((k_triplet<4, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
+            hipLaunchKernelGGL((k_triplet<4, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
             break;
     }
     return hipGetLastError();

@@ -799,7 +799,7 @@ LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
     L.ls.grid_t = std::max(1u, ctx->num_cus * shp.grid_t_per_cu);
     L.T.g = L.P.g;
     L.T.ws = ws;
-    L.T.q = r.mode == 3 ? r.q : 3u;
+    L.T.q = r.mode >= 3 ? r.q : 3u;
     L.mode = r.mode;
     L.G = set.G; L.NS = set.NS; L.NO = set.NO;
     L.ptmp = w.ptmp.p;
@@ -818,7 +818,7 @@ void enqueue_args(bbc_ctx *ctx, const LaunchArgs &L, hipStream_t s, bool timed)
     if (timed) HIP_OK(hipEventRecord(ctx->ev[0], s));
     HIP_OK(count_pairs(L.P, L.ls, s));
     if (timed) HIP_OK(hipEventRecord(ctx->ev[1], s));
-    HIP_OK(count_plan(ws, L.P.chunk_base, L.ptmp, L.ptmp_bytes, s));
+    HIP_OK(count_plan(ws, L.P.chunk_base, L.ptmp, L.ptmp_bytes, L.mode == 4, s));
     if (timed) HIP_OK(hipEventRecord(ctx->ev[2], s));
     HIP_OK(count_triplets(L.T, L.mode, L.ls.grid_t, s));
     if (timed) HIP_OK(hipEventRecord(ctx->ev[3], s));
@@ -1322,25 +1322,25 @@ bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int6
     if (!ctx) return BBC_E_INVAL;
     return guard(ctx, [&] {
         if (!g || !out_count) fail(BBC_E_INVAL, "null argument");
-        // (3, q) anchors triples on U, (p, 3) on V (the same count with the
-        // sides exchanged); (3, 3) runs on whichever side the graph was built
+        // the vertices on the graph's anchor side form the enumerated
+        // subsets (3: pairs of candidates, 4: triples), those on the other
+        // side are chosen by C(n, q); (p, q) with the sides exchanged is the
+        // same count on the transposed graph
         const uint32_t side = g->set->desc[g->idx].side;
-        uint32_t qq = 3;
-        if (p == 3 && q == 3) {
-            qq = 3;
-        } else if (p == 3 && q >= 4 && q <= 7) {
-            if (side != 0) fail(BBC_E_UNSUPPORTED, "(3, %d) needs a graph built with BBC_ANCHOR_U", q);
-            qq = (uint32_t)q;
-        } else if (q == 3 && p >= 4 && p <= 7) {
-            if (side != 1) fail(BBC_E_UNSUPPORTED, "(%d, 3) needs a graph built with BBC_ANCHOR_V", p);
-            qq = (uint32_t)p;
-        } else {
-            fail(BBC_E_UNSUPPORTED, "(p, q) = (%d, %d): supported are (3, 3..7) and (3..7, 3)", p, q);
-        }
+        const int na = side == 0 ? p : q, nb = side == 0 ? q : p;
+        int mode = 0;
+        if (na == 3 && nb == 3) mode = 0;
+        else if (na == 3 && nb >= 4 && nb <= 7) mode = 3;
+        else if (na == 4 && nb >= 3 && nb <= 7) mode = 4;
+        else
+            fail(BBC_E_UNSUPPORTED,
+                 "(p, q) = (%d, %d) on a graph anchored on %s: supported are 3 or 4 vertices on the "
+                 "anchor side (BBC_ANCHOR_U / BBC_ANCHOR_V) and 3..7 on the other",
+                 p, q, side ? "V" : "U");
         (void)hipSetDevice(ctx->device);
         int64_t v = 0;
-        count_sync(ctx, ctx->work, *g->set, g->idx, g->idx + 1, qq == 3 ? 0 : 3, default_shape(),
-                   ctx->stream, &v, qq);
+        count_sync(ctx, ctx->work, *g->set, g->idx, g->idx + 1, mode, default_shape(), ctx->stream,
+                   &v, (uint32_t)nb);
         *out_count = v;
     });
 }

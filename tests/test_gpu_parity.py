@@ -211,7 +211,7 @@ def test_invalid_inputs(ctx, B):
     assert ei.value.name == "BBC_E_SIGN"
     h = build(ctx, G.config1(1))
     with pytest.raises(B.BBCError) as ei:
-        ctx.count_global(h, 4, 4)
+        ctx.count_global(h, 5, 5)
     assert ei.value.name == "BBC_E_UNSUPPORTED"
     # the context is still usable after errors
     assert ctx.count_global(h) > 0
@@ -480,7 +480,7 @@ def test_general_q_rejected(ctx, B):
     say("general q rejected")
     g = G.config1(2)
     hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
-    for h, p, q in [(hv, 3, 4), (hu, 4, 3), (hu, 3, 8), (hu, 4, 4), (hu, 2, 3), (hv, 3, 2)]:
+    for h, p, q in [(hv, 3, 5), (hu, 5, 3), (hu, 3, 8), (hu, 5, 5), (hv, 4, 5), (hu, 2, 3), (hv, 3, 2)]:
         with pytest.raises(B.BBCError) as ei:
             ctx.count_global(h, p, q)
         assert ei.value.name == "BBC_E_UNSUPPORTED", (p, q)
@@ -500,3 +500,67 @@ def test_general_q_config2_full(ctx):
         p, q = (int(x) for x in key.split(","))
         got = ctx.count_global(hu if p == 3 else hv, p, q)
         assert got == want, key
+
+
+# ------------------------------------------------- 4 vertices on the anchor side
+def test_p4_closed_forms(ctx):
+    """All-positive K_{n,m}: C(n,4) C(m,q) for (4, q) anchored on U and for
+    (q, 4) anchored on V; the two-block sign pattern for (4, q)."""
+    C = math.comb
+    for n, m in [(5, 6), (9, 40), (70, 5)]:
+        g = G.from_rows(["+" * m] * n)
+        hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
+        for q in range(3, 8):
+            say("p4 complete", n, m, q)
+            assert ctx.count_global(hu, 4, q) == C(n, 4) * C(m, q)
+            assert ctx.count_global(hv, q, 4) == C(n, q) * C(m, 4)
+    for (n1, n2, m1, m2, q) in [(3, 4, 4, 3, 3), (10, 20, 15, 5, 4), (33, 31, 40, 2, 5)]:
+        n, m = n1 + n2, m1 + m2
+        rows = ["".join("-" if (i >= n1 and j >= m1) else "+" for j in range(m)) for i in range(n)]
+        pure = C(n1, 4) + C(n2, 4)
+        want = pure * C(m, q) + (C(n, 4) - pure) * (C(m1, q) + C(m2, q))
+        assert ctx.count_global(build(ctx, G.from_rows(rows), 1 << 4), 4, q) == want
+
+
+def test_p4_vs_oracle(ctx, oracle):
+    """Config 1 (seeds 1, 2, planted blocks included) against Algorithm 2 with
+    p = 4 on both sides; (4, 3) and (3, 4) also through the p = 3 path on the
+    other side."""
+    for seed in (1, 2):
+        g = G.config1(seed)
+        hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
+        for q in (3, 4, 5):
+            say("p4 config1", seed, q)
+            want_u = oracle.count_bbvp_p4(g, q, 0, threads=8)["total"]
+            want_v = oracle.count_bbvp_p4(g, q, 1, threads=8)["total"]
+            assert ctx.count_global(hu, 4, q) == want_u
+            assert ctx.count_global(hv, q, 4) == want_v
+        assert ctx.count_global(hu, 4, 3) == ctx.count_global(hv, 4, 3)
+        assert ctx.count_global(hv, 3, 4) == ctx.count_global(hu, 3, 4)
+
+
+def test_p4_tiny_vs_bruteforce(ctx, oracle):
+    rng = np.random.default_rng(23)
+    for t in range(80):
+        n_u, n_v = int(rng.integers(4, 10)), int(rng.integers(4, 10))
+        dense = rng.random((n_u, n_v)) < rng.uniform(0.5, 1.0)
+        u, v = np.nonzero(dense)
+        s = np.where(rng.random(u.size) < rng.uniform(0.3, 1.0), 1, -1).astype(np.int8)
+        g = G._finish(n_u, n_v, u, v, s)
+        hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
+        for q in (3, 4, 5):
+            assert ctx.count_global(hu, 4, q) == oracle.count_bruteforce_pq(g, 4, q), (t, q)
+            assert ctx.count_global(hv, q, 4) == oracle.count_bruteforce_pq(g, q, 4), (t, q)
+
+
+def test_p4_config2_full(ctx):
+    """Config 2 at full size through the path with 4 vertices on the anchor
+    side: (4, 3) anchored on U and (3, 4) anchored on V equal the oracle's
+    counts of the same bicliques through 3 vertices on the other side
+    (tests/golden/cfg2_seed1_general_q.json)."""
+    gold = golden("cfg2_seed1_general_q.json")["counts"]
+    g = G.config2(1)
+    say("p4 config2 (4,3) U")
+    assert ctx.count_global(build(ctx, g, 1 << 4), 4, 3) == gold["4,3"]
+    say("p4 config2 (3,4) V")
+    assert ctx.count_global(build(ctx, g, 1 << 5), 3, 4) == gold["3,4"]
