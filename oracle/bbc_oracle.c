@@ -554,6 +554,76 @@ static void bbvp_anchor_p4(const graph_t *g, uint32_t u, scratch_t *w, tally_t *
             }
 }
 
+/* One anchor u of Algorithm 2 with p - 1 = r partners (p = 4 or 5), in the
+ * plainest form: the candidate set C as above, then for every candidate w a
+ * dense vector over the positions of Gamma(u) holding 0 (w not adjacent) or
+ * the product s(u, v) s(w, v); every r-subset A of C walks the positions, and
+ * a position where all of A is adjacent falls in the class given by the signs
+ * of the r products (2^r classes); the subset adds C(x_c, q) over the
+ * classes. Oriented (partners of higher priority) only. */
+static void bbvp_anchor_dense(const graph_t *g, uint32_t u, scratch_t *w, tally_t *t, int p, int q)
+{
+    const int r = p - 1;
+    int64_t n_touched = 0;
+    for (int64_t a = g->off_s[u]; a < g->off_s[u + 1]; a++) {
+        uint32_t v = g->adj_s[a];
+        for (int64_t b = g->off_o[v]; b < g->off_o[v + 1]; b++) {
+            uint32_t x = g->adj_o[b];
+            if (x == u || !higher_priority(g, x, u)) continue;
+            if (w->cnt[x] == 0) w->touched[n_touched++] = x;
+            w->cnt[x]++;
+        }
+    }
+    int64_t n_c = 0;
+    for (int64_t i = 0; i < n_touched; i++)
+        if (w->cnt[w->touched[i]] >= q) w->cand[n_c++] = w->touched[i];
+    for (int64_t i = 0; i < n_touched; i++) w->cnt[w->touched[i]] = 0;
+    if (n_c < r) return;
+    const int64_t du = g->off_s[u + 1] - g->off_s[u];
+    int8_t *vec = calloc((size_t)(n_c * du + 1), 1);
+    for (int64_t i = 0; i < n_c; i++) {
+        const uint32_t x = w->cand[i];
+        int64_t a = g->off_s[u], ae = g->off_s[u + 1];
+        int64_t b = g->off_s[x], be = g->off_s[x + 1];
+        while (a < ae && b < be) {
+            if (g->adj_s[a] < g->adj_s[b]) a++;
+            else if (g->adj_s[a] > g->adj_s[b]) b++;
+            else {
+                vec[i * du + (a - g->off_s[u])] = (int8_t)(g->sg_s[a] * g->sg_s[b]);
+                a++; b++;
+            }
+        }
+    }
+    int64_t A[4];
+    for (int k = 0; k < r; k++) A[k] = k;
+    for (;;) {
+        t->candidates++;
+        uint64_t x[16];
+        memset(x, 0, sizeof(x));
+        uint64_t size_t_ = 0;
+        for (int64_t pos = 0; pos < du; pos++) {
+            int cls = 0, all = 1;
+            for (int k = 0; k < r && all; k++) {
+                const int8_t e = vec[A[k] * du + pos];
+                if (e == 0) all = 0;
+                else if (e < 0) cls |= 1 << k;
+            }
+            if (all) { x[cls]++; size_t_++; }
+        }
+        if (size_t_ >= (uint64_t)q) {
+            t->feasible++;
+            for (int c = 0; c < (1 << r); c++) t->total += choose_k(x[c], q);
+        }
+        /* next r-subset of C */
+        int k = r - 1;
+        while (k >= 0 && A[k] == n_c - r + k) k--;
+        if (k < 0) break;
+        A[k]++;
+        for (int k2 = k + 1; k2 < r; k2++) A[k2] = A[k2 - 1] + 1;
+    }
+    free(vec);
+}
+
 typedef struct {
     const graph_t *g;
     int64_t next;            /* shared anchor cursor (dynamic chunks) */
@@ -585,6 +655,7 @@ static void *worker(void *arg)
         for (int64_t u = begin; u < end; u++) {
             if (u % jb->stride != 0) continue;
             if (jb->p == 4) bbvp_anchor_p4(g, (uint32_t)u, &w, &t, jb->q);
+            else if (jb->p > 4 || jb->p < 0) bbvp_anchor_dense(g, (uint32_t)u, &w, &t, jb->p < 0 ? -jb->p : jb->p, jb->q);
             else bbvp_anchor(g, (uint32_t)u, 1, &w, &t, per, NULL, jb->q);
         }
     }
@@ -656,16 +727,19 @@ int orc_count_bbvp_q(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
     return rc;
 }
 
-/* Algorithm 2 with p = 4 on the anchor side and q (3..7) on the other
- * (side 0: balanced (4, q)-bicliques, anchored on U; side 1: balanced
- * (q, 4)-bicliques, anchored on V). out_total: 128-bit count, words lo, hi;
- * out_stats: [subsets with |T| >= q, 3-subsets of C enumerated].
- * Returns 0, or -1 on a bad edge list, p or q. */
-int orc_count_bbvp_p4(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
-                      const uint32_t *ev, const int8_t *sign, int side, int n_threads, int q,
-                      uint64_t *out_total, uint64_t *out_stats)
+/* Algorithm 2 with p = 4 or 5 on the anchor side and q (3..7) on the other
+ * (side 0: balanced (p, q)-bicliques, anchored on U; side 1: balanced
+ * (q, p)-bicliques, anchored on V). p = 4 intersects the L lists by merges,
+ * p = 5 (and p = -4, the same count as p = 4) walks dense sign vectors.
+ * out_total: 128-bit count, words lo, hi; out_stats: [subsets with |T| >= q,
+ * (p - 1)-subsets of C enumerated]. Returns 0, or -1 on a bad edge list, p
+ * or q. */
+int orc_count_bbvp_pk(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
+                      const uint32_t *ev, const int8_t *sign, int side, int n_threads, int p,
+                      int q, uint64_t *out_total, uint64_t *out_stats)
 {
     if (q < 3 || q > 7 || (side != 0 && side != 1)) return -1;
+    if (p != 4 && p != 5 && p != -4) return -1;
     graph_t g;
     if (build_graph(&g, n_u, n_v, m, eu, ev, sign, side) != 0) { free_graph(&g); return -1; }
     if (n_threads < 1) n_threads = 1;
@@ -673,7 +747,7 @@ int orc_count_bbvp_p4(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
     memset(&jb, 0, sizeof(jb));
     jb.g = &g;
     jb.stride = 1;
-    jb.p = 4;
+    jb.p = p;
     jb.q = q;
     pthread_mutex_init(&jb.lock, NULL);
     pthread_t *th = malloc(sizeof(pthread_t) * n_threads);

@@ -71,9 +71,10 @@ def _bind(L):
                                    _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                    _u64p, _u64p, _i64p]
     L.orc_count_bbvp_q.restype = ctypes.c_int
-    L.orc_count_bbvp_p4.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _u32p, _u32p,
-                                    _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p, _u64p]
-    L.orc_count_bbvp_p4.restype = ctypes.c_int
+    L.orc_count_bbvp_pk.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _u32p, _u32p,
+                                    _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    _u64p, _u64p]
+    L.orc_count_bbvp_pk.restype = ctypes.c_int
     L.orc_count_bruteforce_pq.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _u32p,
                                           _u32p, _i8p, ctypes.c_int, ctypes.c_int, _u64p]
     L.orc_count_bruteforce_pq.restype = ctypes.c_int
@@ -170,19 +171,21 @@ def count_bbvp_q(g, q: int, side: int = 0, threads: int = 1, anchor_stride: int 
     return {"total": total, "feasible": int(st[0]), "candidates": int(st[1]), "side": int(st[2])}
 
 
-def count_bbvp_p4(g, q: int, side: int = 0, threads: int = 1) -> dict:
-    """Algorithm 2 with p = 4 on the anchor side (3-subsets of the candidate
-    set, 2^3 wedge-type classes) and q (3..7) on the other: side 0 counts
-    balanced (4, q)-bicliques, side 1 balanced (q, 4)-bicliques.
+def count_bbvp_pk(g, p: int, q: int, side: int = 0, threads: int = 1, dense: bool = False) -> dict:
+    """Algorithm 2 with p = 4 or 5 on the anchor side ((p - 1)-subsets of the
+    candidate set, 2^(p-1) wedge-type classes) and q (3..7) on the other:
+    side 0 counts balanced (p, q)-bicliques, side 1 balanced (q, p)-bicliques.
+    dense=True takes the dense-vector form for p = 4 as well.
 
     Returns dict(total, feasible, candidates)."""
     eu, ev, sg = _arrs(g)
     out = np.zeros(2, np.uint64)
     st = np.zeros(2, np.uint64)
-    rc = lib().orc_count_bbvp_p4(g.n_u, g.n_v, eu.size, _p(eu, _u32p), _p(ev, _u32p),
-                                 _p(sg, _i8p), side, threads, q, _p(out, _u64p), _p(st, _u64p))
+    pp = -4 if (dense and p == 4) else p
+    rc = lib().orc_count_bbvp_pk(g.n_u, g.n_v, eu.size, _p(eu, _u32p), _p(ev, _u32p),
+                                 _p(sg, _i8p), side, threads, pp, q, _p(out, _u64p), _p(st, _u64p))
     if rc != 0:
-        raise ValueError(f"orc_count_bbvp_p4 failed ({rc})")
+        raise ValueError(f"orc_count_bbvp_pk failed ({rc})")
     total = int(out[0]) | (int(out[1]) << 64)
     return {"total": total, "feasible": int(st[0]), "candidates": int(st[1])}
 
@@ -260,3 +263,8 @@ def count_through_edge(g, u: int, v: int, s: int, brute: bool = False, threads: 
     if brute:
         return count_bruteforce(with_e) - count_bruteforce(without)
     return count_bbvp(with_e, 0, threads=threads)["total"] - count_bbvp(without, 0, threads=threads)["total"]
+
+
+def count_bbvp_p4(g, q: int, side: int = 0, threads: int = 1) -> dict:
+    """count_bbvp_pk with p = 4 (merges of the L lists)."""
+    return count_bbvp_pk(g, 4, q, side, threads)

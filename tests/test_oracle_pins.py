@@ -396,3 +396,36 @@ def test_p4_equals_definition_tiny(oracle):
             assert oracle.count_bbvp_p4(g, q, 1)["total"] == oracle.count_bruteforce_pq(g, q, 4)
             nonzero += want > 0
     assert nonzero > 40
+
+
+# ------------------------------------------------- p = 5 on the anchor side
+def test_p5_closed_forms_and_definition(oracle):
+    """Algorithm 2 with p = 5 (4-subsets of the candidate set, 16 classes):
+    C(n,5) C(m,q) on all-positive K_{n,m}, the two-block closed form, the
+    definition on dense tiny graphs (both sides), and the dense form with
+    p = 4 equals the merge form."""
+    C = math.comb
+    for n, m, q in [(6, 6, 3), (7, 8, 4), (8, 5, 5)]:
+        g = G.from_rows(["+" * m] * n)
+        assert oracle.count_bbvp_pk(g, 5, q, 0)["total"] == C(n, 5) * C(m, q)
+    for (n1, n2, m1, m2, q) in [(4, 5, 4, 3, 3), (5, 3, 5, 4, 4)]:
+        n, m = n1 + n2, m1 + m2
+        rows = ["".join("-" if (i >= n1 and j >= m1) else "+" for j in range(m)) for i in range(n)]
+        pure = C(n1, 5) + C(n2, 5)
+        want = pure * C(m, q) + (C(n, 5) - pure) * (C(m1, q) + C(m2, q))
+        assert oracle.count_bbvp_pk(G.from_rows(rows), 5, q, 0)["total"] == want
+    rng = np.random.default_rng(55)
+    nonzero = 0
+    for _ in range(80):
+        n_u, n_v = int(rng.integers(5, 9)), int(rng.integers(5, 9))
+        dense = rng.random((n_u, n_v)) < rng.uniform(0.6, 1.0)
+        u, v = np.nonzero(dense)
+        s = np.where(rng.random(u.size) < rng.uniform(0.3, 1.0), 1, -1).astype(np.int8)
+        g = G._finish(n_u, n_v, u, v, s)
+        for q in (3, 4):
+            want = oracle.count_bruteforce_pq(g, 5, q)
+            assert oracle.count_bbvp_pk(g, 5, q, 0)["total"] == want
+            assert oracle.count_bbvp_pk(g, 5, q, 1)["total"] == oracle.count_bruteforce_pq(g, q, 5)
+            assert oracle.count_bbvp_pk(g, 4, q, 0, dense=True)["total"] == oracle.count_bbvp_p4(g, q, 0)["total"]
+            nonzero += want > 0
+    assert nonzero > 20
