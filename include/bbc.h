@@ -111,9 +111,9 @@ bbc_status bbc_get_graph_info(bbc_ctx *ctx, const bbc_graph *g, bbc_graph_info *
 /* Number of balanced (p,q)-bicliques of g (Problem statement, Section 3):
  * |L| = p vertices of U, |R| = q of V. Algorithm 2 enumerates the vertices
  * of the graph's anchor side (U with BBC_ANCHOR_U, V with BBC_ANCHOR_V, else
- * the side the build chose) and takes C(n, .) on the other: supported are 3
- * or 4 vertices on the anchor side and 3..7 on the other, e.g. (3, 3) on any
- * graph, (3, q) and (4, q) anchored on U, (p, 3) and (p, 4) anchored on V.
+ * the side the build chose) and takes C(n, .) on the other: supported are 3,
+ * 4 or 5 vertices on the anchor side and 3..7 on the other, e.g. (3, 3) on
+ * any graph, (3..5, q) anchored on U, (p, 3..5) anchored on V.
  * out_count: host int64. Errors: BBC_E_UNSUPPORTED (other (p, q) for the
  * graph's anchor side), BBC_E_OVERFLOW (the count, or a single C(n, q) term,
  * does not fit 64 bits), BBC_E_NOMEM, BBC_E_HIP. */

@@ -30,13 +30,14 @@ struct LaunchShape {
 };
 
 hipError_t count_pairs(const PairArgs &P, const LaunchShape &sh, hipStream_t s);
-// cut the anchors' pair matrices into triplet work units (p4: the pair
-// triangles after every candidate, for 4 vertices on the anchor side)
+// cut the anchors' pair matrices into triplet work units for p (3, 4 or 5)
+// vertices on the anchor side (4: the pair triangles after every candidate,
+// 5: after every pair of candidates)
 hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_t tmp_bytes,
-                      bool p4, hipStream_t s);
+                      uint32_t p, hipStream_t s);
 // mode 0: totals only; 1: also per vertex of the anchor side; 2: per vertex of
 // the opposite side; 3: totals with q (T.q, 4..7) vertices on the opposite side;
-// 4: totals with 4 vertices on the anchor side and q (T.q, 3..7) on the other
+// 4, 5: totals with 4 or 5 vertices on the anchor side and q (T.q, 3..7) on the other
 hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t s);
 // workgroups (and waves) of the per-wave tier that fit on one compute unit
 uint32_t wave_tier_blocks_per_cu();

@@ -1221,10 +1221,11 @@ __device__ __forceinline__ uint32_t unit_class(uint32_t w32)
 }
 
 // Units per anchor record, in the slice of its class.
-// With p4 set (p = 4 on the anchor side) every candidate x of a record
-// opens the triangle of the candidates after it: units of all those
-// triangles, with x + 1 in the upper half of Unit::rb.
-__global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk_base, uint32_t p4)
+// p is the number of vertices on the anchor side. p = 4: every candidate x
+// of a record opens the triangle of the candidates after it (units with x + 1
+// in the upper half of Unit::rb); p = 5: every pair x < y opens the triangle
+// after y (x in the upper half of rb, c0 | c1 << 16 in c0, y + 1 in c1).
+__global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk_base, uint32_t p)
 {
     // after a capacity overflow the records are incomplete: plan nothing
     const uint32_t n_rec = ws.ctr->over_cap ? 0u
@@ -1235,8 +1236,11 @@ __global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk
         if (a < n_rec) {
             const AnchorRec &r = ws.anchors[a];
             if (r.k <= 65535u) {
-                if (p4) {
+                if (p == 4) {
                     for (uint32_t x = 0; x + 2 < r.k; x++) c += anchor_units(r.k - x - 1, r.w32, chunk_base);
+                } else if (p == 5) {
+                    // y pairs (x, y) for every y, each with the triangle after y
+                    for (uint32_t y = 1; y + 2 < r.k; y++) c += y * anchor_units(r.k - y - 1, r.w32, chunk_base);
                 } else {
                     c = anchor_units(r.k, r.w32, chunk_base);
                 }
@@ -1249,7 +1253,7 @@ __global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk
 }
 
 // One wave per anchor record writes its units.
-__global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk_base, uint32_t p4)
+__global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk_base, uint32_t p)
 {
     Counters *C = ws.ctr;
     const uint32_t n_rec = C->over_cap ? 0u : (uint32_t)min((uint64_t)C->n_anchor, ws.cap_anchors);
@@ -1272,24 +1276,33 @@ __global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk
         const uint64_t base = ws.uoff[unit_class(r.w32) * ws.cap_anchors + a];
         const uint32_t CH = unit_cols(r.w32, chunk_base);
         uint32_t u0 = 0;
-        // p = 3: one triangle; p = 4: the triangle after every candidate x
-        const uint32_t nx = p4 ? (r.k >= 3 ? r.k - 2 : 0) : 1;
-        for (uint32_t x = 0; x < nx; x++) {
-            const uint32_t kk = p4 ? r.k - x - 1 : r.k;
-            const uint32_t tag = p4 ? (x + 1) << 16 : 0u;
-            const uint32_t nb = (kk + kWave - 1) / kWave;
-            for (uint32_t b = 0; b < nb; b++) {
-                const uint32_t ncols = min(kWave * (b + 1), kk) - 1;
-                const uint32_t nu = (ncols + CH - 1) / CH;
-                for (uint32_t c = lane; c < nu; c += kWave) {
-                    const uint64_t idx = base + u0 + c;
-                    if (idx < ws.cap_units) {
-                        Unit un;
-                        un.anchor = a; un.rb = b | tag; un.c0 = c * CH; un.c1 = min(un.c0 + CH, ncols);
-                        ws.units[idx] = un;
+        // p = 3: one triangle; p = 4: the triangle after every candidate x;
+        // p = 5: the triangle after y for every pair x < y
+        const uint32_t ny = p == 3 ? 1 : (r.k >= 3 ? r.k - 2 : 0);
+        for (uint32_t y = p == 5 ? 1 : 0; y < ny; y++) {
+            const uint32_t kk = p == 3 ? r.k : r.k - y - 1;
+            const uint32_t nx = p == 5 ? y : 1;
+            for (uint32_t x = 0; x < nx; x++) {
+                const uint32_t nb = (kk + kWave - 1) / kWave;
+                for (uint32_t b = 0; b < nb; b++) {
+                    const uint32_t ncols = min(kWave * (b + 1), kk) - 1;
+                    const uint32_t nu = (ncols + CH - 1) / CH;
+                    for (uint32_t c = lane; c < nu; c += kWave) {
+                        const uint64_t idx = base + u0 + c;
+                        if (idx < ws.cap_units) {
+                            const uint32_t c0 = c * CH, c1 = min(c0 + CH, ncols);
+                            Unit un;
+                            un.anchor = a;
+                            if (p == 5) {
+                                un.rb = b | (x << 16); un.c0 = c0 | (c1 << 16); un.c1 = y + 1;
+                            } else {
+                                un.rb = b | (p == 4 ? (y + 1) << 16 : 0u); un.c0 = c0; un.c1 = c1;
+                            }
+                            ws.units[idx] = un;
+                        }
                     }
+                    u0 += nu;
                 }
-                u0 += nu;
             }
         }
     }
@@ -1427,7 +1440,8 @@ __device__ __forceinline__ uint64_t tri_rows(const Unit &un, const AnchorRec &a,
 template <int MODE>
 __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
                                   const uint32_t *__restrict__ masks, uint64_t *colacc,
-                                  const TriArgs &T, const uint32_t *xm = nullptr)
+                                  const TriArgs &T, const uint32_t *xm = nullptr,
+                                  const uint32_t *ym = nullptr)
 {
     const uint32_t lane = __lane_id();
     const uint32_t i = un.rb * kWave + lane;
@@ -1447,7 +1461,7 @@ __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
 #pragma unroll
             for (int w = 0; w < (int)kRegW; w++) {
                 row[w] = (vi && (uint32_t)w < wn) ? M[(uint64_t)i * W + w0 + w] : 0u;
-                if (MODE == 4 && (uint32_t)w < wn) row[w] &= xm[w0 + w];   // rows meet the first candidate
+                if (MODE >= 4 && (uint32_t)w < wn) row[w] &= xm[w0 + w] & ym[w0 + w];   // rows meet x (and y)
             }
 #pragma unroll
             for (int c = 0; c < 8; c++) {
@@ -1466,7 +1480,7 @@ __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
             const uint32_t j = un.c0 + cg + c;
             uint64_t t = 0;
             if (cg + c < ncol && j < i) {
-                if (MODE == 3 || MODE == 4) {
+                if (MODE >= 3) {
                     bool ovf = false;
                     t = choose_q(n[c], T.q, ovf);
                     if (ovf) atomicOr(&T.ws.ctr->over_cap, 16u);
@@ -1759,7 +1773,8 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
 template <int W, int MODE>
 __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
                                  const uint32_t *__restrict__ masks, const uint64_t *cq,
-                                 const uint32_t *c3, uint64_t *colacc, const uint32_t *xm)
+                                 const uint32_t *c3, uint64_t *colacc, const uint32_t *xm,
+                                 const uint32_t *ym)
 {
     constexpr int NC = (W + 3) / 4;          // 128-bit K-chunks
     constexpr int SB = 4;
@@ -1782,10 +1797,11 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
     auto piece = [&](uint32_t raw, int t, bool valid) {
         return spread_fp4(raw, valid && wf + t < (uint32_t)W);
     };
-    // MODE 4: the rows meet the first candidate's mask xm (same word layout)
+    // MODE 4 and 5: the rows meet the masks xm and ym of the candidates
+    // chosen before them (the same mask for MODE 4; same word layout)
     uint32_t xw[NC];
 #pragma unroll
-    for (int t = 0; t < NC; t++) xw[t] = MODE == 4 ? xm[ws + t] : ~0u;
+    for (int t = 0; t < NC; t++) xw[t] = MODE >= 4 ? xm[ws + t] & ym[ws + t] : ~0u;
     v8i32 A[SB][NC];
 #pragma unroll
     for (int sb = 0; sb < SB; sb++) {
@@ -1833,7 +1849,7 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
             cs += __shfl_xor(cs, 32, kWave);
             if (g == 0 && j < un.c1 && cs) colacc[j - un.c0] += cs;
             return 0;
-        } else if constexpr (MODE == 3 || MODE == 4) {
+        } else if constexpr (MODE >= 3) {
             // element e of block sb: row rbase + 16 sb + 4 g + e, column j0 + r16
             const bool diag = j0 + 16 > rbase;
             const uint32_t j = j0 + r16, i0 = rbase + 4 * g;
@@ -1901,7 +1917,7 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
             }
         return mine;
     }
-    return (MODE == 3 || MODE == 4) ? sum : sum / 6;
+    return MODE >= 3 ? sum : sum / 6;
 }
 
 // Masks wider than 16 words (totals): 64 rows x up to 64 columns per unit,
@@ -2018,13 +2034,13 @@ template <int MODE, int CLS>
 __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(TriArgs T)
 {
     __shared__ uint32_t c3[kC3Max + 1];
-    __shared__ uint64_t cq[MODE == 3 || MODE == 4 ? kC3Max + 1 : 1];   // C(n, q), n <= 32 kRegW
+    __shared__ uint64_t cq[MODE >= 3 ? kC3Max + 1 : 1];   // C(n, q), n <= 32 kRegW
     // per wave: column totals of a unit (MODE 1) or totals per anchor position,
     // masks up to kRegW words (MODE 2)
     constexpr uint32_t kLacc = MODE == 1 ? kMaxChunk : (MODE == 2 ? 32 * kRegW : 1);
     __shared__ unsigned long long colacc_all[MODE == 1 || MODE == 2 ? kTThreads / kWave : 1][kLacc];
     for (uint32_t i = threadIdx.x; i <= kC3Max; i += kTThreads) c3[i] = (uint32_t)choose3(i);
-    if (MODE == 3 || MODE == 4) {
+    if (MODE >= 3) {
         bool ovf = false;   // C(512, 7) < 2^51
         for (uint32_t i = threadIdx.x; i <= kC3Max; i += kTThreads) cq[i] = choose_q(i, T.q, ovf);
     }
@@ -2075,13 +2091,23 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
         const uint32_t u = u_base + (n_units - 1 - qlo++);
         Unit un = load_unit(T.ws.units + u);
         AnchorRec a = load_anchor(T.ws.anchors + un.anchor);
-        const uint32_t *xm = nullptr;
+        const uint32_t *xm = nullptr, *ym = nullptr;
         if constexpr (MODE == 4) {
             // the triangle of the candidates after x = base - 1, whose mask
             // every row meets: a record of k - base candidates from base on
             const uint32_t base = un.rb >> 16;
             un.rb &= 0xffffu;
-            xm = T.ws.masks + a.mask_off + (uint64_t)(base - 1) * a.w32;
+            xm = ym = T.ws.masks + a.mask_off + (uint64_t)(base - 1) * a.w32;
+            a.k -= base;
+            a.mask_off += (uint64_t)base * a.w32;
+        } else if constexpr (MODE == 5) {
+            // the triangle after y = base - 1, rows meeting the masks of x and y
+            const uint32_t base = un.c1, x = un.rb >> 16;
+            un.rb &= 0xffffu;
+            un.c1 = un.c0 >> 16;
+            un.c0 &= 0xffffu;
+            xm = T.ws.masks + a.mask_off + (uint64_t)x * a.w32;
+            ym = T.ws.masks + a.mask_off + (uint64_t)(base - 1) * a.w32;
             a.k -= base;
             a.mask_off += (uint64_t)base * a.w32;
         }
@@ -2094,7 +2120,7 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
         if (wide) {
             if constexpr (CLS != 0) {
                 if (MODE == 0) acc = tri_rows_mfma_wide(un, a, T.ws.masks);
-                else acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T, xm);
+                else acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T, xm, ym);
             }
         } else {
             // only the widths of this kernel's class are instantiated
@@ -2106,7 +2132,7 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
 #define BBC_W(n)                                                                                       \
     case n:                                                                                            \
         if constexpr (MODE != 0 || n >= kFp4MinW)                                                      \
-            acc = tri_rows_fp4<n, MODE>(un, a, T.ws.masks, cq, c3, colacc, xm);                        \
+            acc = tri_rows_fp4<n, MODE>(un, a, T.ws.masks, cq, c3, colacc, xm, ym);                    \
         else                                                                                           \
             acc = tri_rows_mfma<n>(un, a, T.ws.masks);                                                 \
         break;
@@ -2247,13 +2273,13 @@ hipError_t count_pairs(const PairArgs &base, const LaunchShape &sh, hipStream_t 
 }
 
 hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_t tmp_bytes,
-                      bool p4, hipStream_t s)
+                      uint32_t p, hipStream_t s)
 {
     uint32_t grid = (uint32_t)std::min<uint64_t>((ws.cap_anchors + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_plan_count, dim3(grid), dim3(256), 0, s, ws, chunk_base, p4 ? 1u : 0u);
+    hipLaunchKernelGGL(k_plan_count, dim3(grid), dim3(256), 0, s, ws, chunk_base, p);
     hipError_t e = scan_u32_to_u64(ws.ucnt, ws.uoff, 3 * ws.cap_anchors, tmp, tmp_bytes, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_write, dim3(1024), dim3(256), 0, s, ws, chunk_base, p4 ? 1u : 0u);
+    hipLaunchKernelGGL(k_plan_write, dim3(1024), dim3(256), 0, s, ws, chunk_base, p);
     return hipGetLastError();
 }
 
@@ -2279,9 +2305,13 @@ hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t
             hipLaunchKernelGGL((k_triplet<3, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
             hipLaunchKernelGGL((k_triplet<3, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
             break;
-        default:
+        case 4:
             hipLaunchKernelGGL((k_triplet<4, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
             hipLaunchKernelGGL((k_triplet<4, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
+            break;
+        default:
+            hipLaunchKernelGGL((k_triplet<5, 0>), dim3(grid), dim3(kTThreads), 0, s, T);
+            hipLaunchKernelGGL((k_triplet<5, 1>), dim3(grid), dim3(kTThreads), 0, s, T);
             break;
     }
     return hipGetLastError();

@@ -818,7 +818,7 @@ void enqueue_args(bbc_ctx *ctx, const LaunchArgs &L, hipStream_t s, bool timed)
     if (timed) HIP_OK(hipEventRecord(ctx->ev[0], s));
     HIP_OK(count_pairs(L.P, L.ls, s));
     if (timed) HIP_OK(hipEventRecord(ctx->ev[1], s));
-    HIP_OK(count_plan(ws, L.P.chunk_base, L.ptmp, L.ptmp_bytes, L.mode == 4, s));
+    HIP_OK(count_plan(ws, L.P.chunk_base, L.ptmp, L.ptmp_bytes, L.mode >= 4 ? (uint32_t)L.mode : 3u, s));
     if (timed) HIP_OK(hipEventRecord(ctx->ev[2], s));
     HIP_OK(count_triplets(L.T, L.mode, L.ls.grid_t, s));
     if (timed) HIP_OK(hipEventRecord(ctx->ev[3], s));
@@ -1331,11 +1331,11 @@ bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int6
         int mode = 0;
         if (na == 3 && nb == 3) mode = 0;
         else if (na == 3 && nb >= 4 && nb <= 7) mode = 3;
-        else if (na == 4 && nb >= 3 && nb <= 7) mode = 4;
+        else if ((na == 4 || na == 5) && nb >= 3 && nb <= 7) mode = na;
         else
             fail(BBC_E_UNSUPPORTED,
-                 "(p, q) = (%d, %d) on a graph anchored on %s: supported are 3 or 4 vertices on the "
-                 "anchor side (BBC_ANCHOR_U / BBC_ANCHOR_V) and 3..7 on the other",
+                 "(p, q) = (%d, %d) on a graph anchored on %s: supported are 3, 4 or 5 vertices on "
+                 "the anchor side (BBC_ANCHOR_U / BBC_ANCHOR_V) and 3..7 on the other",
                  p, q, side ? "V" : "U");
         (void)hipSetDevice(ctx->device);
         int64_t v = 0;

@@ -211,7 +211,7 @@ def test_invalid_inputs(ctx, B):
     assert ei.value.name == "BBC_E_SIGN"
     h = build(ctx, G.config1(1))
     with pytest.raises(B.BBCError) as ei:
-        ctx.count_global(h, 5, 5)
+        ctx.count_global(h, 6, 6)
     assert ei.value.name == "BBC_E_UNSUPPORTED"
     # the context is still usable after errors
     assert ctx.count_global(h) > 0
@@ -480,7 +480,7 @@ def test_general_q_rejected(ctx, B):
     say("general q rejected")
     g = G.config1(2)
     hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
-    for h, p, q in [(hv, 3, 5), (hu, 5, 3), (hu, 3, 8), (hu, 5, 5), (hv, 4, 5), (hu, 2, 3), (hv, 3, 2)]:
+    for h, p, q in [(hv, 3, 6), (hu, 6, 3), (hu, 3, 8), (hu, 6, 6), (hv, 4, 8), (hu, 2, 3), (hv, 3, 2)]:
         with pytest.raises(B.BBCError) as ei:
             ctx.count_global(h, p, q)
         assert ei.value.name == "BBC_E_UNSUPPORTED", (p, q)
@@ -564,3 +564,43 @@ def test_p4_config2_full(ctx):
     assert ctx.count_global(build(ctx, g, 1 << 4), 4, 3) == gold["4,3"]
     say("p4 config2 (3,4) V")
     assert ctx.count_global(build(ctx, g, 1 << 5), 3, 4) == gold["3,4"]
+
+
+# ------------------------------------------------- 5 vertices on the anchor side
+def test_p5_closed_forms(ctx):
+    C = math.comb
+    for n, m in [(6, 7), (12, 33), (40, 5)]:
+        g = G.from_rows(["+" * m] * n)
+        hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
+        for q in range(3, 8):
+            say("p5 complete", n, m, q)
+            assert ctx.count_global(hu, 5, q) == C(n, 5) * C(m, q)
+            assert ctx.count_global(hv, q, 5) == C(n, q) * C(m, 5)
+    for (n1, n2, m1, m2, q) in [(4, 5, 4, 3, 3), (10, 12, 15, 5, 4)]:
+        n, m = n1 + n2, m1 + m2
+        rows = ["".join("-" if (i >= n1 and j >= m1) else "+" for j in range(m)) for i in range(n)]
+        pure = C(n1, 5) + C(n2, 5)
+        want = pure * C(m, q) + (C(n, 5) - pure) * (C(m1, q) + C(m2, q))
+        assert ctx.count_global(build(ctx, G.from_rows(rows), 1 << 4), 5, q) == want
+
+
+def test_p5_vs_oracle(ctx, oracle):
+    """Config 1 (seed 1) against Algorithm 2 with p = 5 on both sides, and 40
+    dense tiny graphs against the definition."""
+    g = G.config1(1)
+    hu, hv = build(ctx, g, 1 << 4), build(ctx, g, 1 << 5)
+    for q in (3, 4):
+        say("p5 config1", q)
+        assert ctx.count_global(hu, 5, q) == oracle.count_bbvp_pk(g, 5, q, 0, threads=8)["total"]
+        assert ctx.count_global(hv, q, 5) == oracle.count_bbvp_pk(g, 5, q, 1, threads=8)["total"]
+    rng = np.random.default_rng(31)
+    for t in range(40):
+        n_u, n_v = int(rng.integers(5, 10)), int(rng.integers(5, 10))
+        dense = rng.random((n_u, n_v)) < rng.uniform(0.6, 1.0)
+        u, v = np.nonzero(dense)
+        s = np.where(rng.random(u.size) < rng.uniform(0.3, 1.0), 1, -1).astype(np.int8)
+        gt = G._finish(n_u, n_v, u, v, s)
+        hu, hv = build(ctx, gt, 1 << 4), build(ctx, gt, 1 << 5)
+        for q in (3, 4):
+            assert ctx.count_global(hu, 5, q) == oracle.count_bruteforce_pq(gt, 5, q), (t, q)
+            assert ctx.count_global(hv, q, 5) == oracle.count_bruteforce_pq(gt, q, 5), (t, q)
