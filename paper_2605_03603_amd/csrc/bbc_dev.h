@@ -97,7 +97,8 @@ struct Counters {           // device-side cursors and flags, zeroed per count
     unsigned long long pairs_examined;
     unsigned long long pair_words;
     uint32_t n_anchor;      // anchor records reserved (including unused slots)
-    uint32_t over_cap;      // 1, 2: a workspace capacity was exceeded; 4: unsupported anchor
+    uint32_t over_cap;      // 1, 2: a workspace capacity was exceeded; 4: unsupported anchor;
+                            // 8: lookup failure; 16: C(n, q) overflow; 32: more than 2^32 - 1 units
     uint32_t n_list[4];     // anchors handed to the workgroup tiers A, B, C, D
     uint32_t n_units;       // written by the plan kernel: all units
     uint32_t n_cls_end[2];  // units of class 0 (masks <= 4 words) come first, then

@@ -1236,14 +1236,19 @@ __global__ void __launch_bounds__(256) k_plan_count(Workspace ws, uint32_t chunk
         if (a < n_rec) {
             const AnchorRec &r = ws.anchors[a];
             if (r.k <= 65535u) {
+                uint64_t c64 = 0;
                 if (p == 4) {
-                    for (uint32_t x = 0; x + 2 < r.k; x++) c += anchor_units(r.k - x - 1, r.w32, chunk_base);
+                    for (uint32_t x = 0; x + 2 < r.k; x++) c64 += anchor_units(r.k - x - 1, r.w32, chunk_base);
                 } else if (p == 5) {
                     // y pairs (x, y) for every y, each with the triangle after y
-                    for (uint32_t y = 1; y + 2 < r.k; y++) c += y * anchor_units(r.k - y - 1, r.w32, chunk_base);
+                    for (uint32_t y = 1; y + 2 < r.k; y++)
+                        c64 += (uint64_t)y * anchor_units(r.k - y - 1, r.w32, chunk_base);
                 } else {
-                    c = anchor_units(r.k, r.w32, chunk_base);
+                    c64 = anchor_units(r.k, r.w32, chunk_base);
                 }
+                // units are numbered in 32 bits: a larger plan is reported, not cut
+                if (c64 > 0xffffffffull) atomicOr(&ws.ctr->over_cap, 32u);
+                c = c64 > 0xffffffffull ? 0u : (uint32_t)c64;
             }
             cls = unit_class(r.w32);
         }
@@ -1262,7 +1267,8 @@ __global__ void __launch_bounds__(256) k_plan_write(Workspace ws, uint32_t chunk
         C->n_units = (uint32_t)min(total, ws.cap_units);
         C->n_cls_end[0] = (uint32_t)min(ws.uoff[ws.cap_anchors], ws.cap_units);
         C->n_cls_end[1] = (uint32_t)min(ws.uoff[2 * ws.cap_anchors], ws.cap_units);
-        if (total > ws.cap_units) {
+        if (total > 0xffffffffull) atomicOr(&C->over_cap, 32u);   // units are numbered in 32 bits
+        else if (total > ws.cap_units) {
             atomicOr(&C->over_cap, 2u);
             if (total > C->need_units) C->need_units = total;   // the exact demand
         }

@@ -847,6 +847,9 @@ bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set)
     const Counters *c = w.host.as<Counters>();
     if (c->over_cap & 8u) fail(BBC_E_HIP, "internal error: pair table lookup failed");
     if (c->over_cap & 16u) fail(BBC_E_OVERFLOW, "a term C(n, q) of the count needs more than 64 bits");
+    if (c->over_cap & 32u)
+        fail(BBC_E_UNSUPPORTED, "the count needs more than 2^32 - 1 triplet work units (too many "
+                                "candidate subsets for this graph)");
     if (c->over_cap & 4u)
         fail(BBC_E_UNSUPPORTED, "an anchor has degree above %u or more than %u candidate classes",
              tier_c_max_degree(), tier_c_max_k());
