@@ -119,6 +119,14 @@ bbc_status bbc_get_graph_info(bbc_ctx *ctx, const bbc_graph *g, bbc_graph_info *
  * does not fit 64 bits), BBC_E_NOMEM, BBC_E_HIP. */
 bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int64_t *out_count);
 
+/* The k vertices of the requested side (0 = U, 1 = V) that lie in the most
+ * balanced (3,3)-bicliques, by the per-vertex counts above: out_ids[i],
+ * out_counts[i] for i < *out_n = min(k, side size), counts descending, ties
+ * to the smaller id. Host arrays of k entries (caller-owned). Errors as for
+ * bbc_count_per_vertex. */
+bbc_status bbc_top_vertices(bbc_ctx *ctx, const bbc_graph *g, int side, uint32_t k,
+                            uint32_t *out_ids, int64_t *out_counts, uint32_t *out_n);
+
 /* Edge queries for dynamic graphs (Section 6 names dynamic signed bipartite
  * graphs as the next direction). For query i, out[i] = number of balanced
  * (3,3)-bicliques that contain the edge (eu[i], ev[i]) (ids of U and V) in g

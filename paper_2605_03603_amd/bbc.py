@@ -35,7 +35,7 @@ BBC_ANCHOR_SMALLER = 1 << 6
 
 EXPORTED = ["bbc_ctx_create", "bbc_ctx_destroy", "bbc_build_csr", "bbc_build_csr_batch",
             "bbc_graph_free", "bbc_get_graph_info", "bbc_count_global", "bbc_count_per_vertex",
-            "bbc_count_through_edges",
+            "bbc_count_through_edges", "bbc_top_vertices",
             "bbc_count_batch", "bbc_submit", "bbc_submit_coo", "bbc_poll", "bbc_wait",
             "bbc_get_last_stats", "bbc_set_timing", "bbc_status_string", "bbc_last_error"]
 
@@ -89,6 +89,7 @@ def _load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.bbc_count_per_vertex.argtypes = [_vp, _vp, _i32, _i32, _i32, _vp,
                                        ctypes.POINTER(ctypes.c_int64)]
     L.bbc_count_through_edges.argtypes = [_vp, _vp, _u64, _vp, _vp, _vp, _vp]
+    L.bbc_top_vertices.argtypes = [_vp, _vp, _i32, _u32, _vp, _vp, ctypes.POINTER(_u32)]
     L.bbc_count_batch.argtypes = [_vp, _vp, _u32, _vp]
     L.bbc_submit.argtypes = [_vp, _vp, ctypes.POINTER(_u64)]
     L.bbc_submit_coo.argtypes = [_vp, _u32, _u32, _u64, _vp, _vp, _vp, _u32, ctypes.POINTER(_u64)]
@@ -210,6 +211,17 @@ class Context:
         out = ctypes.c_int64()
         self._check(lib.bbc_count_global(self.handle, g.handle, p, q, ctypes.byref(out)))
         return out.value
+
+    def top_vertices(self, g: Graph, side: int, k: int) -> Tuple[np.ndarray, np.ndarray]:
+        """The k vertices of a side in the most balanced (3,3)-bicliques:
+        (ids, counts), counts descending, ties to the smaller id."""
+        ids = np.zeros(max(k, 1), dtype=np.uint32)
+        cnt = np.zeros(max(k, 1), dtype=np.int64)
+        n = _u32(0)
+        self._check(lib.bbc_top_vertices(self.handle, g.handle, side, k,
+                                         ids.ctypes.data_as(ctypes.c_void_p),
+                                         cnt.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+        return ids[:n.value].copy(), cnt[:n.value].copy()
 
     def count_through_edges(self, g: Graph, eu, ev, es) -> np.ndarray:
         """Balanced (3,3)-bicliques through each queried edge (eu[i], ev[i])

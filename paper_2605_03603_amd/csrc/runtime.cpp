@@ -1456,6 +1456,33 @@ bbc_status bbc_count_per_vertex(bbc_ctx *ctx, const bbc_graph *g, int p, int q, 
     });
 }
 
+bbc_status bbc_top_vertices(bbc_ctx *ctx, const bbc_graph *g, int side, uint32_t k,
+                            uint32_t *out_ids, int64_t *out_counts, uint32_t *out_n)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return guard(ctx, [&] {
+        if (!g || !out_n || (k > 0 && (!out_ids || !out_counts))) fail(BBC_E_INVAL, "null argument");
+        if (side != 0 && side != 1) fail(BBC_E_INVAL, "side must be 0 (U) or 1 (V)");
+        const GraphDesc &d = g->set->desc[g->idx];
+        const uint32_t n = side == 0 ? d.n_u : d.n_v;
+        std::vector<int64_t> pv(std::max<uint32_t>(n, 1));
+        const bbc_status st = bbc_count_per_vertex(ctx, g, 3, 3, side, pv.data(), nullptr);
+        if (st != BBC_OK) fail(st, "%s", ctx->last_error.c_str());
+        // the k largest counts, ties to the smaller id
+        std::vector<uint32_t> ids(n);
+        for (uint32_t i = 0; i < n; i++) ids[i] = i;
+        const uint32_t kk = std::min(k, n);
+        std::partial_sort(ids.begin(), ids.begin() + kk, ids.end(), [&](uint32_t a, uint32_t b) {
+            return pv[a] != pv[b] ? pv[a] > pv[b] : a < b;
+        });
+        for (uint32_t i = 0; i < kk; i++) {
+            out_ids[i] = ids[i];
+            out_counts[i] = pv[ids[i]];
+        }
+        *out_n = kk;
+    });
+}
+
 bbc_status bbc_count_batch(bbc_ctx *ctx, const bbc_graph *const *graphs, uint32_t n_graphs,
                            int64_t *out_counts)
 {

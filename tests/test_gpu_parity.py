@@ -604,3 +604,23 @@ def test_p5_vs_oracle(ctx, oracle):
         for q in (3, 4):
             assert ctx.count_global(hu, 5, q) == oracle.count_bruteforce_pq(gt, 5, q), (t, q)
             assert ctx.count_global(hv, q, 5) == oracle.count_bruteforce_pq(gt, q, 5), (t, q)
+
+
+def test_top_vertices(ctx, oracle):
+    """The k vertices in the most balanced (3,3)-bicliques, from the oracle's
+    per-vertex counts (descending, ties to the smaller id), on both sides and
+    for either anchor side of the build."""
+    g = G.config1(1)
+    per = {0: oracle.count_bbvp(g, 0, per_vertex=True)["per_vertex"],
+           1: oracle.count_bbvp(g, 1, per_vertex=True)["per_vertex"]}
+    for flags in (1 << 4, 1 << 5):
+        h = build(ctx, g, flags)
+        for side in (0, 1):
+            pv = per[side]
+            order = sorted(range(len(pv)), key=lambda i: (-int(pv[i]), i))
+            for k in (1, 10, len(pv) + 5):
+                ids, cnt = ctx.top_vertices(h, side, k)
+                want = order[:k]
+                assert ids.tolist() == want, (flags, side, k)
+                assert cnt.tolist() == [int(pv[i]) for i in want]
+    assert ctx.top_vertices(build(ctx, g), 0, 0)[0].size == 0
