@@ -355,25 +355,27 @@ def main():
 
     if not args.no_edges:
         # edge queries (balanced bicliques through an edge: the change of the
-        # count on inserting, deleting or re-signing it), 200 existing edges
-        # with their own sign and 200 new pairs, one after the other;
+        # count on inserting, deleting or re-signing it), 20000 existing edges
+        # with their own sign and 2000 new pairs in one call (batched);
         # exactness against the oracle is in the GPU tests
         log("edge queries")
         rng = np.random.default_rng(7)
         h = ctx.build_csr(g.n_u, g.n_v, d_eu, d_ev, d_sg, 1 << 4)
-        idx = rng.choice(g.m, size=200, replace=False)
-        qu = np.concatenate([g.eu[idx], rng.integers(0, g.n_u, 200)]).astype(np.uint32)
-        qv = np.concatenate([g.ev[idx], rng.integers(0, g.n_v, 200)]).astype(np.uint32)
-        qs = np.concatenate([g.sign[idx], np.ones(200, np.int8)]).astype(np.int8)
-        ctx.count_through_edges(h, qu[:8], qv[:8], qs[:8])
+        ne, nn = 20000, 2000
+        idx = rng.choice(g.m, size=ne, replace=False)
+        qu = np.concatenate([g.eu[idx], rng.integers(0, g.n_u, nn)]).astype(np.uint32)
+        qv = np.concatenate([g.ev[idx], rng.integers(0, g.n_v, nn)]).astype(np.uint32)
+        qs = np.concatenate([g.sign[idx], np.ones(nn, np.int8)]).astype(np.int8)
+        ctx.count_through_edges(h, qu[:64], qv[:64], qs[:64])
         torch.cuda.synchronize()
         t = time.time()
         through = ctx.count_through_edges(h, qu, qv, qs)
         ms = 1e3 * (time.time() - t)
         h.free()
-        out["edge_queries"] = {"queries": int(qu.size), "ms_per_query": round(ms / qu.size, 4),
-                               "existing_edges_sum": int(through[:200].sum()),
-                               "new_pairs_sum": int(through[200:].sum())}
+        out["edge_queries"] = {"queries": int(qu.size), "ms_total": round(ms, 2),
+                               "us_per_query": round(1e3 * ms / qu.size, 3),
+                               "existing_edges_sum": int(through[:ne].sum()),
+                               "new_pairs_sum": int(through[ne:].sum())}
 
     if not args.no_cpu:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)

@@ -136,7 +136,7 @@ bbc_status bbc_top_vertices(bbc_ctx *ctx, const bbc_graph *g, int side, uint32_t
  * of sign s changes the count by minus the query with s, and flipping it by
  * the query with -s minus the query with s. Every other edge is as in g.
  * All arrays are host memory of n_queries entries (out caller-owned); the
- * queries run one after the other on the context's stream. Errors:
+ * queries run in batches on the context's stream. Errors:
  * BBC_E_RANGE (an id outside the graph), BBC_E_SIGN (a sign other than
  * +1 / -1), BBC_E_OVERFLOW, BBC_E_NOMEM, BBC_E_HIP; out is then unspecified. */
 bbc_status bbc_count_through_edges(bbc_ctx *ctx, const bbc_graph *g, uint64_t n_queries,

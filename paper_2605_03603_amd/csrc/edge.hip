@@ -1,4 +1,4 @@
-// edge.hip -- balanced (3,3)-bicliques through one edge: the change of the
+// edge.hip -- balanced (3,3)-bicliques through an edge: the change of the
 // count when the edge is inserted, deleted or re-signed (Section 6 names
 // dynamic signed bipartite graphs as the next direction).
 //
@@ -26,80 +26,95 @@ namespace {
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr int kSetupThreads = 1024;
 constexpr int kT = 256;
+constexpr uint32_t kBlocksPerQuery = 4;   // workgroups of the mask and pair kernels per query
 
 __device__ __forceinline__ uint32_t edge_hash(uint32_t x, uint32_t lg)
 {
     return (x * 0x9E3779B1u) >> (32 - lg);
 }
 
-// the S rank of a: the one rank of the graph whose input id is a_id
-__global__ void __launch_bounds__(kT) k_edge_locate(CsrView g, uint32_t s_base, uint32_t n_s,
-                                                    uint32_t a_id, EdgeScratch x)
+// S rank of every input id of the graph
+__global__ void __launch_bounds__(kT) k_edge_inverse(CsrView g, uint32_t s_base, uint32_t n_s,
+                                                     EdgeScratch x)
 {
     for (uint32_t r = blockIdx.x * kT + threadIdx.x; r < n_s; r += gridDim.x * kT)
-        if (g.s_vert[s_base + r] == a_id) x.ctl[0] = s_base + r;
+        x.inv[g.s_vert[s_base + r]] = s_base + r;
 }
 
-// N(a) into the hash table (b left out: its position stands for the queried
-// sign), the partners N(b) \ {a} with their class bit, cleared masks
-__global__ void __launch_bounds__(kSetupThreads) k_edge_setup(CsrView g, uint32_t b_idx,
-                                                              uint32_t neg_q, EdgeScratch x)
+// one workgroup per query: N(a) into the query's hash table (b left out: its
+// position stands for the queried sign), the partners N(b) \ {a} with their
+// class bit, cleared masks
+__global__ void __launch_bounds__(kSetupThreads) k_edge_setup(CsrView g, const EdgeQuery *qs,
+                                                              EdgeScratch x)
 {
     __shared__ uint32_t sh_pb, sh_np;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t r = x.ctl[0];
+    const uint32_t tid = threadIdx.x, qi = blockIdx.x;
+    const EdgeQuery q = qs[qi];
+    uint32_t *ctl = x.ctl + 8 * qi;
+    const uint32_t H = 1u << x.lg;
+    uint32_t *hkey = x.hkey + (uint64_t)qi * H, *hval = x.hval + (uint64_t)qi * H;
+    uint32_t *part = x.part + (uint64_t)qi * x.part_stride;
+    uint32_t *masks = x.masks + (uint64_t)qi * x.mask_stride;
+    const uint32_t r = x.inv[q.a_id];
     const uint64_t s0 = g.s_off[r];
     const uint32_t da = (uint32_t)(g.s_off[r + 1] - s0);
-    const uint32_t H = 1u << x.lg;
-    for (uint32_t h = tid; h < H; h += kSetupThreads) x.hkey[h] = kNone;
+    for (uint32_t h = tid; h < H; h += kSetupThreads) hkey[h] = kNone;
     if (tid == 0) { sh_pb = da; sh_np = 0; }
     __syncthreads();
     // position of b in N(a), or da when the edge is new
     for (uint32_t t = tid; t < da; t += kSetupThreads)
-        if ((g.s_adj[s0 + t] >> 1) == b_idx) atomicMin(&sh_pb, t);
+        if ((g.s_adj[s0 + t] >> 1) == q.b_idx) atomicMin(&sh_pb, t);
     for (uint32_t t = tid; t < da; t += kSetupThreads) {
         const uint32_t e = g.s_adj[s0 + t];
         const uint32_t key = e >> 1;
-        if (key == b_idx) continue;
+        if (key == q.b_idx) continue;
         uint32_t h = edge_hash(key, x.lg);
         for (;;) {
-            const uint32_t old = atomicCAS(&x.hkey[h], kNone, key);
-            if (old == kNone) { x.hval[h] = (t << 1) | (e & 1u); break; }
+            const uint32_t old = atomicCAS(&hkey[h], kNone, key);
+            if (old == kNone) { hval[h] = (t << 1) | (e & 1u); break; }
             h = (h + 1) & (H - 1);
         }
     }
-    const uint64_t b0 = g.o_off[b_idx];
-    const uint32_t db = (uint32_t)(g.o_off[b_idx + 1] - b0);
+    const uint64_t b0 = g.o_off[q.b_idx];
+    const uint32_t db = (uint32_t)(g.o_off[q.b_idx + 1] - b0);
     for (uint32_t t = tid; t < db; t += kSetupThreads) {
         const uint32_t e = g.o_adj[b0 + t];
         const uint32_t w = e >> 1;
         if (w == r) continue;
         const uint32_t i = atomicAdd(&sh_np, 1u);
-        x.part[i] = w | (((e & 1u) ^ neg_q) << 31);
+        part[i] = w | (((e & 1u) ^ q.neg) << 31);
     }
     __syncthreads();
     const uint32_t W = da / 32 + 1;   // positions 0 .. da
-    for (uint64_t i = tid; i < (uint64_t)sh_np * W; i += kSetupThreads) x.masks[i] = 0;
+    for (uint64_t i = tid; i < (uint64_t)sh_np * W; i += kSetupThreads) masks[i] = 0;
     if (tid == 0) {
-        x.ctl[1] = sh_pb;
-        x.ctl[2] = da;
-        x.ctl[3] = W;
-        x.ctl[4] = sh_np;
+        ctl[0] = r;
+        ctl[1] = sh_pb;
+        ctl[2] = da;
+        ctl[3] = W;
+        ctl[4] = sh_np;
     }
 }
 
-// one wave per partner w: bit p of M_w for every neighbour of w at position
-// p of N(a) whose wedge type is w's class at b
-__global__ void __launch_bounds__(kT) k_edge_masks(CsrView g, uint32_t b_idx, EdgeScratch x)
+// kBlocksPerQuery workgroups per query, one wave per partner w: bit p of M_w
+// for every neighbour of w at position p of N(a) whose wedge type is w's
+// class at b
+__global__ void __launch_bounds__(kT) k_edge_masks(CsrView g, const EdgeQuery *qs, EdgeScratch x)
 {
-    const uint32_t np = x.ctl[4], W = x.ctl[3], pb = x.ctl[1];
+    const uint32_t qi = blockIdx.x / kBlocksPerQuery, sub = blockIdx.x % kBlocksPerQuery;
+    const uint32_t *ctl = x.ctl + 8 * qi;
+    const uint32_t np = ctl[4], W = ctl[3], pb = ctl[1];
+    const uint32_t b_idx = qs[qi].b_idx;
     const uint32_t lane = __lane_id();
     const uint32_t H = 1u << x.lg;
-    const uint32_t nw = gridDim.x * (kT / kWave);
-    for (uint32_t i = blockIdx.x * (kT / kWave) + threadIdx.x / kWave; i < np; i += nw) {
-        const uint32_t pw = x.part[i];
+    const uint32_t *hkey = x.hkey + (uint64_t)qi * H, *hval = x.hval + (uint64_t)qi * H;
+    const uint32_t *part = x.part + (uint64_t)qi * x.part_stride;
+    uint32_t *masks = x.masks + (uint64_t)qi * x.mask_stride;
+    const uint32_t nw = kBlocksPerQuery * (kT / kWave);
+    for (uint32_t i = sub * (kT / kWave) + threadIdx.x / kWave; i < np; i += nw) {
+        const uint32_t pw = part[i];
         const uint32_t w = pw & 0x7fffffffu, cls = pw >> 31;
-        uint32_t *M = x.masks + (uint64_t)i * W;
+        uint32_t *M = masks + (uint64_t)i * W;
         if (lane == 0) atomicOr(&M[pb >> 5], 1u << (pb & 31));
         const uint64_t s0 = g.s_off[w];
         const uint32_t dw = (uint32_t)(g.s_off[w + 1] - s0);
@@ -109,10 +124,10 @@ __global__ void __launch_bounds__(kT) k_edge_masks(CsrView g, uint32_t b_idx, Ed
             if (key == b_idx) continue;
             uint32_t h = edge_hash(key, x.lg);
             for (;;) {
-                const uint32_t k = x.hkey[h];
+                const uint32_t k = hkey[h];
                 if (k == kNone) break;
                 if (k == key) {
-                    const uint32_t v = x.hval[h];
+                    const uint32_t v = hval[h];
                     const uint32_t p = v >> 1;
                     if (((v ^ e) & 1u) == cls) atomicOr(&M[p >> 5], 1u << (p & 31));
                     break;
@@ -123,39 +138,49 @@ __global__ void __launch_bounds__(kT) k_edge_masks(CsrView g, uint32_t b_idx, Ed
     }
 }
 
-// one wave per partner i: C(|M_i n M_j| - 1, 2) over the partners j > i
+// kBlocksPerQuery workgroups per query, one wave per partner i:
+// C(|M_i n M_j| - 1, 2) over the partners j > i
 __global__ void __launch_bounds__(kT) k_edge_pairs(EdgeScratch x)
 {
-    const uint32_t np = x.ctl[4], W = x.ctl[3];
+    const uint32_t qi = blockIdx.x / kBlocksPerQuery, sub = blockIdx.x % kBlocksPerQuery;
+    const uint32_t *ctl = x.ctl + 8 * qi;
+    const uint32_t np = ctl[4], W = ctl[3];
+    const uint32_t *masks = x.masks + (uint64_t)qi * x.mask_stride;
     const uint32_t lane = __lane_id();
-    const uint32_t nw = gridDim.x * (kT / kWave);
+    const uint32_t nw = kBlocksPerQuery * (kT / kWave);
     uint64_t acc = 0;
-    for (uint32_t i = blockIdx.x * (kT / kWave) + threadIdx.x / kWave; i < np; i += nw) {
-        const uint32_t *Mi = x.masks + (uint64_t)i * W;
+    for (uint32_t i = sub * (kT / kWave) + threadIdx.x / kWave; i < np; i += nw) {
+        const uint32_t *Mi = masks + (uint64_t)i * W;
         for (uint32_t j = i + 1 + lane; j < np; j += kWave) {
-            const uint32_t *Mj = x.masks + (uint64_t)j * W;
+            const uint32_t *Mj = masks + (uint64_t)j * W;
             uint32_t n = 0;
             for (uint32_t w = 0; w < W; w++) n += __popc(Mi[w] & Mj[w]);
             if (n >= 3) acc += (uint64_t)(n - 1) * (n - 2) / 2;
         }
     }
     acc = wave_sum<uint64_t>(acc);
-    if (lane == 0 && acc) atomicAdd(x.result, (unsigned long long)acc);
+    if (lane == 0 && acc) atomicAdd(&x.result[qi], (unsigned long long)acc);
 }
 
 }  // namespace
 
-hipError_t edge_through(const CsrView &g, uint32_t s_base, uint32_t n_s, uint32_t a_id,
-                        uint32_t b_idx, uint32_t neg_q, const EdgeScratch &x, uint32_t grid,
+hipError_t edge_inverse(const CsrView &g, uint32_t s_base, uint32_t n_s, const EdgeScratch &x,
                         hipStream_t s)
 {
-    hipError_t e = fill_u32(x.ctl, 0, 8, s);
-    if (e == hipSuccess) e = fill_u64(x.result, 0, 1, s);
+    const uint32_t grid = std::max(1u, std::min((n_s + kT - 1) / kT, 4096u));
+    hipLaunchKernelGGL(k_edge_inverse, dim3(grid), dim3(kT), 0, s, g, s_base, n_s, x);
+    return hipGetLastError();
+}
+
+hipError_t edge_through(const CsrView &g, const EdgeQuery *q, uint32_t n, const EdgeScratch &x,
+                        hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipError_t e = fill_u64(x.result, 0, n, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_edge_locate, dim3(grid), dim3(kT), 0, s, g, s_base, n_s, a_id, x);
-    hipLaunchKernelGGL(k_edge_setup, dim3(1), dim3(kSetupThreads), 0, s, g, b_idx, neg_q, x);
-    hipLaunchKernelGGL(k_edge_masks, dim3(grid), dim3(kT), 0, s, g, b_idx, x);
-    hipLaunchKernelGGL(k_edge_pairs, dim3(grid), dim3(kT), 0, s, x);
+    hipLaunchKernelGGL(k_edge_setup, dim3(n), dim3(kSetupThreads), 0, s, g, q, x);
+    hipLaunchKernelGGL(k_edge_masks, dim3(n * kBlocksPerQuery), dim3(kT), 0, s, g, q, x);
+    hipLaunchKernelGGL(k_edge_pairs, dim3(n * kBlocksPerQuery), dim3(kT), 0, s, x);
     return hipGetLastError();
 }
 

@@ -1369,40 +1369,58 @@ bbc_status bbc_count_through_edges(bbc_ctx *ctx, const bbc_graph *g, uint64_t n_
         (void)hipSetDevice(ctx->device);
         Allocator *al = ctx->al.get();
         hipStream_t s = ctx->stream;
-        // scratch for the largest degree D of the set
+        // scratch for the largest degree D of the set, per query of a batch;
+        // the batch holds as many queries as fit 512 MiB
         const uint64_t D = set.max_deg;
         uint32_t lg = 6;
         while ((1ull << lg) < 2 * (D + 1)) lg++;
         const uint64_t H = 1ull << lg;
-        const uint64_t mask_words = (D + 1) * (D / 32 + 1);
-        DBuf ctl, res, hk, hv, part, masks;
-        ctl.ensure(al, 8 * 4);
-        res.ensure(al, 8);
-        hk.ensure(al, H * 4);
-        hv.ensure(al, H * 4);
-        part.ensure(al, (D + 1) * 4);
-        masks.ensure(al, mask_words * 4);
+        const uint64_t mask_stride = (D + 1) * (D / 32 + 1);
+        const uint64_t per_query = 4 * (8 + 2 + 2 * H + (D + 1) + mask_stride) + 16;
+        const uint64_t Q = std::max<uint64_t>(1, std::min<uint64_t>({n_queries, (512ull << 20) / per_query, 65536}));
+        DBuf inv, ctl, res, hk, hv, part, masks, qbuf;
+        inv.ensure(al, std::max<uint64_t>(d.n_s, 1) * 4);
+        ctl.ensure(al, Q * 8 * 4);
+        res.ensure(al, Q * 8);
+        hk.ensure(al, Q * H * 4);
+        hv.ensure(al, Q * H * 4);
+        part.ensure(al, Q * (D + 1) * 4);
+        masks.ensure(al, Q * mask_stride * 4);
+        qbuf.ensure(al, Q * sizeof(EdgeQuery));
         EdgeScratch x;
+        x.inv = inv.as<uint32_t>();
         x.ctl = ctl.as<uint32_t>();
         x.result = res.as<unsigned long long>();
         x.hkey = hk.as<uint32_t>();
         x.hval = hv.as<uint32_t>();
         x.lg = lg;
         x.part = part.as<uint32_t>();
+        x.part_stride = (uint32_t)(D + 1);
         x.masks = masks.as<uint32_t>();
+        x.mask_stride = mask_stride;
         const CsrView view = set.view();
-        const uint32_t grid = std::max(1u, (uint32_t)ctx->num_cus * 4);
-        for (uint64_t i = 0; i < n_queries; i++) {
-            // a on the anchor side S, b on the other
-            const uint32_t a = d.side ? ev[i] : eu[i];
-            const uint32_t b = d.side ? eu[i] : ev[i];
-            HIP_OK(edge_through(view, d.s_base, d.n_s, a, d.o_base + b, es[i] < 0 ? 1u : 0u, x, grid, s));
-            unsigned long long v = 0;
-            HIP_OK(hipMemcpyAsync(&v, x.result, 8, hipMemcpyDeviceToHost, s));
+        HIP_OK(edge_inverse(view, d.s_base, d.n_s, x, s));
+        std::vector<EdgeQuery> hq(Q);
+        std::vector<unsigned long long> hr(Q);
+        for (uint64_t q0 = 0; q0 < n_queries; q0 += Q) {
+            const uint32_t n = (uint32_t)std::min<uint64_t>(Q, n_queries - q0);
+            for (uint32_t i = 0; i < n; i++) {
+                // a on the anchor side S, b on the other
+                const uint64_t j = q0 + i;
+                hq[i].a_id = d.side ? ev[j] : eu[j];
+                hq[i].b_idx = d.o_base + (d.side ? eu[j] : ev[j]);
+                hq[i].neg = es[j] < 0 ? 1u : 0u;
+                hq[i].pad = 0;
+            }
+            HIP_OK(hipMemcpyAsync(qbuf.p, hq.data(), n * sizeof(EdgeQuery), hipMemcpyHostToDevice, s));
+            HIP_OK(edge_through(view, qbuf.as<EdgeQuery>(), n, x, s));
+            HIP_OK(hipMemcpyAsync(hr.data(), x.result, n * 8ull, hipMemcpyDeviceToHost, s));
             HIP_OK(hipStreamSynchronize(s));
-            if (v > (unsigned long long)INT64_MAX) fail(BBC_E_OVERFLOW, "query %llu: count needs more than 63 bits",
-                                                        (unsigned long long)i);
-            out[i] = (int64_t)v;
+            for (uint32_t i = 0; i < n; i++) {
+                if (hr[i] > (unsigned long long)INT64_MAX)
+                    fail(BBC_E_OVERFLOW, "query %llu: count needs more than 63 bits", (unsigned long long)(q0 + i));
+                out[q0 + i] = (int64_t)hr[i];
+            }
         }
     });
 }

@@ -116,3 +116,16 @@ def test_edges_errors(ctx, B):
         ctx.count_through_edges(h, [0], [0], [0])
     assert e.value.name == "BBC_E_SIGN"
     assert ctx.count_through_edges(h, [], [], []).tolist() == []
+
+
+def test_edges_config2_all_edges(ctx):
+    """Config 2 at full size: the queries of all 2,057,578 edges with their own
+    signs sum to 9 B, B from tests/golden/cfg2_seed1.json (the oracle's count)."""
+    from tests.gpu_common import golden
+    want = golden("cfg2_seed1.json")["total"]
+    g = G.config2(1)
+    h = build(ctx, g, 1 << 4)
+    say("edges config2 all", g.m)
+    got = ctx.count_through_edges(h, g.eu, g.ev, g.sign)
+    assert int(got.sum()) == 9 * want
+    assert (got >= 0).all()
