@@ -119,6 +119,17 @@ bbc_status bbc_get_graph_info(bbc_ctx *ctx, const bbc_graph *g, bbc_graph_info *
  * does not fit 64 bits), BBC_E_NOMEM, BBC_E_HIP. */
 bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int64_t *out_count);
 
+/* The same count as bbc_count_global for 3 vertices on the graph's anchor
+ * side and q = 3..7 on the other, by Algorithm 1 (BBWC, wedge-centric): for
+ * every anchor, the signed 3-wedges through pairs of lower-priority partners
+ * are bucketed by (partner pair, wedge type) and each bucket of size n adds
+ * C(n, q). A second, independent path (it shares only the CSR with
+ * bbc_count_global), for cross-checks on small and medium graphs.
+ * out_count: host int64. Errors: BBC_E_UNSUPPORTED (other (p, q), or an
+ * anchor with more than 393,216 wedge pairs: the path's per-anchor table),
+ * BBC_E_OVERFLOW, BBC_E_NOMEM, BBC_E_HIP. */
+bbc_status bbc_count_bbwc(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int64_t *out_count);
+
 /* The k vertices of the requested side (0 = U, 1 = V) that lie in the most
  * balanced (3,3)-bicliques, by the per-vertex counts above: out_ids[i],
  * out_counts[i] for i < *out_n = min(k, side size), counts descending, ties

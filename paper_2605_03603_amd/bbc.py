@@ -35,7 +35,7 @@ BBC_ANCHOR_SMALLER = 1 << 6
 
 EXPORTED = ["bbc_ctx_create", "bbc_ctx_destroy", "bbc_build_csr", "bbc_build_csr_batch",
             "bbc_graph_free", "bbc_get_graph_info", "bbc_count_global", "bbc_count_per_vertex",
-            "bbc_count_through_edges", "bbc_top_vertices",
+            "bbc_count_through_edges", "bbc_top_vertices", "bbc_count_bbwc",
             "bbc_count_batch", "bbc_submit", "bbc_submit_coo", "bbc_poll", "bbc_wait",
             "bbc_get_last_stats", "bbc_set_timing", "bbc_status_string", "bbc_last_error"]
 
@@ -90,6 +90,7 @@ def _load(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(ctypes.c_int64)]
     L.bbc_count_through_edges.argtypes = [_vp, _vp, _u64, _vp, _vp, _vp, _vp]
     L.bbc_top_vertices.argtypes = [_vp, _vp, _i32, _u32, _vp, _vp, ctypes.POINTER(_u32)]
+    L.bbc_count_bbwc.argtypes = [_vp, _vp, _i32, _i32, ctypes.POINTER(ctypes.c_int64)]
     L.bbc_count_batch.argtypes = [_vp, _vp, _u32, _vp]
     L.bbc_submit.argtypes = [_vp, _vp, ctypes.POINTER(_u64)]
     L.bbc_submit_coo.argtypes = [_vp, _u32, _u32, _u64, _vp, _vp, _vp, _u32, ctypes.POINTER(_u64)]
@@ -210,6 +211,12 @@ class Context:
     def count_global(self, g: Graph, p: int = 3, q: int = 3) -> int:
         out = ctypes.c_int64()
         self._check(lib.bbc_count_global(self.handle, g.handle, p, q, ctypes.byref(out)))
+        return out.value
+
+    def count_bbwc(self, g: Graph, p: int = 3, q: int = 3) -> int:
+        """The count by the wedge-centric path (bbc_count_bbwc)."""
+        out = ctypes.c_int64(0)
+        self._check(lib.bbc_count_bbwc(self.handle, g.handle, p, q, ctypes.byref(out)))
         return out.value
 
     def top_vertices(self, g: Graph, side: int, k: int) -> Tuple[np.ndarray, np.ndarray]:

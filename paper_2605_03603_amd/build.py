@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbbc.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["prims.hip", "build.hip", "count.hip", "edge.hip", "runtime.cpp"]
+SOURCES = ["prims.hip", "build.hip", "count.hip", "edge.hip", "bbwc.hip", "runtime.cpp"]
 ARCH = os.environ.get("BBC_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -27,6 +27,7 @@
 #include "bbc_build.h"
 #include "bbc_count.h"
 #include "bbc_edge.h"
+#include "bbc_bbwc.h"
 
 using namespace bbc;
 
@@ -1422,6 +1423,55 @@ bbc_status bbc_count_through_edges(bbc_ctx *ctx, const bbc_graph *g, uint64_t n_
                 out[q0 + i] = (int64_t)hr[i];
             }
         }
+    });
+}
+
+bbc_status bbc_count_bbwc(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int64_t *out_count)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return guard(ctx, [&] {
+        if (!g || !out_count) fail(BBC_E_INVAL, "null argument");
+        const GraphDesc &d = g->set->desc[g->idx];
+        const int na = d.side == 0 ? p : q, nb = d.side == 0 ? q : p;
+        if (na != 3 || nb < 3 || nb > 7)
+            fail(BBC_E_UNSUPPORTED, "(p, q) = (%d, %d): the wedge-centric path takes 3 vertices on "
+                                    "the anchor side (%s) and 3..7 on the other",
+                 p, q, d.side ? "V" : "U");
+        (void)hipSetDevice(ctx->device);
+        Allocator *al = ctx->al.get();
+        hipStream_t s = ctx->stream;
+        const uint32_t lg = 19;
+        const uint32_t grid = std::max(1u, (uint32_t)ctx->num_cus / 2);
+        const uint64_t slots = (uint64_t)grid << lg;
+        DBuf keys, cnt, used, small;
+        keys.ensure(al, slots * 8);
+        cnt.ensure(al, slots * 16);
+        used.ensure(al, slots * 4);
+        small.ensure(al, 64);
+        BbwcArgs A;
+        A.g = g->set->view();
+        A.a0 = d.s_base;
+        A.a1 = d.s_base + d.n_s;
+        A.q = (uint32_t)nb;
+        A.lg = lg;
+        A.keys = keys.as<unsigned long long>();
+        A.cnt = cnt.as<uint32_t>();
+        A.used = used.as<uint32_t>();
+        A.total = small.as<unsigned long long>();
+        A.cursor = small.as<uint32_t>() + 2;
+        A.flags = small.as<uint32_t>() + 3;
+        HIP_OK(bbwc_count(A, grid, s));
+        uint32_t h[4];
+        HIP_OK(hipMemcpyAsync(h, small.p, 16, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        const uint32_t flags = h[3];
+        if (flags & 1u)
+            fail(BBC_E_UNSUPPORTED, "an anchor has more than %llu wedge pairs (the wedge-centric "
+                                    "path's table)", (unsigned long long)((1u << lg) - (1u << lg) / 4));
+        if (flags & 2u) fail(BBC_E_OVERFLOW, "the count does not fit 64 bits");
+        const unsigned long long v = (unsigned long long)h[0] | ((unsigned long long)h[1] << 32);
+        if (v > (unsigned long long)INT64_MAX) fail(BBC_E_OVERFLOW, "the count does not fit int64");
+        *out_count = (int64_t)v;
     });
 }
 
