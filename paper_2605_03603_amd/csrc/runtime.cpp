@@ -1036,7 +1036,7 @@ void count_set_batched(bbc_ctx *ctx, Work &w, GraphSet &set, hipStream_t s, int6
 // ---------------------------------------------------------------- serving
 constexpr int kServeStreams = 4;
 constexpr size_t kServeBatchMax = 4096;
-constexpr uint64_t kServeBatchEdges = 64ull << 20;   // bounds the time of one launch
+constexpr uint64_t kServeBatchEdges = 8ull << 20;    // bounds one batch (and the wait of its small requests)
 
 uint64_t footprint_estimate(uint64_t m, uint64_t nu, uint64_t nv)
 {
