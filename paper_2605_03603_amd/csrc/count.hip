@@ -414,7 +414,9 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
         __syncthreads();
         const uint32_t item = sh.item;
         if (item >= n_items) break;
-        const uint32_t r = list[item];
+        // the list from its end: the anchors deferred last (the later ranks of
+        // each slice of the previous tier) start first
+        const uint32_t r = list[n_items - 1 - item];
         const uint64_t s0 = g.s_off[r];
         const uint32_t d = (uint32_t)(g.s_off[r + 1] - s0);
         if (d < 3) continue;
