@@ -1937,10 +1937,15 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
 // group g: word 4 t + g), so that no chunk past the mask is issued and no
 // word past a row is read. n can reach 32 W, so the epilogue is 64-bit:
 // n (n - 1) (n - 2) = n ((n^2 + 2) - 3 n), which is 0 for n = 0, 1, 2 with
-// unsigned wrap-around.
+// unsigned wrap-around. MODE 3-5 take C(n, q) instead (the table, or the
+// exact 64-bit product above its end), and MODE 4-5 meet the row words with
+// the masks of the candidates chosen before the rows.
+template <int MODE>
 __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
-                                       const uint32_t *__restrict__ masks)
+                                       const uint32_t *__restrict__ masks, const uint64_t *cq,
+                                       const TriArgs &T, const uint32_t *xm, const uint32_t *ym)
 {
+    static_assert(MODE == 0 || MODE >= 3, "totals only");
     constexpr uint32_t KW = 16;              // words per K-block
     const uint32_t lane = __lane_id();
     const uint32_t g = lane >> 4, r16 = lane & 15u;
@@ -1975,6 +1980,16 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
             const u32x4a4 v = *reinterpret_cast<const u32x4a4 *>(M + (ro[sb] + wl));
             ra[sb][0] = v.x; ra[sb][1] = v.y; ra[sb][2] = v.z; ra[sb][3] = v.w;
         }
+        if constexpr (MODE >= 4) {
+            // the rows meet the masks of the candidates chosen before them
+            const u32x4a4 x = *reinterpret_cast<const u32x4a4 *>(xm + wl);
+            const u32x4a4 y = *reinterpret_cast<const u32x4a4 *>(ym + wl);
+            const uint32_t xy[4] = {x.x & y.x, x.y & y.y, x.z & y.z, x.w & y.w};
+#pragma unroll
+            for (int sb = 0; sb < 4; sb++)
+#pragma unroll
+                for (int t = 0; t < 4; t++) ra[sb][t] &= xy[t];
+        }
 #pragma unroll
         for (int tt = 0; tt < 4; tt++) {
             if ((uint32_t)tt >= nt) break;
@@ -1999,9 +2014,10 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
         const uint32_t wg = w + g;
         const bool kw = wg < W;
         const uint32_t wa = kw ? wg : W - 1;
+        const uint32_t xy = MODE >= 4 ? xm[wa] & ym[wa] : ~0u;
         v8i32 A[4];
 #pragma unroll
-        for (int sb = 0; sb < 4; sb++) A[sb] = spread_fp4(M[ro[sb] + wa], rv[sb] && kw);
+        for (int sb = 0; sb < 4; sb++) A[sb] = spread_fp4(M[ro[sb] + wa] & xy, rv[sb] && kw);
 #pragma unroll
         for (int tt = 0; tt < 4; tt++) {
             if ((uint32_t)tt >= nt) break;
@@ -2011,6 +2027,7 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
         }
     }
     uint64_t sum = 0;
+    bool ovf = false;
 #pragma unroll
     for (int tt = 0; tt < 4; tt++) {
         if ((uint32_t)tt >= nt) break;
@@ -2020,11 +2037,17 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const uint32_t n = j < rbase + 16 * sb + 4 * g + e ? (uint32_t)acc[tt][sb][e] : 0u;
-                const uint32_t t2 = n * n + 2u - 3u * n;   // (n - 1)(n - 2) mod 2^32, n < 2^16
-                sum += (uint64_t)n * t2;
+                if constexpr (MODE >= 3) {
+                    // C(n, q): the table up to kC3Max, computed above it
+                    sum += n <= kC3Max ? cq[n] : choose_q(n, T.q, ovf);
+                } else {
+                    const uint32_t t2 = n * n + 2u - 3u * n;   // (n - 1)(n - 2) mod 2^32, n < 2^16
+                    sum += (uint64_t)n * t2;
+                }
             }
     }
-    return sum / 6;
+    if (MODE >= 3 && ovf) atomicOr(&T.ws.ctr->over_cap, 16u);
+    return MODE >= 3 ? sum : sum / 6;
 }
 
 // Two kernels per mode: CLS 0 takes the units of class 0, CLS 1 those of
@@ -2127,7 +2150,8 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
         const bool wide = CLS != 0 && a.w32 > kRegW;
         if (wide) {
             if constexpr (CLS != 0) {
-                if (MODE == 0) acc = tri_rows_mfma_wide(un, a, T.ws.masks);
+                if constexpr (MODE == 0 || MODE >= 3)
+                    acc = tri_rows_mfma_wide<MODE>(un, a, T.ws.masks, cq, T, xm, ym);
                 else acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T, xm, ym);
             }
         } else {

@@ -503,6 +503,26 @@ def test_general_q_config2_full(ctx):
 
 
 # ------------------------------------------------- 4 vertices on the anchor side
+@pytest.mark.parametrize("n,n1,m,m1", [(12, 5, 544, 200), (10, 4, 633, 400), (9, 3, 1056, 700)])
+def test_general_pq_wide_masks(ctx, n, n1, m, m1):
+    """Masks of 17, 20 (ragged) and 33 words, anchored on U, for every count
+    mode: K_{n,m} with sign -1 on U2 x V2 holds pure(p) C(m, q) + (C(n, p) -
+    pure(p)) (C(m1, q) + C(m2, q)) balanced (p, q)-bicliques, pure(p) = C(n1, p)
+    + C(n2, p). The pure pairs meet in m > 512 common bits and the mixed ones
+    in m1 or m2."""
+    C = math.comb
+    n2, m2 = n - n1, m - m1
+    h = build(ctx, _complete_signed(n, m, n1, m1), 1 << 4)
+    qs = {3: (3, 4, 5, 7), 4: (3, 4, 5), 5: (3, 4)} if m < 1000 else {3: (3, 4, 5), 4: (3, 4), 5: (3,)}
+    for p, ql in qs.items():
+        for q in ql:
+            say("wide masks", n, m, p, q)
+            pure = C(n1, p) + C(n2, p)
+            want = pure * C(m, q) + (C(n, p) - pure) * (C(m1, q) + C(m2, q))
+            assert want < 1 << 64
+            assert ctx.count_global(h, p, q) == want, (n, m, p, q)
+
+
 def test_p4_closed_forms(ctx):
     """All-positive K_{n,m}: C(n,4) C(m,q) for (4, q) anchored on U and for
     (q, 4) anchored on V; the two-block sign pattern for (4, q)."""
