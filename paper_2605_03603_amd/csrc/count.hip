@@ -1939,13 +1939,15 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
 // n (n - 1) (n - 2) = n ((n^2 + 2) - 3 n), which is 0 for n = 0, 1, 2 with
 // unsigned wrap-around. MODE 3-5 take C(n, q) instead (the table, or the
 // exact 64-bit product above its end), and MODE 4-5 meet the row words with
-// the masks of the candidates chosen before the rows.
+// the masks of the candidates chosen before the rows. MODE 1 returns lane L's
+// row total (row 64 rb + L) and adds the column totals to colacc.
 template <int MODE>
 __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
                                        const uint32_t *__restrict__ masks, const uint64_t *cq,
-                                       const TriArgs &T, const uint32_t *xm, const uint32_t *ym)
+                                       uint64_t *colacc, const TriArgs &T, const uint32_t *xm,
+                                       const uint32_t *ym)
 {
-    static_assert(MODE == 0 || MODE >= 3, "totals only");
+    static_assert(MODE != 2, "no per-vertex counts of the other side");
     constexpr uint32_t KW = 16;              // words per K-block
     const uint32_t lane = __lane_id();
     const uint32_t g = lane >> 4, r16 = lane & 15u;
@@ -2025,6 +2027,51 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
 #pragma unroll
             for (int sb = 0; sb < 4; sb++) acc[tt][sb] = mfma_fp4(A[sb], B, acc[tt][sb]);
         }
+    }
+    if constexpr (MODE == 1) {
+        // C(n, 3) per pair (64-bit: n can pass 512), summed per column into
+        // the wave's column totals and per row into the lane's 16 rows
+        uint64_t rs[4][4];
+#pragma unroll
+        for (int sb = 0; sb < 4; sb++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) rs[sb][e] = 0;
+#pragma unroll
+        for (int tt = 0; tt < 4; tt++) {
+            if ((uint32_t)tt >= nt) break;
+            const uint32_t j = un.c0 + 16 * tt + r16;
+            uint64_t cs = 0;
+#pragma unroll
+            for (int sb = 0; sb < 4; sb++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const uint64_t n = j < rbase + 16 * sb + 4 * g + e ? (uint32_t)acc[tt][sb][e] : 0u;
+                    const uint64_t t = n >= 3 ? n * (n - 1) * (n - 2) / 6 : 0;
+                    rs[sb][e] += t;
+                    cs += t;
+                }
+            cs += __shfl_xor(cs, 16, kWave);
+            cs += __shfl_xor(cs, 32, kWave);
+            if (g == 0 && j < un.c1 && cs) colacc[j - un.c0] += cs;
+        }
+        // row totals over the 16 lanes of the group, then lane L takes row
+        // 64 rb + L: block L / 16, group (L / 4) % 4, element L % 4
+#pragma unroll
+        for (int sb = 0; sb < 4; sb++)
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) rs[sb][e] += __shfl_xor(rs[sb][e], o, kWave);
+        const uint32_t src = 16 * ((lane >> 2) & 3u), want = 4 * (lane >> 4) + (lane & 3u);
+        uint64_t mine = 0;
+#pragma unroll
+        for (int sb = 0; sb < 4; sb++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint64_t v = __shfl(rs[sb][e], src, kWave);
+                mine = (uint32_t)(4 * sb + e) == want ? v : mine;
+            }
+        return mine;
     }
     uint64_t sum = 0;
     bool ovf = false;
@@ -2150,8 +2197,8 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
         const bool wide = CLS != 0 && a.w32 > kRegW;
         if (wide) {
             if constexpr (CLS != 0) {
-                if constexpr (MODE == 0 || MODE >= 3)
-                    acc = tri_rows_mfma_wide<MODE>(un, a, T.ws.masks, cq, T, xm, ym);
+                if constexpr (MODE != 2)
+                    acc = tri_rows_mfma_wide<MODE>(un, a, T.ws.masks, cq, colacc, T, xm, ym);
                 else acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T, xm, ym);
             }
         } else {

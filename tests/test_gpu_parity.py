@@ -523,6 +523,33 @@ def test_general_pq_wide_masks(ctx, n, n1, m, m1):
             assert ctx.count_global(h, p, q) == want, (n, m, p, q)
 
 
+@pytest.mark.parametrize("n,n1,m,m1", [(12, 5, 544, 200), (10, 4, 633, 400), (9, 3, 1056, 700)])
+def test_per_vertex_wide_masks(ctx, n, n1, m, m1):
+    """Per-vertex counts on both sides with masks of 17, 20 and 33 words
+    (anchored on U), K_{n,m} with sign -1 on U2 x V2. A U vertex of block b
+    lies in C(n_b - 1, 2) pure triples (all of V one class) and C(n - 1, 2) -
+    C(n_b - 1, 2) mixed ones (classes V1, V2); a V vertex of block c lies in
+    C(m - 1, 2) of the R-sets of each pure triple and C(m_c - 1, 2) of each
+    mixed one."""
+    C = math.comb
+    n2, m2 = n - n1, m - m1
+    h = build(ctx, _complete_signed(n, m, n1, m1), 1 << 4)
+    pure_l = C3(n1) + C3(n2)
+    mixed_l = C3(n) - pure_l
+    total = pure_l * C3(m) + mixed_l * (C3(m1) + C3(m2))
+    say("per-vertex wide", n, m)
+    pu, tu = ctx.count_per_vertex(h, 0)
+    pv, tv = ctx.count_per_vertex(h, 1)
+    assert tu == total and tv == total
+    for u in range(n):
+        nb = n1 if u < n1 else n2
+        want = C(nb - 1, 2) * C3(m) + (C(n - 1, 2) - C(nb - 1, 2)) * (C3(m1) + C3(m2))
+        assert pu[u] == want, u
+    for v in range(m):
+        mc = m1 if v < m1 else m2
+        assert pv[v] == pure_l * C(m - 1, 2) + mixed_l * C(mc - 1, 2), v
+
+
 def test_p4_closed_forms(ctx):
     """All-positive K_{n,m}: C(n,4) C(m,q) for (4, q) anchored on U and for
     (q, 4) anchored on V; the two-block sign pattern for (4, q)."""
