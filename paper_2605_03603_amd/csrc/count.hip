@@ -832,7 +832,7 @@ __global__ void __launch_bounds__(kGThreads) k_pair_global(PairArgs P)
 // workgroup tiers; anchors of higher degree, or with more partners than the
 // table holds, are listed for tier A.
 constexpr uint32_t kWvMaxD = 32;
-constexpr int kWvUnroll = 8;              // loads in flight per lane, non-top positions
+constexpr int kWvUnroll = 2;              // loads in flight per lane, non-top positions
 constexpr int kWvTopUnroll = 16;          // and along the two longest suffixes
 constexpr uint64_t kWvMaskChunk = 4096;   // mask words reserved per workgroup at a time
 constexpr uint64_t kWvCandChunk = 4096;
