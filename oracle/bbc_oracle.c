@@ -628,7 +628,8 @@ typedef struct {
     const graph_t *g;
     int64_t next;            /* shared anchor cursor (dynamic chunks) */
     pthread_mutex_t lock;
-    int64_t stride;          /* process anchors whose index is a multiple of stride */
+    int64_t stride;          /* process anchors whose index is residue modulo stride */
+    int64_t residue;
     int want_per_vertex;
     int p, q;
     tally_t tally;
@@ -653,7 +654,7 @@ static void *worker(void *arg)
         if (begin >= g->n_s) break;
         int64_t end = begin + chunk < g->n_s ? begin + chunk : g->n_s;
         for (int64_t u = begin; u < end; u++) {
-            if (u % jb->stride != 0) continue;
+            if (u % jb->stride != jb->residue) continue;
             if (jb->p == 4) bbvp_anchor_p4(g, (uint32_t)u, &w, &t, jb->q);
             else if (jb->p > 4 || jb->p < 0) bbvp_anchor_dense(g, (uint32_t)u, &w, &t, jb->p < 0 ? -jb->p : jb->p, jb->q);
             else bbvp_anchor(g, (uint32_t)u, 1, &w, &t, per, NULL, jb->q);
@@ -679,25 +680,30 @@ static void *worker(void *arg)
  *   n_threads: worker threads over anchors (dynamic chunks of 64).
  *   anchor_stride: 1 for the whole count; k > 1 keeps only anchors whose id is
  *         a multiple of k (a bounded sample for timing).
+ *   (orc_count_bbvp_shard takes a residue r as well and keeps the anchors
+ *   whose id is r modulo k: the k shards r = 0..k-1 partition the anchors, so
+ *   their totals, statistics and per-vertex arrays add up to the whole count.)
  *   out_total: the count as a 128-bit integer, little-endian words lo, hi.
  *   out_stats: [feasible triples (|T| >= 3), candidate pairs of C, side used].
  *   per_vertex: optional int64 per vertex of the side used.
  * Returns 0, -1 on a bad edge list or q, -2 if a per-vertex value exceeds int64. */
-int orc_count_bbvp_q(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
-                     const uint32_t *ev, const int8_t *sign, int side, int n_threads,
-                     int64_t anchor_stride, int q, uint64_t *out_total, uint64_t *out_stats,
-                     int64_t *per_vertex)
+static int count_bbvp_part(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
+                           const uint32_t *ev, const int8_t *sign, int side, int n_threads,
+                           int64_t anchor_stride, int64_t residue, int q, uint64_t *out_total,
+                           uint64_t *out_stats, int64_t *per_vertex)
 {
     if (q < 3 || q > 7) return -1;
+    if (anchor_stride < 1) anchor_stride = 1;
+    if (residue < 0 || residue >= anchor_stride) return -1;
     if (side < 0) side = (n_v < n_u) ? 1 : 0;
     graph_t g;
     if (build_graph(&g, n_u, n_v, m, eu, ev, sign, side) != 0) { free_graph(&g); return -1; }
     if (n_threads < 1) n_threads = 1;
-    if (anchor_stride < 1) anchor_stride = 1;
     job_t jb;
     memset(&jb, 0, sizeof(jb));
     jb.g = &g;
     jb.stride = anchor_stride;
+    jb.residue = residue;
     jb.want_per_vertex = per_vertex != NULL;
     jb.p = 3;
     jb.q = q;
@@ -763,6 +769,24 @@ int orc_count_bbvp_pk(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
     }
     free_graph(&g);
     return 0;
+}
+
+int orc_count_bbvp_q(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
+                     const uint32_t *ev, const int8_t *sign, int side, int n_threads,
+                     int64_t anchor_stride, int q, uint64_t *out_total, uint64_t *out_stats,
+                     int64_t *per_vertex)
+{
+    return count_bbvp_part(n_u, n_v, m, eu, ev, sign, side, n_threads, anchor_stride, 0, q,
+                           out_total, out_stats, per_vertex);
+}
+
+int orc_count_bbvp_shard(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
+                         const uint32_t *ev, const int8_t *sign, int side, int n_threads,
+                         int64_t n_shards, int64_t shard, uint64_t *out_total,
+                         uint64_t *out_stats, int64_t *per_vertex)
+{
+    return count_bbvp_part(n_u, n_v, m, eu, ev, sign, side, n_threads, n_shards, shard, 3,
+                           out_total, out_stats, per_vertex);
 }
 
 int orc_count_bbvp(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu, const uint32_t *ev,

@@ -18,6 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bbc_oracle.c")
 _LIB = os.path.join(_HERE, "libbbc_oracle.so")
+_LIB_NATIVE = os.path.join(_HERE, "libbbc_oracle_native.so")
 _lib = None
 
 _u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -26,13 +27,18 @@ _u64p = ctypes.POINTER(ctypes.c_uint64)
 _i64p = ctypes.POINTER(ctypes.c_int64)
 
 
-def build(force: bool = False, out: Optional[str] = None, mutant: int = 0) -> str:
-    """Compile the oracle with gcc (plain -O2, no target-specific tuning).
-    `mutant` > 0 builds a variant with a planted mistake (mutation test)."""
-    target = out or _LIB
+def build(force: bool = False, out: Optional[str] = None, mutant: int = 0,
+          native: bool = False) -> str:
+    """Compile the oracle with gcc: plain -O2 for the tests (the library then
+    runs on any x86-64 host), or -O3 -march=native (native=True, into
+    libbbc_oracle_native.so unless `out` is given) for timing it on the host
+    that runs it. Same source, same arithmetic. `mutant` > 0 builds a variant
+    with a planted mistake (mutation test)."""
+    target = out or (_LIB_NATIVE if native else _LIB)
     if force or out or not os.path.exists(target) or os.path.getmtime(target) < os.path.getmtime(_SRC):
         tmp = target + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-shared", "-fPIC", "-pthread",
+        opt = ["-O3", "-march=native"] if native else ["-O2"]
+        subprocess.check_call(["gcc", *opt, "-std=gnu11", "-shared", "-fPIC", "-pthread",
                                f"-DORC_MUTANT={int(mutant)}", "-o", tmp, _SRC])
         os.replace(tmp, target)
     return target
@@ -67,6 +73,10 @@ def _bind(L):
                                  _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _u64p, _u64p,
                                  _i64p]
     L.orc_count_bbvp.restype = ctypes.c_int
+    L.orc_count_bbvp_shard.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _u32p,
+                                       _u32p, _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                       ctypes.c_int64, _u64p, _u64p, _i64p]
+    L.orc_count_bbvp_shard.restype = ctypes.c_int
     L.orc_count_bbvp_q.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _u32p, _u32p,
                                    _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                    _u64p, _u64p, _i64p]
@@ -150,6 +160,34 @@ def count_bbvp(g, side: int = 0, threads: int = 1, anchor_stride: int = 1,
     if per_vertex:
         if rc == -2:
             raise OverflowError("per-vertex count exceeds int64")
+        res["per_vertex"] = pv[:n_side].copy()
+    return res
+
+
+def count_bbvp_shard(g, side: int, n_shards: int, shard: int, threads: int = 1,
+                     per_vertex: bool = False) -> dict:
+    """Algorithm 2 for p = q = 3 over the anchors whose id is `shard` modulo
+    `n_shards` (side 0: U, 1: V). The shards partition the anchors, so their
+    totals, feasible and candidate counts and per-vertex arrays sum to those
+    of count_bbvp over the whole side.
+
+    Returns dict(total, feasible, candidates, side[, per_vertex])."""
+    eu, ev, sg = _arrs(g)
+    out = np.zeros(2, np.uint64)
+    st = np.zeros(3, np.uint64)
+    n_side = g.n_v if side == 1 else g.n_u
+    pv = np.zeros(max(n_side, 1), np.int64) if per_vertex else None
+    rc = lib().orc_count_bbvp_shard(g.n_u, g.n_v, eu.size, _p(eu, _u32p), _p(ev, _u32p),
+                                    _p(sg, _i8p), side, threads, n_shards, shard,
+                                    _p(out, _u64p), _p(st, _u64p),
+                                    _p(pv, _i64p) if pv is not None else None)
+    if rc == -2:
+        raise OverflowError("per-vertex count exceeds int64")
+    if rc != 0:
+        raise ValueError(f"orc_count_bbvp_shard failed ({rc})")
+    total = int(out[0]) | (int(out[1]) << 64)
+    res = {"total": total, "feasible": int(st[0]), "candidates": int(st[1]), "side": int(st[2])}
+    if per_vertex:
         res["per_vertex"] = pv[:n_side].copy()
     return res
 

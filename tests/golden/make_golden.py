@@ -2,7 +2,12 @@
 
 Calls only the CPU oracle (oracle/) on the seeded generators; nothing here
 touches the HIP library. Run from the repository root:
-    python tests/golden/make_golden.py [cfg2] [cfg3] [cfg2q]
+    python tests/golden/make_golden.py [cfg2] [cfg3] [cfg2q] [cfg3full] [cfg3hubs] [cfg4]
+
+cfg3full runs Algorithm 2 over config 3 in anchor shards (anchor id modulo
+CFG3_SHARDS) and keeps each finished shard under GOLDEN_CACHE (default
+tests/golden/.cache, not versioned), so an interrupted run resumes; the shards
+partition the anchors, so their sums are the whole count.
 """
 import hashlib
 import json
@@ -20,6 +25,8 @@ from paper_2605_03603_amd import generators as G  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 THREADS = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+CACHE = os.environ.get("GOLDEN_CACHE", os.path.join(HERE, ".cache"))
+CFG3_SHARDS = 16
 
 
 def digest(a: np.ndarray) -> str:
@@ -106,8 +113,120 @@ def cfg2q():
     print("cfg2q", counts, out["oracle_seconds"])
 
 
+def _cfg3_graph():
+    """Config 3 seed 1, cached as arrays (the generator takes about 30 s)."""
+    os.makedirs(CACHE, exist_ok=True)
+    path = os.path.join(CACHE, "cfg3_seed1_graph.npz")
+    if not os.path.exists(path):
+        g = G.config3(1)
+        np.savez(path, n=np.array([g.n_u, g.n_v]), eu=g.eu, ev=g.ev, sign=g.sign)
+    d = np.load(path)
+    n_u, n_v = (int(x) for x in d["n"])
+    return G.SignedBipartite(n_u, n_v, d["eu"], d["ev"], d["sign"])
+
+
+def cfg3full():
+    """Config 3 seed 1 anchored on U: total, feasible triplets, candidate
+    pairs and the per-U-vertex counts (sha256 of the whole array and the values
+    of the highest-degree vertices), from Algorithm 2 run shard by shard."""
+    g = _cfg3_graph()
+    t_all = 0.0
+    total, feas, cand = 0, 0, 0
+    per = np.zeros(g.n_u, np.int64)
+    for r in range(CFG3_SHARDS):
+        path = os.path.join(CACHE, f"cfg3_seed1_u_shard{r}of{CFG3_SHARDS}.npz")
+        if not os.path.exists(path):
+            t = time.time()
+            res = O.count_bbvp_shard(g, 0, CFG3_SHARDS, r, threads=THREADS, per_vertex=True)
+            dt = time.time() - t
+            np.savez(path + ".tmp.npz", per=res["per_vertex"],
+                     meta=np.array([str(res["total"]), str(res["feasible"]),
+                                    str(res["candidates"]), repr(dt)]))
+            os.replace(path + ".tmp.npz", path)
+            print(f"cfg3 shard {r}: {res['total']} in {dt:.0f} s", flush=True)
+        d = np.load(path)
+        m = [str(x) for x in d["meta"]]
+        total += int(m[0]); feas += int(m[1]); cand += int(m[2]); t_all += float(m[3])
+        per += d["per"]
+    assert int(per.sum(dtype=object)) == 3 * total
+    du = degree(g.n_u, g.eu)
+    hubs = [int(x) for x in np.argsort(-du, kind="stable")[:16]]
+    rng = np.random.default_rng(31)
+    busy = np.flatnonzero(per > 0)
+    sample = sorted(int(x) for x in rng.choice(busy, size=min(64, busy.size), replace=False))
+    out = {
+        "workload": "config3 seed 1: Chung-Lu 2M x 500k, 40M edges, gamma 1.9/2.3, hidden-label signs "
+                    "with 10% flips",
+        "source": "oracle/ Algorithm 2 (p=q=3) anchored on U, run in anchor shards "
+                  "(tests/golden/make_golden.py cfg3full)",
+        "n_u": g.n_u, "n_v": g.n_v, "m": g.m,
+        "total": total, "feasible_triplets_u": feas, "candidate_pairs_u": cand,
+        "per_u_sha256": digest(per),
+        "per_u_hubs": {str(x): int(per[x]) for x in hubs},
+        "hub_degrees": {str(x): int(du[x]) for x in hubs},
+        "per_u_sample": {str(x): int(per[x]) for x in sample},
+        "oracle_seconds": round(t_all, 1), "oracle_threads": THREADS, "shards": CFG3_SHARDS,
+    }
+    with open(os.path.join(HERE, "cfg3_seed1_full.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("cfg3full", total, feas, round(t_all, 1))
+
+
+def cfg3hubs():
+    """Per-vertex counts of the highest-degree V vertices of config 3 seed 1
+    (every balanced biclique through the vertex, no priority filter)."""
+    g = _cfg3_graph()
+    dv = degree(g.n_v, g.ev)
+    n = int(os.environ.get("CFG3_V_HUBS", "8"))
+    hubs = [int(x) for x in np.argsort(-dv, kind="stable")[:n]]
+    path = os.path.join(HERE, "cfg3_seed1_v_hubs.json")
+    done = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            done = json.load(f)["per_v_hubs"]
+    for x in hubs:
+        if str(x) in done:
+            continue
+        t = time.time()
+        done[str(x)] = O.vertex_counts(g, 1, [x])[0]
+        print(f"cfg3 V hub {x} (degree {int(dv[x])}): {done[str(x)]} in {time.time() - t:.0f} s",
+              flush=True)
+        out = {
+            "workload": "config3 seed 1 (as cfg3_seed1_full.json)",
+            "source": "oracle/ per-vertex counts of the highest-degree V vertices "
+                      "(tests/golden/make_golden.py cfg3hubs)",
+            "per_v_hubs": done,
+            "hub_degrees": {k: int(dv[int(k)]) for k in done},
+        }
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+
+
+def cfg4():
+    """All 8192 graphs of config 4 seed 1: Algorithm 2 count of each graph
+    (anchored on U), their sum and the sha256 of the int64 array."""
+    gs = G.config4(1)
+    t = time.time()
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(THREADS) as ex:
+        totals = list(ex.map(lambda g: O.count_bbvp(g, 0, threads=1)["total"], gs))
+    counts = np.array(totals, dtype=np.int64)
+    out = {
+        "workload": "config4 seed 1: 8192 ER graphs, |U|+|V| log-uniform on [50, 20000], mean "
+                    "degree U(8, 40), 75% positive, 0-5 planted balanced 5x5 blocks",
+        "source": "oracle/ Algorithm 2 (p=q=3) per graph, anchored on U (tests/golden/make_golden.py cfg4)",
+        "n_graphs": len(gs), "edges": int(sum(g.m for g in gs)),
+        "sum": int(counts.sum()), "sha256": digest(counts),
+        "counts": [int(c) for c in counts],
+        "oracle_seconds": round(time.time() - t, 1),
+    }
+    with open(os.path.join(HERE, "cfg4_seed1.json"), "w") as f:
+        json.dump(out, f)
+    print("cfg4", out["sum"], out["oracle_seconds"])
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["cfg2", "cfg3", "cfg2q"]
-    O.build()
+    O.use_library(O.build(native=True))
     for w in which:
         globals()[w]()

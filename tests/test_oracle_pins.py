@@ -256,6 +256,28 @@ def test_config3_switching_reduction(oracle):
     assert oracle.count_bbvp(g, 0, threads=4)["total"] == oracle.count_bbvp(unsw, 0, threads=4)["total"]
 
 
+def test_anchor_shards_partition_the_count(oracle):
+    """Algorithm 2 sums per-anchor contributions, so running it over the
+    anchors of each residue class (id modulo k) and adding the parts gives the
+    whole count, feasible and candidate tallies and per-vertex arrays: the
+    basis of the sharded runs that store the large-graph golden values."""
+    for g in (G.config1(2), G.config2(1, scale=0.02)):
+        for side in (0, 1):
+            whole = oracle.count_bbvp(g, side, threads=4, per_vertex=True)
+            for k in (1, 3, 7):
+                parts = [oracle.count_bbvp_shard(g, side, k, r, threads=4, per_vertex=True)
+                         for r in range(k)]
+                for key in ("total", "feasible", "candidates"):
+                    assert sum(p[key] for p in parts) == whole[key]
+                assert (sum(p["per_vertex"] for p in parts) == whole["per_vertex"]).all()
+            # each shard keeps only its own anchors: a shard with no anchors is empty
+            n = g.n_u if side == 0 else g.n_v
+            empty = oracle.count_bbvp_shard(g, side, n + 5, n + 4, threads=2, per_vertex=True)
+            assert empty["total"] == 0 and empty["candidates"] == 0
+    with pytest.raises(ValueError):
+        oracle.count_bbvp_shard(G.config1(1), 0, 4, 4)
+
+
 def test_bad_edges_rejected(oracle):
     g = G.from_rows(["++", "+-"])
     dup = G._finish(2, 2, np.array([0, 0]), np.array([1, 1]), np.array([1, 1], np.int8))
