@@ -211,10 +211,27 @@ typedef struct {
     uint32_t deferred_d;        /* anchors handed to the full-size global-memory tier */
     uint32_t deferred_a;        /* anchors handed from the per-wave tier to the workgroup tiers
                                    (degree above 32, or more partners than a wave's table) */
+    uint32_t deferred_r;        /* anchors handed to the rank-window tier (heavy anchors whose
+                                   partners all rank within 2^17 above them) */
 } bbc_count_stats;
 bbc_status bbc_get_last_stats(bbc_ctx *ctx, bbc_count_stats *out);
 /* Enable (1) or disable (0) per-phase event timing on this context. */
 bbc_status bbc_set_timing(bbc_ctx *ctx, int enable);
+
+/* Test hooks: conditions forced from the host so that tests can reach paths
+ * real inputs reach only at sizes too large to test, without changing any
+ * kernel. They apply to every later count of the context (serving workers
+ * included) until reset with value 0.
+ *   BBC_HOOK_NO_WINDOW_TIER: value != 0 keeps heavy anchors in the hash-table
+ *     tiers of the pair kernels (the rank-window tier is skipped), so both
+ *     routes can be compared on the same graph. Counts are unchanged.
+ *   BBC_HOOK_PRELOAD_COUNT: every graph's 64-bit accumulator starts at
+ *     (uint64_t)value instead of 0, so a count whose true value plus the
+ *     preload passes 2^63 - 1 returns BBC_E_OVERFLOW (the carry path).
+ * Errors: BBC_E_INVAL (null context or unknown hook). */
+#define BBC_HOOK_NO_WINDOW_TIER 1
+#define BBC_HOOK_PRELOAD_COUNT  2
+bbc_status bbc_set_test_hook(bbc_ctx *ctx, int hook, int64_t value);
 
 const char *bbc_status_string(bbc_status s);
 /* Detail of the last error on this context (empty string if none). */

@@ -37,7 +37,11 @@ EXPORTED = ["bbc_ctx_create", "bbc_ctx_destroy", "bbc_build_csr", "bbc_build_csr
             "bbc_graph_free", "bbc_get_graph_info", "bbc_count_global", "bbc_count_per_vertex",
             "bbc_count_through_edges", "bbc_top_vertices", "bbc_count_bbwc",
             "bbc_count_batch", "bbc_submit", "bbc_submit_coo", "bbc_poll", "bbc_wait",
-            "bbc_get_last_stats", "bbc_set_timing", "bbc_status_string", "bbc_last_error"]
+            "bbc_get_last_stats", "bbc_set_timing", "bbc_set_test_hook", "bbc_status_string",
+            "bbc_last_error"]
+
+BBC_HOOK_NO_WINDOW_TIER = 1
+BBC_HOOK_PRELOAD_COUNT = 2
 
 
 class BBCError(RuntimeError):
@@ -60,7 +64,8 @@ class CountStats(ctypes.Structure):
                 ("ms_pair", ctypes.c_float), ("ms_plan", ctypes.c_float),
                 ("ms_triplet", ctypes.c_float), ("attempts", ctypes.c_uint32),
                 ("deferred_b", ctypes.c_uint32), ("deferred_c", ctypes.c_uint32),
-                ("deferred_d", ctypes.c_uint32), ("deferred_a", ctypes.c_uint32)]
+                ("deferred_d", ctypes.c_uint32), ("deferred_a", ctypes.c_uint32),
+                ("deferred_r", ctypes.c_uint32)]
 
 
 _vp = ctypes.c_void_p
@@ -70,6 +75,13 @@ _i32 = ctypes.c_int
 
 
 def _load(path: str = LIB_PATH) -> ctypes.CDLL:
+    # torch ships its own HIP runtime under the same soname as the system one
+    # libbbc.so links: whichever is loaded first serves the whole process, and
+    # torch needs its own, so it is loaded before the library when present
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise ImportError(f"libbbc.so not found at {path}; build it with "
                           "`python -m paper_2605_03603_amd.build` (there is no CPU fallback)")
@@ -98,6 +110,7 @@ def _load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.bbc_wait.argtypes = [_vp, _u64, ctypes.POINTER(ctypes.c_int64)]
     L.bbc_get_last_stats.argtypes = [_vp, ctypes.POINTER(CountStats)]
     L.bbc_set_timing.argtypes = [_vp, _i32]
+    L.bbc_set_test_hook.argtypes = [_vp, _i32, ctypes.c_int64]
     for name in EXPORTED:
         fn = getattr(L, name)
         if name not in ("bbc_status_string", "bbc_last_error", "bbc_ctx_destroy"):
@@ -271,6 +284,10 @@ class Context:
 
     def set_timing(self, enable: bool = True):
         self._check(lib.bbc_set_timing(self.handle, 1 if enable else 0))
+
+    def set_test_hook(self, hook: int, value: int):
+        """Host-forced test conditions (BBC_HOOK_*); value 0 resets."""
+        self._check(lib.bbc_set_test_hook(self.handle, hook, int(value)))
 
     # -- serving
     def submit(self, g: Graph) -> int:

@@ -10,14 +10,18 @@ struct PairArgs {
     Workspace ws;
     uint32_t a0, a1;        // anchor range (global ranks) scanned by the per-wave tier
     int tier;               // 0: per-wave LDS tables; 1, 2: per-workgroup LDS tables;
-                            // 3: bounded global tables; 4: full-size global tables
+                            // 3: bounded global tables; 4: full-size global tables;
+                            // 5: rank-window LDS tables
     uint32_t chunk_base;    // triplet unit width in columns for 1-word masks (<= 2048)
     uint32_t gH;            // tier-2 table slots (power of two)
     int glog2h;
     uint32_t dH;            // tier-3 table slots
     int dlog2h;
     uint32_t gmaxd, gkmax;  // degree and candidate limits of tiers 2, 3 and 4
+    uint32_t flags;         // kPairNoWindow: heavy anchors stay in the hash tiers
 };
+
+constexpr uint32_t kPairNoWindow = 1u;
 
 struct TriArgs {
     CsrView g;

@@ -99,12 +99,13 @@ struct Counters {           // device-side cursors and flags, zeroed per count
     uint32_t n_anchor;      // anchor records reserved (including unused slots)
     uint32_t over_cap;      // 1, 2: a workspace capacity was exceeded; 4: unsupported anchor;
                             // 8: lookup failure; 16: C(n, q) overflow; 32: more than 2^32 - 1 units
-    uint32_t n_list[4];     // anchors handed to the workgroup tiers A, B, C, D
+    uint32_t n_list[5];     // anchors handed to the workgroup tiers A, B, C, D and to the
+                            // rank-window tier
     uint32_t n_units;       // written by the plan kernel: all units
     uint32_t n_cls_end[2];  // units of class 0 (masks <= 4 words) come first, then
                             // class 1 (up to 16 words), then class 2 (wider)
     unsigned long long need_masks, need_cands, need_recs, need_units;   // exact demand
-    Cursor q_pair[5][kXcd]; // work-queue cursors of the pair tiers, one per XCD slice
+    Cursor q_pair[6][kXcd]; // work-queue cursors of the pair tiers, one per XCD slice
     Cursor q_tri[2][kXcd];  // queues of the two triplet kernels
 };
 
@@ -114,10 +115,11 @@ struct Workspace {
     Unit *units;         uint64_t cap_units;
     uint32_t *masks;     uint64_t cap_mask_words;
     uint32_t *cands;     uint64_t cap_cands;
-    uint32_t *defer[4];  uint64_t cap_defer;     // anchors for tiers A, B, C, D
+    uint32_t *defer[5];  uint64_t cap_defer;     // anchors for tiers A, B, C, D, rank window
     uint32_t *gtab;      uint64_t gtab_words_per_block; uint32_t gtab_blocks;  // tier C tables
     uint32_t *dtab;      uint64_t dtab_words_per_block; uint32_t dtab_blocks;  // tier D tables
-    uint32_t *bscr;      uint64_t bscr_words_per_block;   // tier B per-block position lists
+    uint32_t *bscr;      uint64_t bscr_words_per_block;   // per-block position lists of tier B
+                                                           // and of the rank-window tier
     uint32_t *ucnt;      // [3 cap_anchors] units per anchor record, one slice per unit class
     uint64_t *uoff;      // [3 cap_anchors + 1] exclusive prefix of ucnt
     unsigned long long *count;   // [G] totals

@@ -79,6 +79,14 @@ constexpr uint32_t kMaskChunk = 1u << 16;   // mask words reserved per workgroup
 constexpr uint32_t kCandChunk = 1u << 13;
 constexpr uint32_t kRecChunk = 16;
 constexpr int kUnroll = 4;              // independent neighbour-list loads per lane
+// rank-window tier (k_pair_window): its threads, widest partner window (bytes
+// of its table), LDS words, and the wedge count from which tiers A and B hand
+// an anchor to it without counting it themselves
+constexpr int kRThreads = 1024;
+constexpr uint32_t kRWin = 1u << 17;
+constexpr uint32_t kRWords = 38912;
+constexpr uint32_t kRMinWedges = 32768;
+constexpr int kListR = 4;               // index of its anchor list (defer[], n_list[])
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t x, int log2h)
 {
@@ -116,6 +124,14 @@ __host__ __device__ __forceinline__ uint32_t unit_cols(uint32_t w32, uint32_t ba
     uint32_t c = base / w32;
     c = c < 32 ? 32 : c;
     return (c + 15) & ~15u;   // whole 16-column matrix-core tiles
+}
+
+// Whether every partner of anchor r (ranked in (r, end of r's graph)) lies in
+// a window the rank-window tier can index.
+__device__ __forceinline__ bool window_fits(const CsrView &g, uint32_t r)
+{
+    const GraphDesc &gd = g.desc[g.s_graph[r]];
+    return gd.s_base + gd.n_s - r - 1 <= kRWin;
 }
 
 __device__ __forceinline__ uint32_t slice_lo(uint32_t n, uint32_t s)
@@ -390,10 +406,14 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
         sh.vm = sh.vm_end = sh.vc = sh.vc_end = 0;
     }
 
+    // tier B hands anchors whose partner window fits to the rank-window tier,
+    // the others to tier C
     auto defer_anchor = [&](uint32_t r) {
         if (next_list) {
-            uint32_t t = atomicAdd(&C->n_list[P.tier], 1u);
-            if (t < P.ws.cap_defer) next_list[t] = r; else atomicOr(&C->over_cap, 1u);
+            const int li = (P.tier == 2 && !(P.flags & kPairNoWindow) && window_fits(g, r)) ? kListR
+                                                                                          : P.tier;
+            uint32_t t = atomicAdd(&C->n_list[li], 1u);
+            if (t < P.ws.cap_defer) P.ws.defer[li][t] = r; else atomicOr(&C->over_cap, 1u);
         } else {
             atomicOr(&C->over_cap, 4u);
         }
@@ -448,6 +468,15 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
         }
         __syncthreads();
         if (sh.wedges < 6) continue;   // fewer than 2 classes of 3 are impossible
+        if (P.tier <= 2 && !(P.flags & kPairNoWindow) && sh.wedges >= kRMinWedges &&
+            window_fits(g, r)) {
+            // heavy anchor near the top of the order: the rank-window tier
+            if (tid == 0) {
+                uint32_t t = atomicAdd(&C->n_list[kListR], 1u);
+                if (t < P.ws.cap_defer) P.ws.defer[kListR][t] = r; else atomicOr(&C->over_cap, 1u);
+            }
+            continue;
+        }
         const uint32_t t1 = sh.top1 ? (uint32_t)sh.top1 : kEmpty;
         {
             uint64_t wtop = 0;
@@ -816,6 +845,335 @@ __global__ void __launch_bounds__(kGThreads) k_pair_global(PairArgs P)
     m.vc = m.pln + P.gmaxd;
     m.kmax = P.gkmax;
     pair_loop<kGThreads, PACKED>(P, m, sh);
+}
+
+// --------------------------------------------------- rank-window tier (R)
+// Every partner of anchor r is ranked in (r, end of r's graph), so for an
+// anchor near the top of the priority order the partner keys form a short
+// window. Such anchors are the heavy ones (high degree, long suffix lists,
+// often thousands of candidate classes): their counting table is indexed by
+// rank - r - 1 directly, one byte per partner holding a 3-bit thermometer per
+// sign class, with no keys, no probing and no overflow. The classes with >= 3
+// hits become the virtual candidates, numbered by a rank structure (one bitmap
+// per class and per-word prefix counts) built in place of the table, so the
+// mask pass finds a wedge's candidate with two LDS reads and a popcount.
+
+// One hit on a 3-bit thermometer whose lowest bit is b0 (bits b0, 2 b0, 4 b0
+// set by the first, second and third hit; later hits change nothing). A hit
+// that finds a bit taken by a concurrent one moves on to the next bit.
+__device__ __forceinline__ void win_hit(uint32_t *w, uint32_t b0)
+{
+    const uint32_t b1 = b0 << 1, b2 = b0 << 2;
+    const uint32_t o = atomicOr(w, b0);
+    if (!(o & b0) || (o & b2)) return;
+    if (!(o & b1)) {
+        const uint32_t o2 = atomicOr(w, b1);
+        if (!(o2 & b1) || (o2 & b2)) return;
+    }
+    atomicOr(w, b2);
+}
+
+// Exclusive prefix over the workgroup's threads (thread order) of two values;
+// also returns both totals. Contains barriers: every thread must call it.
+template <int THREADS>
+__device__ __forceinline__ void block_excl_scan2(uint32_t &a, uint32_t &b, uint32_t *tmp,
+                                                 uint32_t &tot_a, uint32_t &tot_b)
+{
+    constexpr int NW = THREADS / kWave;
+    const int lane = __lane_id(), wv = threadIdx.x / kWave;
+    const uint32_t ia = wave_incl_scan(a), ib = wave_incl_scan(b);
+    if (lane == kWave - 1) { tmp[wv] = ia; tmp[NW + wv] = ib; }
+    __syncthreads();
+    uint32_t pa = 0, pb = 0;
+    tot_a = 0; tot_b = 0;
+    for (int i = 0; i < NW; i++) {
+        const uint32_t ta = tmp[i], tb = tmp[NW + i];
+        if (i < wv) { pa += ta; pb += tb; }
+        tot_a += ta; tot_b += tb;
+    }
+    a = pa + ia - a;
+    b = pb + ib - b;
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kRThreads) k_pair_window(PairArgs P)
+{
+    __shared__ __align__(16) uint32_t lds[kRWords];
+    __shared__ PairShared sh;
+    __shared__ uint32_t scan_tmp[2 * (kRThreads / kWave)];
+    __shared__ uint32_t s_k0, s_k1;
+    constexpr int THREADS = kRThreads;
+    constexpr uint32_t kPerThread = kRWin / 32 / THREADS;   // bitmap words per thread and class
+    const int tid = threadIdx.x, lane = __lane_id();
+    const CsrView &g = P.g;
+    Counters *C = P.ws.ctr;
+    uint64_t my_wedges = 0;
+    const uint32_t n_items =
+        (uint32_t)min((uint64_t)__atomic_load_n(&C->n_list[P.tier - 1], __ATOMIC_RELAXED),
+                      P.ws.cap_defer);
+    if (n_items == 0) return;
+    const uint32_t *list = P.ws.defer[P.tier - 1];
+    PairMem m{};
+    m.pst = P.ws.bscr + (uint64_t)blockIdx.x * P.ws.bscr_words_per_block;
+    m.pln = m.pst + P.gmaxd;
+    m.maxd = P.gmaxd;
+    if (tid == 0) {
+        sh.qlo = sh.qhi = 0; sh.qslice = blockIdx.x % kXcd; sh.qtried = 0;
+        sh.moff = sh.mres_end = 0; sh.coff = sh.cres_end = 0;
+        sh.aidx = sh.arec_end = 0;
+        sh.need_m = sh.need_c = sh.need_r = sh.need_u = 0;
+        sh.vm = sh.vm_end = sh.vc = sh.vc_end = 0;
+    }
+    // anchors this tier cannot take go to the bounded global-memory tier
+    auto to_global = [&](uint32_t r) {
+        const uint32_t t = atomicAdd(&C->n_list[2], 1u);
+        if (t < P.ws.cap_defer) P.ws.defer[2][t] = r; else atomicOr(&C->over_cap, 1u);
+    };
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            if (sh.qlo >= sh.qhi) {
+                uint32_t lo = 0, hi = 0, s = sh.qslice, tr = sh.qtried;
+                if (!queue_take(C->q_pair[P.tier], n_items, 1, &s, &tr, &lo, &hi)) lo = hi = n_items;
+                sh.qslice = s; sh.qtried = tr; sh.qlo = lo; sh.qhi = hi;
+            }
+            sh.item = sh.qlo < sh.qhi ? sh.qlo++ : n_items;
+            sh.wedges = 0;
+        }
+        __syncthreads();
+        const uint32_t item = sh.item;
+        if (item >= n_items) break;
+        const uint32_t r = list[n_items - 1 - item];
+        const uint64_t s0 = g.s_off[r];
+        const uint32_t d = (uint32_t)(g.s_off[r + 1] - s0);
+        if (d < 3) continue;
+        const GraphDesc &gd = g.desc[g.s_graph[r]];
+        const uint32_t win = gd.s_base + gd.n_s - r - 1;
+        if (d > m.maxd || win > kRWin) {
+            if (tid == 0) to_global(r);
+            continue;
+        }
+        // phase 0: suffix starts and lengths of the positions
+        {
+            uint32_t wsum = 0;
+            for (uint32_t p = tid; p < d; p += THREADS) {
+                const uint2 sf = g.s_suf[s0 + p];
+                m.pst[p] = sf.x;
+                m.pln[p] = sf.y;
+                wsum += sf.y & 0x7fffffffu;
+            }
+            wsum = wave_sum<uint32_t>(wsum);
+            if (lane == 0 && wsum) atomicAdd(&sh.wedges, wsum);
+        }
+        // the table: 8 words (32 partners) per bitmap word of the rank structure
+        const uint32_t nbw = (win + 31) / 32;
+        for (uint32_t i = tid; i < 8 * nbw; i += THREADS) lds[i] = 0;
+        __syncthreads();
+        if (sh.wedges < 6) continue;
+        // phase 1: thermometer hits of every wedge
+        walk_positions<THREADS>(g, m, d, kEmpty, kEmpty, true, false,
+                                [&](const uint32_t (&e2)[kUnroll], const uint32_t (&)[kUnroll],
+                                    const uint32_t (&sg)[kUnroll]) {
+#pragma unroll
+                                    for (int u = 0; u < kUnroll; u++) {
+                                        if (e2[u] == kEmpty) continue;
+                                        my_wedges++;
+                                        const uint32_t idx = (e2[u] >> 1) - r - 1;
+                                        const uint32_t cls = (e2[u] & 1u) ^ sg[u];
+                                        win_hit(&lds[idx >> 2], 1u << (8 * (idx & 3) + 3 * cls));
+                                    }
+                                });
+        __syncthreads();
+        // phase 2: candidate bitmaps (bit 2 of a class's thermometer) and their
+        // prefix counts; thread t owns bitmap words kPerThread t .. + kPerThread
+        uint32_t b0[kPerThread], b1[kPerThread];
+        uint32_t c0 = 0, c1 = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < kPerThread; i++) {
+            const uint32_t j = kPerThread * tid + i;
+            uint32_t x0 = 0, x1 = 0;
+            if (j < nbw) {
+                const uint4 *T4 = reinterpret_cast<const uint4 *>(lds + 8 * j);
+                const uint4 lo4 = T4[0], hi4 = T4[1];
+                const uint32_t tw[8] = {lo4.x, lo4.y, lo4.z, lo4.w, hi4.x, hi4.y, hi4.z, hi4.w};
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        x0 |= ((tw[q] >> (8 * e + 2)) & 1u) << (4 * q + e);
+                        x1 |= ((tw[q] >> (8 * e + 5)) & 1u) << (4 * q + e);
+                    }
+                }
+            }
+            b0[i] = x0; b1[i] = x1;
+            c0 += __popc(x0); c1 += __popc(x1);
+        }
+        uint32_t k0 = 0, k1 = 0;
+        block_excl_scan2<THREADS>(c0, c1, scan_tmp, k0, k1);
+        // (every table word has been read: the scan's barriers order the reads
+        // before these writes)
+#pragma unroll
+        for (uint32_t i = 0; i < kPerThread; i++) {
+            const uint32_t j = kPerThread * tid + i;
+            if (j < nbw) {
+                lds[j] = b0[i];
+                lds[nbw + j] = b1[i];
+                lds[2 * nbw + j] = c0;
+                lds[3 * nbw + j] = c1;
+            }
+            c0 += __popc(b0[i]);
+            c1 += __popc(b1[i]);
+        }
+        if (tid == 0) { s_k0 = k0; s_k1 = k1; }
+        __syncthreads();
+        const uint32_t K0 = s_k0, k = s_k0 + s_k1;
+        if (k < 2) continue;
+        const uint32_t W = (d + 31) >> 5;
+        const uint32_t stage_cap = kRWords - 4 * nbw;
+        if (k > P.gkmax || stage_cap < k) {
+            if (tid == 0) to_global(r);
+            continue;
+        }
+        uint32_t *stage = lds + 4 * nbw;
+        const uint64_t words = (uint64_t)k * W;
+        if (tid == 0) {
+            // output reservations as in the hash tiers (workgroup-local chunks
+            // for small outputs, a reservation of its own for a large one)
+            sh.big_m = words > kMaskChunk / 4;
+            sh.big_c = k > kCandChunk / 4;
+            if (sh.big_m) {
+                sh.need_m += words;
+            } else {
+                if (sh.vm + words > sh.vm_end) { sh.need_m += kMaskChunk; sh.vm = 0; sh.vm_end = kMaskChunk; }
+                sh.vm += words;
+            }
+            if (sh.big_c) {
+                sh.need_c += k;
+            } else {
+                if (sh.vc + k > sh.vc_end) { sh.need_c += kCandChunk; sh.vc = 0; sh.vc_end = kCandChunk; }
+                sh.vc += k;
+            }
+            sh.need_r += 1;
+            sh.need_u += anchor_units(k, W, P.chunk_base);
+            bool bad = (__atomic_load_n(&C->over_cap, __ATOMIC_RELAXED) & 2u) != 0;
+            if (!bad) {
+                if (sh.big_m) {
+                    uint64_t o = atomicAdd(&C->mask_cursor, (unsigned long long)words);
+                    sh.bm = o;
+                    if (o + words > P.ws.cap_mask_words) bad = true;
+                } else if (sh.moff + words > sh.mres_end) {
+                    uint64_t o = atomicAdd(&C->mask_cursor, (unsigned long long)kMaskChunk);
+                    sh.moff = o; sh.mres_end = o + kMaskChunk;
+                    if (o + kMaskChunk > P.ws.cap_mask_words) bad = true;
+                }
+                if (sh.big_c) {
+                    uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)k);
+                    sh.bc = o;
+                    if (o + k > P.ws.cap_cands) bad = true;
+                } else if (sh.coff + k > sh.cres_end) {
+                    uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)kCandChunk);
+                    sh.coff = o; sh.cres_end = o + kCandChunk;
+                    if (o + kCandChunk > P.ws.cap_cands) bad = true;
+                }
+                if (sh.aidx >= sh.arec_end) {
+                    uint32_t o = atomicAdd(&C->n_anchor, kRecChunk);
+                    sh.aidx = o; sh.arec_end = o + kRecChunk;
+                    if ((uint64_t)o + kRecChunk > P.ws.cap_anchors) bad = true;
+                }
+            }
+            sh.skip = bad;
+            if (bad) {
+                atomicOr(&C->over_cap, 2u);
+                sh.moff = sh.mres_end = sh.coff = sh.cres_end = 0;
+                sh.aidx = sh.arec_end = 0;
+            }
+        }
+        __syncthreads();
+        if (sh.skip) continue;
+        const uint64_t moff = sh.big_m ? sh.bm : sh.moff, coff = sh.big_c ? sh.bc : sh.coff;
+        const uint32_t aidx = sh.aidx;
+        // candidate ids: class 0 (same sign product) in rank order, then class 1
+        for (uint32_t j = tid; j < nbw; j += THREADS) {
+#pragma unroll
+            for (uint32_t c = 0; c < 2; c++) {
+                uint32_t bm = lds[c * nbw + j];
+                uint64_t o = coff + (c ? K0 : 0u) + lds[(2 + c) * nbw + j];
+                while (bm) {
+                    const uint32_t b = (uint32_t)__builtin_ctz(bm);
+                    bm &= bm - 1;
+                    P.ws.cands[o++] = r + 1 + 32 * j + b;
+                }
+            }
+        }
+        // phase 3: bit p of the candidate's mask for every wedge through
+        // position p, staged in slabs of whole mask words (a slab walks only
+        // the positions of its words)
+        const uint32_t sw = min(W, stage_cap / k);
+        for (uint32_t w0 = 0; w0 < W; w0 += sw) {
+            const uint32_t nw = min(sw, W - w0);
+            const uint32_t slab = k * nw;
+            for (uint32_t i = tid; i < slab; i += THREADS) stage[i] = 0;
+            __syncthreads();
+            walk_positions<THREADS>(g, m, d, kEmpty, kEmpty, true, false,
+                                    [&](const uint32_t (&e2)[kUnroll], const uint32_t (&pp)[kUnroll],
+                                        const uint32_t (&sg)[kUnroll]) {
+                                        uint32_t bmv[kUnroll], pre[kUnroll];
+#pragma unroll
+                                        for (int u = 0; u < kUnroll; u++) {
+                                            const uint32_t idx = (e2[u] >> 1) - r - 1;
+                                            const uint32_t cls = (e2[u] & 1u) ^ sg[u];
+                                            const uint32_t j = e2[u] == kEmpty ? 0u : idx >> 5;
+                                            bmv[u] = lds[cls * nbw + j];
+                                            pre[u] = lds[(2 + cls) * nbw + j];
+                                        }
+#pragma unroll
+                                        for (int u = 0; u < kUnroll; u++) {
+                                            if (e2[u] == kEmpty) continue;
+                                            const uint32_t idx = (e2[u] >> 1) - r - 1;
+                                            const uint32_t b = idx & 31;
+                                            if (!((bmv[u] >> b) & 1u)) continue;
+                                            const uint32_t cls = (e2[u] & 1u) ^ sg[u];
+                                            const uint32_t ci = (cls ? K0 : 0u) + pre[u] +
+                                                                __popc(bmv[u] & ((1u << b) - 1u));
+                                            const uint32_t p = pp[u];
+                                            atomicOr(&stage[ci * nw + (p >> 5) - w0], 1u << (p & 31));
+                                        }
+                                    },
+                                    32 * w0, 32 * (w0 + nw));
+            __syncthreads();
+            if (nw == W) {
+                for (uint32_t i = tid; i < slab; i += THREADS) P.ws.masks[moff + i] = stage[i];
+            } else {
+                for (uint32_t i = tid; i < slab; i += THREADS) {
+                    const uint32_t c = i / nw;
+                    P.ws.masks[moff + (uint64_t)c * W + w0 + (i - c * nw)] = stage[i];
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            AnchorRec a;
+            a.rank = r; a.k = k; a.w32 = W; a.graph = g.s_graph[r];
+            a.mask_off = moff; a.cand_off = coff;
+            P.ws.anchors[aidx] = a;
+            if (!sh.big_m) sh.moff = moff + words;
+            if (!sh.big_c) sh.coff = coff + k;
+            sh.aidx = aidx + 1;
+        }
+    }
+    if (tid == 0) {
+        if (sh.need_m) atomicAdd(&C->need_masks, sh.need_m);
+        if (sh.need_c) atomicAdd(&C->need_cands, sh.need_c);
+        if (sh.need_r) atomicAdd(&C->need_recs, sh.need_r);
+        if (sh.need_u) atomicAdd(&C->need_units, sh.need_u);
+        for (uint32_t i = sh.aidx; i < sh.arec_end; i++) {
+            AnchorRec a;
+            a.rank = 0; a.k = 0; a.w32 = 0; a.graph = 0; a.mask_off = 0; a.cand_off = 0;
+            P.ws.anchors[i] = a;
+        }
+    }
+    my_wedges = wave_sum<uint64_t>(my_wedges);
+    if (lane == 0 && my_wedges) atomicAdd(&C->wedges, (unsigned long long)my_wedges);
 }
 
 // ----------------------------------------------------- per-wave tier
@@ -2337,6 +2695,8 @@ static void launch_pairs(const PairArgs &base, const LaunchShape &sh, hipStream_
     P.tier = 2;
     hipLaunchKernelGGL((k_pair_big<kBThreads, kBH, kBKmax, PACKED>), dim3(sh.grid_b),
                        dim3(kBThreads), 0, s, P);
+    P.tier = kListR + 1;
+    hipLaunchKernelGGL(k_pair_window, dim3(sh.grid_b), dim3(kRThreads), 0, s, P);
     P.tier = 3;
     hipLaunchKernelGGL((k_pair_global<PACKED>), dim3(sh.grid_c), dim3(kGThreads), 0, s, P);
     P.tier = 4;

@@ -241,7 +241,7 @@ namespace {
 
 // Count workspace (one per stream that counts).
 struct Work {
-    DBuf ctr, anchors, units, masks, cands, defer0, defer1, defer2, defer3, gtab, dtab, bscr, count,
+    DBuf ctr, anchors, units, masks, cands, defer0, defer1, defer2, defer3, defer4, gtab, dtab, bscr, count,
         carry, pv, pv_o, pv_slot;
     DBuf ucnt, uoff, ptmp;
     HBuf host;          // counters + counts + carries read back
@@ -296,6 +296,9 @@ struct bbc_ctx {
     Work work;
     bbc_count_stats stats{};
     bool timing = false;
+    // test hooks (bbc_set_test_hook): host-forced conditions
+    bool hook_no_window = false;
+    uint64_t hook_preload = 0;
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     std::map<uint64_t, Shape> tuned;   // autotuner cache by size class
     struct SideTime { float ms[2] = {0, 0}; bool tried[2] = {false, false}; };
@@ -377,9 +380,11 @@ void check_flags(uint32_t flags)
 // Anchor side of one graph. Work of the pair table anchored on S is about the
 // number of 2-hop wedges through O, sum_o C(d_o, 2); work of the triplet
 // phase grows with the mask width, about the edge-weighted mean degree of S.
+// Estimated cost ratio of the two sides (larger / smaller) goes to *ratio.
 uint32_t choose_side(uint32_t flags, uint32_t n_u, uint32_t n_v, uint64_t m, uint64_t c2_u,
-                     uint64_t c2_v, uint64_t d2_u, uint64_t d2_v)
+                     uint64_t c2_v, uint64_t d2_u, uint64_t d2_v, double *ratio = nullptr)
 {
+    if (ratio) *ratio = 1.0;
     if (flags & BBC_ANCHOR_U) return 0;
     if (flags & BBC_ANCHOR_V) return 1;
     if (flags & BBC_ANCHOR_SMALLER) return n_v < n_u ? 1 : 0;
@@ -387,10 +392,19 @@ uint32_t choose_side(uint32_t flags, uint32_t n_u, uint32_t n_v, uint64_t m, uin
     double wu = (double)d2_u / (double)m, wv = (double)d2_v / (double)m;
     double cost_u = (double)c2_v * (1.0 + wu / 32.0);   // anchored on U: wedges centred in V
     double cost_v = (double)c2_u * (1.0 + wv / 32.0);
+    if (ratio) {
+        const double lo = std::min(cost_u, cost_v), hi = std::max(cost_u, cost_v);
+        *ratio = lo > 0 ? hi / lo : 1e30;
+    }
     return cost_v < cost_u ? 1 : 0;
 }
 
 constexpr uint64_t kSideTuneMinEdges = 1u << 18;
+// Only shapes whose two side estimates are within this factor are timed on
+// both sides: beyond it the estimate has always picked the faster side (a
+// 2M x 500k graph with estimates 3.9x apart counts 12x slower on the other
+// side, so timing it once would cost more than the estimate ever loses).
+constexpr double kSideTuneMaxRatio = 2.0;
 // vertex slots (|U| + |V| over the set) up to which the ingest counts degrees
 // in per-XCD copies (8 words per slot)
 constexpr uint64_t kDegCopyMaxSlots = 1u << 22;
@@ -534,9 +548,10 @@ std::shared_ptr<GraphSet> build_set(bbc_ctx *ctx, const CooIn &in, hipStream_t s
     const bool auto_side = !(in.flags & (BBC_ANCHOR_U | BBC_ANCHOR_V | BBC_ANCHOR_SMALLER));
     for (uint32_t g = 0; g < G; g++) {
         GraphDesc &d = set->desc[g];
+        double ratio = 1.0;
         d.side = choose_side(in.flags, d.n_u, d.n_v, d.m, h_stats[g], h_stats[G + g],
-                             h_stats[2 * G + g], h_stats[3 * G + g]);
-        if (G == 1 && auto_side && d.m >= kSideTuneMinEdges) {
+                             h_stats[2 * G + g], h_stats[3 * G + g], &ratio);
+        if (G == 1 && auto_side && d.m >= kSideTuneMinEdges && ratio <= kSideTuneMaxRatio) {
             // a recurring large shape: time each side once, then keep the faster
             const uint64_t key = side_key(d.n_u, d.n_v, d.m, h_stats[0], h_stats[1],
                                           h_stats[2], h_stats[3]);
@@ -694,6 +709,7 @@ void ensure_work(bbc_ctx *ctx, Work &w, GraphSet &set)
     if (w.cap_defer < set.NS + 1ull) {
         w.defer0.ensure(al, (set.NS + 1ull) * 4); w.defer1.ensure(al, (set.NS + 1ull) * 4);
         w.defer2.ensure(al, (set.NS + 1ull) * 4); w.defer3.ensure(al, (set.NS + 1ull) * 4);
+        w.defer4.ensure(al, (set.NS + 1ull) * 4);
         w.cap_defer = set.NS + 1ull;
     }
     w.ctr.ensure(al, sizeof(Counters));
@@ -748,6 +764,7 @@ Workspace ws_view(Work &w, bool pv, bool pvo)
     ws.cands = w.cands.as<uint32_t>(); ws.cap_cands = w.cap_cands;
     ws.defer[0] = w.defer0.as<uint32_t>(); ws.defer[1] = w.defer1.as<uint32_t>();
     ws.defer[2] = w.defer2.as<uint32_t>(); ws.defer[3] = w.defer3.as<uint32_t>();
+    ws.defer[4] = w.defer4.as<uint32_t>();
     ws.cap_defer = w.cap_defer;
     ws.gtab = w.gtab.as<uint32_t>(); ws.gtab_words_per_block = w.gtab_words;
     ws.gtab_blocks = w.gtab_blocks;
@@ -775,6 +792,7 @@ struct LaunchArgs {
     uint32_t G, NS, NO;
     void *ptmp;
     uint64_t ptmp_bytes;
+    uint64_t preload;       // starting value of every graph's accumulator (0 but in tests)
 };
 
 LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
@@ -805,6 +823,8 @@ LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
     L.G = set.G; L.NS = set.NS; L.NO = set.NO;
     L.ptmp = w.ptmp.p;
     L.ptmp_bytes = w.ptmp_bytes;
+    L.P.flags = ctx->hook_no_window ? kPairNoWindow : 0u;
+    L.preload = ctx->hook_preload;
     return L;
 }
 
@@ -812,7 +832,7 @@ void enqueue_args(bbc_ctx *ctx, const LaunchArgs &L, hipStream_t s, bool timed)
 {
     const Workspace &ws = L.P.ws;
     HIP_OK(fill_u32((uint32_t *)ws.ctr, 0, sizeof(Counters) / 4, s));
-    HIP_OK(fill_u64(ws.count, 0, L.G, s));
+    HIP_OK(fill_u64(ws.count, L.preload, L.G, s));
     HIP_OK(fill_u32(ws.carry, 0, L.G, s));
     if (L.mode == 1) HIP_OK(fill_u64(ws.pv, 0, L.NS, s));
     if (L.mode == 2) HIP_OK(fill_u64(ws.pv_o, 0, L.NO, s));
@@ -884,6 +904,7 @@ bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set)
     ctx->stats.deferred_b = c->n_list[1];
     ctx->stats.deferred_c = c->n_list[2];
     ctx->stats.deferred_d = c->n_list[3];
+    ctx->stats.deferred_r = c->n_list[4];
     return true;
 }
 
@@ -1654,6 +1675,16 @@ bbc_status bbc_set_timing(bbc_ctx *ctx, int enable)
             for (auto &e : ctx->ev) HIP_OK(hipEventCreate(&e));
         ctx->timing = enable != 0;
     });
+}
+
+bbc_status bbc_set_test_hook(bbc_ctx *ctx, int hook, int64_t value)
+{
+    if (!ctx) return BBC_E_INVAL;
+    switch (hook) {
+        case BBC_HOOK_NO_WINDOW_TIER: ctx->hook_no_window = value != 0; return BBC_OK;
+        case BBC_HOOK_PRELOAD_COUNT: ctx->hook_preload = (uint64_t)value; return BBC_OK;
+        default: return BBC_E_INVAL;
+    }
 }
 
 bbc_status bbc_get_last_stats(bbc_ctx *ctx, bbc_count_stats *out)
