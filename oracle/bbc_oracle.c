@@ -312,6 +312,7 @@ typedef struct {
     int32_t *l_pos;
     int8_t *l_su, *l_sw;
     int64_t l_cap;
+    int8_t *mark;        /* per position of Gamma(u): sign(w1,v) while L[w1] is marked, else 0 */
 } scratch_t;
 
 typedef struct {
@@ -340,12 +341,16 @@ static void scratch_init(scratch_t *w, const graph_t *g)
     w->l_pos = malloc(sizeof(int32_t) * w->l_cap);
     w->l_su = malloc(w->l_cap);
     w->l_sw = malloc(w->l_cap);
+    int64_t max_d = 0;
+    for (int64_t i = 0; i < g->n_s; i++)
+        if (g->off_s[i + 1] - g->off_s[i] > max_d) max_d = g->off_s[i + 1] - g->off_s[i];
+    w->mark = calloc(max_d + 1, 1);
 }
 
 static void scratch_free(scratch_t *w)
 {
     free(w->cnt); free(w->touched); free(w->cand); free(w->l_off);
-    free(w->l_pos); free(w->l_su); free(w->l_sw);
+    free(w->l_pos); free(w->l_su); free(w->l_sw); free(w->mark);
 }
 
 /* One anchor u of Algorithm 2. With oriented != 0 only partners of higher
@@ -420,28 +425,26 @@ static void bbvp_anchor(const graph_t *g, uint32_t u, int oriented, scratch_t *w
     }
     w->l_off[n_c] = fill;
 
-    /* every pair A = (w1, w2) of C */
+    /* every pair A = (w1, w2) of C: T = L[w1] n L[w2]. The positions of
+     * L[w1] are marked (with sign(w1, v)) in an array over Gamma(u); each
+     * entry of L[w2] then looks its position up, and a marked one is a common
+     * neighbour v with its wedge type. */
     for (int64_t i = 0; i < n_c; i++) {
+        for (int64_t a = w->l_off[i]; a < w->l_off[i + 1]; a++) w->mark[w->l_pos[a]] = w->l_sw[a];
         for (int64_t j = i + 1; j < n_c; j++) {
             t->candidates++;
-            /* T = L[w1] n L[w2] with the wedge type of each v in T */
             uint64_t x[4] = {0, 0, 0, 0};
             uint64_t size_t_ = 0;
-            int64_t a = w->l_off[i], ae = w->l_off[i + 1];
-            int64_t b = w->l_off[j], be = w->l_off[j + 1];
-            while (a < ae && b < be) {
-                if (w->l_pos[a] < w->l_pos[b]) a++;
-                else if (w->l_pos[a] > w->l_pos[b]) b++;
-                else {
+            for (int64_t b = w->l_off[j]; b < w->l_off[j + 1]; b++) {
+                const int8_t s_w1v = w->mark[w->l_pos[b]];
+                if (!s_w1v) continue;   /* v not in L[w1] */
 #if ORC_MUTANT == 6
-                    int kappa = orc_wedge_type(w->l_su[a], w->l_sw[a], w->l_sw[a]);
+                int kappa = orc_wedge_type(w->l_su[b], s_w1v, s_w1v);
 #else
-                    int kappa = orc_wedge_type(w->l_su[a], w->l_sw[a], w->l_sw[b]);
+                int kappa = orc_wedge_type(w->l_su[b], s_w1v, w->l_sw[b]);
 #endif
-                    x[kappa]++;
-                    size_t_++;
-                    a++; b++;
-                }
+                x[kappa]++;
+                size_t_++;
             }
             if (tr && tr->n_pairs < tr->cap_pairs) {
                 int64_t *r = tr->pairs + 7 * tr->n_pairs++;
@@ -467,6 +470,7 @@ static void bbvp_anchor(const graph_t *g, uint32_t u, int oriented, scratch_t *w
 #endif
             }
         }
+        for (int64_t a = w->l_off[i]; a < w->l_off[i + 1]; a++) w->mark[w->l_pos[a]] = 0;
     }
 }
 
