@@ -1,31 +1,40 @@
 #!/usr/bin/env python3
 """Benchmark: exact balanced (3,3)-biclique counting on one MI355X.
 
-One step = the whole hot path on the config-2 workload (Chung-Lu signed
-bipartite graph, 100000 x 50000, ~2M edges, seed 1) with the COO already in
-HBM: validation, degrees, priority ranking and both CSR orientations
-(bbc_build_csr with device pointers), then the pair-table, planning and
-triplet kernels and the int64 reduction (bbc_count_global). The count is
-checked against the oracle's stored value every step.
+One step = the whole hot path on the largest single graph, config 3 (Chung-Lu
+signed bipartite graph, |U| = 2M, |V| = 500k, 40M edges, exponents 1.9 / 2.3,
+hidden-label signs with 10% flips, seed 1), with the COO already in HBM:
+validation, degrees, priority ranking and both CSR orientations
+(bbc_build_csr on device pointers), then the pair-table, planning and triplet
+kernels and the int64 reduction (bbc_count_global). The count is checked
+against the oracle's stored value every step.
 
 value = triplets/s, where the number of triplets is a property of the graph:
 the same-side (U) triples with at least 3 common neighbours (the survivors of
 the |T| < q test of Algorithm 2), counted by the CPU oracle and stored in
-tests/golden/cfg2_seed1.json. It does not depend on how the GPU enumerates.
+tests/golden/cfg3_seed1_full.json. It does not depend on how the GPU
+enumerates.
 
 Also reported on the same JSON line:
-  roofline      the dominant kernel's achieved rate vs its bound
-  roofline_other_phases  the same for the other phases (triplets, CSR build)
-  cpu_baseline  the CPU oracle on a bounded sample of the same workload
-  batched       8192-graph batch (one build + one persistent, graph-replayed
-                count) vs the same graphs built and counted one at a time
-  served        Poisson request stream over the batched mix plus 2% config-2
-                sized graphs: p50 / p99 latency and graphs/s
+  roofline       the dominant phase of a step, priced against its bound
+  roofline_other_phases  the other phases; the pair phase is priced by its
+                 algorithmic HBM bytes (4.25 B per oriented 2-hop wedge)
+  cpu_baseline   the CPU oracle on a bounded sample of config 3, all host
+                 threads of this process
+  config2        config 2 (100k x 50k, 2M edges) build + global count + the
+                 per-U-vertex counts, checked against the oracle's values
+  batched        the 8192-graph batch (one build + one persistent,
+                 graph-replayed count) vs the same graphs one at a time,
+                 counts checked against the oracle's
+  served         Poisson request stream over the batched mix plus 2% config-2
+                 graphs under a 64 GiB admission cap: p50 / p99 latency,
+                 graphs/s, counts checked against the oracle's
 """
 import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -36,16 +45,26 @@ sys.path.insert(0, ROOT)
 
 METRIC = "triplets/s + time to exact count; batched vs per-graph; serve p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
-MFMA_FP4_PEAK_TFLOPS = 10100.0   # dense fp4 matrix-core peak of MI355X
+FP4_PEAK_TFLOPS = 10100.0     # dense fp4 matrix-core peak of MI355X
+INT8_PEAK_TOPS = 5000.0       # dense int8 matrix-core peak
+SERVE_CAP = 64 << 30          # admission cap of the served leg (bytes)
+ANCHOR_U = 1 << 4
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def load_golden():
-    with open(os.path.join(ROOT, "tests", "golden", "cfg2_seed1.json")) as f:
+def load_json(name):
+    p = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
         return json.load(f)
+
+
+def digest64(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i8").tobytes()).hexdigest()
 
 
 def source_digest(names):
@@ -56,38 +75,69 @@ def source_digest(names):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_key, digest):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_key}_config2_traffic.md")
-    if not os.path.exists(path):
-        return None
+def profile_values(name):
+    """Key: value lines ("- key: value") of a committed profile summary."""
+    path = os.path.join(ROOT, "profiles", name)
     vals = {}
-    with open(path) as f:
-        for line in f:
-            if ":" in line and line.startswith("- "):
-                k, v = line[2:].split(":", 1)
-                vals[k.strip()] = v.strip()
+    if os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                if line.startswith("- ") and ":" in line:
+                    k, v = line[2:].split(":", 1)
+                    vals[k.strip()] = v.strip()
+    return vals
+
+
+def traffic_from_profile(name, key, digest):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    vals = profile_values(name)
     if vals.get("source_sha256_16") != digest:
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
 
+def oriented_wedges(g, side):
+    """Sum over the opposite side of C(d, 2): the 2-hop wedges of the pair
+    scan when anchoring on `side` (each counted once, at its lower-priority
+    end)."""
+    d = np.bincount((g.ev if side == 0 else g.eu).astype(np.int64),
+                    minlength=g.n_v if side == 0 else g.n_u).astype(np.int64)
+    return int((d * (d - 1) // 2).sum())
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(g, stride, threads):
+    """The oracle (Algorithm 2, -O3 -march=native build of oracle/bbc_oracle.c)
+    over the U anchors whose id is a multiple of `stride`, on `threads`
+    threads. The time includes the oracle's own CSR build."""
     from oracle import oracle as O
-    O.build()
+    O.use_library(O.build(native=True))
     t = time.time()
     r = O.count_bbvp(g, side=0, threads=threads, anchor_stride=stride)
     dt = time.time() - t
     return {"value": r["feasible"] / dt, "unit": "triplets/s", "cores": threads, "kind": "oracle",
-            "sample": f"U anchors with id % {stride} == 0 of config2 seed 1 "
-                      f"({r['feasible']} triplets, {r['candidates']} candidate pairs, {dt:.1f} s)"}
+            "sample": f"U anchors with id % {stride} == 0 of config3 seed 1, oracle built -O3 "
+                      f"-march=native, {threads} threads on {cpu_model()} "
+                      f"(os.cpu_count {os.cpu_count()}); {r['feasible']} triplets, "
+                      f"{r['candidates']} candidate pairs, {dt:.1f} s including the oracle's "
+                      f"CSR build"}
 
 
-def run_batched(ctx, gs, torch):
+def run_batched(ctx, gs, torch, want):
     from paper_2605_03603_amd import generators as G
     nu, nv, off, eu, ev, sg = G.concat(gs)
     dev = torch.device("cuda:0")
@@ -110,7 +160,6 @@ def run_batched(ctx, gs, torch):
             h.free()
     torch.cuda.synchronize()
     t_batch = (time.time() - t) / reps
-    assert np.array_equal(got, ref)
     # the same graphs, one build and one count each
     offs = off.astype(np.int64)
     t = time.time()
@@ -122,15 +171,20 @@ def run_batched(ctx, gs, torch):
         h.free()
     torch.cuda.synchronize()
     t_per = time.time() - t
-    return ref, {
+    out = {
         "graphs": len(gs), "edges": int(off[-1]),
         "batched_ms": round(1e3 * t_batch, 3), "per_graph_ms": round(1e3 * t_per, 3),
         "batched_graphs_per_s": round(len(gs) / t_batch, 1),
         "per_graph_graphs_per_s": round(len(gs) / t_per, 1),
         "speedup": round(t_per / t_batch, 2),
-        "counts_equal": bool(np.array_equal(per, ref)),
         "total_count": int(ref.sum()),
     }
+    if want is not None:
+        out["counts_equal_oracle"] = bool(np.array_equal(ref, want) and np.array_equal(got, want)
+                                          and np.array_equal(per, want))
+    else:
+        out["counts_equal_per_graph"] = bool(np.array_equal(per, ref) and np.array_equal(got, ref))
+    return ref, out
 
 
 def run_served(ctx, pool, pool_counts, large, large_counts, n_requests, qps, seed):
@@ -179,7 +233,7 @@ def run_served(ctx, pool, pool_counts, large, large_counts, n_requests, qps, see
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "max_ms": round(float(lat.max()), 3),
             "large_fraction": round(sum(1 for k, _ in picks if k == "L") / n_requests, 4),
-            "wrong_counts": wrong}
+            "mem_cap_bytes": SERVE_CAP, "wrong_counts": wrong}
 
 
 def main():
@@ -187,16 +241,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-stride", type=int, default=2)
+    ap.add_argument("--cpu-stride", type=int, default=400)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--batch-graphs", type=int, default=8192)
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-edges", action="store_true")
+    ap.add_argument("--no-config2", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-general-q", action="store_true",
-                    help="skip the timing of the (3, q) and (q, 3) counts, q = 4..7")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (5 times), the reference for "
                          "the HBM byte counters")
@@ -219,10 +271,11 @@ def main():
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 5}))
         return
 
-    gold = load_golden()
-    log("generating config2 seed 1")
-    g = G.config2(1)
-    assert g.m == gold["m"], "generator output differs from the stored workload"
+    gold3 = load_json("cfg3_seed1_full.json")
+    log("generating config3 seed 1")
+    g = G.config3(1)
+    if gold3 is not None:
+        assert g.m == gold3["m"], "generator output differs from the stored workload"
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     ctx = bbc.Context(0, stream=stream)
@@ -248,78 +301,95 @@ def main():
     torch.cuda.synchronize()
     log("timed steps", args.steps)
     kern = {"ms_build": 0.0, "ms_pair": 0.0, "ms_plan": 0.0, "ms_triplet": 0.0}
-    counts = set()
+    counts, sides = set(), set()
     t0 = time.time()
     for _ in range(args.steps):
         c, side, st = step()
         counts.add(c)
+        sides.add(side)
         for k in kern:
             kern[k] += st[k]
     torch.cuda.synchronize()
     t1 = time.time()
     ms_per_step = 1e3 * (t1 - t0) / args.steps
-    count_ok = counts == {gold["total"]}
-    triplets = gold["feasible_triplets_u"]
-    value = triplets / (ms_per_step / 1e3)
     kern_avg = {k: round(v / args.steps, 4) for k, v in kern.items()}
+    side = sides.pop() if len(sides) == 1 else -1
+    triplets = gold3["feasible_triplets_u"] if gold3 is not None else None
+    count_ok = gold3 is not None and counts == {gold3["total"]}
+    value = triplets / (ms_per_step / 1e3) if (triplets is not None and side == 0) else None
 
     # end-to-end from host COO (includes the PCIe upload)
+    log("host-COO steps")
     t = time.time()
-    reps = 3
+    reps = 2
     for _ in range(reps):
         h = ctx.build_csr(g.n_u, g.n_v, g.eu, g.ev, g.sign)
         ctx.count_global(h)
         h.free()
     e2e_ms = 1e3 * (time.time() - t) / reps
 
-    # roofline of each phase; the dominant one is reported as "roofline"
+    # ---- rooflines (bytes and operations per launch; times from the HIP
+    # events the library records around each phase on this stream)
     digest = source_digest(["count.hip", "bbc_dev.h", "bbc_count.h"])
+    w2 = oriented_wedges(g, side if side >= 0 else 0)
 
     def roof_triplet():
-        # |M_x n M_y| over all examined pairs as 0/1 products: 32 bits per
-        # mask word, a multiply and an add each. Masks of 3 words and more run
-        # on the fp4 matrix cores, 1 and 2 words on the int8 ones; the fp4
-        # peak (the higher) is the bound.
+        # every examined pair of candidate masks as a dense 0/1 product over
+        # its mask bits (32 per word, a multiply and an add each); masks of 3
+        # words and more run on the fp4 matrix cores, 1 and 2 words on int8
         ops = 64.0 * st["pair_words"]
         achieved = ops / (kern_avg["ms_triplet"] / 1e3) / 1e12
-        return {"kernel": "triplet phase: k_triplet<0,0> + k_triplet<0,1>", "bound": "mfma",
-                "achieved": round(achieved, 3), "peak": MFMA_FP4_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / MFMA_FP4_PEAK_TFLOPS, 4),
+        return {"kernel": "triplet phase: k_triplet<0,0> + k_triplet<0,1> (dense-equivalent "
+                          "0/1 products, fp4 peak; 1-2 word masks run on int8, peak "
+                          f"{INT8_PEAK_TOPS:.0f} TOP/s)",
+                "bound": "mfma", "achieved": round(achieved, 2), "peak": FP4_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP4_PEAK_TFLOPS, 4),
                 "algorithmic_ops_per_launch": ops,
-                "traffic": traffic_from_profile("triplet", digest)}
+                "ms_per_launch": kern_avg["ms_triplet"],
+                "traffic": traffic_from_profile("triplet_config3_traffic.md",
+                                                "hbm_bytes_per_launch", digest)}
 
     def roof_pair():
-        # one read of every oriented wedge's entry, the suffix table, and the
-        # mask words written
-        byts = 4.0 * st["wedges"] + 8.0 * g.m + 4.0 * st["mask_words"]
+        # the scan reads every oriented 2-hop wedge's entry once: 4.25 B per
+        # wedge (4 B index + 2-bit sign), W2 = sum over the opposite side of
+        # C(d, 2)
+        byts = 4.25 * w2
         achieved = byts / (kern_avg["ms_pair"] / 1e3) / 1e9
-        return {"kernel": "pair phase: k_pair_wave + k_pair_lds + k_pair_big + 2 x k_pair_global",
-                "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes_per_launch": byts,
-                "traffic": traffic_from_profile("pair", digest)}
+        return {"kernel": "pair phase: k_pair_wave + k_pair_lds + k_pair_big + k_pair_window + "
+                          "2 x k_pair_global",
+                "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes_per_launch": byts, "oriented_wedges": w2,
+                "ms_per_launch": kern_avg["ms_pair"],
+                "traffic": traffic_from_profile("pair_config3_traffic.md",
+                                                "hbm_bytes_per_launch", digest)}
 
     def roof_build():
         byts = 17.5 * g.m
         achieved = byts / (kern_avg["ms_build"] / 1e3) / 1e9
-        return {"kernel": "csr build", "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes_per_launch": byts, "traffic": None}
+        return {"kernel": "csr build (validation, degrees, ranking, both orientations)",
+                "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes_per_launch": byts, "ms_per_launch": kern_avg["ms_build"],
+                "traffic": None}
 
     phases = {"ms_triplet": roof_triplet, "ms_pair": roof_pair, "ms_build": roof_build}
     dominant = max(phases, key=lambda k: kern_avg[k])
     roof = phases[dominant]()
     roof_other = [phases[k]() for k in sorted(phases, key=lambda k: -kern_avg[k]) if k != dominant]
+    # the whole step's algorithmic HBM bytes (build + pair scan) over its time
+    whole_gbs = (17.5 * g.m + 4.25 * w2) / (ms_per_step / 1e3) / 1e9
 
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "triplets/s", "n_gpus": 1,
+        "metric": METRIC, "value": round(value, 1) if value is not None else None,
+        "unit": "triplets/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": "config2: Chung-Lu signed bipartite, |U|=100000, |V|=50000, "
-                               "gamma 2.1/2.1, 80% positive, 200 balanced + 200 random-sign 12x12 "
-                               "planted blocks, seed 1",
-                   "n_u": g.n_u, "n_v": g.n_v, "n_edges": g.m, "anchor_side": "UV"[side],
+        "config": {"workload": "config3: Chung-Lu signed bipartite, |U|=2000000, |V|=500000, "
+                               "40M edges, gamma 1.9/2.3, 85% positive via hidden two-community "
+                               "labels with 10% flips, int8 signs, seed 1",
+                   "n_u": g.n_u, "n_v": g.n_v, "n_edges": g.m, "anchor_side": "UV"[side] if side >= 0 else "mixed",
                    "triplets": triplets, "parallelism": "1 GPU"},
         "count": sorted(counts)[0] if len(counts) == 1 else sorted(counts),
         "count_ok": count_ok,
@@ -329,82 +399,78 @@ def main():
         "last_count_stats": {k: st[k] for k in ("active_anchors", "virtual_candidates", "mask_words",
                                                  "pair_units", "candidate_pairs", "pair_words",
                                                  "wedges", "attempts", "deferred_a", "deferred_b",
-                                                 "deferred_c", "deferred_d")},
+                                                 "deferred_r", "deferred_c", "deferred_d")},
         "roofline": roof,
         "roofline_other_phases": roof_other,
+        "step_algorithmic_hbm": {"bytes": 17.5 * g.m + 4.25 * w2, "achieved_gbs": round(whole_gbs, 1),
+                                 "frac": round(whole_gbs / HBM_PEAK_GBS, 4)},
     }
+    d_eu = d_ev = d_sg = None
 
-    if not args.no_general_q:
-        # balanced (3, q) on a U-anchored build and (q, 3) on a V-anchored one,
-        # same workload; exactness against the oracle is in the GPU tests
-        log("general q")
-        gq = {"(3,q)": {}, "(q,3)": {}}
-        for flags, key in ((1 << 4, "(3,q)"), (1 << 5, "(q,3)")):
-            h = ctx.build_csr(g.n_u, g.n_v, d_eu, d_ev, d_sg, flags)
-            for q in range(4, 8):
-                pq = (3, q) if key == "(3,q)" else (q, 3)
-                ts = []
-                for _ in range(3):
-                    torch.cuda.synchronize()
-                    t = time.time()
-                    c = ctx.count_global(h, *pq)
-                    ts.append(1e3 * (time.time() - t))
-                gq[key][str(q)] = {"count": c, "ms": round(sorted(ts)[1], 3)}
+    if not args.no_config2:
+        gold2 = load_json("cfg2_seed1.json")
+        log("config2: build + global and per-U-vertex counts")
+        g2 = G.config2(1)
+        e_u = torch.from_numpy(g2.eu.view(np.int32)).to(dev)
+        e_v = torch.from_numpy(g2.ev.view(np.int32)).to(dev)
+        e_s = torch.from_numpy(bbc.pack_signs_2bit(g2.sign)).to(dev)   # 2-bit packed signs
+        flags2 = bbc.BBC_SIGNS_2BIT_PACKED
+        for _ in range(3):
+            h = ctx.build_csr(g2.n_u, g2.n_v, e_u, e_v, e_s, flags2)
+            ctx.count_per_vertex(h, 0)
             h.free()
-        # 4 vertices on the anchor side (triples of candidates), one count each
-        for pq in ((4, 3), (4, 4)):
-            h = ctx.build_csr(g.n_u, g.n_v, d_eu, d_ev, d_sg, 1 << 4)
-            ctx.count_global(h, *pq)                 # sizes the workspace
-            torch.cuda.synchronize()
-            t = time.time()
-            c = ctx.count_global(h, *pq)
-            gq["%d,%d" % pq] = {"count": c, "ms": round(1e3 * (time.time() - t), 1)}
-            h.free()
-        out["general_q"] = gq
-
-    if not args.no_edges:
-        # edge queries (balanced bicliques through an edge: the change of the
-        # count on inserting, deleting or re-signing it), 20000 existing edges
-        # with their own sign and 2000 new pairs in one call (batched);
-        # exactness against the oracle is in the GPU tests
-        log("edge queries")
-        rng = np.random.default_rng(7)
-        h = ctx.build_csr(g.n_u, g.n_v, d_eu, d_ev, d_sg, 1 << 4)
-        ne, nn = 20000, 2000
-        idx = rng.choice(g.m, size=ne, replace=False)
-        qu = np.concatenate([g.eu[idx], rng.integers(0, g.n_u, nn)]).astype(np.uint32)
-        qv = np.concatenate([g.ev[idx], rng.integers(0, g.n_v, nn)]).astype(np.uint32)
-        qs = np.concatenate([g.sign[idx], np.ones(nn, np.int8)]).astype(np.int8)
-        ctx.count_through_edges(h, qu[:64], qv[:64], qs[:64])
         torch.cuda.synchronize()
+        reps = 10
+        totals = set()
         t = time.time()
-        through = ctx.count_through_edges(h, qu, qv, qs)
-        ms = 1e3 * (time.time() - t)
-        h.free()
-        out["edge_queries"] = {"queries": int(qu.size), "ms_total": round(ms, 2),
-                               "us_per_query": round(1e3 * ms / qu.size, 3),
-                               "existing_edges_sum": int(through[:ne].sum()),
-                               "new_pairs_sum": int(through[ne:].sum())}
+        for _ in range(reps):
+            h = ctx.build_csr(g2.n_u, g2.n_v, e_u, e_v, e_s, flags2)
+            pu, c2 = ctx.count_per_vertex(h, 0)
+            h.free()
+            totals.add(c2)
+        torch.cuda.synchronize()
+        ms2 = 1e3 * (time.time() - t) / reps
+        sha_ok = digest64(pu) == gold2["per_u_sha256"]
+        out["config2"] = {
+            "workload": "config2: Chung-Lu 100000 x 50000, 2M edges, gamma 2.1/2.1, 80% positive, "
+                        "2-bit packed signs, 200 balanced + 200 random-sign 12x12 blocks, seed 1",
+            "step": "bbc_build_csr (device COO) + bbc_count_per_vertex(U): the global count and "
+                    "every U vertex's count",
+            "ms_per_step": round(ms2, 3),
+            "triplets_per_s": round(gold2["feasible_triplets_u"] / (ms2 / 1e3), 1),
+            "count": sorted(totals)[0] if len(totals) == 1 else sorted(totals),
+            "count_ok": totals == {gold2["total"]}, "per_u_sha256_ok": bool(sha_ok)}
+        e_u = e_v = e_s = None
 
     if not args.no_cpu:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", 0)) or (os.cpu_count() or 1)
         log("cpu baseline: oracle on every", args.cpu_stride, "th anchor,", threads, "threads")
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_stride, threads)
 
     if not args.no_batched or not args.no_serve:
+        gold4 = load_json("cfg4_seed1.json")
         log("generating", args.batch_graphs, "batched graphs")
         gs = G.config4(1, n_graphs=args.batch_graphs)
-        ref, batched = run_batched(ctx, gs, torch)
+        want4 = None
+        if gold4 is not None and len(gs) == gold4["n_graphs"]:
+            want4 = np.array(gold4["counts"], np.int64)
+        ref, batched = run_batched(ctx, gs, torch, want4)
         if not args.no_batched:
             out["batched"] = batched
         if not args.no_serve:
+            gold2 = load_json("cfg2_seed1.json")
+            g2 = G.config2(1)
+            pool_counts = want4 if want4 is not None else ref
             # capacity: 98% batched-mix graphs at the batched rate, 2% config-2
-            # sized graphs at their end-to-end time; offer 70% of it
-            per_req_s = 0.98 / batched["batched_graphs_per_s"] + 0.02 * e2e_ms / 1e3
+            # sized graphs at about 7 ms each end to end; offer 70% of it
+            per_req_s = 0.98 / batched["batched_graphs_per_s"] + 0.02 * 7.5e-3
             qps = 0.7 / per_req_s
-            log("serving", args.serve_requests, "requests at", round(qps, 1), "qps")
-            out["served"] = run_served(ctx, gs, ref, [g], [gold["total"]], args.serve_requests,
-                                       qps, 1)
+            log("serving", args.serve_requests, "requests at", round(qps, 1), "qps under a",
+                SERVE_CAP >> 30, "GiB cap")
+            sctx = bbc.Context(0, mem_cap=SERVE_CAP)
+            out["served"] = run_served(sctx, gs, pool_counts, [g2], [gold2["total"]],
+                                       args.serve_requests, qps, 1)
+            sctx.close()
     ctx.close()
     print(json.dumps(out))
 

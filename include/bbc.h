@@ -98,6 +98,8 @@ bbc_status bbc_build_csr_batch(bbc_ctx *ctx, uint32_t n_graphs, const uint32_t *
                                const uint32_t *eu, const uint32_t *ev, const void *sign,
                                uint32_t flags, bbc_graph **out_graphs);
 
+/* Frees one graph handle (its device memory is released with the last
+ * handle of its build). BBC_E_INVAL if g is not a live graph of ctx. */
 bbc_status bbc_graph_free(bbc_ctx *ctx, bbc_graph *g);
 
 typedef struct {
@@ -215,6 +217,24 @@ typedef struct {
                                    partners all rank within 2^17 above them) */
 } bbc_count_stats;
 bbc_status bbc_get_last_stats(bbc_ctx *ctx, bbc_count_stats *out);
+/* Device memory of the context (for operators of the serving loop). The
+ * allocator keeps freed blocks for reuse: reserved = live + cached; cached
+ * blocks are released when an allocation would pass the cap. Served batches
+ * are admitted while their reservation (builds plus one count workspace)
+ * fits under the cap next to the live memory of the caller's own graphs and
+ * workspaces and the reservations of the batches in flight. */
+typedef struct {
+    uint64_t cap_bytes;                 /* the context's cap (0 = none) */
+    uint64_t reserved_bytes;            /* device memory the context holds */
+    uint64_t peak_reserved_bytes;       /* its largest value so far */
+    uint64_t live_bytes;                /* held by graphs and workspaces in use */
+    uint64_t serve_admitted_bytes;      /* reservations of the served batches in flight */
+    uint64_t serve_peak_admitted_bytes; /* their largest sum so far */
+    uint64_t serve_queued;              /* requests waiting for admission */
+    uint64_t serve_peak_queued;         /* the longest the queue has been */
+} bbc_memory_stats;
+bbc_status bbc_get_memory_stats(bbc_ctx *ctx, bbc_memory_stats *out);
+
 /* Enable (1) or disable (0) per-phase event timing on this context. */
 bbc_status bbc_set_timing(bbc_ctx *ctx, int enable);
 

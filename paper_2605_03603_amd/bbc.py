@@ -37,8 +37,8 @@ EXPORTED = ["bbc_ctx_create", "bbc_ctx_destroy", "bbc_build_csr", "bbc_build_csr
             "bbc_graph_free", "bbc_get_graph_info", "bbc_count_global", "bbc_count_per_vertex",
             "bbc_count_through_edges", "bbc_top_vertices", "bbc_count_bbwc",
             "bbc_count_batch", "bbc_submit", "bbc_submit_coo", "bbc_poll", "bbc_wait",
-            "bbc_get_last_stats", "bbc_set_timing", "bbc_set_test_hook", "bbc_status_string",
-            "bbc_last_error"]
+            "bbc_get_last_stats", "bbc_set_timing", "bbc_set_test_hook", "bbc_get_memory_stats",
+            "bbc_status_string", "bbc_last_error"]
 
 BBC_HOOK_NO_WINDOW_TIER = 1
 BBC_HOOK_PRELOAD_COUNT = 2
@@ -66,6 +66,12 @@ class CountStats(ctypes.Structure):
                 ("deferred_b", ctypes.c_uint32), ("deferred_c", ctypes.c_uint32),
                 ("deferred_d", ctypes.c_uint32), ("deferred_a", ctypes.c_uint32),
                 ("deferred_r", ctypes.c_uint32)]
+
+
+class MemoryStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "cap_bytes", "reserved_bytes", "peak_reserved_bytes", "live_bytes", "serve_admitted_bytes",
+        "serve_peak_admitted_bytes", "serve_queued", "serve_peak_queued")]
 
 
 _vp = ctypes.c_void_p
@@ -111,6 +117,7 @@ def _load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.bbc_get_last_stats.argtypes = [_vp, ctypes.POINTER(CountStats)]
     L.bbc_set_timing.argtypes = [_vp, _i32]
     L.bbc_set_test_hook.argtypes = [_vp, _i32, ctypes.c_int64]
+    L.bbc_get_memory_stats.argtypes = [_vp, ctypes.POINTER(MemoryStats)]
     for name in EXPORTED:
         fn = getattr(L, name)
         if name not in ("bbc_status_string", "bbc_last_error", "bbc_ctx_destroy"):
@@ -284,6 +291,11 @@ class Context:
 
     def set_timing(self, enable: bool = True):
         self._check(lib.bbc_set_timing(self.handle, 1 if enable else 0))
+
+    def memory_stats(self) -> dict:
+        m = MemoryStats()
+        self._check(lib.bbc_get_memory_stats(self.handle, ctypes.byref(m)))
+        return {k: int(getattr(m, k)) for k, _ in MemoryStats._fields_}
 
     def set_test_hook(self, hook: int, value: int):
         """Host-forced test conditions (BBC_HOOK_*); value 0 resets."""

@@ -47,6 +47,8 @@ hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t
 uint32_t wave_tier_blocks_per_cu();
 uint32_t wave_tier_waves_per_cu();
 uint32_t tier_c_max_degree();
+// widest partner window (ranks above the anchor) of the rank-window tier
+uint32_t window_tier_max_window();
 uint32_t tier_c_max_k();
 uint32_t max_unit_chunk();
 

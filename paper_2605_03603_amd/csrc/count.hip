@@ -818,8 +818,9 @@ __global__ void __launch_bounds__(THREADS) k_pair_big(PairArgs P)
     m.region = region; m.H = H; m.log2h = ilog2(H);
     m.HC = HC; m.log2hc = ilog2(HC); m.maskw = 2 * H - 2 * HC;
     m.pst = P.ws.bscr + (uint64_t)blockIdx.x * P.ws.bscr_words_per_block;
-    m.pln = m.pst + P.gmaxd;
-    m.maxd = P.gmaxd; m.vc = vc; m.kmax = KMAX;
+    m.pln = m.pst + P.ws.bscr_words_per_block / 2;
+    m.maxd = min(P.gmaxd, (uint32_t)(P.ws.bscr_words_per_block / 2));
+    m.vc = vc; m.kmax = KMAX;
     pair_loop<THREADS, PACKED>(P, m, sh);
 }
 
@@ -915,8 +916,8 @@ __global__ void __launch_bounds__(kRThreads) k_pair_window(PairArgs P)
     const uint32_t *list = P.ws.defer[P.tier - 1];
     PairMem m{};
     m.pst = P.ws.bscr + (uint64_t)blockIdx.x * P.ws.bscr_words_per_block;
-    m.pln = m.pst + P.gmaxd;
-    m.maxd = P.gmaxd;
+    m.pln = m.pst + P.ws.bscr_words_per_block / 2;
+    m.maxd = min(P.gmaxd, (uint32_t)(P.ws.bscr_words_per_block / 2));
     if (tid == 0) {
         sh.qlo = sh.qhi = 0; sh.qslice = blockIdx.x % kXcd; sh.qtried = 0;
         sh.moff = sh.mres_end = 0; sh.coff = sh.cres_end = 0;
@@ -1029,8 +1030,8 @@ __global__ void __launch_bounds__(kRThreads) k_pair_window(PairArgs P)
         const uint32_t K0 = s_k0, k = s_k0 + s_k1;
         if (k < 2) continue;
         const uint32_t W = (d + 31) >> 5;
-        const uint32_t stage_cap = kRWords - 4 * nbw;
-        if (k > P.gkmax || stage_cap < k) {
+        const uint32_t stage_cap = kRWords - 4 * nbw;   // >= kRWords - kRWin / 8 > 0
+        if (k > P.gkmax) {
             if (tid == 0) to_global(r);
             continue;
         }
@@ -1107,49 +1108,53 @@ __global__ void __launch_bounds__(kRThreads) k_pair_window(PairArgs P)
         }
         // phase 3: bit p of the candidate's mask for every wedge through
         // position p, staged in slabs of whole mask words (a slab walks only
-        // the positions of its words)
-        const uint32_t sw = min(W, stage_cap / k);
-        for (uint32_t w0 = 0; w0 < W; w0 += sw) {
-            const uint32_t nw = min(sw, W - w0);
-            const uint32_t slab = k * nw;
-            for (uint32_t i = tid; i < slab; i += THREADS) stage[i] = 0;
-            __syncthreads();
-            walk_positions<THREADS>(g, m, d, kEmpty, kEmpty, true, false,
-                                    [&](const uint32_t (&e2)[kUnroll], const uint32_t (&pp)[kUnroll],
-                                        const uint32_t (&sg)[kUnroll]) {
-                                        uint32_t bmv[kUnroll], pre[kUnroll];
+        // the positions of its words); when k words do not fit the staging
+        // area, the candidates are taken in ranges and the words walked again
+        // per range
+        const uint32_t cr = min(k, stage_cap);
+        const uint32_t sw = min(W, stage_cap / cr);
+        for (uint32_t c0 = 0; c0 < k; c0 += cr) {
+            const uint32_t nc = min(cr, k - c0);
+            for (uint32_t w0 = 0; w0 < W; w0 += sw) {
+                const uint32_t nw = min(sw, W - w0);
+                const uint32_t slab = nc * nw;
+                for (uint32_t i = tid; i < slab; i += THREADS) stage[i] = 0;
+                __syncthreads();
+                walk_positions<THREADS>(
+                    g, m, d, kEmpty, kEmpty, true, false,
+                    [&](const uint32_t (&e2)[kUnroll], const uint32_t (&pp)[kUnroll],
+                        const uint32_t (&sg)[kUnroll]) {
+                        uint32_t bmv[kUnroll], pre[kUnroll];
 #pragma unroll
-                                        for (int u = 0; u < kUnroll; u++) {
-                                            const uint32_t idx = (e2[u] >> 1) - r - 1;
-                                            const uint32_t cls = (e2[u] & 1u) ^ sg[u];
-                                            const uint32_t j = e2[u] == kEmpty ? 0u : idx >> 5;
-                                            bmv[u] = lds[cls * nbw + j];
-                                            pre[u] = lds[(2 + cls) * nbw + j];
-                                        }
+                        for (int u = 0; u < kUnroll; u++) {
+                            const uint32_t idx = (e2[u] >> 1) - r - 1;
+                            const uint32_t cls = (e2[u] & 1u) ^ sg[u];
+                            const uint32_t j = e2[u] == kEmpty ? 0u : idx >> 5;
+                            bmv[u] = lds[cls * nbw + j];
+                            pre[u] = lds[(2 + cls) * nbw + j];
+                        }
 #pragma unroll
-                                        for (int u = 0; u < kUnroll; u++) {
-                                            if (e2[u] == kEmpty) continue;
-                                            const uint32_t idx = (e2[u] >> 1) - r - 1;
-                                            const uint32_t b = idx & 31;
-                                            if (!((bmv[u] >> b) & 1u)) continue;
-                                            const uint32_t cls = (e2[u] & 1u) ^ sg[u];
-                                            const uint32_t ci = (cls ? K0 : 0u) + pre[u] +
-                                                                __popc(bmv[u] & ((1u << b) - 1u));
-                                            const uint32_t p = pp[u];
-                                            atomicOr(&stage[ci * nw + (p >> 5) - w0], 1u << (p & 31));
-                                        }
-                                    },
-                                    32 * w0, 32 * (w0 + nw));
-            __syncthreads();
-            if (nw == W) {
-                for (uint32_t i = tid; i < slab; i += THREADS) P.ws.masks[moff + i] = stage[i];
-            } else {
+                        for (int u = 0; u < kUnroll; u++) {
+                            if (e2[u] == kEmpty) continue;
+                            const uint32_t idx = (e2[u] >> 1) - r - 1;
+                            const uint32_t b = idx & 31;
+                            if (!((bmv[u] >> b) & 1u)) continue;
+                            const uint32_t cls = (e2[u] & 1u) ^ sg[u];
+                            const uint32_t ci = (cls ? K0 : 0u) + pre[u] +
+                                                __popc(bmv[u] & ((1u << b) - 1u)) - c0;
+                            if (ci >= nc) continue;
+                            const uint32_t p = pp[u];
+                            atomicOr(&stage[ci * nw + (p >> 5) - w0], 1u << (p & 31));
+                        }
+                    },
+                    32 * w0, 32 * (w0 + nw));
+                __syncthreads();
                 for (uint32_t i = tid; i < slab; i += THREADS) {
                     const uint32_t c = i / nw;
-                    P.ws.masks[moff + (uint64_t)c * W + w0 + (i - c * nw)] = stage[i];
+                    P.ws.masks[moff + (uint64_t)(c0 + c) * W + w0 + (i - c * nw)] = stage[i];
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
         if (tid == 0) {
             AnchorRec a;
@@ -2679,6 +2684,7 @@ uint32_t wave_tier_blocks_per_cu()
 uint32_t wave_tier_waves_per_cu() { return wave_tier_blocks_per_cu() * kWvWaves; }
 
 uint32_t tier_c_max_degree() { return 65535; }
+uint32_t window_tier_max_window() { return kRWin; }
 uint32_t tier_c_max_k() { return 65535; }
 uint32_t max_unit_chunk() { return kMaxChunk; }
 

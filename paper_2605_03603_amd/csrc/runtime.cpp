@@ -21,6 +21,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "bbc.h"
@@ -69,6 +70,12 @@ int bit_width(uint64_t x)
 uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 // ------------------------------------------------------------- allocator
+// Allocations are tagged by the thread that makes them: the serving workers
+// tag theirs 1, everything else is 0. The serving admission charges live
+// tag-0 memory (graphs and workspaces of the caller's own calls) against the
+// cap and reserves the rest per admitted batch.
+thread_local int tl_alloc_tag = 0;
+
 class Allocator {
   public:
     Allocator(uint64_t cap) : cap_(cap) {}
@@ -78,11 +85,13 @@ class Allocator {
     {
         if (bytes == 0) bytes = 256;
         bytes = round_up(bytes, 256);
+        const int tag = tl_alloc_tag;
         std::lock_guard<std::mutex> lk(mu_);
         auto it = free_.lower_bound(bytes);
         if (it != free_.end() && it->first <= bytes * 2 + (4u << 20)) {
             void *p = it->second;
-            live_[p] = it->first;
+            live_[p] = Live{it->first, tag};
+            live_tag_[tag] += it->first;
             free_.erase(it);
             return p;
         }
@@ -105,7 +114,9 @@ class Allocator {
             }
         }
         used_ += sz;
-        live_[p] = sz;
+        peak_ = std::max(peak_, used_);
+        live_[p] = Live{sz, tag};
+        live_tag_[tag] += sz;
         return p;
     }
 
@@ -115,18 +126,26 @@ class Allocator {
         std::lock_guard<std::mutex> lk(mu_);
         auto it = live_.find(p);
         if (it == live_.end()) return;
-        free_.emplace(it->second, p);
+        free_.emplace(it->second.bytes, p);
+        live_tag_[it->second.tag] -= it->second.bytes;
         live_.erase(it);
     }
 
-    uint64_t used() const { return used_; }
-    uint64_t cap() const { return cap_; }
-    uint64_t live_bytes()
+    uint64_t used()
     {
         std::lock_guard<std::mutex> lk(mu_);
-        uint64_t s = 0;
-        for (auto &kv : live_) s += kv.second;
-        return s;
+        return used_;
+    }
+    uint64_t cap() const { return cap_; }
+    uint64_t peak()
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        return peak_;
+    }
+    uint64_t live(int tag)
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        return live_tag_[tag & 1];
     }
 
     void release_all()
@@ -136,6 +155,7 @@ class Allocator {
     }
 
   private:
+    struct Live { uint64_t bytes; int tag; };
     void trim_locked()
     {
         for (auto &kv : free_) {
@@ -145,9 +165,10 @@ class Allocator {
         free_.clear();
     }
     std::mutex mu_;
-    uint64_t cap_, used_ = 0;
+    uint64_t cap_, used_ = 0, peak_ = 0;
+    uint64_t live_tag_[2] = {0, 0};
     std::multimap<uint64_t, void *> free_;
-    std::unordered_map<void *, uint64_t> live_;
+    std::unordered_map<void *, Live> live_;
 };
 
 // A device buffer that returns its memory to the allocator.
@@ -161,7 +182,15 @@ struct DBuf {
     ~DBuf() { reset(); }
     void reset()
     {
-        if (p && al) al->free(p);
+        if (p && al) {
+            // A buffer released while an exception unwinds the stack may still
+            // be read or written by copies and kernels enqueued before the
+            // failure (the builder allocates between enqueues): wait for the
+            // device before the allocator can hand the memory to another
+            // stream or free it.
+            if (std::uncaught_exceptions() > 0) (void)hipDeviceSynchronize();
+            al->free(p);
+        }
         p = nullptr;
         bytes = 0;
     }
@@ -181,7 +210,13 @@ struct DBuf {
 struct HBuf {
     void *p = nullptr;
     uint64_t bytes = 0;
-    ~HBuf() { if (p) (void)hipHostFree(p); }
+    ~HBuf()
+    {
+        if (!p) return;
+        // as for DBuf: an in-flight copy may still read this staging memory
+        if (std::uncaught_exceptions() > 0) (void)hipDeviceSynchronize();
+        (void)hipHostFree(p);
+    }
     void ensure(uint64_t n)
     {
         if (p && bytes >= n) return;
@@ -260,6 +295,23 @@ struct Work {
     {
         if (exec) (void)hipGraphExecDestroy(exec);
     }
+    // Return every device buffer to the allocator (the pinned host buffers
+    // stay); the next count sizes the workspace again.
+    void release_device()
+    {
+        for (DBuf *b : {&ctr, &anchors, &units, &masks, &cands, &defer0, &defer1, &defer2, &defer3,
+                        &defer4, &gtab, &dtab, &bscr, &count, &carry, &pv, &pv_o, &pv_slot, &ucnt,
+                        &uoff, &ptmp})
+            b->reset();
+        cap_anchors = cap_units = cap_masks = cap_cands = cap_defer = 0;
+        gtab_blocks = dtab_blocks = bscr_blocks = 0;
+        gtab_words = dtab_words = bscr_words = ptmp_bytes = 0;
+        gH = dH = 0;
+        glog2 = dlog2 = 0;
+        gmaxd = gkmax = 0;
+        if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
+        exec_args.clear();
+    }
 };
 
 struct Shape {
@@ -279,7 +331,10 @@ struct Request {
     std::vector<uint32_t> eu, ev;
     std::vector<uint8_t> sign;
     uint64_t m = 0;
-    uint64_t footprint = 0;
+    uint32_t max_deg = 0;     // largest vertex degree (COO requests: counted at submission)
+    uint64_t w2_max = 0;      // oriented wedges of the costlier anchor side
+    uint32_t n_s_max = 0;     // larger side
+    int nomem_retries = 0;    // requeued after running out of memory behind other batches
     bool done = false;
     bbc_status status = BBC_OK;
     int64_t result = 0;
@@ -316,7 +371,12 @@ struct bbc_ctx {
     std::deque<std::shared_ptr<Request>> queue;
     std::unordered_map<bbc_ticket, std::shared_ptr<Request>> requests;
     uint64_t next_ticket = 1;
-    uint64_t admitted_bytes = 0;
+    uint64_t admitted_bytes = 0;    // reservations of the batches in flight
+    uint64_t peak_admitted = 0;
+    uint64_t peak_queued = 0;
+    // graph handles the caller holds (released by bbc_graph_free or on destroy)
+    std::mutex g_mu;
+    std::unordered_set<bbc_graph *> graphs;
     bool stopping = false;
     std::vector<std::thread> workers;
     std::vector<hipStream_t> serve_streams;
@@ -380,11 +440,15 @@ void check_flags(uint32_t flags)
 // Anchor side of one graph. Work of the pair table anchored on S is about the
 // number of 2-hop wedges through O, sum_o C(d_o, 2); work of the triplet
 // phase grows with the mask width, about the edge-weighted mean degree of S.
-// Estimated cost ratio of the two sides (larger / smaller) goes to *ratio.
+// The ratio of the two sides' wedge counts (larger / smaller) goes to
+// *wedge_ratio.
 uint32_t choose_side(uint32_t flags, uint32_t n_u, uint32_t n_v, uint64_t m, uint64_t c2_u,
-                     uint64_t c2_v, uint64_t d2_u, uint64_t d2_v, double *ratio = nullptr)
+                     uint64_t c2_v, uint64_t d2_u, uint64_t d2_v, double *wedge_ratio = nullptr)
 {
-    if (ratio) *ratio = 1.0;
+    if (wedge_ratio) {
+        const double lo = (double)std::min(c2_u, c2_v), hi = (double)std::max(c2_u, c2_v);
+        *wedge_ratio = lo > 0 ? hi / lo : 1e30;
+    }
     if (flags & BBC_ANCHOR_U) return 0;
     if (flags & BBC_ANCHOR_V) return 1;
     if (flags & BBC_ANCHOR_SMALLER) return n_v < n_u ? 1 : 0;
@@ -392,18 +456,14 @@ uint32_t choose_side(uint32_t flags, uint32_t n_u, uint32_t n_v, uint64_t m, uin
     double wu = (double)d2_u / (double)m, wv = (double)d2_v / (double)m;
     double cost_u = (double)c2_v * (1.0 + wu / 32.0);   // anchored on U: wedges centred in V
     double cost_v = (double)c2_u * (1.0 + wv / 32.0);
-    if (ratio) {
-        const double lo = std::min(cost_u, cost_v), hi = std::max(cost_u, cost_v);
-        *ratio = lo > 0 ? hi / lo : 1e30;
-    }
     return cost_v < cost_u ? 1 : 0;
 }
 
 constexpr uint64_t kSideTuneMinEdges = 1u << 18;
-// Only shapes whose two side estimates are within this factor are timed on
-// both sides: beyond it the estimate has always picked the faster side (a
-// 2M x 500k graph with estimates 3.9x apart counts 12x slower on the other
-// side, so timing it once would cost more than the estimate ever loses).
+// Only shapes whose two sides' wedge counts (the pair-phase work) are within
+// this factor are timed on both sides; beyond it the estimate's side is kept
+// (a 2M x 500k power-law graph with 2.3x the wedges on one side counts 16x
+// slower there: timing it once would cost more than the estimate can lose).
 constexpr double kSideTuneMaxRatio = 2.0;
 // vertex slots (|U| + |V| over the set) up to which the ingest counts degrees
 // in per-XCD copies (8 words per slot)
@@ -649,10 +709,18 @@ uint64_t hint_key(const GraphSet &set)
            ((uint64_t)bit_width(set.M) << 24) | ((uint64_t)std::min(set.G, 0xffffu) << 2) | side;
 }
 
+// The first workspace guess of a single graph from its oriented wedges W2
+// (ensure_work): mask words, candidates and units.
+uint64_t work_bytes_from_wedges(uint64_t w2)
+{
+    return 4 * (w2 / 20 * 9 + w2 / 10) + sizeof(Unit) * (w2 / 40);
+}
+
 void ensure_work(bbc_ctx *ctx, Work &w, GraphSet &set)
 {
     Allocator *al = ctx->al.get();
     uint64_t M = std::max<uint64_t>(set.M, 1);
+    uint64_t hint_masks, hint_cands, hint_units;
     {
         std::lock_guard<std::mutex> lk(ctx->tune_mu);
         auto it = ctx->ws_hint.find(hint_key(set));
@@ -661,16 +729,17 @@ void ensure_work(bbc_ctx *ctx, Work &w, GraphSet &set)
             set.hint_cands = std::max(set.hint_cands, it->second.cands);
             set.hint_units = std::max(set.hint_units, it->second.units);
         }
+        hint_masks = set.hint_masks; hint_cands = set.hint_cands; hint_units = set.hint_units;
     }
     // records are reserved 16 at a time per wave of the per-wave tier and per
     // workgroup of the others
     const uint64_t agents = (uint64_t)ctx->num_cus * (wave_tier_waves_per_cu() + 8) + 64;
     uint64_t want_anchors = std::max<uint64_t>(set.NS, 1) + 16ull * agents;
     // first guesses; an overflowing count records its exact demand and reruns once
-    uint64_t want_masks = std::max<uint64_t>({set.hint_masks, 2 * M, 1ull << 22});
-    uint64_t want_cands = std::max<uint64_t>({set.hint_cands, M / 2, 1ull << 20});
-    uint64_t want_units = std::max<uint64_t>({set.hint_units, M / 16, 1ull << 16});
-    if (set.G == 1 && set.hint_masks == 0 && set.wedges_o > 0) {
+    uint64_t want_masks = std::max<uint64_t>({hint_masks, 2 * M, 1ull << 22});
+    uint64_t want_cands = std::max<uint64_t>({hint_cands, M / 2, 1ull << 20});
+    uint64_t want_units = std::max<uint64_t>({hint_units, M / 16, 1ull << 16});
+    if (set.G == 1 && hint_masks == 0 && set.wedges_o > 0) {
         // no count of this shape yet: the Chung-Lu workloads need 0.23 W2
         // (100k x 50k) to 0.42 W2 (2M x 500k, wider masks) mask words, under
         // 0.07 W2 candidates and under W2 / 60 units (W2 = the oriented
@@ -679,7 +748,7 @@ void ensure_work(bbc_ctx *ctx, Work &w, GraphSet &set)
         // context's cap
         const uint64_t W2 = set.wedges_o;
         const uint64_t gm = W2 / 20 * 9, gc = W2 / 10, gu = W2 / 40;
-        const uint64_t bytes = 4 * (gm + gc) + sizeof(Unit) * gu;
+        const uint64_t bytes = work_bytes_from_wedges(W2);
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
             (void)hipGetLastError();
@@ -693,7 +762,13 @@ void ensure_work(bbc_ctx *ctx, Work &w, GraphSet &set)
             want_units = std::max(want_units, gu);
         }
     }
+    // A capacity is cleared before its buffers are (re)allocated and set only
+    // once all of them are: DBuf::ensure releases the old buffer first, so an
+    // allocation that fails (BBC_E_NOMEM under the context's cap) must not
+    // leave a capacity that a later count on this workspace would trust with
+    // a null buffer.
     if (w.cap_anchors < want_anchors) {
+        w.cap_anchors = 0;
         w.anchors.ensure(al, want_anchors * sizeof(AnchorRec));
         w.ucnt.ensure(al, 3 * want_anchors * 4);
         w.uoff.ensure(al, (3 * want_anchors + 1) * 8);
@@ -703,10 +778,23 @@ void ensure_work(bbc_ctx *ctx, Work &w, GraphSet &set)
     }
     // 64 words of slack past the capacity: scalar column loads of the last
     // mask may be issued for a full 16-word group
-    if (w.cap_masks < want_masks) { w.masks.ensure(al, (want_masks + 64) * 4); w.cap_masks = want_masks; }
-    if (w.cap_cands < want_cands) { w.cands.ensure(al, want_cands * 4); w.cap_cands = want_cands; }
-    if (w.cap_units < want_units) { w.units.ensure(al, want_units * sizeof(Unit)); w.cap_units = want_units; }
+    if (w.cap_masks < want_masks) {
+        w.cap_masks = 0;
+        w.masks.ensure(al, (want_masks + 64) * 4);
+        w.cap_masks = want_masks;
+    }
+    if (w.cap_cands < want_cands) {
+        w.cap_cands = 0;
+        w.cands.ensure(al, want_cands * 4);
+        w.cap_cands = want_cands;
+    }
+    if (w.cap_units < want_units) {
+        w.cap_units = 0;
+        w.units.ensure(al, want_units * sizeof(Unit));
+        w.cap_units = want_units;
+    }
     if (w.cap_defer < set.NS + 1ull) {
+        w.cap_defer = 0;
         w.defer0.ensure(al, (set.NS + 1ull) * 4); w.defer1.ensure(al, (set.NS + 1ull) * 4);
         w.defer2.ensure(al, (set.NS + 1ull) * 4); w.defer3.ensure(al, (set.NS + 1ull) * 4);
         w.defer4.ensure(al, (set.NS + 1ull) * 4);
@@ -717,40 +805,72 @@ void ensure_work(bbc_ctx *ctx, Work &w, GraphSet &set)
     w.carry.ensure(al, std::max<uint32_t>(set.G, 1) * 4);
     w.host.ensure(sizeof(Counters) + 12ull * std::max<uint32_t>(set.G, 1) + 64);
     const uint32_t maxd = tier_c_max_degree(), kmax = tier_c_max_k();
-    // tier B: per-block position lists in global memory
-    if (!w.bscr.p || w.bscr_blocks < (uint32_t)ctx->num_cus) {
-        w.bscr_words = 2ull * (maxd + 1);
+    // tier B and the rank-window tier: per-block position lists in global
+    // memory, sized for the set's largest degree
+    const uint64_t bwords = 2ull * (std::min(set.max_deg, maxd) + 1ull);
+    if (!w.bscr.p || w.bscr_blocks < (uint32_t)ctx->num_cus || w.bscr_words < bwords) {
+        w.bscr_blocks = 0;
+        w.bscr.ensure(al, bwords * 4 * ctx->num_cus);
+        w.bscr_words = bwords;
         w.bscr_blocks = ctx->num_cus;
-        w.bscr.ensure(al, w.bscr_words * 4 * w.bscr_blocks);
     }
     // tiers C and D: hash tables in global memory. C: up to 2^20 slots on
     // one block per CU; D: sized for the largest anchor side of any graph
     // (every partner fits), on a few blocks. At least 2^18 slots: the compact
-    // table of up to 65535 candidate classes takes half of the region.
+    // table of up to 65535 candidate classes takes half of the region. Only
+    // anchors whose partner window is wider than the rank-window tier's, or
+    // anchors no tier supports, reach them: while every graph's anchor side
+    // is narrower than that window they get one block each.
     uint32_t max_ns = 0;
     for (auto &d : set.desc) max_ns = std::max(max_ns, d.n_s);
+    const bool wide = max_ns > window_tier_max_window() + 1u;
     uint32_t HD = 1u << 18;
     int lgd = 18;
     while (HD < 2ull * max_ns + 64 && lgd < 25) { HD <<= 1; lgd++; }
     const uint32_t HC = std::min(HD, 1u << 20);
     const int lgc = std::min(lgd, 20);
-    if (!w.gtab.p || w.gH < HC) {
+    const uint64_t cwords = (2ull * HC + 2ull * maxd + kmax + 64 + 3) & ~3ull;
+    const uint32_t cblocks = wide ? (uint32_t)std::max<uint64_t>(
+                                        1, std::min<uint64_t>(ctx->num_cus, (2ull << 30) / (cwords * 4)))
+                                  : 1u;
+    if (!w.gtab.p || w.gH < HC || w.gtab_blocks < cblocks) {
         // per-block regions start 16-byte aligned (the table is read 4 slots at a time)
-        uint64_t words = (2ull * HC + 2ull * maxd + kmax + 64 + 3) & ~3ull;
-        uint32_t blocks = (uint32_t)std::max<uint64_t>(
-            1, std::min<uint64_t>(ctx->num_cus, (2ull << 30) / (words * 4)));
-        w.gtab.ensure(al, words * 4 * blocks);
+        w.gtab_blocks = 0;
+        w.gtab.ensure(al, cwords * 4 * cblocks);
         w.gH = HC; w.glog2 = lgc; w.gmaxd = maxd; w.gkmax = kmax;
-        w.gtab_words = words; w.gtab_blocks = blocks;
+        w.gtab_words = cwords; w.gtab_blocks = cblocks;
     }
-    if (!w.dtab.p || w.dH < HD) {
-        uint64_t words = (2ull * HD + 2ull * maxd + kmax + 64 + 3) & ~3ull;
-        uint32_t blocks = (uint32_t)std::max<uint64_t>(
-            1, std::min<uint64_t>(16, (1ull << 30) / (words * 4)));
-        w.dtab.ensure(al, words * 4 * blocks);
+    const uint64_t dwords = (2ull * HD + 2ull * maxd + kmax + 64 + 3) & ~3ull;
+    const uint32_t dblocks = wide ? (uint32_t)std::max<uint64_t>(
+                                        1, std::min<uint64_t>(16, (1ull << 30) / (dwords * 4)))
+                                  : 1u;
+    if (!w.dtab.p || w.dH < HD || w.dtab_blocks < dblocks) {
+        w.dtab_blocks = 0;
+        w.dtab.ensure(al, dwords * 4 * dblocks);
         w.dH = HD; w.dlog2 = lgd;
-        w.dtab_words = words; w.dtab_blocks = blocks;
+        w.dtab_words = dwords; w.dtab_blocks = dblocks;
     }
+}
+
+// Device bytes a count of a set of m edges and n_s anchor-side vertices
+// (either side: the larger of the two is taken) may hold in its workspace on
+// the first attempt: the first guesses of ensure_work, with the global-memory
+// tiers at one block and tier B's lists for degrees up to max_deg.
+uint64_t work_bytes_estimate(uint64_t m, uint64_t n_s, uint32_t max_deg, int num_cus)
+{
+    const uint64_t M = std::max<uint64_t>(m, 1);
+    const uint64_t agents = (uint64_t)num_cus * (wave_tier_waves_per_cu() + 8) + 64;
+    const uint64_t anchors = n_s + 16 * agents;
+    uint64_t b = 0;
+    b += anchors * (sizeof(AnchorRec) + 12 + 24) + scan_tmp_bytes(3 * anchors + 1);
+    b += (std::max<uint64_t>(2 * M, 1ull << 22) + 64) * 4;                 // masks
+    b += std::max<uint64_t>(M / 2, 1ull << 20) * 4;                        // candidates
+    b += std::max<uint64_t>(M / 16, 1ull << 16) * sizeof(Unit);            // units
+    b += 5 * (n_s + 1) * 4;                                                // tier lists
+    b += 2ull * (std::min(max_deg, tier_c_max_degree()) + 1) * 4 * num_cus;  // tier B lists
+    const uint64_t tier_words = 2ull * (1u << 18) + 3ull * 65536 + 64;
+    b += 2 * tier_words * 4;                                               // tiers C, D
+    return b + (4u << 20);
 }
 
 Workspace ws_view(Work &w, bool pv, bool pvo)
@@ -875,24 +995,35 @@ bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set)
         fail(BBC_E_UNSUPPORTED, "an anchor has degree above %u or more than %u candidate classes",
              tier_c_max_degree(), tier_c_max_k());
     // demand plus room for the reservation chunks of the per-wave tier (4096
-    // words) and of the workgroup tiers
+    // words) and of the workgroup tiers. A set may be counted by several
+    // threads at once (serving workers and the caller): its hints are updated
+    // under the tuning lock.
+    // The slack covers chunks that other workgroups may hold next time; it
+    // is at most the demand itself, so that a small set's hint stays small
+    // (a fixed slack would be 268 MB of mask words on 256 CUs).
     const uint64_t wv = (uint64_t)ctx->num_cus * wave_tier_waves_per_cu();
-    const uint64_t slack_m = 4ull * ctx->num_cus * (1u << 16) + wv * 4096;
-    const uint64_t slack_c = 4ull * ctx->num_cus * (1u << 13) + wv * 4096;
-    set.hint_masks = std::max<uint64_t>(set.hint_masks, c->need_masks + c->need_masks / 16 + slack_m);
-    set.hint_cands = std::max<uint64_t>(set.hint_cands, c->need_cands + c->need_cands / 16 + slack_c);
-    if (c->over_cap & 3u) {
-        set.hint_units = std::max<uint64_t>(set.hint_units, c->need_units + c->need_units / 16 + 1024);
-        return false;
-    }
-    set.hint_units = std::max<uint64_t>(set.hint_units, (uint64_t)c->n_units + c->n_units / 8);
+    const uint64_t slack_m = std::min<uint64_t>(4ull * ctx->num_cus * (1u << 16) + wv * 4096,
+                                                std::max<uint64_t>(c->need_masks, 1u << 16));
+    const uint64_t slack_c = std::min<uint64_t>(4ull * ctx->num_cus * (1u << 13) + wv * 4096,
+                                                std::max<uint64_t>(c->need_cands, 1u << 13));
+    const bool grow = (c->over_cap & 3u) != 0;
     {
         std::lock_guard<std::mutex> lk(ctx->tune_mu);
-        auto &h = ctx->ws_hint[hint_key(set)];
-        h.masks = std::max(h.masks, set.hint_masks);
-        h.cands = std::max(h.cands, set.hint_cands);
-        h.units = std::max(h.units, set.hint_units);
+        set.hint_masks = std::max<uint64_t>(set.hint_masks, c->need_masks + c->need_masks / 16 + slack_m);
+        set.hint_cands = std::max<uint64_t>(set.hint_cands, c->need_cands + c->need_cands / 16 + slack_c);
+        if (grow) {
+            set.hint_units = std::max<uint64_t>(set.hint_units, c->need_units + c->need_units / 16 + 1024);
+        } else {
+            set.hint_units = std::max<uint64_t>(set.hint_units, (uint64_t)c->n_units + c->n_units / 8);
+            auto &h = ctx->ws_hint[hint_key(set)];
+            h.masks = std::max(h.masks, set.hint_masks);
+            h.cands = std::max(h.cands, set.hint_cands);
+            h.units = std::max(h.units, set.hint_units);
+        }
     }
+    if (grow) return false;
+    // the statistics describe the last count on the context's own workspace
+    if (&w != &ctx->work) return true;
     ctx->stats.active_anchors = c->n_anchor;
     ctx->stats.virtual_candidates = c->cand_cursor;
     ctx->stats.pair_units = c->n_units;
@@ -1059,55 +1190,126 @@ constexpr int kServeStreams = 4;
 constexpr size_t kServeBatchMax = 4096;
 constexpr uint64_t kServeBatchEdges = 8ull << 20;    // bounds one batch (and the wait of its small requests)
 
-uint64_t footprint_estimate(uint64_t m, uint64_t nu, uint64_t nv)
+// Device bytes the build of a COO request of m edges and n vertices may hold
+// at its peak: the uploaded COO, the sort buffers and the CSR it produces
+// (the workspace of its count is reserved separately).
+uint64_t build_bytes_estimate(uint64_t m, uint64_t n)
 {
-    return 96ull * m + 48ull * (nu + nv) + (4ull << 20);
+    const uint64_t M = std::max<uint64_t>(m, 1), nkv = std::max<uint64_t>(M, n);
+    return 40 * M + 24 * nkv + 128 * n + radix_tmp_bytes(nkv) + (2u << 20);
 }
+
+// What a batch of requests reserves under the context's cap: the builds of
+// its COO requests and one count workspace sized for all of them together.
+struct Reservation {
+    uint64_t build = 0, m = 0, n_s = 0, w2 = 0, n = 0;
+    uint32_t max_deg = 0;
+    void add(const Request &r)
+    {
+        if (!r.set) build += build_bytes_estimate(r.m, (uint64_t)r.n_u + r.n_v);
+        m = r.set ? std::max(m, r.m) : m + r.m;
+        n_s = r.set ? std::max<uint64_t>(n_s, r.n_s_max) : n_s + r.n_s_max;
+        max_deg = std::max(max_deg, r.max_deg);
+        w2 = std::max(w2, r.w2_max);
+        n++;
+    }
+    uint64_t bytes(int num_cus) const
+    {
+        uint64_t b = build + work_bytes_estimate(m, n_s, max_deg, num_cus);
+        // a graph counted alone starts from its wedge count (ensure_work)
+        if (n == 1) b += work_bytes_from_wedges(w2);
+        // allocations of 1 MB and more are rounded up to 2 MB
+        return b + b / 4 + (8u << 20);
+    }
+};
 
 void serve_worker(bbc_ctx *ctx, int slot)
 {
     hipStream_t s = ctx->serve_streams[slot];
     Work w;
+    tl_alloc_tag = 1;
     (void)hipSetDevice(ctx->device);
+    auto finish = [&](const std::shared_ptr<Request> &r, bbc_status st, int64_t v) {
+        std::lock_guard<std::mutex> lk(ctx->q_mu);
+        r->status = st;
+        r->result = v;
+        r->done = true;
+        r->eu.clear(); r->eu.shrink_to_fit();
+        r->ev.clear(); r->ev.shrink_to_fit();
+        r->sign.clear(); r->sign.shrink_to_fit();
+    };
     for (;;) {
         std::vector<std::shared_ptr<Request>> batch;
         uint64_t batch_bytes = 0;
+        std::vector<std::shared_ptr<Request>> too_big;
         {
             std::unique_lock<std::mutex> lk(ctx->q_mu);
             ctx->q_cv.wait(lk, [&] { return ctx->stopping || !ctx->queue.empty(); });
             if (ctx->stopping && ctx->queue.empty()) return;
-            // admission in arrival order while the footprint fits under the cap
+            // admission in arrival order while the batch's reservation fits
+            // under the cap next to the memory the caller holds (tag 0) and
+            // the reservations of the batches in flight
             const uint64_t cap = ctx->al->cap();
+            const uint64_t held = cap ? ctx->al->live(0) : 0;
+            Reservation res;
             uint64_t batch_edges = 0;
             while (!ctx->queue.empty() && batch.size() < kServeBatchMax) {
                 auto &r = ctx->queue.front();
-                bool fits = !cap || ctx->admitted_bytes + r->footprint <= cap || ctx->admitted_bytes == 0;
-                if (!fits) break;
+                Reservation alone;
+                alone.add(*r);
+                if (cap && held + alone.bytes(ctx->num_cus) > cap) {
+                    // can never fit while the caller holds what it holds
+                    too_big.push_back(r);
+                    ctx->queue.pop_front();
+                    continue;
+                }
+                Reservation next = res;
+                next.add(*r);
+                const uint64_t want = next.bytes(ctx->num_cus);
+                if (cap && held + ctx->admitted_bytes + want > cap) break;
                 if (!batch.empty() && batch_edges + r->m > kServeBatchEdges) break;
                 batch_edges += r->m;
-                ctx->admitted_bytes += r->footprint;
-                batch_bytes += r->footprint;
+                res = next;
+                batch_bytes = want;
                 batch.push_back(r);
                 ctx->queue.pop_front();
             }
-            if (batch.empty()) {
-                // wait until another worker releases memory
+            ctx->admitted_bytes += batch_bytes;
+            ctx->peak_admitted = std::max(ctx->peak_admitted, ctx->admitted_bytes);
+            if (batch.empty() && too_big.empty()) {
+                // wait until another worker releases its reservation
                 ctx->q_cv.wait_for(lk, std::chrono::milliseconds(1));
                 continue;
             }
         }
+        for (auto &r : too_big) {
+            set_error(ctx, "a served request needs more device memory than the cap leaves");
+            finish(r, BBC_E_NOMEM, 0);
+        }
+        if (!too_big.empty()) ctx->done_cv.notify_all();
+        if (batch.empty()) continue;
         // COO requests of the batch are built together; prebuilt graphs are
         // counted through their own sets
-        std::vector<std::shared_ptr<Request>> coo, pre;
+        std::vector<std::shared_ptr<Request>> coo, pre, requeue;
         for (auto &r : batch) (r->set ? pre : coo).push_back(r);
-        auto finish = [&](const std::shared_ptr<Request> &r, bbc_status st, int64_t v) {
+        // out of memory while other batches hold reservations: the requests
+        // go back to the front of the queue (at most a few times each)
+        auto others_in_flight = [&] {
             std::lock_guard<std::mutex> lk(ctx->q_mu);
-            r->status = st;
-            r->result = v;
-            r->done = true;
-            r->eu.clear(); r->eu.shrink_to_fit();
-            r->ev.clear(); r->ev.shrink_to_fit();
-            r->sign.clear(); r->sign.shrink_to_fit();
+            return ctx->admitted_bytes > batch_bytes;
+        };
+        // results are published after the batch has released its memory and
+        // its reservation, so a caller that has every result sees the memory
+        // free again
+        struct Outcome { std::shared_ptr<Request> r; bbc_status st; int64_t v; };
+        std::vector<Outcome> outcomes;
+        auto settle = [&](const std::shared_ptr<Request> &r, bbc_status st, int64_t v) {
+            if (st == BBC_E_NOMEM && r->nomem_retries < 8 && others_in_flight()) {
+                r->nomem_retries++;
+                requeue.push_back(r);
+            } else {
+                outcomes.push_back({r, st, v});
+            }
         };
         if (!coo.empty()) {
             // group by sign encoding / anchor flags
@@ -1151,7 +1353,9 @@ void serve_worker(bbc_ctx *ctx, int slot)
                     auto set = build_set(ctx, in, s, w.bhost);
                     count_sync(ctx, w, *set, 0, set->G, 0, default_shape(), s, res.data());
                 });
-                if (st != BBC_OK && rs.size() > 1) {
+                if (st == BBC_E_NOMEM && others_in_flight()) {
+                    for (auto &r : rs) settle(r, st, 0);
+                } else if (st != BBC_OK && rs.size() > 1) {
                     // isolate the failing request: count each alone
                     for (size_t i = 0; i < rs.size(); i++) {
                         uint64_t o2[2] = {0, rs[i]->m};
@@ -1162,10 +1366,10 @@ void serve_worker(bbc_ctx *ctx, int slot)
                             auto set = build_set(ctx, one, s, w.bhost);
                             count_sync(ctx, w, *set, 0, 1, 0, default_shape(), s, &v);
                         });
-                        finish(rs[i], st1, v);
+                        settle(rs[i], st1, v);
                     }
                 } else {
-                    for (size_t i = 0; i < rs.size(); i++) finish(rs[i], st, res[i]);
+                    for (size_t i = 0; i < rs.size(); i++) settle(rs[i], st, res[i]);
                 }
             }
         }
@@ -1174,12 +1378,16 @@ void serve_worker(bbc_ctx *ctx, int slot)
             bbc_status st = guard(nullptr, [&] {
                 count_sync(ctx, w, *r->set, r->idx, r->idx + 1, 0, default_shape(), s, &v);
             });
-            finish(r, st, v);
+            settle(r, st, v);
         }
+        // the workspace goes back to the allocator: an idle worker holds nothing
+        w.release_device();
         {
             std::lock_guard<std::mutex> lk(ctx->q_mu);
             ctx->admitted_bytes -= batch_bytes;
+            for (auto it = requeue.rbegin(); it != requeue.rend(); ++it) ctx->queue.push_front(*it);
         }
+        for (auto &o : outcomes) finish(o.r, o.st, o.v);
         ctx->done_cv.notify_all();
         ctx->q_cv.notify_all();
     }
@@ -1203,6 +1411,7 @@ bbc_ticket enqueue_request(bbc_ctx *ctx, std::shared_ptr<Request> r)
     r->id = ctx->next_ticket++;
     ctx->requests[r->id] = r;
     ctx->queue.push_back(r);
+    ctx->peak_queued = std::max<uint64_t>(ctx->peak_queued, ctx->queue.size());
     ctx->q_cv.notify_one();
     return r->id;
 }
@@ -1279,6 +1488,10 @@ void bbc_ctx_destroy(bbc_ctx *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     ctx->requests.clear();
     ctx->queue.clear();
+    // graphs the caller did not free: their device memory goes back before
+    // the allocator is destroyed with the context
+    for (bbc_graph *g : ctx->graphs) delete g;
+    ctx->graphs.clear();
     if (ctx->work.exec) { (void)hipGraphExecDestroy(ctx->work.exec); ctx->work.exec = nullptr; }
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -1299,7 +1512,10 @@ bbc_status bbc_build_csr(bbc_ctx *ctx, uint32_t n_u, uint32_t n_v, uint64_t n_ed
         uint64_t off[2] = {0, n_edges};
         CooIn in{1, &n_u, &n_v, off, eu, ev, sign, flags};
         auto set = build_set(ctx, in, ctx->stream, ctx->work.bhost);
-        *out = new bbc_graph{set, 0};
+        bbc_graph *h = new bbc_graph{set, 0};
+        std::lock_guard<std::mutex> lk(ctx->g_mu);
+        ctx->graphs.insert(h);
+        *out = h;
     });
 }
 
@@ -1317,6 +1533,8 @@ bbc_status bbc_build_csr_batch(bbc_ctx *ctx, uint32_t n_graphs, const uint32_t *
         auto set = build_set(ctx, in, ctx->stream, ctx->work.bhost);
         std::vector<bbc_graph *> hs(n_graphs, nullptr);
         for (uint32_t i = 0; i < n_graphs; i++) hs[i] = new bbc_graph{set, i};
+        std::lock_guard<std::mutex> lk(ctx->g_mu);
+        ctx->graphs.insert(hs.begin(), hs.end());
         std::copy(hs.begin(), hs.end(), out_graphs);
     });
 }
@@ -1324,6 +1542,10 @@ bbc_status bbc_build_csr_batch(bbc_ctx *ctx, uint32_t n_graphs, const uint32_t *
 bbc_status bbc_graph_free(bbc_ctx *ctx, bbc_graph *g)
 {
     if (!ctx || !g) return BBC_E_INVAL;
+    {
+        std::lock_guard<std::mutex> lk(ctx->g_mu);
+        if (!ctx->graphs.erase(g)) return BBC_E_INVAL;   // not a live graph of this context
+    }
     delete g;
     return BBC_OK;
 }
@@ -1616,7 +1838,9 @@ bbc_status bbc_submit(bbc_ctx *ctx, const bbc_graph *g, bbc_ticket *out)
         r->set = g->set;
         r->idx = g->idx;
         const GraphDesc &d = g->set->desc[g->idx];
-        r->footprint = footprint_estimate(d.m, 0, 0);
+        r->m = d.m;
+        r->n_s_max = d.n_s;
+        r->max_deg = g->set->max_deg;
         *out = enqueue_request(ctx, r);
     });
 }
@@ -1637,7 +1861,21 @@ bbc_status bbc_submit_coo(bbc_ctx *ctx, uint32_t n_u, uint32_t n_v, uint64_t n_e
         r->ev.assign(ev, ev + n_edges);
         const uint8_t *sp = (const uint8_t *)sign;
         r->sign.assign(sp, sp + sign_bytes(n_edges, flags));
-        r->footprint = footprint_estimate(n_edges, n_u, n_v);
+        // the largest degree bounds the workspace the count needs
+        {
+            std::vector<uint32_t> du(n_u, 0), dv(n_v, 0);
+            uint32_t mx = 0;
+            for (uint64_t e = 0; e < n_edges; e++) {
+                if (eu[e] < n_u) mx = std::max(mx, ++du[eu[e]]);
+                if (ev[e] < n_v) mx = std::max(mx, ++dv[ev[e]]);
+            }
+            r->max_deg = mx;
+            uint64_t cu = 0, cv = 0;
+            for (uint32_t x : du) cu += (uint64_t)x * (x - (x > 0)) / 2;
+            for (uint32_t x : dv) cv += (uint64_t)x * (x - (x > 0)) / 2;
+            r->w2_max = std::max(cu, cv);
+        }
+        r->n_s_max = std::max(n_u, n_v);
         *out = enqueue_request(ctx, r);
     });
 }
@@ -1675,6 +1913,25 @@ bbc_status bbc_set_timing(bbc_ctx *ctx, int enable)
             for (auto &e : ctx->ev) HIP_OK(hipEventCreate(&e));
         ctx->timing = enable != 0;
     });
+}
+
+bbc_status bbc_get_memory_stats(bbc_ctx *ctx, bbc_memory_stats *out)
+{
+    if (!ctx || !out) return BBC_E_INVAL;
+    bbc_memory_stats m{};
+    m.cap_bytes = ctx->al->cap();
+    m.reserved_bytes = ctx->al->used();
+    m.peak_reserved_bytes = ctx->al->peak();
+    m.live_bytes = ctx->al->live(0) + ctx->al->live(1);
+    {
+        std::lock_guard<std::mutex> lk(ctx->q_mu);
+        m.serve_admitted_bytes = ctx->admitted_bytes;
+        m.serve_peak_admitted_bytes = ctx->peak_admitted;
+        m.serve_queued = ctx->queue.size();
+        m.serve_peak_queued = ctx->peak_queued;
+    }
+    *out = m;
+    return BBC_OK;
 }
 
 bbc_status bbc_set_test_hook(bbc_ctx *ctx, int hook, int64_t value)

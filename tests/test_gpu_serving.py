@@ -1,0 +1,156 @@
+"""GPU tests of the serving loop under a memory cap and of the failure paths
+that real inputs reach only at sizes too large to test: a request larger
+than the cap, counts past 2^63 - 1 (the accumulator preloaded from the host),
+graphs left to the context's destruction. Every count is compared with the
+oracle, tolerance 0."""
+import numpy as np
+import pytest
+
+from paper_2605_03603_amd import generators as G
+from tests.gpu_common import build, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+MiB = 1 << 20
+INT64_MAX = (1 << 63) - 1
+
+
+@pytest.fixture(scope="module")
+def B():
+    need_gpu()
+    from paper_2605_03603_amd import bbc
+    return bbc
+
+
+@pytest.fixture(scope="module")
+def mix(oracle):
+    """120 graphs of the batched mix and their oracle counts."""
+    gs = G.config4(17, n_graphs=120)
+    return gs, [oracle.count_bbvp(g, 0, threads=8)["total"] for g in gs]
+
+
+def submit_all(ctx, gs):
+    return [ctx.submit_coo(g.n_u, g.n_v, g.eu, g.ev, g.sign) for g in gs]
+
+
+# Serving under a cap small enough to run out of device memory faulted the
+# GPU twice: an allocation that failed inside the count workspace's sizing
+# left a stale capacity beside a null buffer, and the worker's retry of each
+# request alone counted through that null buffer. The sizing now clears a
+# capacity before reallocating it; the case stays off the GPU until the next
+# round, as its fix has not been run there.
+CAP_CASE_SKIP = pytest.mark.skip(
+    reason="faulted the GPU before the stale-capacity fix in ensure_work; held off the GPU "
+           "until its fix is tested in a later session")
+
+
+@CAP_CASE_SKIP
+def test_serving_under_small_cap(B, mix):
+    """A 256 MiB cap holds a few batches at a time: the requests queue behind
+    it, the context's memory never passes it, and every result equals the
+    oracle's."""
+    gs, want = mix
+    cap = 256 * MiB
+    with B.Context(0, mem_cap=cap) as ctx:
+        say("serving under a 256 MiB cap")
+        tickets = submit_all(ctx, gs)
+        got = [ctx.wait(t) for t in tickets]
+        assert got == want
+        m = ctx.memory_stats()
+        say("memory", m)
+        assert m["cap_bytes"] == cap
+        assert m["peak_reserved_bytes"] <= cap
+        assert m["serve_peak_admitted_bytes"] <= cap
+        assert m["serve_peak_queued"] > 8          # requests waited for admission
+        assert m["serve_admitted_bytes"] == 0 and m["serve_queued"] == 0
+        # a second wave after the first has drained: the workers hold nothing
+        assert m["live_bytes"] == 0
+        got = [ctx.wait(t) for t in submit_all(ctx, gs[:40])]
+        assert got == want[:40]
+
+
+@CAP_CASE_SKIP
+def test_request_larger_than_cap_fails_alone(B, mix, oracle):
+    """Config 2 at full size (2M edges) needs more than a 256 MiB cap allows:
+    it fails with BBC_E_NOMEM, the small requests around it complete."""
+    gs, want = mix
+    big = G.config2(1)
+    with B.Context(0, mem_cap=256 * MiB) as ctx:
+        say("request larger than the cap")
+        before = submit_all(ctx, gs[:30])
+        tb = ctx.submit_coo(big.n_u, big.n_v, big.eu, big.ev, big.sign)
+        after = submit_all(ctx, gs[30:60])
+        with pytest.raises(B.BBCError) as ei:
+            ctx.wait(tb)
+        assert ei.value.name == "BBC_E_NOMEM"
+        assert [ctx.wait(t) for t in before + after] == want[:60]
+        # the same graph counted directly on a context without a cap
+    with B.Context(0) as ctx:
+        r = oracle.count_bbvp(G.config2(1, scale=0.05), 0, threads=8)["total"]
+        g5 = G.config2(1, scale=0.05)
+        t = ctx.submit_coo(g5.n_u, g5.n_v, g5.eu, g5.ev, g5.sign)
+        assert ctx.wait(t) == r
+
+
+def test_count_overflow(B, oracle):
+    """A count whose 64-bit accumulator passes 2^63 - 1 returns
+    BBC_E_OVERFLOW: the accumulator is preloaded from the host so that the
+    true count of config 1 seed 1 lands exactly on the boundary."""
+    g = G.config1(1)
+    c = oracle.count_bbvp(g, 0)["total"]
+    assert c > 5
+    with B.Context(0) as ctx:
+        h = build(ctx, g)
+        assert ctx.count_global(h) == c
+        say("overflow boundary")
+        ctx.set_test_hook(B.BBC_HOOK_PRELOAD_COUNT, INT64_MAX - c)
+        assert ctx.count_global(h) == INT64_MAX            # exactly 2^63 - 1 still fits
+        ctx.set_test_hook(B.BBC_HOOK_PRELOAD_COUNT, INT64_MAX - c + 1)
+        with pytest.raises(B.BBCError) as ei:
+            ctx.count_global(h)
+        assert ei.value.name == "BBC_E_OVERFLOW"
+        # past 2^64: the carry word
+        ctx.set_test_hook(B.BBC_HOOK_PRELOAD_COUNT, -5)
+        with pytest.raises(B.BBCError) as ei:
+            ctx.count_global(h)
+        assert ei.value.name == "BBC_E_OVERFLOW"
+        ctx.set_test_hook(B.BBC_HOOK_PRELOAD_COUNT, 0)
+        assert ctx.count_global(h) == c
+
+
+def test_overflow_fails_only_its_ticket(B, mix):
+    """Served together, the requests whose count passes 2^63 - 1 with the
+    preload fail alone; the others return their count plus the preload."""
+    gs, want = mix
+    P = INT64_MAX - 1000
+    with B.Context(0) as ctx:
+        ctx.set_test_hook(B.BBC_HOOK_PRELOAD_COUNT, P)
+        say("overflow in a served batch")
+        tickets = submit_all(ctx, gs[:60])
+        n_over = 0
+        for t, w in zip(tickets, want[:60]):
+            if w > 1000:
+                with pytest.raises(B.BBCError) as ei:
+                    ctx.wait(t)
+                assert ei.value.name == "BBC_E_OVERFLOW"
+                n_over += 1
+            else:
+                assert ctx.wait(t) == w + P
+        assert 0 < n_over < 60
+
+
+def test_graphs_left_to_destroy(B, mix):
+    """Graphs the caller never frees are released with the context; freeing
+    a handle twice, or on another context, is refused."""
+    gs, want = mix
+    ctx = B.Context(0)
+    hs = [build(ctx, g) for g in gs[:5]]
+    assert [ctx.count_global(h) for h in hs] == want[:5]
+    other = B.Context(0)
+    assert B.lib.bbc_graph_free(other.handle, hs[0].handle) == 1      # BBC_E_INVAL
+    assert B.lib.bbc_graph_free(ctx.handle, hs[0].handle) == 0
+    assert B.lib.bbc_graph_free(ctx.handle, hs[0].handle) == 1
+    live = ctx.memory_stats()["live_bytes"]
+    assert live > 0
+    ctx.close()                                  # hs[1:] are released here
+    other.close()
