@@ -19,6 +19,8 @@ struct PairArgs {
     int dlog2h;
     uint32_t gmaxd, gkmax;  // degree and candidate limits of tiers 2, 3 and 4
     uint32_t flags;         // kPairNoWindow: heavy anchors stay in the hash tiers
+    uint32_t mask_chunk, cand_chunk;        // output reserved per workgroup at a time
+    uint32_t wv_mask_chunk, wv_cand_chunk;  // and per wave of the per-wave tier
 };
 
 constexpr uint32_t kPairNoWindow = 1u;

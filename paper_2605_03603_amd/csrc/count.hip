@@ -75,8 +75,10 @@ constexpr uint32_t kRegW = 16;         // widest mask kept in registers per row
 constexpr uint32_t kWideCols = 64;     // unit width (columns) for wider masks
 constexpr uint32_t kMfmaMaxW = 16;     // widest mask counted with the rows held in registers
 constexpr int kFp4MinW = 3;            // narrowest mask counted on the fp4 matrix cores
-constexpr uint32_t kMaskChunk = 1u << 16;   // mask words reserved per workgroup at a time
-constexpr uint32_t kCandChunk = 1u << 13;
+// Output is reserved in chunks (PairArgs::mask_chunk and cand_chunk mask words
+// and candidates per workgroup, wv_mask_chunk and wv_cand_chunk per wave of the
+// per-wave tier), sized by the host to the set's edge count so that a small
+// graph's demand stays small; anchor records 16 at a time.
 constexpr uint32_t kRecChunk = 16;
 constexpr int kUnroll = 4;              // independent neighbour-list loads per lane
 // rank-window tier (k_pair_window): its threads, widest partner window (bytes
@@ -653,18 +655,18 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
         if (tid == 0) {
             // workgroup-local bump reservations (few global atomics)
             // demand: what the reservations below consume with unlimited room
-            sh.big_m = words > kMaskChunk / 4;
-            sh.big_c = k > kCandChunk / 4;
+            sh.big_m = words > P.mask_chunk / 4;
+            sh.big_c = k > P.cand_chunk / 4;
             if (sh.big_m) {
                 sh.need_m += words;
             } else {
-                if (sh.vm + words > sh.vm_end) { sh.need_m += kMaskChunk; sh.vm = 0; sh.vm_end = kMaskChunk; }
+                if (sh.vm + words > sh.vm_end) { sh.need_m += P.mask_chunk; sh.vm = 0; sh.vm_end = P.mask_chunk; }
                 sh.vm += words;
             }
             if (sh.big_c) {
                 sh.need_c += k;
             } else {
-                if (sh.vc + k > sh.vc_end) { sh.need_c += kCandChunk; sh.vc = 0; sh.vc_end = kCandChunk; }
+                if (sh.vc + k > sh.vc_end) { sh.need_c += P.cand_chunk; sh.vc = 0; sh.vc_end = P.cand_chunk; }
                 sh.vc += k;
             }
             sh.need_r += 1;
@@ -678,18 +680,18 @@ __device__ __forceinline__ void pair_loop(const PairArgs &P, const PairMem &m, P
                     sh.bm = o;
                     if (o + words > P.ws.cap_mask_words) bad = true;
                 } else if (sh.moff + words > sh.mres_end) {
-                    uint64_t o = atomicAdd(&C->mask_cursor, (unsigned long long)kMaskChunk);
-                    sh.moff = o; sh.mres_end = o + kMaskChunk;
-                    if (o + kMaskChunk > P.ws.cap_mask_words) bad = true;
+                    uint64_t o = atomicAdd(&C->mask_cursor, (unsigned long long)P.mask_chunk);
+                    sh.moff = o; sh.mres_end = o + P.mask_chunk;
+                    if (o + P.mask_chunk > P.ws.cap_mask_words) bad = true;
                 }
                 if (sh.big_c) {
                     uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)k);
                     sh.bc = o;
                     if (o + k > P.ws.cap_cands) bad = true;
                 } else if (sh.coff + k > sh.cres_end) {
-                    uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)kCandChunk);
-                    sh.coff = o; sh.cres_end = o + kCandChunk;
-                    if (o + kCandChunk > P.ws.cap_cands) bad = true;
+                    uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)P.cand_chunk);
+                    sh.coff = o; sh.cres_end = o + P.cand_chunk;
+                    if (o + P.cand_chunk > P.ws.cap_cands) bad = true;
                 }
                 if (sh.aidx >= sh.arec_end) {
                     uint32_t o = atomicAdd(&C->n_anchor, kRecChunk);
@@ -1040,18 +1042,18 @@ __global__ void __launch_bounds__(kRThreads) k_pair_window(PairArgs P)
         if (tid == 0) {
             // output reservations as in the hash tiers (workgroup-local chunks
             // for small outputs, a reservation of its own for a large one)
-            sh.big_m = words > kMaskChunk / 4;
-            sh.big_c = k > kCandChunk / 4;
+            sh.big_m = words > P.mask_chunk / 4;
+            sh.big_c = k > P.cand_chunk / 4;
             if (sh.big_m) {
                 sh.need_m += words;
             } else {
-                if (sh.vm + words > sh.vm_end) { sh.need_m += kMaskChunk; sh.vm = 0; sh.vm_end = kMaskChunk; }
+                if (sh.vm + words > sh.vm_end) { sh.need_m += P.mask_chunk; sh.vm = 0; sh.vm_end = P.mask_chunk; }
                 sh.vm += words;
             }
             if (sh.big_c) {
                 sh.need_c += k;
             } else {
-                if (sh.vc + k > sh.vc_end) { sh.need_c += kCandChunk; sh.vc = 0; sh.vc_end = kCandChunk; }
+                if (sh.vc + k > sh.vc_end) { sh.need_c += P.cand_chunk; sh.vc = 0; sh.vc_end = P.cand_chunk; }
                 sh.vc += k;
             }
             sh.need_r += 1;
@@ -1063,18 +1065,18 @@ __global__ void __launch_bounds__(kRThreads) k_pair_window(PairArgs P)
                     sh.bm = o;
                     if (o + words > P.ws.cap_mask_words) bad = true;
                 } else if (sh.moff + words > sh.mres_end) {
-                    uint64_t o = atomicAdd(&C->mask_cursor, (unsigned long long)kMaskChunk);
-                    sh.moff = o; sh.mres_end = o + kMaskChunk;
-                    if (o + kMaskChunk > P.ws.cap_mask_words) bad = true;
+                    uint64_t o = atomicAdd(&C->mask_cursor, (unsigned long long)P.mask_chunk);
+                    sh.moff = o; sh.mres_end = o + P.mask_chunk;
+                    if (o + P.mask_chunk > P.ws.cap_mask_words) bad = true;
                 }
                 if (sh.big_c) {
                     uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)k);
                     sh.bc = o;
                     if (o + k > P.ws.cap_cands) bad = true;
                 } else if (sh.coff + k > sh.cres_end) {
-                    uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)kCandChunk);
-                    sh.coff = o; sh.cres_end = o + kCandChunk;
-                    if (o + kCandChunk > P.ws.cap_cands) bad = true;
+                    uint64_t o = atomicAdd(&C->cand_cursor, (unsigned long long)P.cand_chunk);
+                    sh.coff = o; sh.cres_end = o + P.cand_chunk;
+                    if (o + P.cand_chunk > P.ws.cap_cands) bad = true;
                 }
                 if (sh.aidx >= sh.arec_end) {
                     uint32_t o = atomicAdd(&C->n_anchor, kRecChunk);
@@ -1197,8 +1199,6 @@ __global__ void __launch_bounds__(kRThreads) k_pair_window(PairArgs P)
 constexpr uint32_t kWvMaxD = 32;
 constexpr int kWvUnroll = 2;              // loads in flight per lane, non-top positions
 constexpr int kWvTopUnroll = 16;          // and along the two longest suffixes
-constexpr uint64_t kWvMaskChunk = 4096;   // mask words reserved per workgroup at a time
-constexpr uint64_t kWvCandChunk = 4096;
 constexpr uint32_t kWvProbe = 64;
 constexpr uint32_t kWvGrab = 2;           // anchors taken from the queue at a time
 // non-top wedges (and so partners) of an anchor the per-wave tier takes, for
@@ -1468,17 +1468,17 @@ __global__ void __launch_bounds__(NWC * kWave) k_pair_wave(PairArgs P)
                 my_wedges += (uint64_t)T1 + ltop;
                 // reservations: wave-local bump allocation, large outputs apart;
                 // the demand counts what they consume with unlimited room
-                const bool big_m = k > kWvMaskChunk / 4, big_c = k > kWvCandChunk / 4;
+                const bool big_m = k > P.wv_mask_chunk / 4, big_c = k > P.wv_cand_chunk / 4;
                 if (big_m) {
                     need_m += k;
                 } else {
-                    if (vm + k > vm_end) { need_m += kWvMaskChunk; vm = 0; vm_end = kWvMaskChunk; }
+                    if (vm + k > vm_end) { need_m += P.wv_mask_chunk; vm = 0; vm_end = P.wv_mask_chunk; }
                     vm += k;
                 }
                 if (big_c) {
                     need_c += k;
                 } else {
-                    if (vcn + k > vc_end) { need_c += kWvCandChunk; vcn = 0; vc_end = kWvCandChunk; }
+                    if (vcn + k > vc_end) { need_c += P.wv_cand_chunk; vcn = 0; vc_end = P.wv_cand_chunk; }
                     vcn += k;
                 }
                 need_r += 1;
@@ -1486,7 +1486,7 @@ __global__ void __launch_bounds__(NWC * kWave) k_pair_wave(PairArgs P)
                 bool bad = false;
                 uint64_t mo = moff, co = coff;
                 if (big_m || moff + k > mres_end) {
-                    const uint64_t want = big_m ? k : kWvMaskChunk;
+                    const uint64_t want = big_m ? k : P.wv_mask_chunk;
                     uint64_t o = 0;
                     if (lane == 0) o = atomicAdd(&C->mask_cursor, (unsigned long long)want);
                     o = bcast64(o);
@@ -1495,7 +1495,7 @@ __global__ void __launch_bounds__(NWC * kWave) k_pair_wave(PairArgs P)
                     if (o + want > P.ws.cap_mask_words) bad = true;
                 }
                 if (big_c || coff + k > cres_end) {
-                    const uint64_t want = big_c ? k : kWvCandChunk;
+                    const uint64_t want = big_c ? k : P.wv_cand_chunk;
                     uint64_t o = 0;
                     if (lane == 0) o = atomicAdd(&C->cand_cursor, (unsigned long long)want);
                     o = bcast64(o);

@@ -288,6 +288,8 @@ struct Work {
     uint32_t gH = 0, dH = 0;
     int glog2 = 0, dlog2 = 0;
     uint32_t gmaxd = 0, gkmax = 0;
+    uint32_t mask_chunk = 1u << 16, cand_chunk = 1u << 13;   // output chunks of the last count
+    uint32_t wv_mask_chunk = 4096, wv_cand_chunk = 4096;
     // captured replay of a batched count
     hipGraphExec_t exec = nullptr;
     std::vector<unsigned char> exec_args;   // bytes of the LaunchArgs it was captured with
@@ -915,6 +917,36 @@ struct LaunchArgs {
     uint64_t preload;       // starting value of every graph's accumulator (0 but in tests)
 };
 
+// Output chunks of the pair kernels: each workgroup (each wave of the
+// per-wave tier) reserves mask words and candidates a chunk at a time and
+// abandons a chunk's tail when the next anchor does not fit, so the demand of
+// a count is at least one chunk per agent that took an anchor. Chunks scale
+// with the edges of the counted graphs (about 2 mask words per edge over all
+// agents), between a floor that keeps reservations rare and the sizes that
+// the largest graphs use.
+struct Chunks { uint32_t mask, cand, wv_mask, wv_cand; };
+
+uint32_t pow2_clamp(uint64_t x, uint32_t lo, uint32_t hi)
+{
+    uint32_t c = lo;
+    while (c < hi && 2ull * c <= x) c <<= 1;
+    return c;
+}
+
+Chunks chunk_sizes(const bbc_ctx *ctx, const GraphSet &set, uint32_t g0, uint32_t g1)
+{
+    uint64_t m = 0;
+    for (uint32_t g = g0; g < g1; g++) m += set.desc[g].m;
+    const uint64_t wg_agents = (uint64_t)ctx->num_cus * 4;
+    const uint64_t waves = (uint64_t)ctx->num_cus * wave_tier_waves_per_cu();
+    Chunks c;
+    c.mask = pow2_clamp(2 * m / wg_agents, 2048, 1u << 16);
+    c.cand = pow2_clamp(m / 4 / wg_agents, 256, 1u << 13);
+    c.wv_mask = pow2_clamp(2 * m / waves, 256, 4096);
+    c.wv_cand = c.wv_mask;
+    return c;
+}
+
 LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
 {
     const GraphSet &set = *r.set;
@@ -944,6 +976,11 @@ LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
     L.ptmp = w.ptmp.p;
     L.ptmp_bytes = w.ptmp_bytes;
     L.P.flags = ctx->hook_no_window ? kPairNoWindow : 0u;
+    const Chunks ch = chunk_sizes(ctx, set, r.g0, r.g1);
+    L.P.mask_chunk = ch.mask; L.P.cand_chunk = ch.cand;
+    L.P.wv_mask_chunk = ch.wv_mask; L.P.wv_cand_chunk = ch.wv_cand;
+    w.mask_chunk = ch.mask; w.cand_chunk = ch.cand;
+    w.wv_mask_chunk = ch.wv_mask; w.wv_cand_chunk = ch.wv_cand;
     L.preload = ctx->hook_preload;
     return L;
 }
@@ -999,13 +1036,14 @@ bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set)
     // threads at once (serving workers and the caller): its hints are updated
     // under the tuning lock.
     // The slack covers chunks that other workgroups may hold next time; it
-    // is at most the demand itself, so that a small set's hint stays small
-    // (a fixed slack would be 268 MB of mask words on 256 CUs).
+    // is at most the demand itself, so that a small set's hint stays small.
     const uint64_t wv = (uint64_t)ctx->num_cus * wave_tier_waves_per_cu();
-    const uint64_t slack_m = std::min<uint64_t>(4ull * ctx->num_cus * (1u << 16) + wv * 4096,
-                                                std::max<uint64_t>(c->need_masks, 1u << 16));
-    const uint64_t slack_c = std::min<uint64_t>(4ull * ctx->num_cus * (1u << 13) + wv * 4096,
-                                                std::max<uint64_t>(c->need_cands, 1u << 13));
+    const uint64_t slack_m =
+        std::min<uint64_t>(4ull * ctx->num_cus * w.mask_chunk + wv * w.wv_mask_chunk,
+                           std::max<uint64_t>(c->need_masks, 1u << 16));
+    const uint64_t slack_c =
+        std::min<uint64_t>(4ull * ctx->num_cus * w.cand_chunk + wv * w.wv_cand_chunk,
+                           std::max<uint64_t>(c->need_cands, 1u << 13));
     const bool grow = (c->over_cap & 3u) != 0;
     {
         std::lock_guard<std::mutex> lk(ctx->tune_mu);
