@@ -121,6 +121,21 @@ bbc_status bbc_get_graph_info(bbc_ctx *ctx, const bbc_graph *g, bbc_graph_info *
  * does not fit 64 bits), BBC_E_NOMEM, BBC_E_HIP. */
 bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int64_t *out_count);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * count as bbc_count_global, with every count buffer carved from a static
+ * device array of 256 MiB that the library holds on each device it runs on
+ * (looked up when a context is created there). The call allocates no device
+ * or pinned host memory; the graph and out_count are the caller's.
+ * Limits: a count that needs more than 256 MiB of workspace (roughly graphs
+ * beyond a few hundred thousand edges, or fewer with many dense anchors)
+ * returns BBC_E_NOMEM before any kernel runs on a buffer it lacks. Calls in
+ * one process are serialized; the array keeps the last call's contents, and
+ * everything a count needs zeroed is cleared by the call. Errors as for
+ * bbc_count_global. */
+bbc_status bbc_count_global_noalloc(bbc_ctx *ctx, const bbc_graph *g, int p, int q,
+                                    int64_t *out_count);
+
 /* The same count as bbc_count_global for 3 vertices on the graph's anchor
  * side and q = 3..7 on the other, by Algorithm 1 (BBWC, wedge-centric): for
  * every anchor, the signed 3-wedges through pairs of lower-priority partners

@@ -37,7 +37,8 @@ EXPORTED = ["bbc_ctx_create", "bbc_ctx_destroy", "bbc_build_csr", "bbc_build_csr
             "bbc_graph_free", "bbc_get_graph_info", "bbc_count_global", "bbc_count_per_vertex",
             "bbc_count_through_edges", "bbc_top_vertices", "bbc_count_bbwc",
             "bbc_count_batch", "bbc_submit", "bbc_submit_coo", "bbc_poll", "bbc_wait",
-            "bbc_get_last_stats", "bbc_set_timing", "bbc_set_test_hook", "bbc_get_memory_stats",
+            "bbc_count_global_noalloc", "bbc_get_last_stats", "bbc_set_timing",
+            "bbc_set_test_hook", "bbc_get_memory_stats",
             "bbc_status_string", "bbc_last_error"]
 
 BBC_HOOK_NO_WINDOW_TIER = 1
@@ -104,6 +105,7 @@ def _load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.bbc_graph_free.argtypes = [_vp, _vp]
     L.bbc_get_graph_info.argtypes = [_vp, _vp, ctypes.POINTER(GraphInfo)]
     L.bbc_count_global.argtypes = [_vp, _vp, _i32, _i32, ctypes.POINTER(ctypes.c_int64)]
+    L.bbc_count_global_noalloc.argtypes = [_vp, _vp, _i32, _i32, ctypes.POINTER(ctypes.c_int64)]
     L.bbc_count_per_vertex.argtypes = [_vp, _vp, _i32, _i32, _i32, _vp,
                                        ctypes.POINTER(ctypes.c_int64)]
     L.bbc_count_through_edges.argtypes = [_vp, _vp, _u64, _vp, _vp, _vp, _vp]

@@ -79,6 +79,10 @@ thread_local int tl_alloc_tag = 0;
 class Allocator {
   public:
     Allocator(uint64_t cap) : cap_(cap) {}
+    // Arena mode: every allocation is carved from [base, base + size) by a
+    // bump pointer and nothing is freed until arena_reset(); no device memory
+    // is ever allocated or freed.
+    Allocator(void *base, uint64_t size) : cap_(size), arena_((char *)base) {}
     ~Allocator() { release_all(); }
 
     void *alloc(uint64_t bytes)
@@ -87,6 +91,16 @@ class Allocator {
         bytes = round_up(bytes, 256);
         const int tag = tl_alloc_tag;
         std::lock_guard<std::mutex> lk(mu_);
+        if (arena_) {
+            if (used_ + bytes > cap_)
+                fail(BBC_E_NOMEM, "the count needs more than the %llu-byte static scratch of the "
+                                  "no-allocation entry point (%llu bytes more)",
+                     (unsigned long long)cap_, (unsigned long long)(used_ + bytes - cap_));
+            void *p = arena_ + used_;
+            used_ += bytes;
+            peak_ = std::max(peak_, used_);
+            return p;
+        }
         auto it = free_.lower_bound(bytes);
         if (it != free_.end() && it->first <= bytes * 2 + (4u << 20)) {
             void *p = it->second;
@@ -122,7 +136,7 @@ class Allocator {
 
     void free(void *p)
     {
-        if (!p) return;
+        if (!p || arena_) return;
         std::lock_guard<std::mutex> lk(mu_);
         auto it = live_.find(p);
         if (it == live_.end()) return;
@@ -154,6 +168,12 @@ class Allocator {
         trim_locked();
     }
 
+    void arena_reset()
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (arena_) used_ = 0;
+    }
+
   private:
     struct Live { uint64_t bytes; int tag; };
     void trim_locked()
@@ -166,6 +186,7 @@ class Allocator {
     }
     std::mutex mu_;
     uint64_t cap_, used_ = 0, peak_ = 0;
+    char *arena_ = nullptr;
     uint64_t live_tag_[2] = {0, 0};
     std::multimap<uint64_t, void *> free_;
     std::unordered_map<void *, Live> live_;
@@ -206,13 +227,21 @@ struct DBuf {
     T *as() const { return (T *)p; }
 };
 
-// Pinned host staging area.
+// Pinned host staging area (or, with use_external, memory the caller owns:
+// then nothing is allocated and a request beyond its size fails).
 struct HBuf {
     void *p = nullptr;
     uint64_t bytes = 0;
+    bool external = false;
+    void use_external(void *q, uint64_t n)
+    {
+        p = q;
+        bytes = n;
+        external = true;
+    }
     ~HBuf()
     {
-        if (!p) return;
+        if (!p || external) return;
         // as for DBuf: an in-flight copy may still read this staging memory
         if (std::uncaught_exceptions() > 0) (void)hipDeviceSynchronize();
         (void)hipHostFree(p);
@@ -220,6 +249,9 @@ struct HBuf {
     void ensure(uint64_t n)
     {
         if (p && bytes >= n) return;
+        if (external)
+            fail(BBC_E_NOMEM, "host staging of %llu bytes exceeds the %llu-byte static buffer",
+                 (unsigned long long)n, (unsigned long long)bytes);
         if (p) (void)hipHostFree(p);
         p = nullptr;
         HIP_OK(hipHostMalloc(&p, n, hipHostMallocDefault));
@@ -288,6 +320,7 @@ struct Work {
     uint32_t gH = 0, dH = 0;
     int glog2 = 0, dlog2 = 0;
     uint32_t gmaxd = 0, gkmax = 0;
+    Allocator *arena = nullptr;   // no-allocation counts: every buffer from this arena
     uint32_t mask_chunk = 1u << 16, cand_chunk = 1u << 13;   // output chunks of the last count
     uint32_t wv_mask_chunk = 4096, wv_cand_chunk = 4096;
     // captured replay of a batched count
@@ -720,7 +753,7 @@ uint64_t work_bytes_from_wedges(uint64_t w2)
 
 void ensure_work(bbc_ctx *ctx, Work &w, GraphSet &set)
 {
-    Allocator *al = ctx->al.get();
+    Allocator *al = w.arena ? w.arena : ctx->al.get();
     uint64_t M = std::max<uint64_t>(set.M, 1);
     uint64_t hint_masks, hint_cands, hint_units;
     {
@@ -1053,10 +1086,12 @@ bool check_counters(bbc_ctx *ctx, Work &w, GraphSet &set)
             set.hint_units = std::max<uint64_t>(set.hint_units, c->need_units + c->need_units / 16 + 1024);
         } else {
             set.hint_units = std::max<uint64_t>(set.hint_units, (uint64_t)c->n_units + c->n_units / 8);
-            auto &h = ctx->ws_hint[hint_key(set)];
-            h.masks = std::max(h.masks, set.hint_masks);
-            h.cands = std::max(h.cands, set.hint_cands);
-            h.units = std::max(h.units, set.hint_units);
+            if (!w.arena) {   // (a no-allocation count keeps its hints in the set only)
+                auto &h = ctx->ws_hint[hint_key(set)];
+                h.masks = std::max(h.masks, set.hint_masks);
+                h.cands = std::max(h.cands, set.hint_cands);
+                h.units = std::max(h.units, set.hint_units);
+            }
         }
     }
     if (grow) return false;
@@ -1103,6 +1138,11 @@ void count_sync(bbc_ctx *ctx, Work &w, GraphSet &set, uint32_t g0, uint32_t g1, 
         HIP_OK(hipEventCreate(&ctx->tev[1]));
     }
     for (int attempt = 0; attempt < 8; attempt++) {
+        if (w.arena) {
+            // an arena cannot free: every attempt carves its buffers afresh
+            w.release_device();
+            w.arena->arena_reset();
+        }
         ensure_work(ctx, w, set);
         if (mode == 1) {
             w.pv.ensure(ctx->al.get(), std::max<uint64_t>(set.NS, 1) * 8);
@@ -1456,6 +1496,43 @@ bbc_ticket enqueue_request(bbc_ctx *ctx, std::shared_ptr<Request> r)
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------- no-allocation counts
+// The workspace of bbc_count_global_noalloc: a static device array (each
+// device the library runs on holds its own copy until the process ends). Its
+// device address is looked up once per device when a context is created on
+// it; host code passes that address, never the array's name.
+constexpr uint64_t kNoallocScratchBytes = 256ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_noalloc_mu;
+char g_noalloc_host[1u << 20];     // counters, counts and carries read back
+
+// Look the array up on the current device (called with `device` current).
+hipError_t init_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void *scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 // ================================================================== C ABI
 extern "C" {
 
@@ -1494,6 +1571,7 @@ bbc_status bbc_ctx_create(int device, void *hip_stream, uint64_t mem_cap_bytes, 
     if (!ctx) return BBC_E_NOMEM;
     ctx->device = device;
     if (hipSetDevice(device) != hipSuccess) { (void)hipGetLastError(); return BBC_E_HIP; }
+    if (init_scratch(device) != hipSuccess) { (void)hipGetLastError(); return BBC_E_HIP; }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
     ctx->al.reset(new Allocator(mem_cap_bytes));
@@ -1602,30 +1680,61 @@ bbc_status bbc_get_graph_info(bbc_ctx *ctx, const bbc_graph *g, bbc_graph_info *
     return BBC_OK;
 }
 
+// Count mode of a global count of balanced (p, q)-bicliques on g: the
+// vertices on the graph's anchor side form the enumerated subsets (3: pairs
+// of candidates, 4: triples), those on the other side are chosen by C(n, q);
+// (p, q) with the sides exchanged is the same count on the transposed graph.
+// *nb receives the number taken on the other side.
+static int global_count_mode(const bbc_graph *g, int p, int q, int *nb)
+{
+    const uint32_t side = g->set->desc[g->idx].side;
+    const int na = side == 0 ? p : q;
+    *nb = side == 0 ? q : p;
+    if (na == 3 && *nb == 3) return 0;
+    if (na == 3 && *nb >= 4 && *nb <= 7) return 3;
+    if ((na == 4 || na == 5) && *nb >= 3 && *nb <= 7) return na;
+    fail(BBC_E_UNSUPPORTED,
+         "(p, q) = (%d, %d) on a graph anchored on %s: supported are 3, 4 or 5 vertices on "
+         "the anchor side (BBC_ANCHOR_U / BBC_ANCHOR_V) and 3..7 on the other",
+         p, q, side ? "V" : "U");
+}
+
 bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int64_t *out_count)
 {
     if (!ctx) return BBC_E_INVAL;
     return guard(ctx, [&] {
         if (!g || !out_count) fail(BBC_E_INVAL, "null argument");
-        // the vertices on the graph's anchor side form the enumerated
-        // subsets (3: pairs of candidates, 4: triples), those on the other
-        // side are chosen by C(n, q); (p, q) with the sides exchanged is the
-        // same count on the transposed graph
-        const uint32_t side = g->set->desc[g->idx].side;
-        const int na = side == 0 ? p : q, nb = side == 0 ? q : p;
-        int mode = 0;
-        if (na == 3 && nb == 3) mode = 0;
-        else if (na == 3 && nb >= 4 && nb <= 7) mode = 3;
-        else if ((na == 4 || na == 5) && nb >= 3 && nb <= 7) mode = na;
-        else
-            fail(BBC_E_UNSUPPORTED,
-                 "(p, q) = (%d, %d) on a graph anchored on %s: supported are 3, 4 or 5 vertices on "
-                 "the anchor side (BBC_ANCHOR_U / BBC_ANCHOR_V) and 3..7 on the other",
-                 p, q, side ? "V" : "U");
+        int nb = 3;
+        const int mode = global_count_mode(g, p, q, &nb);
         (void)hipSetDevice(ctx->device);
         int64_t v = 0;
         count_sync(ctx, ctx->work, *g->set, g->idx, g->idx + 1, mode, default_shape(), ctx->stream,
                    &v, (uint32_t)nb);
+        *out_count = v;
+    });
+}
+
+bbc_status bbc_count_global_noalloc(bbc_ctx *ctx, const bbc_graph *g, int p, int q,
+                                    int64_t *out_count)
+{
+    if (!ctx) return BBC_E_INVAL;
+    return guard(ctx, [&] {
+        if (!g || !out_count) fail(BBC_E_INVAL, "null argument");
+        int nb = 3;
+        const int mode = global_count_mode(g, p, q, &nb);
+        (void)hipSetDevice(ctx->device);
+        void *base = scratch_of(ctx->device);
+        if (!base) fail(BBC_E_HIP, "no static scratch address for device %d", ctx->device);
+        // one no-allocation count at a time in this process: the calls share
+        // the device's scratch array and the host readback buffer
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        Allocator arena(base, kNoallocScratchBytes);
+        Work w;
+        w.arena = &arena;
+        w.host.use_external(g_noalloc_host, sizeof(g_noalloc_host));
+        int64_t v = 0;
+        count_sync(ctx, w, *g->set, g->idx, g->idx + 1, mode, default_shape(), ctx->stream, &v,
+                   (uint32_t)nb);
         *out_count = v;
     });
 }
