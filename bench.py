@@ -414,7 +414,7 @@ def main():
         e_u = torch.from_numpy(g2.eu.view(np.int32)).to(dev)
         e_v = torch.from_numpy(g2.ev.view(np.int32)).to(dev)
         e_s = torch.from_numpy(bbc.pack_signs_2bit(g2.sign)).to(dev)   # 2-bit packed signs
-        flags2 = bbc.BBC_SIGNS_2BIT_PACKED
+        flags2 = bbc.BBC_SIGNS_2BIT_PACKED | bbc.BBC_ANCHOR_U   # per-U counts on the anchor side
         for _ in range(3):
             h = ctx.build_csr(g2.n_u, g2.n_v, e_u, e_v, e_s, flags2)
             ctx.count_per_vertex(h, 0)

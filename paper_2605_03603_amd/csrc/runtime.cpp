@@ -330,6 +330,15 @@ struct Work {
     {
         if (exec) (void)hipGraphExecDestroy(exec);
     }
+    uint64_t device_bytes() const
+    {
+        uint64_t b = 0;
+        for (const DBuf *x : {&ctr, &anchors, &units, &masks, &cands, &defer0, &defer1, &defer2,
+                              &defer3, &defer4, &gtab, &dtab, &bscr, &count, &carry, &pv, &pv_o,
+                              &pv_slot, &ucnt, &uoff, &ptmp})
+            b += x->bytes;
+        return b;
+    }
     // Return every device buffer to the allocator (the pinned host buffers
     // stay); the next count sizes the workspace again.
     void release_device()
@@ -1301,6 +1310,14 @@ struct Reservation {
     }
 };
 
+// Device bytes a serving worker may keep between batches: a sixteenth of the
+// cap (four workers keep at most a quarter of it), 1 GiB without a cap.
+uint64_t serve_keep_bytes(const bbc_ctx *ctx)
+{
+    const uint64_t cap = ctx->al->cap();
+    return cap ? cap / 16 : (1ull << 30);
+}
+
 void serve_worker(bbc_ctx *ctx, int slot)
 {
     hipStream_t s = ctx->serve_streams[slot];
@@ -1327,7 +1344,10 @@ void serve_worker(bbc_ctx *ctx, int slot)
             // admission in arrival order while the batch's reservation fits
             // under the cap next to the memory the caller holds (tag 0) and
             // the reservations of the batches in flight
-            const uint64_t cap = ctx->al->cap();
+            // every worker may keep a workspace of up to keep bytes between
+            // batches: that allowance is set aside from the cap
+            const uint64_t cap = ctx->al->cap() ? ctx->al->cap() - kServeStreams * serve_keep_bytes(ctx)
+                                                : 0;
             const uint64_t held = cap ? ctx->al->live(0) : 0;
             Reservation res;
             uint64_t batch_edges = 0;
@@ -1458,8 +1478,10 @@ void serve_worker(bbc_ctx *ctx, int slot)
             });
             settle(r, st, v);
         }
-        // the workspace goes back to the allocator: an idle worker holds nothing
-        w.release_device();
+        // a workspace larger than the kept allowance goes back to the
+        // allocator; a smaller one stays for the next batch (reallocating it
+        // for every batch costs more than the counts of small graphs)
+        if (w.device_bytes() > serve_keep_bytes(ctx)) w.release_device();
         {
             std::lock_guard<std::mutex> lk(ctx->q_mu);
             ctx->admitted_bytes -= batch_bytes;

@@ -63,8 +63,8 @@ def test_serving_under_small_cap(B, mix):
         assert m["serve_peak_admitted_bytes"] <= cap
         assert m["serve_peak_queued"] > 8          # requests waited for admission
         assert m["serve_admitted_bytes"] == 0 and m["serve_queued"] == 0
-        # a second wave after the first has drained: the workers hold nothing
-        assert m["live_bytes"] == 0
+        # drained: each of the 4 workers keeps at most a sixteenth of the cap
+        assert m["live_bytes"] <= 4 * (cap // 16)
         got = [ctx.wait(t) for t in submit_all(ctx, gs[:40])]
         assert got == want[:40]
 
