@@ -8,8 +8,9 @@
  * |L| = p vertices of one side and |R| = q of the other, all p*q edges
  * present; it is balanced when none of its butterflies (2x2 sub-bicliques)
  * has an odd number of negative edges (Section 1, Fig. 2). The library
- * returns the number of balanced (3,3)-bicliques. p = q = 3 is the only
- * supported pair.
+ * returns the number of balanced (p,q)-bicliques: (3,3) everywhere, and for
+ * global counts 3, 4 or 5 vertices on the graph's anchor side with 3..7 on
+ * the other (bbc_count_global).
  *
  * Method (Section 4, Lemma 1 and Algorithm 2): every same-side triple
  * {u1,u2,u3} is visited once, from its lowest-priority vertex (priority:
@@ -47,7 +48,7 @@ typedef enum {
     BBC_E_DUP_EDGE = 4,      /* the same (u, v) pair twice (E is a set) */
     BBC_E_NOMEM = 5,         /* device memory, or the context's memory cap */
     BBC_E_OVERFLOW = 6,      /* a count does not fit in int64 */
-    BBC_E_UNSUPPORTED = 7,   /* (p, q) other than (3, 3) */
+    BBC_E_UNSUPPORTED = 7,   /* a (p, q) or size the call does not support */
     BBC_E_NOT_READY = 8,     /* bbc_poll: the request is still queued or running */
     BBC_E_UNKNOWN_TICKET = 9,
     BBC_E_HIP = 10           /* HIP runtime error; see bbc_last_error */
@@ -172,7 +173,9 @@ bbc_status bbc_count_through_edges(bbc_ctx *ctx, const bbc_graph *g, uint64_t n_
                                    int64_t *out);
 
 /* Per-vertex counts: out_per_vertex[x] (caller-owned, n_u or n_v int64
- * entries, host memory) = number of balanced (3,3)-bicliques that contain
+ * entries; host memory, or device memory of the context's device, which the
+ * call detects and then fills on the GPU without a host copy) = number of
+ * balanced (3,3)-bicliques that contain
  * vertex x of the requested side (0 = U, 1 = V); their sum is 3 * count.
  * out_count (optional) receives the global count. Only (p, q) = (3, 3).
  * Either side works whichever side the graph is anchored on: the triples stay

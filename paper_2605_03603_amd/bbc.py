@@ -269,14 +269,23 @@ class Context:
                                                 out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
-    def count_per_vertex(self, g: Graph, side: int, p: int = 3, q: int = 3) -> Tuple[np.ndarray, int]:
+    def count_per_vertex(self, g: Graph, side: int, p: int = 3, q: int = 3, out=None):
+        """(per-vertex counts, global count). `out` may be a device tensor of
+        int64 (n_u or n_v entries) on the context's device: it is filled on
+        the GPU and returned; otherwise a numpy array is returned."""
         info = g.info()
         n = info.n_u if side == 0 else info.n_v
+        total = ctypes.c_int64()
+        if out is not None:
+            if not hasattr(out, "data_ptr") or out.numel() < n or out.element_size() != 8:
+                raise ValueError("out must be a tensor of at least n int64 entries")
+            self._check(lib.bbc_count_per_vertex(self.handle, g.handle, p, q, side,
+                                                 ctypes.c_void_p(out.data_ptr()), ctypes.byref(total)))
+            return out, total.value
         arr = np.zeros(max(n, 1), np.int64)
-        out = ctypes.c_int64()
         self._check(lib.bbc_count_per_vertex(self.handle, g.handle, p, q, side,
-                                             arr.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out)))
-        return arr[:n], out.value
+                                             arr.ctypes.data_as(ctypes.c_void_p), ctypes.byref(total)))
+        return arr[:n], total.value
 
     def count_batch(self, graphs: Sequence[Graph]) -> np.ndarray:
         n = len(graphs)

@@ -45,6 +45,10 @@ hipError_t count_plan(const Workspace &ws, uint32_t chunk_base, void *tmp, size_
 // the opposite side; 3: totals with q (T.q, 4..7) vertices on the opposite side;
 // 4, 5: totals with 4 or 5 vertices on the anchor side and q (T.q, 3..7) on the other
 hipError_t count_triplets(const TriArgs &T, int mode, uint32_t grid, hipStream_t s);
+// per-vertex counts into a device array: out[id[i]] = pv[i] for i < n (id
+// null: out[i] = pv[i]); *bad |= 1 if a value does not fit int64
+hipError_t per_vertex_to_device(const unsigned long long *pv, const uint32_t *id, uint32_t n,
+                                int64_t *out, uint32_t *bad, hipStream_t s);
 // workgroups (and waves) of the per-wave tier that fit on one compute unit
 uint32_t wave_tier_blocks_per_cu();
 uint32_t wave_tier_waves_per_cu();

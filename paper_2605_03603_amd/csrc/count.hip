@@ -2668,7 +2668,29 @@ __global__ void __launch_bounds__(256) k_pv_slot_scatter(Workspace ws)
     }
 }
 
+// Per-vertex counts into a caller's device array: out[id[i]] = pv[i] (id
+// null: out[i] = pv[i]); a value above 2^63 - 1 sets *bad.
+__global__ void __launch_bounds__(256) k_pv_out(const unsigned long long *__restrict__ pv,
+                                                 const uint32_t *__restrict__ id, uint32_t n,
+                                                 int64_t *__restrict__ out, uint32_t *bad)
+{
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const unsigned long long v = pv[i];
+        if (v > (unsigned long long)INT64_MAX) atomicOr(bad, 1u);
+        out[id ? id[i] : i] = (int64_t)v;
+    }
+}
+
 }  // namespace
+
+hipError_t per_vertex_to_device(const unsigned long long *pv, const uint32_t *id, uint32_t n,
+                                int64_t *out, uint32_t *bad, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const uint32_t grid = std::min<uint32_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_pv_out, dim3(grid), dim3(256), 0, s, pv, id, n, out, bad);
+    return hipGetLastError();
+}
 
 // Tier parameters (LDS use per block: tier A ~ 80 KiB, two blocks per CU;
 // tier B ~ 144 KiB).

@@ -1707,6 +1707,18 @@ bbc_status bbc_get_graph_info(bbc_ctx *ctx, const bbc_graph *g, bbc_graph_info *
 // of candidates, 4: triples), those on the other side are chosen by C(n, q);
 // (p, q) with the sides exchanged is the same count on the transposed graph.
 // *nb receives the number taken on the other side.
+// Device of p if it is device memory the HIP runtime knows, else -1 (host
+// memory).
+static int device_of_pointer(const void *p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    return a.type == hipMemoryTypeDevice ? a.device : -1;
+}
+
 static int global_count_mode(const bbc_graph *g, int p, int q, int *nb)
 {
     const uint32_t side = g->set->desc[g->idx].side;
@@ -1902,7 +1914,24 @@ bbc_status bbc_count_per_vertex(bbc_ctx *ctx, const bbc_graph *g, int p, int q, 
         int64_t v = 0;
         count_sync(ctx, ctx->work, set, g->idx, g->idx + 1, mode, default_shape(), ctx->stream, &v);
         Work &w = ctx->work;
-        if (mode == 1) {
+        const int out_dev = device_of_pointer(out_per_vertex);
+        if (out_dev >= 0 && out_dev != ctx->device)
+            fail(BBC_E_INVAL, "out_per_vertex is memory of device %d, the context's is %d", out_dev,
+                 ctx->device);
+        if (out_dev >= 0) {
+            // a device array of this device: remapped and checked on the GPU
+            const uint32_t n = mode == 1 ? d.n_s : d.n_o;
+            const unsigned long long *pv = mode == 1 ? w.pv.as<unsigned long long>() + d.s_base
+                                                     : w.pv_o.as<unsigned long long>() + d.o_base;
+            const uint32_t *id = mode == 1 ? set.s_vert.as<uint32_t>() + d.s_base : nullptr;
+            uint32_t *bad = w.carry.as<uint32_t>();   // (the count's carries were read already)
+            HIP_OK(fill_u32(bad, 0, 1, ctx->stream));
+            HIP_OK(per_vertex_to_device(pv, id, n, out_per_vertex, bad, ctx->stream));
+            uint32_t hb = 0;
+            HIP_OK(hipMemcpyAsync(&hb, bad, 4, hipMemcpyDeviceToHost, ctx->stream));
+            HIP_OK(hipStreamSynchronize(ctx->stream));
+            if (hb) fail(BBC_E_OVERFLOW, "per-vertex count exceeds int64");
+        } else if (mode == 1) {
             const uint32_t n = d.n_s;
             std::vector<uint64_t> pv(n);
             std::vector<uint32_t> vert(n);

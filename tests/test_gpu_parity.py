@@ -181,6 +181,27 @@ def test_device_pointer_input(ctx):
     assert ctx.count_global(h) == want
 
 
+def test_per_vertex_device_output(ctx, oracle):
+    """Per-vertex counts written straight into a device tensor (both sides,
+    so both the anchor side's rank-to-id remap and the other side's copy run
+    on the GPU) equal the host-array results and the oracle's."""
+    import torch
+    d = torch.device("cuda:0")
+    for g in (G.config1(2), G.config2(1, scale=0.02)):
+        h = build(ctx, g, 1 << 4)
+        for side in (0, 1):
+            n = g.n_u if side == 0 else g.n_v
+            say("per-vertex to device", g.m, side)
+            want = oracle.count_bbvp(g, side, threads=8, per_vertex=True)
+            host, t_host = ctx.count_per_vertex(h, side)
+            out = torch.full((n,), -7, dtype=torch.int64, device=d)
+            got, t_dev = ctx.count_per_vertex(h, side, out=out)
+            torch.cuda.synchronize()
+            assert t_dev == t_host == want["total"]
+            assert (got.cpu().numpy() == host).all() and (host == want["per_vertex"]).all()
+        h.free()
+
+
 # ------------------------------------------------ edge and error cases
 def test_degenerate_inputs(ctx):
     say("degenerate")
