@@ -2335,7 +2335,8 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
 #pragma unroll
     for (int tt = 0; tt < 4; tt++)
 #pragma unroll
-        for (int sb = 0; sb < 4; sb++) acc[tt][sb] = (v4f32){0.f, 0.f, 0.f, 0.f};
+        for (int sb = 0; sb < 4; sb++)
+            acc[tt][sb] = MODE == 0 ? (v4f32){-1.f, -1.f, -1.f, -1.f} : (v4f32){0.f, 0.f, 0.f, 0.f};
     const uint32_t Wf = W & ~(KW - 1);
     for (uint32_t w0 = 0; w0 < Wf; w0 += KW) {
         const uint32_t wl = w0 + 4 * g;
@@ -2438,6 +2439,42 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
     }
     uint64_t sum = 0;
     bool ovf = false;
+    if constexpr (MODE == 0) {
+        // The accumulators hold D = n - 1. Masks this wide still meet in at
+        // most 256 bits in nearly every tile (their members are sparse): a
+        // column tile whose 1024 pairs all have D <= 255 takes the packed
+        // 16-bit cubic of the narrow masks (exact there), any other tile the
+        // 64-bit one. The test is wave-uniform.
+#pragma unroll
+        for (int tt = 0; tt < 4; tt++) {
+            if ((uint32_t)tt >= nt) break;
+            const uint32_t j = un.c0 + 16 * tt + r16;
+            v4i32 d[4];
+            int dmax = -1;
+#pragma unroll
+            for (int sb = 0; sb < 4; sb++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    d[sb][e] = (int)acc[tt][sb][e];
+                    dmax = max(dmax, d[sb][e]);
+                }
+            if (!__any(dmax > 255)) {
+                const bool diag = un.c0 + 16 * tt + 16 > rbase;   // some column j >= some row
+                sum += diag ? cubic_sum<8, 4, true>(d, j, rbase + 4 * g)
+                            : cubic_sum<8, 4, false>(d, 0, 0);
+            } else {
+#pragma unroll
+                for (int sb = 0; sb < 4; sb++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const uint32_t n = j < rbase + 16 * sb + 4 * g + e ? (uint32_t)(d[sb][e] + 1) : 0u;
+                        const uint32_t t2 = n * n + 2u - 3u * n;   // (n - 1)(n - 2) mod 2^32, n < 2^16
+                        sum += (uint64_t)n * t2;
+                    }
+            }
+        }
+        return sum / 6;
+    }
 #pragma unroll
     for (int tt = 0; tt < 4; tt++) {
         if ((uint32_t)tt >= nt) break;
@@ -2447,17 +2484,12 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const uint32_t n = j < rbase + 16 * sb + 4 * g + e ? (uint32_t)acc[tt][sb][e] : 0u;
-                if constexpr (MODE >= 3) {
-                    // C(n, q): the table up to kC3Max, computed above it
-                    sum += n <= kC3Max ? cq[n] : choose_q(n, T.q, ovf);
-                } else {
-                    const uint32_t t2 = n * n + 2u - 3u * n;   // (n - 1)(n - 2) mod 2^32, n < 2^16
-                    sum += (uint64_t)n * t2;
-                }
+                // C(n, q): the table up to kC3Max, computed above it
+                sum += n <= kC3Max ? cq[n] : choose_q(n, T.q, ovf);
             }
     }
-    if (MODE >= 3 && ovf) atomicOr(&T.ws.ctr->over_cap, 16u);
-    return MODE >= 3 ? sum : sum / 6;
+    if (ovf) atomicOr(&T.ws.ctr->over_cap, 16u);
+    return sum;
 }
 
 // Two kernels per mode: CLS 0 takes the units of class 0, CLS 1 those of

@@ -181,6 +181,53 @@ def test_device_pointer_input(ctx):
     assert ctx.count_global(h) == want
 
 
+def _wide_sparse(seed):
+    """Wide masks that meet in few bits: 40 U vertices of degree 700 over a
+    random part of V[0, 3000) (22-word masks) and 200 of degree 800 that share
+    about 40 neighbours with that part and take the rest from V[3000, 6000)."""
+    rng = np.random.default_rng(seed)
+    eu, ev = [], []
+    for u in range(40):
+        vs = rng.choice(3000, 700, replace=False)
+        eu.append(np.full(700, u)); ev.append(vs)
+    for u in range(40, 240):
+        vs = np.concatenate([rng.choice(3000, 40, replace=False),
+                             3000 + rng.choice(3000, 760, replace=False)])
+        eu.append(np.full(800, u)); ev.append(vs)
+    u = np.concatenate(eu); v = np.concatenate(ev)
+    s = np.where(rng.random(u.size) < 0.8, 1, -1).astype(np.int8)
+    return G._finish(240, 6000, u, v, s)
+
+
+def test_wide_masks_small_and_large_intersections(ctx, oracle):
+    """Masks over 16 words whose pairs meet in at most 256 bits take the
+    packed 16-bit epilogue tile by tile, the others the 64-bit one: a graph of
+    wide sparse masks against the oracle (total and per vertex), and all-ones
+    masks of 19 and 38 words (every pair meets in 608 or 1216 bits) against
+    the closed form, alone and in one batch."""
+    g = _wide_sparse(3)
+    say("wide sparse masks: oracle")
+    r = oracle.count_bbvp(g, 0, threads=8, per_vertex=True)
+    h = build(ctx, g, 1 << 4)
+    assert ctx.count_global(h) == r["total"]
+    pu, t = ctx.count_per_vertex(h, 0)
+    assert t == r["total"] and (pu == r["per_vertex"]).all()
+    h.free()
+    full = [_complete_signed(70, 608, 70, 608), _complete_signed(40, 1216, 25, 1000)]
+    want_full = [C3(70) * C3(608),
+                 (C3(25) + C3(15)) * C3(1216) + (C3(40) - C3(25) - C3(15)) * (C3(1000) + C3(216))]
+    for gf, w in zip(full, want_full):
+        hf = build(ctx, gf, 1 << 4)
+        assert ctx.count_global(hf) == w
+        hf.free()
+    gs = [g] + full
+    nu, nv, off, eu, ev, sg = G.concat(gs)
+    hs = ctx.build_csr_batch(nu, nv, off, eu, ev, sg, 1 << 4)
+    assert list(ctx.count_batch(hs)) == [r["total"]] + want_full
+    for hh in hs:
+        hh.free()
+
+
 def test_per_vertex_device_output(ctx, oracle):
     """Per-vertex counts written straight into a device tensor (both sides,
     so both the anchor side's rank-to-id remap and the other side's copy run
