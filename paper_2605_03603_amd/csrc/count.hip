@@ -1901,6 +1901,7 @@ constexpr uint32_t kUnitGrab = 8;   // units per queue take of a triplet wave
 // and columns, whose masks are zero, and for masked pairs, set to D = -1).
 // Each term is 6 C(n, 3), so a lane's sum is divided by 6 once.
 typedef int v4i32 __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
 
 // a * b + c with a and b taken as 24-bit signed integers (full rate)
 __device__ __forceinline__ uint32_t mad_i24(int a, int b, uint32_t c)
@@ -1918,16 +1919,34 @@ __device__ __forceinline__ int mad_i24(int a, int b, int c)
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
-// For -1 <= D < 256 the sum of D (D^2 - 1) runs in 16-bit halves: converted
-// to 16 bits (truncated or clamped), -1 (2^32 - 1 unsigned) becomes 0xffff,
-// whose square minus one wraps to 0, and D^2 - 1 < 2^16 for the others, so
-// one packed multiply-add and one two-term dot product serve two pairs.
+// Sum of D (D^2 - 1) over N pairs of packed 16-bit D, each -1 (0xffff) or
+// 0 <= D < 256: D^2 - 1 wraps to 0 for 0xffff and fits 16 bits for the
+// others, so one packed multiply-add and one two-term dot product serve two
+// pairs. All squares are formed before the first product that reads one.
+template <int N>
+__device__ __forceinline__ uint32_t cubic_sum_u16(const u16x2 (&p)[N][2])
+{
+    u16x2 e[N][2];
+    uint32_t s[N];
+#pragma unroll
+    for (int n = 0; n < N; n++)
+#pragma unroll
+        for (int h = 0; h < 2; h++) e[n][h] = p[n][h] * p[n][h] + (u16x2){0xffff, 0xffff};
+#pragma unroll
+    for (int n = 0; n < N; n++) s[n] = __builtin_amdgcn_udot2(p[n][0], e[n][0], 0u, false);
+#pragma unroll
+    for (int n = 0; n < N; n++) s[n] = __builtin_amdgcn_udot2(p[n][1], e[n][1], s[n], false);
+    uint32_t t = 0;
+#pragma unroll
+    for (int n = 0; n < N; n++) t += s[n];
+    return t;
+}
+
 // Sum of D (D^2 - 1) over N accumulators, D = n - 1 with n <= 32 W: packed
-// for W <= 8 (n <= 256), 24-bit multiply-adds above (-1 <= D < 512: both
-// products fit, which the compiler cannot prove). Every accumulator has a
-// partial sum of its own, and in the packed form all squares are formed
-// before the first product that reads one, so that consecutive instructions
-// do not depend on each other.
+// for W <= 8 (n <= 256; converted to 16 bits with clamping, -1 becomes
+// 0xffff), 24-bit multiply-adds above (-1 <= D < 512: both products fit,
+// which the compiler cannot prove). Every accumulator has a partial sum of
+// its own, so that consecutive instructions do not depend on each other.
 // With MASKED set, element k of accumulator n (row i0 + 16 n + k, column j)
 // counts only for j < i0 + 16 n + k, the others are taken as D = -1.
 template <int W, int N, bool MASKED>
@@ -1938,21 +1957,14 @@ __device__ __forceinline__ uint32_t cubic_sum(const v4i32 (&acc)[N], uint32_t j,
     };
     uint32_t s[N];
     if constexpr (W <= 8) {
-        u16x2 p[N][2], e[N][2];
+        u16x2 p[N][2];
 #pragma unroll
         for (int n = 0; n < N; n++)
 #pragma unroll
             for (int h = 0; h < 2; h++)
                 p[n][h] = __builtin_bit_cast(
                     u16x2, __builtin_amdgcn_cvt_pk_u16((uint32_t)D(n, 2 * h), (uint32_t)D(n, 2 * h + 1)));
-#pragma unroll
-        for (int n = 0; n < N; n++)
-#pragma unroll
-            for (int h = 0; h < 2; h++) e[n][h] = p[n][h] * p[n][h] + (u16x2){0xffff, 0xffff};
-#pragma unroll
-        for (int n = 0; n < N; n++) s[n] = __builtin_amdgcn_udot2(p[n][0], e[n][0], 0u, false);
-#pragma unroll
-        for (int n = 0; n < N; n++) s[n] = __builtin_amdgcn_udot2(p[n][1], e[n][1], s[n], false);
+        return cubic_sum_u16<N>(p);
     } else {
 #pragma unroll
         for (int n = 0; n < N; n++) s[n] = 0;
@@ -1968,6 +1980,44 @@ __device__ __forceinline__ uint32_t cubic_sum(const v4i32 (&acc)[N], uint32_t j,
 #pragma unroll
     for (int n = 0; n < N; n++) t += s[n];
     return t;
+}
+
+// The fp32 accumulators of the C(n, 3) totals start at 2^23 + 2^16 - 1
+// instead of -1. Every partial sum is an integer below 2^24 (n < 2^16), so
+// the sums are exact and each ends at 2^23 + 2^16 + D (D = n - 1 >= -1),
+// whose encoding is kDBits + D: its low 16 bits are D mod 2^16 (0xffff for
+// n = 0) with no conversion, and D is one integer subtraction away.
+constexpr float kDInit = 8454143.0f;       // 2^23 + 2^16 - 1
+constexpr uint32_t kDBits = 0x4b010000u;   // encoding of 2^23 + 2^16
+
+__device__ __forceinline__ int enc_d(float x) { return (int)(__float_as_uint(x) - kDBits); }
+
+// cubic_sum of encoded accumulators, every D <= 255: one byte permutation
+// packs the low halves of two encodings
+template <int N>
+__device__ __forceinline__ uint32_t cubic_sum_enc(const v4f32 (&acc)[N])
+{
+    u16x2 p[N][2];
+#pragma unroll
+    for (int n = 0; n < N; n++)
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+            p[n][h] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(__float_as_uint(acc[n][2 * h + 1]),
+                                                                     __float_as_uint(acc[n][2 * h]),
+                                                                     0x05040100u));
+    return cubic_sum_u16<N>(p);
+}
+
+// largest accumulator of N, compared with the encoding of D = 255
+template <int N>
+__device__ __forceinline__ bool enc_over_255(const v4f32 (&acc)[N])
+{
+    float m = acc[0][0];
+#pragma unroll
+    for (int n = 0; n < N; n++)
+#pragma unroll
+        for (int k = 0; k < 4; k++) m = fmaxf(m, acc[n][k]);
+    return m > kDInit + 256.f;
 }
 
 // Lane group g feeds K-chunk t from mask word w = 2 t + (g >> 1): byte b of
@@ -2013,26 +2063,50 @@ __device__ __forceinline__ v4i32 mask_piece(uint32_t raw, int t, uint32_t g, boo
 
 // fp4 operands: v_mfma_scale_f32_16x16x128_f8f6f4 with both operands in e2m1
 // (and unit scales) multiplies 16 x 128 by 128 x 16; lane l supplies row (or
-// column) l % 16, elements 32 (l / 16) .. + 31, eight per register. A mask
-// bit becomes the element 1.0 (code 0b0010) or 0, so every product is 0 or 1
-// and the fp32 sums are exact integers (n <= 32 W < 2^24). One 32-bit mask
-// word fills a lane's four registers: element i of register q is bit 4 i + q
-// (spread_fp4), half the VALU work per bit of the int8 form, and each
-// instruction covers twice its K.
+// column) l % 16, elements 32 (l / 16) .. + 31, eight per register. One
+// 32-bit mask word fills a lane's four registers: element i of register q is
+// bit 4 i + q, for rows and columns alike. A set bit becomes a power of two
+// whose e2m1 code is that bit, moved within its nibble only where needed:
+// column registers 0 to 3 hold 0.5, 1.0, 2.0, 2.0 (codes 0b0001, 0b0010,
+// 0b0100; bit 3 is the sign, so register 3 is shifted) and row registers
+// 2.0, 1.0, 0.5, 0.5. Every product of two set bits is then exactly 1 and
+// the fp32 sums are exact integers (n <= 32 W < 2^24). Columns are spread
+// once per tile and cost five instructions per word (one shift, four ands);
+// rows are spread once per unit. Each instruction covers twice the K of the
+// int8 form.
 typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
 typedef int v8i32 __attribute__((ext_vector_type(8)));
-typedef float v4f32 __attribute__((ext_vector_type(4)));
 constexpr int kFp4 = 4;       // operand format code of e2m1 (A and B)
 constexpr int kScale1 = 127;  // e8m0 scale 2^0
 
-__device__ __forceinline__ v8i32 spread_fp4(uint32_t x, bool keep)
+typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
+// a buffer range of `bytes` bytes from p (p and bytes wave-uniform); raw
+// loads past it return 0
+__device__ __forceinline__ Rsrc mask_rsrc(const uint32_t *p, uint32_t bytes)
 {
-    const uint32_t m = keep ? 0x22222222u : 0u;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(p), 0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ v8i32 spread_col(uint32_t x)
+{
     v8i32 r = {0, 0, 0, 0, 0, 0, 0, 0};
-    r[0] = (int)((x << 1) & m);
-    r[1] = (int)(x & m);
-    r[2] = (int)((x >> 1) & m);
-    r[3] = (int)((x >> 2) & m);
+    r[0] = (int)(x & 0x11111111u);
+    r[1] = (int)(x & 0x22222222u);
+    r[2] = (int)(x & 0x44444444u);
+    r[3] = (int)((x >> 1) & 0x44444444u);
+    return r;
+}
+
+__device__ __forceinline__ v8i32 spread_row(uint32_t x)
+{
+    v8i32 r = {0, 0, 0, 0, 0, 0, 0, 0};
+    r[0] = (int)((x << 2) & 0x44444444u);
+    r[1] = (int)(x & 0x22222222u);
+    r[2] = (int)((x >> 2) & 0x11111111u);
+    r[3] = (int)((x >> 3) & 0x11111111u);
     return r;
 }
 
@@ -2132,9 +2206,9 @@ __device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
 // NC consecutive words, at most NC - 1 of them past the row) and chunk t takes
 // word NC g + t, the same placement for rows and columns; words past the mask
 // width are dropped by the spread. The rows of all four blocks stay in
-// registers (4 NC x 4), so every unit is one pass; accumulators start at -1
-// and the epilogue converts D = n - 1 to integers. MODE 0 sums C(n, 3) (the
-// cubic, divided by 6 once); MODE 3 sums C(n, q) from the workgroup's table
+// registers (4 NC x 4), so every unit is one pass. MODE 0 sums C(n, 3) (the
+// cubic of D = n - 1, divided by 6 once) from encoded accumulators; the
+// other modes start them at -1 and convert D to an integer. MODE 3 sums C(n, q) from the workgroup's table
 // cq (n <= 32 W <= 512). MODE 1 (per vertex of the anchor side) takes C(n, 3)
 // per pair from the table c3, adds each column's total to the wave's colacc
 // (one lane per column) and keeps 16 row totals per lane, which are summed
@@ -2155,44 +2229,52 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
     const uint32_t rbase = un.rb * kWave;
     const uint32_t wf = g * NC;                           // first word of the lane's piece
     const uint32_t ws = wf < (uint32_t)W ? wf : (uint32_t)W - 1;
-    auto words = [&](uint32_t row, uint32_t (&raw)[NC]) {
-        const uint32_t *p = M + (row * (uint32_t)W + ws);
-        if constexpr (NC == 4) {
-            const u32x4a4 v = *reinterpret_cast<const u32x4a4 *>(p);
+    // The anchor's masks as two buffer ranges from M, rows below a.k and
+    // columns below un.c1 (k W < 2^22 bytes): a load past its range returns
+    // 0, so rows and columns past the candidates take no test. A lane reads
+    // words wf .. wf + NC - 1 of its row, in one load where W is a multiple
+    // of 4 (all of them then lie in the row); otherwise word by word, and kw
+    // clears the words at W or past it (another row's, or 0).
+    const Rsrc rrow = mask_rsrc(M, a.k * (uint32_t)W * 4u);
+    const Rsrc rcol = mask_rsrc(M, un.c1 * (uint32_t)W * 4u);
+    const uint32_t lofs = (r16 * (uint32_t)W + wf) * 4u;
+    uint32_t kw[NC];
+#pragma unroll
+    for (int t = 0; t < NC; t++) kw[t] = W % 4 == 0 || wf + t < (uint32_t)W ? ~0u : 0u;
+    auto words = [&](const Rsrc &r, uint32_t row0, uint32_t (&raw)[NC]) {
+        const int off = (int)(row0 * ((uint32_t)W * 4u) + lofs);
+        if constexpr (W % 4 == 0 && NC == 4) {
+            const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
             raw[0] = v.x; raw[1] = v.y; raw[2] = v.z; raw[3] = v.w;
+        } else if constexpr (W % 4 == 0 && NC == 2) {
+            const v2u32 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+            raw[0] = v.x; raw[1] = v.y;
         } else {
 #pragma unroll
-            for (int t = 0; t < NC; t++) raw[t] = p[t];
+            for (int t = 0; t < NC; t++) raw[t] = __builtin_amdgcn_raw_buffer_load_b32(r, off + 4 * t, 0, 0);
         }
-    };
-    auto piece = [&](uint32_t raw, int t, bool valid) {
-        return spread_fp4(raw, valid && wf + t < (uint32_t)W);
     };
     // MODE 4 and 5: the rows meet the masks xm and ym of the candidates
     // chosen before them (the same mask for MODE 4; same word layout)
     uint32_t xw[NC];
 #pragma unroll
-    for (int t = 0; t < NC; t++) xw[t] = MODE >= 4 ? xm[ws + t] & ym[ws + t] : ~0u;
+    for (int t = 0; t < NC; t++) xw[t] = (MODE >= 4 ? xm[ws + t] & ym[ws + t] : ~0u) & kw[t];
     v8i32 A[SB][NC];
 #pragma unroll
     for (int sb = 0; sb < SB; sb++) {
-        const uint32_t i = rbase + 16 * sb + r16;
         uint32_t raw[NC];
-        words(i < a.k ? i : a.k - 1, raw);
+        words(rrow, rbase + 16 * sb, raw);
 #pragma unroll
-        for (int t = 0; t < NC; t++) A[sb][t] = piece(raw[t] & xw[t], t, i < a.k);
+        for (int t = 0; t < NC; t++) A[sb][t] = spread_row(raw[t] & xw[t]);
     }
-    auto col_words = [&](uint32_t j0, uint32_t (&raw)[NC]) {
-        const uint32_t j = j0 + r16;
-        words(j < un.c1 ? j : un.c1 - 1, raw);
-    };
+    auto col_words = [&](uint32_t j0, uint32_t (&raw)[NC]) { words(rcol, j0, raw); };
     auto products = [&](const uint32_t (&raw)[NC], uint32_t j0, v4f32 (&acc)[SB]) {
-        const bool vj = j0 + r16 < un.c1;
+        constexpr float a0 = MODE == 0 ? kDInit : -1.f;
 #pragma unroll
-        for (int sb = 0; sb < SB; sb++) acc[sb] = (v4f32){-1.f, -1.f, -1.f, -1.f};
+        for (int sb = 0; sb < SB; sb++) acc[sb] = (v4f32){a0, a0, a0, a0};
 #pragma unroll
         for (int t = 0; t < NC; t++) {
-            const v8i32 B = piece(raw[t], t, vj);
+            const v8i32 B = spread_col(W % 4 == 0 ? raw[t] : raw[t] & kw[t]);
 #pragma unroll
             for (int sb = 0; sb < SB; sb++) acc[sb] = mfma_fp4(A[sb][t], B, acc[sb]);
         }
@@ -2234,12 +2316,17 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
                 }
             return t;
         } else {
+            // encoded accumulators; masks over 9 to 16 words take the packed
+            // form in a tile whose pairs all meet in at most 256 bits (a
+            // wave-uniform test), as do masks up to 8 words always
+            const bool full = j0 + 16 <= rbase;   // every column before every row
+            if (full && (W <= 8 || !__any(enc_over_255<SB>(acc)))) return cubic_sum_enc<SB>(acc);
             v4i32 d[SB];
 #pragma unroll
             for (int sb = 0; sb < SB; sb++)
 #pragma unroll
-                for (int e = 0; e < 4; e++) d[sb][e] = (int)acc[sb][e];
-            if (j0 + 16 <= rbase) return cubic_sum<W, SB, false>(d, 0, 0);
+                for (int e = 0; e < 4; e++) d[sb][e] = enc_d(acc[sb][e]);
+            if (full) return cubic_sum<W, SB, false>(d, 0, 0);
             return cubic_sum<W, SB, true>(d, j0 + r16, rbase + 4 * g);
         }
     };
@@ -2336,7 +2423,7 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
     for (int tt = 0; tt < 4; tt++)
 #pragma unroll
         for (int sb = 0; sb < 4; sb++)
-            acc[tt][sb] = MODE == 0 ? (v4f32){-1.f, -1.f, -1.f, -1.f} : (v4f32){0.f, 0.f, 0.f, 0.f};
+            acc[tt][sb] = MODE == 0 ? (v4f32){kDInit, kDInit, kDInit, kDInit} : (v4f32){0.f, 0.f, 0.f, 0.f};
     const uint32_t Wf = W & ~(KW - 1);
     for (uint32_t w0 = 0; w0 < Wf; w0 += KW) {
         const uint32_t wl = w0 + 4 * g;
@@ -2366,11 +2453,11 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
         for (int t = 0; t < 4; t++) {
             v8i32 A[4];
 #pragma unroll
-            for (int sb = 0; sb < 4; sb++) A[sb] = spread_fp4(ra[sb][t], rv[sb]);
+            for (int sb = 0; sb < 4; sb++) A[sb] = spread_row(rv[sb] ? ra[sb][t] : 0u);
 #pragma unroll
             for (int tt = 0; tt < 4; tt++) {
                 if ((uint32_t)tt >= nt) break;
-                const v8i32 B = spread_fp4(rc[tt][t], cv[tt]);
+                const v8i32 B = spread_col(cv[tt] ? rc[tt][t] : 0u);
 #pragma unroll
                 for (int sb = 0; sb < 4; sb++) acc[tt][sb] = mfma_fp4(A[sb], B, acc[tt][sb]);
             }
@@ -2383,11 +2470,15 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
         const uint32_t xy = MODE >= 4 ? xm[wa] & ym[wa] : ~0u;
         v8i32 A[4];
 #pragma unroll
-        for (int sb = 0; sb < 4; sb++) A[sb] = spread_fp4(M[ro[sb] + wa] & xy, rv[sb] && kw);
+        for (int sb = 0; sb < 4; sb++) {
+            const uint32_t x = M[ro[sb] + wa] & xy;
+            A[sb] = spread_row(rv[sb] && kw ? x : 0u);
+        }
 #pragma unroll
         for (int tt = 0; tt < 4; tt++) {
             if ((uint32_t)tt >= nt) break;
-            const v8i32 B = spread_fp4(M[co[tt] + wa], cv[tt] && kw);
+            const uint32_t x = M[co[tt] + wa];
+            const v8i32 B = spread_col(cv[tt] && kw ? x : 0u);
 #pragma unroll
             for (int sb = 0; sb < 4; sb++) acc[tt][sb] = mfma_fp4(A[sb], B, acc[tt][sb]);
         }
@@ -2440,28 +2531,28 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
     uint64_t sum = 0;
     bool ovf = false;
     if constexpr (MODE == 0) {
-        // The accumulators hold D = n - 1. Masks this wide still meet in at
-        // most 256 bits in nearly every tile (their members are sparse): a
-        // column tile whose 1024 pairs all have D <= 255 takes the packed
-        // 16-bit cubic of the narrow masks (exact there), any other tile the
-        // 64-bit one. The test is wave-uniform.
+        // The accumulators are encoded (D = n - 1). Masks this wide still
+        // meet in at most 256 bits in nearly every tile (their members are
+        // sparse): a column tile whose 1024 pairs all have D <= 255 takes the
+        // packed 16-bit cubic of the narrow masks (exact there), any other
+        // tile the 64-bit one. The test is wave-uniform.
 #pragma unroll
         for (int tt = 0; tt < 4; tt++) {
             if ((uint32_t)tt >= nt) break;
             const uint32_t j = un.c0 + 16 * tt + r16;
+            const bool diag = un.c0 + 16 * tt + 16 > rbase;   // some column j >= some row
+            const bool small = !__any(enc_over_255<4>(acc[tt]));
+            if (small && !diag) {
+                sum += cubic_sum_enc<4>(acc[tt]);
+                continue;
+            }
             v4i32 d[4];
-            int dmax = -1;
 #pragma unroll
             for (int sb = 0; sb < 4; sb++)
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    d[sb][e] = (int)acc[tt][sb][e];
-                    dmax = max(dmax, d[sb][e]);
-                }
-            if (!__any(dmax > 255)) {
-                const bool diag = un.c0 + 16 * tt + 16 > rbase;   // some column j >= some row
-                sum += diag ? cubic_sum<8, 4, true>(d, j, rbase + 4 * g)
-                            : cubic_sum<8, 4, false>(d, 0, 0);
+                for (int e = 0; e < 4; e++) d[sb][e] = enc_d(acc[tt][sb][e]);
+            if (small) {
+                sum += cubic_sum<8, 4, true>(d, j, rbase + 4 * g);
             } else {
 #pragma unroll
                 for (int sb = 0; sb < 4; sb++)

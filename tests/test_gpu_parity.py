@@ -99,6 +99,47 @@ def test_full_masks_every_width(ctx, w):
     assert ctx.count_global(build(ctx, g, 1 << 4)) == want
 
 
+def _width_mix(w, seed):
+    """Random masks of exactly w words: 40 U vertices of degree 32 w - 3 over
+    V[0, 48 w), and 150 of degree 32 w - 1 that take a random share of their
+    neighbours there (0 to all of them) and the rest from V[48 w, 96 w), so
+    that candidate pairs meet in anywhere from 0 to most of their bits."""
+    rng = np.random.default_rng(seed)
+    d_a, d_c, half = 32 * w - 3, 32 * w - 1, 48 * w
+    eu, ev = [], []
+    for u in range(40):
+        eu.append(np.full(d_a, u)); ev.append(rng.choice(half, d_a, replace=False))
+    for u in range(40, 190):
+        k = int(rng.integers(0, d_c + 1))
+        eu.append(np.full(d_c, u))
+        ev.append(np.concatenate([rng.choice(half, k, replace=False),
+                                  half + rng.choice(half, d_c - k, replace=False)]))
+    u = np.concatenate(eu); v = np.concatenate(ev)
+    s = np.where(rng.random(u.size) < 0.8, 1, -1).astype(np.int8)
+    return G._finish(190, 2 * half, u, v, s)
+
+
+@pytest.mark.parametrize("w", list(range(1, 21)))
+def test_every_width_random_vs_oracle(ctx, oracle, w):
+    """Every mask width of the triplet kernels up to 20 words (the int8 and
+    fp4 forms, word-by-word and whole loads, the 16-bit epilogue and its
+    wider fallback, the wide path): totals and per-vertex counts of both
+    sides against the oracle. Anchors have 189 candidates in two classes, so
+    row blocks and column tiles are ragged."""
+    g = _width_mix(w, 100 + w)
+    say("every width", w)
+    ru = oracle.count_bbvp(g, 0, threads=8, per_vertex=True)
+    rv = oracle.count_bbvp(g, 1, threads=8, per_vertex=True)
+    assert ru["total"] == rv["total"] > 0
+    h = build(ctx, g, 1 << 4)
+    assert ctx.count_global(h) == ru["total"]
+    pu, t = ctx.count_per_vertex(h, 0)
+    assert t == ru["total"] and (pu == ru["per_vertex"]).all()
+    pv, t = ctx.count_per_vertex(h, 1)
+    assert t == ru["total"] and (pv == rv["per_vertex"]).all()
+    h.free()
+
+
 # --------------------------------------------------------- random tiny
 def test_tiny_random_batch_vs_bruteforce(ctx, oracle):
     say("tiny batch")
