@@ -266,9 +266,16 @@ bbc_status bbc_set_timing(bbc_ctx *ctx, int enable);
  *   BBC_HOOK_PRELOAD_COUNT: every graph's 64-bit accumulator starts at
  *     (uint64_t)value instead of 0, so a count whose true value plus the
  *     preload passes 2^63 - 1 returns BBC_E_OVERFLOW (the carry path).
- * Errors: BBC_E_INVAL (null context or unknown hook). */
+ *   BBC_HOOK_LAUNCH_SHAPE: every count (batched ones too, instead of the
+ *     tuned shape) uses the launch shape given by value: bits 0-31 the unit
+ *     column base (a power of two, 256 to 16384; a unit of w-word masks has
+ *     about base / w columns), bits 32-39 triplet workgroups per compute
+ *     unit (1 to 16), bits 40-47 tier-A pair workgroups per compute unit
+ *     (1 to 8). Counts are unchanged; other values return BBC_E_INVAL.
+ * Errors: BBC_E_INVAL (null context, unknown hook or invalid value). */
 #define BBC_HOOK_NO_WINDOW_TIER 1
 #define BBC_HOOK_PRELOAD_COUNT  2
+#define BBC_HOOK_LAUNCH_SHAPE   3
 bbc_status bbc_set_test_hook(bbc_ctx *ctx, int hook, int64_t value);
 
 const char *bbc_status_string(bbc_status s);

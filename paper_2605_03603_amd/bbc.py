@@ -43,6 +43,13 @@ EXPORTED = ["bbc_ctx_create", "bbc_ctx_destroy", "bbc_build_csr", "bbc_build_csr
 
 BBC_HOOK_NO_WINDOW_TIER = 1
 BBC_HOOK_PRELOAD_COUNT = 2
+BBC_HOOK_LAUNCH_SHAPE = 3
+
+
+def launch_shape(chunk_base: int, grid_t_per_cu: int, grid_a_per_cu: int = 2) -> int:
+    """Value of BBC_HOOK_LAUNCH_SHAPE for a unit column base, triplet and
+    tier-A workgroups per compute unit."""
+    return chunk_base | (grid_t_per_cu << 32) | (grid_a_per_cu << 40)
 
 
 class BBCError(RuntimeError):

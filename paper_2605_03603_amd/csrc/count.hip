@@ -2260,13 +2260,21 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
 #pragma unroll
     for (int t = 0; t < NC; t++) xw[t] = (MODE >= 4 ? xm[ws + t] & ym[ws + t] : ~0u) & kw[t];
     v8i32 A[SB][NC];
+    uint32_t pmax = 0;   // most set bits in one of the lane's row pieces
 #pragma unroll
     for (int sb = 0; sb < SB; sb++) {
-        uint32_t raw[NC];
+        uint32_t raw[NC], pc = 0;
         words(rrow, rbase + 16 * sb, raw);
 #pragma unroll
-        for (int t = 0; t < NC; t++) A[sb][t] = spread_row(raw[t] & xw[t]);
+        for (int t = 0; t < NC; t++) {
+            A[sb][t] = spread_row(raw[t] & xw[t]);
+            if constexpr (MODE == 0 && W > 8) pc += __popc(raw[t] & xw[t]);
+        }
+        pmax = max(pmax, pc);
     }
+    // MODE 0, masks over 8 words: when no row piece has more than 64 bits
+    // (no row more than 256), no pair of the unit meets in more than 256
+    const bool rows_small = MODE == 0 && W > 8 && !__any(pmax > 64u);
     auto col_words = [&](uint32_t j0, uint32_t (&raw)[NC]) { words(rcol, j0, raw); };
     auto products = [&](const uint32_t (&raw)[NC], uint32_t j0, v4f32 (&acc)[SB]) {
         constexpr float a0 = MODE == 0 ? kDInit : -1.f;
@@ -2317,10 +2325,11 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
             return t;
         } else {
             // encoded accumulators; masks over 9 to 16 words take the packed
-            // form in a tile whose pairs all meet in at most 256 bits (a
-            // wave-uniform test), as do masks up to 8 words always
+            // form in a unit whose rows have at most 256 bits, else in a tile
+            // whose pairs all meet in at most 256 bits (wave-uniform tests),
+            // as do masks up to 8 words always
             const bool full = j0 + 16 <= rbase;   // every column before every row
-            if (full && (W <= 8 || !__any(enc_over_255<SB>(acc)))) return cubic_sum_enc<SB>(acc);
+            if (full && (W <= 8 || rows_small || !__any(enc_over_255<SB>(acc)))) return cubic_sum_enc<SB>(acc);
             v4i32 d[SB];
 #pragma unroll
             for (int sb = 0; sb < SB; sb++)
@@ -2384,8 +2393,8 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
 // group g holds words 4 g .. 4 g + 3 of its row or column (one 16-byte load)
 // and chunk t takes word 4 g + t, the same placement for rows and columns.
 // The last W mod 16 words go by chunks of four consecutive words (chunk t,
-// group g: word 4 t + g), so that no chunk past the mask is issued and no
-// word past a row is read. n can reach 32 W, so the epilogue is 64-bit:
+// group g: word 4 t + g), so that no chunk past the mask is issued; a word
+// past the row is cleared. n can reach 32 W, so the epilogue is 64-bit:
 // n (n - 1) (n - 2) = n ((n^2 + 2) - 3 n), which is 0 for n = 0, 1, 2 with
 // unsigned wrap-around. MODE 3-5 take C(n, q) instead (the table, or the
 // exact 64-bit product above its end), and MODE 4-5 meet the row words with
@@ -2405,19 +2414,18 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
     const uint32_t *M = masks + a.mask_off;
     const uint32_t rbase = un.rb * kWave;
     const uint32_t nt = (un.c1 - un.c0 + 15) / 16;   // column tiles (<= 4)
-    // word offsets of the lane's rows and columns (k W < 2^32), clamped to
-    // valid candidates
+    // The anchor's masks as buffer ranges from the K-block's first word on,
+    // rows below a.k and columns below un.c1 (k W < 2^32 bytes): a load past
+    // its range returns 0, so rows and columns past the candidates take no
+    // test. ro and co: byte offsets of word 4 g of the lane's rows and
+    // columns. A full K-block reads words w0 + 4 g .. + 3, all in the row.
     uint32_t ro[4], co[4];
-    bool rv[4], cv[4];
 #pragma unroll
     for (int sb = 0; sb < 4; sb++) {
-        const uint32_t i = rbase + 16 * sb + r16;
-        rv[sb] = i < a.k;
-        ro[sb] = (rv[sb] ? i : a.k - 1) * W;
-        const uint32_t j = un.c0 + 16 * sb + r16;
-        cv[sb] = j < un.c1;
-        co[sb] = (cv[sb] ? j : un.c1 - 1) * W;
+        ro[sb] = ((rbase + 16 * sb + r16) * W + 4 * g) * 4u;
+        co[sb] = ((un.c0 + 16 * sb + r16) * W + 4 * g) * 4u;
     }
+    const uint32_t rbytes = a.k * W * 4u, cbytes = un.c1 * W * 4u;
     v4f32 acc[4][4];
 #pragma unroll
     for (int tt = 0; tt < 4; tt++)
@@ -2426,15 +2434,16 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
             acc[tt][sb] = MODE == 0 ? (v4f32){kDInit, kDInit, kDInit, kDInit} : (v4f32){0.f, 0.f, 0.f, 0.f};
     const uint32_t Wf = W & ~(KW - 1);
     for (uint32_t w0 = 0; w0 < Wf; w0 += KW) {
-        const uint32_t wl = w0 + 4 * g;
+        const Rsrc rr = mask_rsrc(M + w0, rbytes - 4u * w0), rc_ = mask_rsrc(M + w0, cbytes - 4u * w0);
         uint32_t ra[4][4], rc[4][4];
 #pragma unroll
         for (int sb = 0; sb < 4; sb++) {
-            const u32x4a4 v = *reinterpret_cast<const u32x4a4 *>(M + (ro[sb] + wl));
+            const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(rr, (int)ro[sb], 0, 0);
             ra[sb][0] = v.x; ra[sb][1] = v.y; ra[sb][2] = v.z; ra[sb][3] = v.w;
         }
         if constexpr (MODE >= 4) {
             // the rows meet the masks of the candidates chosen before them
+            const uint32_t wl = w0 + 4 * g;
             const u32x4a4 x = *reinterpret_cast<const u32x4a4 *>(xm + wl);
             const u32x4a4 y = *reinterpret_cast<const u32x4a4 *>(ym + wl);
             const uint32_t xy[4] = {x.x & y.x, x.y & y.y, x.z & y.z, x.w & y.w};
@@ -2446,39 +2455,42 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
 #pragma unroll
         for (int tt = 0; tt < 4; tt++) {
             if ((uint32_t)tt >= nt) break;
-            const u32x4a4 v = *reinterpret_cast<const u32x4a4 *>(M + (co[tt] + wl));
+            const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(rc_, (int)co[tt], 0, 0);
             rc[tt][0] = v.x; rc[tt][1] = v.y; rc[tt][2] = v.z; rc[tt][3] = v.w;
         }
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             v8i32 A[4];
 #pragma unroll
-            for (int sb = 0; sb < 4; sb++) A[sb] = spread_row(rv[sb] ? ra[sb][t] : 0u);
+            for (int sb = 0; sb < 4; sb++) A[sb] = spread_row(ra[sb][t]);
 #pragma unroll
             for (int tt = 0; tt < 4; tt++) {
                 if ((uint32_t)tt >= nt) break;
-                const v8i32 B = spread_col(cv[tt] ? rc[tt][t] : 0u);
+                const v8i32 B = spread_col(rc[tt][t]);
 #pragma unroll
                 for (int sb = 0; sb < 4; sb++) acc[tt][sb] = mfma_fp4(A[sb], B, acc[tt][sb]);
             }
         }
     }
+    // the last W mod 16 words by chunks of four: lane group g takes word
+    // w + g, at byte offset ro - 12 g from the chunk's first word; a word at
+    // W or past it (another row's, or 0) is cleared
     for (uint32_t w = Wf; w < W; w += 4) {
+        const Rsrc rr = mask_rsrc(M + w, rbytes - 4u * w), rc_ = mask_rsrc(M + w, cbytes - 4u * w);
         const uint32_t wg = w + g;
         const bool kw = wg < W;
-        const uint32_t wa = kw ? wg : W - 1;
-        const uint32_t xy = MODE >= 4 ? xm[wa] & ym[wa] : ~0u;
+        const uint32_t xy = MODE >= 4 ? xm[kw ? wg : W - 1] & ym[kw ? wg : W - 1] : ~0u;
         v8i32 A[4];
 #pragma unroll
         for (int sb = 0; sb < 4; sb++) {
-            const uint32_t x = M[ro[sb] + wa] & xy;
-            A[sb] = spread_row(rv[sb] && kw ? x : 0u);
+            const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(rr, (int)(ro[sb] - 12u * g), 0, 0) & xy;
+            A[sb] = spread_row(kw ? x : 0u);
         }
 #pragma unroll
         for (int tt = 0; tt < 4; tt++) {
             if ((uint32_t)tt >= nt) break;
-            const uint32_t x = M[co[tt] + wa];
-            const v8i32 B = spread_col(cv[tt] && kw ? x : 0u);
+            const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(rc_, (int)(co[tt] - 12u * g), 0, 0);
+            const v8i32 B = spread_col(kw ? x : 0u);
 #pragma unroll
             for (int sb = 0; sb < 4; sb++) acc[tt][sb] = mfma_fp4(A[sb], B, acc[tt][sb]);
         }

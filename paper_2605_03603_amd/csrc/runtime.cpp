@@ -398,6 +398,8 @@ struct bbc_ctx {
     // test hooks (bbc_set_test_hook): host-forced conditions
     bool hook_no_window = false;
     uint64_t hook_preload = 0;
+    bool hook_shape_set = false;
+    Shape hook_shape;
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     std::map<uint64_t, Shape> tuned;   // autotuner cache by size class
     struct SideTime { float ms[2] = {0, 0}; bool tried[2] = {false, false}; };
@@ -1133,7 +1135,8 @@ void results_from_host(Work &w, const GraphSet &set, uint32_t g0, uint32_t g1, i
     }
 }
 
-Shape default_shape() { return Shape(); }
+// The fixed launch shape of single-graph counts (a test hook may force another)
+Shape default_shape(const bbc_ctx *ctx) { return ctx->hook_shape_set ? ctx->hook_shape : Shape(); }
 
 // One synchronous count of a graph range; grows buffers and retries as needed.
 void count_sync(bbc_ctx *ctx, Work &w, GraphSet &set, uint32_t g0, uint32_t g1, int mode,
@@ -1196,6 +1199,7 @@ uint64_t size_class(const GraphSet &set)
 // per size class.
 Shape tune_shape(bbc_ctx *ctx, Work &w, GraphSet &set, hipStream_t s)
 {
+    if (ctx->hook_shape_set) return ctx->hook_shape;
     const uint64_t key = size_class(set);
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) return it->second;
@@ -1449,7 +1453,7 @@ void serve_worker(bbc_ctx *ctx, int slot)
                 std::vector<int64_t> res(rs.size());
                 bbc_status st = guard(nullptr, [&] {
                     auto set = build_set(ctx, in, s, w.bhost);
-                    count_sync(ctx, w, *set, 0, set->G, 0, default_shape(), s, res.data());
+                    count_sync(ctx, w, *set, 0, set->G, 0, default_shape(ctx), s, res.data());
                 });
                 if (st == BBC_E_NOMEM && others_in_flight()) {
                     for (auto &r : rs) settle(r, st, 0);
@@ -1462,7 +1466,7 @@ void serve_worker(bbc_ctx *ctx, int slot)
                         int64_t v = 0;
                         bbc_status st1 = guard(nullptr, [&] {
                             auto set = build_set(ctx, one, s, w.bhost);
-                            count_sync(ctx, w, *set, 0, 1, 0, default_shape(), s, &v);
+                            count_sync(ctx, w, *set, 0, 1, 0, default_shape(ctx), s, &v);
                         });
                         settle(rs[i], st1, v);
                     }
@@ -1474,7 +1478,7 @@ void serve_worker(bbc_ctx *ctx, int slot)
         for (auto &r : pre) {
             int64_t v = 0;
             bbc_status st = guard(nullptr, [&] {
-                count_sync(ctx, w, *r->set, r->idx, r->idx + 1, 0, default_shape(), s, &v);
+                count_sync(ctx, w, *r->set, r->idx, r->idx + 1, 0, default_shape(ctx), s, &v);
             });
             settle(r, st, v);
         }
@@ -1742,7 +1746,7 @@ bbc_status bbc_count_global(bbc_ctx *ctx, const bbc_graph *g, int p, int q, int6
         const int mode = global_count_mode(g, p, q, &nb);
         (void)hipSetDevice(ctx->device);
         int64_t v = 0;
-        count_sync(ctx, ctx->work, *g->set, g->idx, g->idx + 1, mode, default_shape(), ctx->stream,
+        count_sync(ctx, ctx->work, *g->set, g->idx, g->idx + 1, mode, default_shape(ctx), ctx->stream,
                    &v, (uint32_t)nb);
         *out_count = v;
     });
@@ -1767,7 +1771,7 @@ bbc_status bbc_count_global_noalloc(bbc_ctx *ctx, const bbc_graph *g, int p, int
         w.arena = &arena;
         w.host.use_external(g_noalloc_host, sizeof(g_noalloc_host));
         int64_t v = 0;
-        count_sync(ctx, w, *g->set, g->idx, g->idx + 1, mode, default_shape(), ctx->stream, &v,
+        count_sync(ctx, w, *g->set, g->idx, g->idx + 1, mode, default_shape(ctx), ctx->stream, &v,
                    (uint32_t)nb);
         *out_count = v;
     });
@@ -1912,7 +1916,7 @@ bbc_status bbc_count_per_vertex(bbc_ctx *ctx, const bbc_graph *g, int p, int q, 
         const GraphDesc &d = set.desc[g->idx];
         const int mode = (uint32_t)side == d.side ? 1 : 2;
         int64_t v = 0;
-        count_sync(ctx, ctx->work, set, g->idx, g->idx + 1, mode, default_shape(), ctx->stream, &v);
+        count_sync(ctx, ctx->work, set, g->idx, g->idx + 1, mode, default_shape(ctx), ctx->stream, &v);
         Work &w = ctx->work;
         const int out_dev = device_of_pointer(out_per_vertex);
         if (out_dev >= 0 && out_dev != ctx->device)
@@ -2020,7 +2024,7 @@ bbc_status bbc_count_batch(bbc_ctx *ctx, const bbc_graph *const *graphs, uint32_
             uint32_t j = i + 1;
             while (j < n_graphs && graphs[j]->set.get() == set && graphs[j]->idx == graphs[j - 1]->idx + 1) j++;
             count_sync(ctx, ctx->work, *set, graphs[i]->idx, graphs[j - 1]->idx + 1, 0,
-                       default_shape(), ctx->stream, res.data() + i);
+                       default_shape(ctx), ctx->stream, res.data() + i);
             i = j;
         }
         std::copy(res.begin(), res.end(), out_counts);
@@ -2138,6 +2142,21 @@ bbc_status bbc_set_test_hook(bbc_ctx *ctx, int hook, int64_t value)
     switch (hook) {
         case BBC_HOOK_NO_WINDOW_TIER: ctx->hook_no_window = value != 0; return BBC_OK;
         case BBC_HOOK_PRELOAD_COUNT: ctx->hook_preload = (uint64_t)value; return BBC_OK;
+        case BBC_HOOK_LAUNCH_SHAPE: {
+            if (value == 0) { ctx->hook_shape_set = false; return BBC_OK; }
+            const uint64_t v = (uint64_t)value;
+            Shape sh;
+            sh.chunk_base = (uint32_t)(v & 0xffffffffu);
+            sh.grid_t_per_cu = (uint32_t)((v >> 32) & 0xffu);
+            sh.grid_a_per_cu = (uint32_t)((v >> 40) & 0xffu);
+            const bool pow2 = (sh.chunk_base & (sh.chunk_base - 1)) == 0;
+            if (!pow2 || sh.chunk_base < 256 || sh.chunk_base > 16384 || sh.grid_t_per_cu < 1 ||
+                sh.grid_t_per_cu > 16 || sh.grid_a_per_cu < 1 || sh.grid_a_per_cu > 8 || (v >> 48))
+                return BBC_E_INVAL;
+            ctx->hook_shape = sh;
+            ctx->hook_shape_set = true;
+            return BBC_OK;
+        }
         default: return BBC_E_INVAL;
     }
 }

@@ -140,6 +140,34 @@ def test_every_width_random_vs_oracle(ctx, oracle, w):
     h.free()
 
 
+def test_launch_shapes_same_count(ctx, oracle, B):
+    """The unit column base and the workgroups per compute unit change how
+    the work is cut and spread, never the count: config 1 seed 2 and random
+    masks of 6 and 13 words, totals and anchor-side per-vertex counts, under
+    the extreme shapes, against the oracle. Invalid shapes are refused."""
+    gs = [G.config1(2), _width_mix(6, 206), _width_mix(13, 213)]
+    want = [oracle.count_bbvp(g, 0, threads=8, per_vertex=True) for g in gs]
+    hs = [build(ctx, g, 1 << 4) for g in gs]
+    try:
+        for cb, gt, ga in [(256, 1, 1), (16384, 16, 8), (512, 3, 2), (4096, 9, 4)]:
+            say("launch shape", cb, gt, ga)
+            ctx.set_test_hook(B.BBC_HOOK_LAUNCH_SHAPE, B.launch_shape(cb, gt, ga))
+            for h, r in zip(hs, want):
+                assert ctx.count_global(h) == r["total"]
+                pu, t = ctx.count_per_vertex(h, 0)
+                assert t == r["total"] and (pu == r["per_vertex"]).all()
+        for bad in [B.launch_shape(3000, 4), B.launch_shape(128, 4), B.launch_shape(32768, 4),
+                    B.launch_shape(2048, 0), B.launch_shape(2048, 17), B.launch_shape(2048, 4, 9),
+                    B.launch_shape(2048, 4) | (1 << 50)]:
+            with pytest.raises(B.BBCError):
+                ctx.set_test_hook(B.BBC_HOOK_LAUNCH_SHAPE, bad)
+    finally:
+        ctx.set_test_hook(B.BBC_HOOK_LAUNCH_SHAPE, 0)
+    for h, r in zip(hs, want):
+        assert ctx.count_global(h) == r["total"]
+        h.free()
+
+
 # --------------------------------------------------------- random tiny
 def test_tiny_random_batch_vs_bruteforce(ctx, oracle):
     say("tiny batch")
