@@ -418,6 +418,7 @@ struct bbc_ctx {
     std::unordered_map<bbc_ticket, std::shared_ptr<Request>> requests;
     uint64_t next_ticket = 1;
     uint64_t admitted_bytes = 0;    // reservations of the batches in flight
+    int serve_large = 0;            // workers holding a large request
     uint64_t peak_admitted = 0;
     uint64_t peak_queued = 0;
     // graph handles the caller holds (released by bbc_graph_free or on destroy)
@@ -746,6 +747,12 @@ struct CountReq {
     uint32_t g0, g1;        // graph range
     int mode;               // 0 totals, 1 per vertex of S, 2 per vertex of O, 3 totals for q > 3
     uint32_t q;             // mode 3: vertices taken on the opposite side
+    // anchors of global rank [alo, ahi) only (alo < ahi; else the whole range
+    // of graphs g0 .. g1 - 1): every count of the method is a sum over its
+    // anchors, so the counts of a partition of the anchors add up to the
+    // graph's count
+    uint32_t alo = 0, ahi = 0;
+    bool preload = true;    // the accumulator preload of the test hook applies
 };
 
 uint64_t hint_key(const GraphSet &set)
@@ -1002,6 +1009,7 @@ LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
     L.P.ws = ws;
     L.P.a0 = set.desc[r.g0].s_base;
     L.P.a1 = set.desc[r.g1 - 1].s_base + set.desc[r.g1 - 1].n_s;
+    if (r.alo < r.ahi) { L.P.a0 = r.alo; L.P.a1 = r.ahi; }
     // per-vertex counts keep one LDS sum per unit column: their units stay narrower
     L.P.chunk_base = std::min(shp.chunk_base, r.mode == 1 ? max_unit_chunk() : 16384u);
     L.P.gH = w.gH; L.P.glog2h = w.glog2; L.P.gmaxd = w.gmaxd; L.P.gkmax = w.gkmax;
@@ -1025,7 +1033,7 @@ LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
     L.P.wv_mask_chunk = ch.wv_mask; L.P.wv_cand_chunk = ch.wv_cand;
     w.mask_chunk = ch.mask; w.cand_chunk = ch.cand;
     w.wv_mask_chunk = ch.wv_mask; w.wv_cand_chunk = ch.wv_cand;
-    L.preload = ctx->hook_preload;
+    L.preload = r.preload ? ctx->hook_preload : 0;
     return L;
 }
 
@@ -1140,9 +1148,10 @@ Shape default_shape(const bbc_ctx *ctx) { return ctx->hook_shape_set ? ctx->hook
 
 // One synchronous count of a graph range; grows buffers and retries as needed.
 void count_sync(bbc_ctx *ctx, Work &w, GraphSet &set, uint32_t g0, uint32_t g1, int mode,
-                const Shape &shp, hipStream_t s, int64_t *out, uint32_t q = 3)
+                const Shape &shp, hipStream_t s, int64_t *out, uint32_t q = 3, uint32_t alo = 0,
+                uint32_t ahi = 0, bool preload = true)
 {
-    CountReq r{&set, g0, g1, mode, q};
+    CountReq r{&set, g0, g1, mode, q, alo, ahi, preload};
     const bool timed = ctx->timing && s == ctx->stream && &w == &ctx->work;
     const bool tune = set.tune_key && mode == 0 && s == ctx->stream && &w == &ctx->work;
     if (tune && !ctx->tev[0]) {
@@ -1280,6 +1289,15 @@ void count_set_batched(bbc_ctx *ctx, Work &w, GraphSet &set, hipStream_t s, int6
 constexpr int kServeStreams = 4;
 constexpr size_t kServeBatchMax = 4096;
 constexpr uint64_t kServeBatchEdges = 8ull << 20;    // bounds one batch (and the wait of its small requests)
+// A request of kServeLargeEdges edges or more is a batch of its own, at most
+// kServeLargeWorkers workers hold one at a time (small requests behind it may
+// go first), and its count runs in anchor ranges of about kServeChunkEdges
+// edges, one synchronous count each, so that the other workers' batches get
+// the GPU between them instead of waiting for the whole count.
+constexpr uint64_t kServeLargeEdges = 1ull << 20;
+constexpr int kServeLargeWorkers = 2;
+constexpr uint64_t kServeChunkEdges = 512ull << 10;
+constexpr uint32_t kServeMaxChunks = 16;
 
 // Device bytes the build of a COO request of m edges and n vertices may hold
 // at its peak: the uploaded COO, the sort buffers and the CSR it produces
@@ -1337,9 +1355,28 @@ void serve_worker(bbc_ctx *ctx, int slot)
         r->ev.clear(); r->ev.shrink_to_fit();
         r->sign.clear(); r->sign.shrink_to_fit();
     };
+    // the count of graph gi of a set (m edges) as the sum of the counts of
+    // anchor ranges of equal size; the test hook's preload goes to the first
+    auto count_chunked = [&](GraphSet &set, uint32_t gi, uint64_t m, int64_t *out) {
+        const GraphDesc &d = set.desc[gi];
+        const uint32_t n = (uint32_t)std::min<uint64_t>(
+            kServeMaxChunks, std::max<uint64_t>(1, std::min<uint64_t>(m / kServeChunkEdges, d.n_s)));
+        uint64_t tot = 0;
+        for (uint32_t c = 0; c < n; c++) {
+            const uint32_t lo = d.s_base + (uint32_t)((uint64_t)d.n_s * c / n);
+            const uint32_t hi = d.s_base + (uint32_t)((uint64_t)d.n_s * (c + 1) / n);
+            int64_t v = 0;
+            if (lo < hi)
+                count_sync(ctx, w, set, gi, gi + 1, 0, default_shape(ctx), s, &v, 3, lo, hi, c == 0);
+            tot += (uint64_t)v;
+            if (tot > (uint64_t)INT64_MAX) fail(BBC_E_OVERFLOW, "count does not fit in int64");
+        }
+        *out = (int64_t)tot;
+    };
     for (;;) {
         std::vector<std::shared_ptr<Request>> batch;
         uint64_t batch_bytes = 0;
+        bool large = false;
         std::vector<std::shared_ptr<Request>> too_big;
         {
             std::unique_lock<std::mutex> lk(ctx->q_mu);
@@ -1355,15 +1392,30 @@ void serve_worker(bbc_ctx *ctx, int slot)
             const uint64_t held = cap ? ctx->al->live(0) : 0;
             Reservation res;
             uint64_t batch_edges = 0;
-            while (!ctx->queue.empty() && batch.size() < kServeBatchMax) {
-                auto &r = ctx->queue.front();
+            for (size_t qi = 0; qi < ctx->queue.size() && batch.size() < kServeBatchMax;) {
+                const std::shared_ptr<Request> r = ctx->queue[qi];
                 Reservation alone;
                 alone.add(*r);
                 if (cap && held + alone.bytes(ctx->num_cus) > cap) {
                     // can never fit while the caller holds what it holds
                     too_big.push_back(r);
-                    ctx->queue.pop_front();
+                    ctx->queue.erase(ctx->queue.begin() + qi);
                     continue;
+                }
+                if (r->m >= kServeLargeEdges) {
+                    // a batch of its own; with kServeLargeWorkers large
+                    // requests in flight, the small ones behind it go first
+                    if (!batch.empty() || ctx->serve_large >= kServeLargeWorkers) {
+                        qi++;
+                        continue;
+                    }
+                    const uint64_t want = alone.bytes(ctx->num_cus);
+                    if (cap && held + ctx->admitted_bytes + want > cap) break;
+                    batch_bytes = want;
+                    batch.push_back(r);
+                    ctx->queue.erase(ctx->queue.begin() + qi);
+                    large = true;
+                    break;
                 }
                 Reservation next = res;
                 next.add(*r);
@@ -1374,8 +1426,9 @@ void serve_worker(bbc_ctx *ctx, int slot)
                 res = next;
                 batch_bytes = want;
                 batch.push_back(r);
-                ctx->queue.pop_front();
+                ctx->queue.erase(ctx->queue.begin() + qi);
             }
+            if (large) ctx->serve_large++;
             ctx->admitted_bytes += batch_bytes;
             ctx->peak_admitted = std::max(ctx->peak_admitted, ctx->admitted_bytes);
             if (batch.empty() && too_big.empty()) {
@@ -1453,7 +1506,8 @@ void serve_worker(bbc_ctx *ctx, int slot)
                 std::vector<int64_t> res(rs.size());
                 bbc_status st = guard(nullptr, [&] {
                     auto set = build_set(ctx, in, s, w.bhost);
-                    count_sync(ctx, w, *set, 0, set->G, 0, default_shape(ctx), s, res.data());
+                    if (large) count_chunked(*set, 0, rs[0]->m, res.data());
+                    else count_sync(ctx, w, *set, 0, set->G, 0, default_shape(ctx), s, res.data());
                 });
                 if (st == BBC_E_NOMEM && others_in_flight()) {
                     for (auto &r : rs) settle(r, st, 0);
@@ -1478,7 +1532,8 @@ void serve_worker(bbc_ctx *ctx, int slot)
         for (auto &r : pre) {
             int64_t v = 0;
             bbc_status st = guard(nullptr, [&] {
-                count_sync(ctx, w, *r->set, r->idx, r->idx + 1, 0, default_shape(ctx), s, &v);
+                if (large) count_chunked(*r->set, r->idx, r->m, &v);
+                else count_sync(ctx, w, *r->set, r->idx, r->idx + 1, 0, default_shape(ctx), s, &v);
             });
             settle(r, st, v);
         }
@@ -1489,6 +1544,7 @@ void serve_worker(bbc_ctx *ctx, int slot)
         {
             std::lock_guard<std::mutex> lk(ctx->q_mu);
             ctx->admitted_bytes -= batch_bytes;
+            if (large) ctx->serve_large--;
             for (auto it = requeue.rbegin(); it != requeue.rend(); ++it) ctx->queue.push_front(*it);
         }
         for (auto &o : outcomes) finish(o.r, o.st, o.v);

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2605_03603_amd import generators as G
-from tests.gpu_common import build, need_gpu, say
+from tests.gpu_common import build, golden, need_gpu, say
 
 pytestmark = pytest.mark.gpu
 
@@ -154,3 +154,34 @@ def test_graphs_left_to_destroy(B, mix):
     assert live > 0
     ctx.close()                                  # hs[1:] are released here
     other.close()
+
+
+def test_large_requests_counted_in_anchor_ranges(B, mix):
+    """Requests of 2^20 edges or more are batches of their own, at most two
+    in flight, counted as the sum of anchor ranges: config 2 seed 1 at full
+    size (2.06M edges, pinned total) submitted three times as COO among the
+    120 small requests and once as a prebuilt graph, then again with the
+    accumulator preload hook, which applies once per request (not per
+    range)."""
+    gs, want = mix
+    gold = golden("cfg2_seed1.json")
+    big = G.config2(1)
+    assert big.m >= 1 << 20
+    rng = np.random.default_rng(7)
+    with B.Context(0) as ctx:
+        for preload in (0, 12345):
+            say("large served requests, preload", preload)
+            ctx.set_test_hook(B.BBC_HOOK_PRELOAD_COUNT, preload)
+            order = list(range(len(gs))) + [-1, -2, -3]
+            rng.shuffle(order)
+            tickets = []
+            for i in order:
+                g = big if i < 0 else gs[i]
+                tickets.append((i, ctx.submit_coo(g.n_u, g.n_v, g.eu, g.ev, g.sign)))
+            h = build(ctx, big)
+            tp = ctx.submit(h)
+            for i, t in tickets:
+                assert ctx.wait(t) == (gold["total"] if i < 0 else want[i]) + preload
+            assert ctx.wait(tp) == gold["total"] + preload
+            h.free()
+        ctx.set_test_hook(B.BBC_HOOK_PRELOAD_COUNT, 0)
