@@ -27,7 +27,8 @@ Also reported on the same JSON line:
                  graph-replayed count) vs the same graphs one at a time,
                  counts checked against the oracle's
   served         Poisson request stream over the batched mix plus 2% config-2
-                 graphs under a 64 GiB admission cap: p50 / p99 latency,
+                 graphs under a 64 GiB admission cap: p50 / p99 latency
+                 (all requests, and small and config-2 sized ones apart),
                  graphs/s, counts checked against the oracle's
 """
 import argparse
@@ -199,6 +200,7 @@ def run_served(ctx, pool, pool_counts, large, large_counts, n_requests, qps, see
     from collections import deque
     pending = deque()     # (ticket, arrival time, kind, index) in submission order
     lat = []
+    kinds = []
     wrong = 0
     t0 = time.time()
     nxt = 0
@@ -220,6 +222,7 @@ def run_served(ctx, pool, pool_counts, large, large_counts, n_requests, qps, see
                 pending.append((tk, ta, kind, i))
                 continue
             lat.append(time.time() - ta)
+            kinds.append(kind)
             want = pool_counts[i] if kind == "S" else large_counts[i]
             wrong += int(v != want)
             progressed = True
@@ -227,11 +230,21 @@ def run_served(ctx, pool, pool_counts, large, large_counts, n_requests, qps, see
             time.sleep(0.0001)
     wall = time.time() - t0
     lat = np.array(lat) * 1e3
+    kinds = np.array(kinds)
+    small, big = lat[kinds == "S"], lat[kinds == "L"]
+
+    def pct(x, q):
+        return round(float(np.percentile(x, q)), 3) if x.size else None
+
     return {"requests": n_requests, "offered_qps": round(qps, 1),
             "graphs_per_s": round(n_requests / wall, 1),
-            "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "p50_ms": pct(lat, 50),
+            "p99_ms": pct(lat, 99),
             "max_ms": round(float(lat.max()), 3),
+            "small": {"p50_ms": pct(small, 50), "p99_ms": pct(small, 99),
+                      "max_ms": round(float(small.max()), 3) if small.size else None},
+            "large": {"p50_ms": pct(big, 50), "p99_ms": pct(big, 99),
+                      "max_ms": round(float(big.max()), 3) if big.size else None},
             "large_fraction": round(sum(1 for k, _ in picks if k == "L") / n_requests, 4),
             "mem_cap_bytes": SERVE_CAP, "wrong_counts": wrong}
 
@@ -244,7 +257,7 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=400)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--batch-graphs", type=int, default=8192)
-    ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--serve-requests", type=int, default=12000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-config2", action="store_true")
     ap.add_argument("--no-batched", action="store_true")

@@ -419,6 +419,8 @@ struct bbc_ctx {
     uint64_t next_ticket = 1;
     uint64_t admitted_bytes = 0;    // reservations of the batches in flight
     int serve_large = 0;            // workers holding a large request
+    int serve_small_gpu = 0;        // batches of small requests building or counting
+    std::condition_variable small_cv;
     uint64_t peak_admitted = 0;
     uint64_t peak_queued = 0;
     // graph handles the caller holds (released by bbc_graph_free or on destroy)
@@ -1298,6 +1300,26 @@ constexpr uint64_t kServeLargeEdges = 1ull << 20;
 constexpr int kServeLargeWorkers = 2;
 constexpr uint64_t kServeChunkEdges = 512ull << 10;
 constexpr uint32_t kServeMaxChunks = 16;
+// Before its build and each of its ranges, a large request waits for the
+// batches of small requests on the GPU to finish, up to this long in all per
+// request: those batches then run without sharing the GPU with a large count.
+constexpr int kServeYieldUs = 2000;
+
+// memcpy split over up to 4 threads for large copies
+void copy_par(void *dst, const void *src, uint64_t bytes)
+{
+    constexpr uint64_t kMin = 4ull << 20;
+    const uint32_t nt = bytes >= kMin ? 4u : 1u;
+    if (nt == 1) { memcpy(dst, src, bytes); return; }
+    auto part = [&](uint32_t t) {
+        const uint64_t b0 = bytes * t / nt, b1 = bytes * (t + 1) / nt;
+        memcpy((char *)dst + b0, (const char *)src + b0, b1 - b0);
+    };
+    std::vector<std::thread> th;
+    for (uint32_t t = 1; t < nt; t++) th.emplace_back(part, t);
+    part(0);
+    for (auto &x : th) x.join();
+}
 
 // Device bytes the build of a COO request of m edges and n vertices may hold
 // at its peak: the uploaded COO, the sort buffers and the CSR it produces
@@ -1340,6 +1362,26 @@ uint64_t serve_keep_bytes(const bbc_ctx *ctx)
     return cap ? cap / 16 : (1ull << 30);
 }
 
+// Marks a batch of small requests as building or counting on the GPU for
+// its lifetime (large requests wait for such batches at their range
+// boundaries).
+struct SmallOnGpu {
+    bbc_ctx *ctx;
+    explicit SmallOnGpu(bbc_ctx *c) : ctx(c)
+    {
+        std::lock_guard<std::mutex> lk(ctx->q_mu);
+        ctx->serve_small_gpu++;
+    }
+    ~SmallOnGpu()
+    {
+        {
+            std::lock_guard<std::mutex> lk(ctx->q_mu);
+            ctx->serve_small_gpu--;
+        }
+        ctx->small_cv.notify_all();
+    }
+};
+
 void serve_worker(bbc_ctx *ctx, int slot)
 {
     hipStream_t s = ctx->serve_streams[slot];
@@ -1355,6 +1397,16 @@ void serve_worker(bbc_ctx *ctx, int slot)
         r->ev.clear(); r->ev.shrink_to_fit();
         r->sign.clear(); r->sign.shrink_to_fit();
     };
+    int64_t yield_left_us = 0;   // what the large request in hand may still wait
+    auto yield_to_small = [&] {
+        if (yield_left_us <= 0) return;
+        const auto t0 = std::chrono::steady_clock::now();
+        std::unique_lock<std::mutex> lk(ctx->q_mu);
+        ctx->small_cv.wait_for(lk, std::chrono::microseconds(yield_left_us),
+                               [&] { return ctx->serve_small_gpu == 0 || ctx->stopping; });
+        yield_left_us -= std::chrono::duration_cast<std::chrono::microseconds>(
+                             std::chrono::steady_clock::now() - t0).count();
+    };
     // the count of graph gi of a set (m edges) as the sum of the counts of
     // anchor ranges of equal size; the test hook's preload goes to the first
     auto count_chunked = [&](GraphSet &set, uint32_t gi, uint64_t m, int64_t *out) {
@@ -1366,8 +1418,10 @@ void serve_worker(bbc_ctx *ctx, int slot)
             const uint32_t lo = d.s_base + (uint32_t)((uint64_t)d.n_s * c / n);
             const uint32_t hi = d.s_base + (uint32_t)((uint64_t)d.n_s * (c + 1) / n);
             int64_t v = 0;
-            if (lo < hi)
+            if (lo < hi) {
+                yield_to_small();
                 count_sync(ctx, w, set, gi, gi + 1, 0, default_shape(ctx), s, &v, 3, lo, hi, c == 0);
+            }
             tot += (uint64_t)v;
             if (tot > (uint64_t)INT64_MAX) fail(BBC_E_OVERFLOW, "count does not fit in int64");
         }
@@ -1429,6 +1483,7 @@ void serve_worker(bbc_ctx *ctx, int slot)
                 ctx->queue.erase(ctx->queue.begin() + qi);
             }
             if (large) ctx->serve_large++;
+            yield_left_us = large ? kServeYieldUs : 0;
             ctx->admitted_bytes += batch_bytes;
             ctx->peak_admitted = std::max(ctx->peak_admitted, ctx->admitted_bytes);
             if (batch.empty() && too_big.empty()) {
@@ -1489,10 +1544,10 @@ void serve_worker(bbc_ctx *ctx, int slot)
                 memset(sg, 0, sbytes);
                 bool packed = flags & BBC_SIGNS_2BIT_PACKED;
                 for (size_t i = 0; i < rs.size(); i++) {
-                    memcpy(eu + off[i], rs[i]->eu.data(), rs[i]->m * 4);
-                    memcpy(ev + off[i], rs[i]->ev.data(), rs[i]->m * 4);
+                    copy_par(eu + off[i], rs[i]->eu.data(), rs[i]->m * 4);
+                    copy_par(ev + off[i], rs[i]->ev.data(), rs[i]->m * 4);
                     if (!packed) {
-                        memcpy(sg + off[i], rs[i]->sign.data(), rs[i]->m);
+                        copy_par(sg + off[i], rs[i]->sign.data(), rs[i]->m);
                     } else {
                         for (uint64_t e = 0; e < rs[i]->m; e++) {
                             uint32_t code = (rs[i]->sign[e >> 2] >> (2 * (e & 3))) & 3u;
@@ -1505,9 +1560,15 @@ void serve_worker(bbc_ctx *ctx, int slot)
                          sg, flags & ~BBC_IN_DEVICE_PTRS};
                 std::vector<int64_t> res(rs.size());
                 bbc_status st = guard(nullptr, [&] {
-                    auto set = build_set(ctx, in, s, w.bhost);
-                    if (large) count_chunked(*set, 0, rs[0]->m, res.data());
-                    else count_sync(ctx, w, *set, 0, set->G, 0, default_shape(ctx), s, res.data());
+                    if (large) {
+                        yield_to_small();
+                        auto set = build_set(ctx, in, s, w.bhost);
+                        count_chunked(*set, 0, rs[0]->m, res.data());
+                    } else {
+                        SmallOnGpu on(ctx);
+                        auto set = build_set(ctx, in, s, w.bhost);
+                        count_sync(ctx, w, *set, 0, set->G, 0, default_shape(ctx), s, res.data());
+                    }
                 });
                 if (st == BBC_E_NOMEM && others_in_flight()) {
                     for (auto &r : rs) settle(r, st, 0);
@@ -1532,8 +1593,12 @@ void serve_worker(bbc_ctx *ctx, int slot)
         for (auto &r : pre) {
             int64_t v = 0;
             bbc_status st = guard(nullptr, [&] {
-                if (large) count_chunked(*r->set, r->idx, r->m, &v);
-                else count_sync(ctx, w, *r->set, r->idx, r->idx + 1, 0, default_shape(ctx), s, &v);
+                if (large) {
+                    count_chunked(*r->set, r->idx, r->m, &v);
+                } else {
+                    SmallOnGpu on(ctx);
+                    count_sync(ctx, w, *r->set, r->idx, r->idx + 1, 0, default_shape(ctx), s, &v);
+                }
             });
             settle(r, st, v);
         }
@@ -2103,6 +2168,11 @@ bbc_status bbc_submit(bbc_ctx *ctx, const bbc_graph *g, bbc_ticket *out)
     });
 }
 
+// requests of this many edges or more are copied and measured by up to
+// kSubmitThreads threads
+constexpr uint64_t kSubmitSplitEdges = 1ull << 18;
+constexpr uint32_t kSubmitThreads = 8;
+
 bbc_status bbc_submit_coo(bbc_ctx *ctx, uint32_t n_u, uint32_t n_v, uint64_t n_edges,
                           const uint32_t *eu, const uint32_t *ev, const void *sign, uint32_t flags,
                           bbc_ticket *out)
@@ -2115,24 +2185,57 @@ bbc_status bbc_submit_coo(bbc_ctx *ctx, uint32_t n_u, uint32_t n_v, uint64_t n_e
         if (n_edges && (!eu || !ev || !sign)) fail(BBC_E_INVAL, "null edge array");
         auto r = std::make_shared<Request>();
         r->n_u = n_u; r->n_v = n_v; r->m = n_edges; r->flags = flags;
-        r->eu.assign(eu, eu + n_edges);
-        r->ev.assign(ev, ev + n_edges);
+        r->eu.resize(n_edges);
+        r->ev.resize(n_edges);
         const uint8_t *sp = (const uint8_t *)sign;
         r->sign.assign(sp, sp + sign_bytes(n_edges, flags));
-        // the largest degree bounds the workspace the count needs
-        {
-            std::vector<uint32_t> du(n_u, 0), dv(n_v, 0);
-            uint32_t mx = 0;
-            for (uint64_t e = 0; e < n_edges; e++) {
-                if (eu[e] < n_u) mx = std::max(mx, ++du[eu[e]]);
-                if (ev[e] < n_v) mx = std::max(mx, ++dv[ev[e]]);
+        // The copy and the degrees (the largest bounds the workspace the count
+        // needs, their wedges its size) run on the caller's thread; a large
+        // request is split over a few threads, each with its own degree arrays.
+        // (all threads' degree arrays together take no more bytes than the
+        // copied edge endpoints)
+        const uint64_t nvx = std::max<uint64_t>(1, (uint64_t)n_u + n_v);
+        const uint32_t nt = n_edges >= kSubmitSplitEdges
+                                ? (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(
+                                      {kSubmitThreads, std::thread::hardware_concurrency(), 2 * n_edges / nvx}))
+                                : 1u;
+        std::vector<std::vector<uint32_t>> du(nt), dv(nt);
+        auto part = [&](uint32_t t) {
+            const uint64_t e0 = n_edges * t / nt, e1 = n_edges * (t + 1) / nt;
+            memcpy(r->eu.data() + e0, eu + e0, (e1 - e0) * 4);
+            memcpy(r->ev.data() + e0, ev + e0, (e1 - e0) * 4);
+            du[t].assign(n_u, 0);
+            dv[t].assign(n_v, 0);
+            uint32_t *pu = du[t].data(), *pv = dv[t].data();
+            for (uint64_t e = e0; e < e1; e++) {
+                if (eu[e] < n_u) pu[eu[e]]++;
+                if (ev[e] < n_v) pv[ev[e]]++;
             }
-            r->max_deg = mx;
-            uint64_t cu = 0, cv = 0;
-            for (uint32_t x : du) cu += (uint64_t)x * (x - (x > 0)) / 2;
-            for (uint32_t x : dv) cv += (uint64_t)x * (x - (x > 0)) / 2;
-            r->w2_max = std::max(cu, cv);
+        };
+        if (nt == 1) {
+            part(0);
+        } else {
+            std::vector<std::thread> th;
+            for (uint32_t t = 1; t < nt; t++) th.emplace_back(part, t);
+            part(0);
+            for (auto &x : th) x.join();
         }
+        uint32_t mx = 0;
+        uint64_t cu = 0, cv = 0;
+        for (uint32_t i = 0; i < n_u; i++) {
+            uint32_t x = 0;
+            for (uint32_t t = 0; t < nt; t++) x += du[t][i];
+            mx = std::max(mx, x);
+            cu += (uint64_t)x * (x - (x > 0)) / 2;
+        }
+        for (uint32_t i = 0; i < n_v; i++) {
+            uint32_t x = 0;
+            for (uint32_t t = 0; t < nt; t++) x += dv[t][i];
+            mx = std::max(mx, x);
+            cv += (uint64_t)x * (x - (x > 0)) / 2;
+        }
+        r->max_deg = mx;
+        r->w2_max = std::max(cu, cv);
         r->n_s_max = std::max(n_u, n_v);
         *out = enqueue_request(ctx, r);
     });
