@@ -2328,7 +2328,7 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
             // form in a unit whose rows have at most 256 bits, else in a tile
             // whose pairs all meet in at most 256 bits (wave-uniform tests),
             // as do masks up to 8 words always
-            const bool full = j0 + 16 <= rbase;   // every column before every row
+            const bool full = __builtin_expect(j0 + 16 <= rbase, 1);   // every column before every row
             if (full && (W <= 8 || rows_small || !__any(enc_over_255<SB>(acc)))) return cubic_sum_enc<SB>(acc);
             v4i32 d[SB];
 #pragma unroll
@@ -2339,27 +2339,25 @@ __device__ uint64_t tri_rows_fp4(const Unit &un, const AnchorRec &a,
             return cubic_sum<W, SB, true>(d, j0 + r16, rbase + 4 * g);
         }
     };
+    // Columns past un.c1 read as 0 (their buffer range ends there), so the
+    // words of the tile after next are loaded without a test.
     uint64_t sum = 0;
     uint32_t w0[NC], w1[NC];
     v4f32 acc0[SB], acc1[SB];
     uint32_t j0 = un.c0;
     col_words(j0, w0);
-    if (j0 + 16 < un.c1) col_words(j0 + 16, w1);
+    col_words(j0 + 16, w1);
     products(w0, j0, acc0);
     for (;;) {
         bool more = j0 + 16 < un.c1;
-        if (more) {
-            if (j0 + 32 < un.c1) col_words(j0 + 32, w0);
-            products(w1, j0 + 16, acc1);
-        }
+        col_words(j0 + 32, w0);
+        if (more) products(w1, j0 + 16, acc1);
         sum += epilogue(acc0, j0);
         if (!more) break;
         j0 += 16;
         more = j0 + 16 < un.c1;
-        if (more) {
-            if (j0 + 32 < un.c1) col_words(j0 + 32, w1);
-            products(w0, j0 + 16, acc0);
-        }
+        col_words(j0 + 32, w1);
+        if (more) products(w0, j0 + 16, acc0);
         sum += epilogue(acc1, j0);
         if (!more) break;
         j0 += 16;
