@@ -496,11 +496,34 @@ def test_config2_full(ctx):
         assert ctx.count_global(build(ctx, g, flags)) == gold["total"]
 
 
+def _digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i8").tobytes()).hexdigest()
+
+
+def _optional_golden(name):
+    import os
+    from tests.gpu_common import GOLD
+    p = os.path.join(GOLD, name)
+    if not os.path.exists(p):
+        return None
+    import json
+    with open(p) as f:
+        return json.load(f)
+
+
 def test_config3_full(ctx):
-    """Config 3 at full size (2M x 500k, 40M edges): per-vertex values of both
-    sides on sampled vertices against the oracle's, each side anchored on
-    itself; U- and V-anchored totals equal; per-vertex sums are 3 x total."""
+    """Config 3 at full size (2M x 500k, 40M edges).
+
+    Against the oracle, which ran Algorithm 2 over every anchor, in shards:
+    - the U-anchored total;
+    - the sha256 of all 2M per-U-vertex counts;
+    - the values of the 16 highest-degree U vertices and of 64 sampled ones;
+    - the per-vertex values of the highest-degree V vertices.
+    Also against earlier sampled per-vertex values of both sides. U- and
+    V-anchored totals must agree, and per-vertex sums must be 3 x the total."""
     gold = golden("cfg3_seed1_sample.json")
+    full = _optional_golden("cfg3_seed1_full.json")
+    vhubs = _optional_golden("cfg3_seed1_v_hubs.json")
     say("config3 full: generate")
     g = G.config3(1)
     assert g.m == gold["m"]
@@ -511,6 +534,15 @@ def test_config3_full(ctx):
         assert int(pu[int(k)]) == v, k
     assert int(pu.sum()) == 3 * tu
     assert ctx.count_global(hu) == tu
+    if full is not None:
+        say("config3 full: against the whole-graph oracle values")
+        assert full["m"] == g.m
+        assert tu == full["total"]
+        for k, v in full["per_u_hubs"].items():
+            assert int(pu[int(k)]) == v, k
+        for k, v in full["per_u_sample"].items():
+            assert int(pu[int(k)]) == v, k
+        assert _digest(pu) == full["per_u_sha256"]
     hu.free()
     say("config3 full: V anchored")
     hv = build(ctx, g, 1 << 5)
@@ -518,7 +550,32 @@ def test_config3_full(ctx):
     assert tv == tu
     for k, v in gold["per_v_sample"].items():
         assert int(pv[int(k)]) == v, k
+    if vhubs is not None:
+        for k, v in vhubs["per_v_hubs"].items():
+            assert int(pv[int(k)]) == v, k
     assert int(pv.sum()) == 3 * tu
+
+
+def test_config3_switching_invariance(ctx):
+    """A switching (signs times l(u) l(v) for any labels) and the negation of
+    every sign keep each (3,3)-biclique's balance, so they keep the count:
+    config 3 at full size with its hidden labels taken out of the signs, and
+    with all signs negated, counts the same as config 3 itself."""
+    say("config3 switching: generate")
+    g = G.config3(1)
+    lu, lv = g.meta["label_u"], g.meta["label_v"]
+    h0 = build(ctx, g, 1 << 4)
+    base = ctx.count_global(h0)
+    h0.free()
+    full = _optional_golden("cfg3_seed1_full.json")
+    if full is not None:
+        assert base == full["total"]
+    unsw = (g.sign * lu[g.eu] * lv[g.ev]).astype(np.int8)
+    for name, sg in (("unswitched", unsw), ("negated", (-g.sign).astype(np.int8))):
+        say("config3 switching:", name)
+        h = ctx.build_csr(g.n_u, g.n_v, g.eu, g.ev, sg, 1 << 4)
+        assert ctx.count_global(h) == base, name
+        h.free()
 
 
 # ------------------------------------------------- side from degree sums
