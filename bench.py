@@ -47,7 +47,6 @@ sys.path.insert(0, ROOT)
 METRIC = "triplets/s + time to exact count; batched vs per-graph; serve p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
 FP4_PEAK_TFLOPS = 10100.0     # dense fp4 matrix-core peak of MI355X
-INT8_PEAK_TOPS = 5000.0       # dense int8 matrix-core peak
 SERVE_CAP = 64 << 30          # admission cap of the served leg (bytes)
 ANCHOR_U = 1 << 4
 
@@ -348,13 +347,12 @@ def main():
 
     def roof_triplet():
         # every examined pair of candidate masks as a dense 0/1 product over
-        # its mask bits (32 per word, a multiply and an add each); masks of 3
-        # words and more run on the fp4 matrix cores, 1 and 2 words on int8
+        # its mask bits (32 per word, a multiply and an add each), all on the
+        # fp4 matrix cores
         ops = 64.0 * st["pair_words"]
         achieved = ops / (kern_avg["ms_triplet"] / 1e3) / 1e12
         return {"kernel": "triplet phase: k_triplet<0,0> + k_triplet<0,1> (dense-equivalent "
-                          "0/1 products, fp4 peak; 1-2 word masks run on int8, peak "
-                          f"{INT8_PEAK_TOPS:.0f} TOP/s)",
+                          "0/1 products on the fp4 matrix cores, fp4 peak)",
                 "bound": "mfma", "achieved": round(achieved, 2), "peak": FP4_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP4_PEAK_TFLOPS, 4),
                 "algorithmic_ops_per_launch": ops,

@@ -74,7 +74,6 @@ constexpr uint32_t kC3Max = 512;       // C(n,3) table covers masks of up to 16 
 constexpr uint32_t kRegW = 16;         // widest mask kept in registers per row
 constexpr uint32_t kWideCols = 64;     // unit width (columns) for wider masks
 constexpr uint32_t kMfmaMaxW = 16;     // widest mask counted with the rows held in registers
-constexpr int kFp4MinW = 3;            // narrowest mask counted on the fp4 matrix cores
 // Output is reserved in chunks (PairArgs::mask_chunk and cand_chunk mask words
 // and candidates per workgroup, wv_mask_chunk and wv_cand_chunk per wave of the
 // per-wave tier), sized by the host to the set's edge count so that a small
@@ -1889,17 +1888,11 @@ constexpr uint32_t kUnitGrab = 8;   // units per queue take of a triplet wave
 
 // ---------------------------------------------- matrix-core triplet path
 // The counts |M_x n M_y| of one unit form an integer matrix product of
-// 0/1 matrices (rows x mask bits times mask bits x columns), so they run on
-// the int8 matrix cores: v_mfma_i32_16x16x64_i8 multiplies a 16 x 64 by a
-// 64 x 16 int8 tile. Lane l supplies row (or column) l % 16, elements
-// 16 (l / 16) .. + 15, and receives rows 4 (l / 16) .. + 3 of column l % 16
-// of the product. A lane's 16 elements are 16 bits of one mask word, one
-// byte per bit (spread_word).
-//
-// With the accumulator started at -1 the product gives D = n - 1, and
-// n (n - 1) (n - 2) = D (D^2 - 1), zero for n <= 2 (also for padding rows
-// and columns, whose masks are zero, and for masked pairs, set to D = -1).
-// Each term is 6 C(n, 3), so a lane's sum is divided by 6 once.
+// 0/1 matrices (rows x mask bits times mask bits x columns), which runs on
+// the fp4 matrix cores (below). The totals need n (n - 1) (n - 2) =
+// D (D^2 - 1) with D = n - 1, zero for n <= 2 (also for padding rows and
+// columns, whose masks are zero, and for masked pairs, set to D = -1). Each
+// term is 6 C(n, 3), so a lane's sum is divided by 6 once.
 typedef int v4i32 __attribute__((ext_vector_type(4)));
 typedef float v4f32 __attribute__((ext_vector_type(4)));
 
@@ -2020,47 +2013,6 @@ __device__ __forceinline__ bool enc_over_255(const v4f32 (&acc)[N])
     return m > kDInit + 256.f;
 }
 
-// Lane group g feeds K-chunk t from mask word w = 2 t + (g >> 1): byte b of
-// its element register q is bit 8 b + q + 4 (g & 1) of the word, so the two
-// lane groups of a word take the low and the high nibble of each of its
-// bytes. Any one-to-one placement of the mask bits on the K positions gives
-// the same products as long as rows and columns share it; this one costs a
-// shift and a mask per register. `keep` is false past the mask width and for
-// an invalid row or column (all zero); it becomes a register mask at once, so
-// that no lane-mask register pair stays live until the bits are used.
-__device__ __forceinline__ v4i32 spread_word(uint32_t raw, uint32_t h4, bool keep)
-{
-    const uint32_t m = keep ? 0x01010101u : 0u;
-    const uint32_t x = raw >> h4;
-    v4i32 r;
-    r[0] = (int)(x & m);
-    r[1] = (int)((x >> 1) & m);
-    r[2] = (int)((x >> 2) & m);
-    r[3] = (int)((x >> 3) & m);
-    return r;
-}
-
-// The raw words of one row or column (word 2 t + (g >> 1) for chunk t) are
-// loaded unconditionally (clamped to valid words) and spread only where they
-// are used, so that a prefetch stays in flight until then.
-template <int W>
-__device__ __forceinline__ void mask_words(const uint32_t *m, uint32_t g, uint32_t (&raw)[(W + 1) / 2])
-{
-#pragma unroll
-    for (int t = 0; t < (W + 1) / 2; t++) {
-        const uint32_t w = 2 * t + (g >> 1);
-        raw[t] = m[w < (uint32_t)W ? w : (uint32_t)W - 1];
-    }
-}
-
-// chunk t of a row or column of W-word masks
-template <int W>
-__device__ __forceinline__ v4i32 mask_piece(uint32_t raw, int t, uint32_t g, bool valid)
-{
-    const uint32_t w = 2 * t + (g >> 1);
-    return spread_word(raw, 4 * (g & 1u), valid && w < (uint32_t)W);
-}
-
 // fp4 operands: v_mfma_scale_f32_16x16x128_f8f6f4 with both operands in e2m1
 // (and unit scales) multiplies 16 x 128 by 128 x 16; lane l supplies row (or
 // column) l % 16, elements 32 (l / 16) .. + 31, eight per register. One
@@ -2072,8 +2024,7 @@ __device__ __forceinline__ v4i32 mask_piece(uint32_t raw, int t, uint32_t g, boo
 // 2.0, 1.0, 0.5, 0.5. Every product of two set bits is then exactly 1 and
 // the fp32 sums are exact integers (n <= 32 W < 2^24). Columns are spread
 // once per tile and cost five instructions per word (one shift, four ands);
-// rows are spread once per unit. Each instruction covers twice the K of the
-// int8 form.
+// rows are spread once per unit.
 typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
 typedef int v8i32 __attribute__((ext_vector_type(8)));
 constexpr int kFp4 = 4;       // operand format code of e2m1 (A and B)
@@ -2113,92 +2064,6 @@ __device__ __forceinline__ v8i32 spread_row(uint32_t x)
 __device__ __forceinline__ v4f32 mfma_fp4(const v8i32 &a, const v8i32 &b, const v4f32 &c)
 {
     return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, kFp4, kFp4, 0, kScale1, 0, kScale1);
-}
-
-// Sum over the unit's pairs (j < i) of C(|M_i n M_j|, 3), masks of W words.
-// The 64 rows go in passes of SBP 16-row blocks, so that the spread row
-// operands (SBP x ceil(W/2) x 4 registers) stay in registers and each spread
-// column tile serves SBP blocks. The column tiles are software-pipelined: the products of tile t + 1 are issued
-// before the epilogue of tile t reads its accumulators (no waiting on the
-// matrix cores), and column words are loaded two tiles ahead. Every block
-// of a pass takes part in every tile (rows past the last candidate have zero
-// masks; the epilogue drops pairs with j >= i): branches around single
-// products would keep the scheduler from interleaving them with the
-// epilogue of the previous tile.
-template <int W>
-__device__ uint64_t tri_rows_mfma(const Unit &un, const AnchorRec &a,
-                                  const uint32_t *__restrict__ masks)
-{
-    constexpr int NC = (W + 1) / 2;          // 64-bit K-chunks
-    constexpr int SBP = W <= 10 ? 4 : 2;     // 16-row blocks per pass
-    const uint32_t lane = __lane_id();
-    const uint32_t g = lane >> 4, r16 = lane & 15u;
-    const uint32_t *M = masks + a.mask_off;
-    const uint32_t rbase = un.rb * kWave;
-    auto col_words = [&](uint32_t j0, uint32_t (&raw)[NC]) {
-        const uint32_t j = j0 + r16;
-        mask_words<W>(M + (uint64_t)(j < un.c1 ? j : un.c1 - 1) * W, g, raw);
-    };
-    uint64_t sum = 0;
-#pragma unroll 1
-    for (int pass = 0; pass < kWave / (16 * SBP); pass++) {
-        const uint32_t pbase = rbase + 16 * SBP * pass;
-        if (pbase >= a.k) break;
-        v4i32 A[SBP][NC];
-#pragma unroll
-        for (int sb = 0; sb < SBP; sb++) {
-            const uint32_t i = pbase + 16 * sb + r16;
-            uint32_t raw[NC];
-            mask_words<W>(M + (uint64_t)(i < a.k ? i : a.k - 1) * W, g, raw);
-#pragma unroll
-            for (int t = 0; t < NC; t++) A[sb][t] = mask_piece<W>(raw[t], t, g, i < a.k);
-        }
-        auto products = [&](const uint32_t (&raw)[NC], uint32_t j0, v4i32 (&acc)[SBP]) {
-            const bool vj = j0 + r16 < un.c1;
-#pragma unroll
-            for (int sb = 0; sb < SBP; sb++) acc[sb] = (v4i32){-1, -1, -1, -1};
-#pragma unroll
-            for (int t = 0; t < NC; t++) {
-                const v4i32 B = mask_piece<W>(raw[t], t, g, vj);
-#pragma unroll
-                for (int sb = 0; sb < SBP; sb++)
-                    acc[sb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[sb][t], B, acc[sb], 0, 0, 0);
-            }
-        };
-        // lane holds rows pbase + 16 sb + 4 g + e of column j0 + r16; only
-        // j < i counts.
-        auto epilogue = [&](const v4i32 (&acc)[SBP], uint32_t j0) -> uint32_t {
-            if (j0 + 16 <= pbase) return cubic_sum<W, SBP, false>(acc, 0, 0);
-            return cubic_sum<W, SBP, true>(acc, j0 + r16, pbase + 4 * g);
-        };
-        uint32_t w0[NC], w1[NC];
-        v4i32 acc0[SBP], acc1[SBP];
-        uint32_t j0 = un.c0;
-        col_words(j0, w0);
-        if (j0 + 16 < un.c1) col_words(j0 + 16, w1);
-        products(w0, j0, acc0);
-        for (;;) {
-            // acc0: tile j0; w1: words of tile j0 + 16
-            bool more = j0 + 16 < un.c1;
-            if (more) {
-                if (j0 + 32 < un.c1) col_words(j0 + 32, w0);
-                products(w1, j0 + 16, acc1);
-            }
-            sum += epilogue(acc0, j0);
-            if (!more) break;
-            j0 += 16;
-            // acc1: tile j0; w0: words of tile j0 + 16
-            more = j0 + 16 < un.c1;
-            if (more) {
-                if (j0 + 32 < un.c1) col_words(j0 + 32, w1);
-                products(w0, j0 + 16, acc0);
-            }
-            sum += epilogue(acc1, j0);
-            if (!more) break;
-            j0 += 16;
-        }
-    }
-    return sum / 6;
 }
 
 // The same sum on the fp4 matrix cores. Lane group g holds words
@@ -2698,19 +2563,12 @@ __global__ void __launch_bounds__(kTThreads, tri_waves(MODE, CLS)) k_triplet(Tri
                 else acc = tri_rows_wide<MODE>(un, a, T.ws.masks, colacc, T, xm, ym);
             }
         } else {
-            // only the widths of this kernel's class are instantiated
-            // the matrix cores for all but the per-vertex counts of the other
-            // side (C(n, 3) totals: fp4 from kFp4MinW words, int8 below; C(n, q)
-            // totals and anchor-side per-vertex counts: fp4 at every width)
+            // only the widths of this kernel's class are instantiated; the
+            // fp4 matrix cores for all but the per-vertex counts of the other
+            // side
             constexpr bool mc = MODE != 2;
             if (mc && a.w32 <= kMfmaMaxW) {
-#define BBC_W(n)                                                                                       \
-    case n:                                                                                            \
-        if constexpr (MODE != 0 || n >= kFp4MinW)                                                      \
-            acc = tri_rows_fp4<n, MODE>(un, a, T.ws.masks, cq, c3, colacc, xm, ym);                    \
-        else                                                                                           \
-            acc = tri_rows_mfma<n>(un, a, T.ws.masks);                                                 \
-        break;
+#define BBC_W(n) case n: acc = tri_rows_fp4<n, MODE>(un, a, T.ws.masks, cq, c3, colacc, xm, ym); break;
                 if constexpr (CLS == 0) {
                     switch (a.w32) { BBC_W(1) BBC_W(2) BBC_W(3) BBC_W(4) default: break; }
                 } else {
