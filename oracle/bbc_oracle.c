@@ -321,6 +321,18 @@ typedef struct {
     uint64_t candidates; /* pairs A enumerated from C */
 } tally_t;
 
+/* Optional watch list of opposite-side vertices. A balanced (3,3)-biclique
+ * found at anchor u from the pair (w1, w2) takes its three opposite vertices
+ * from one wedge-type class of T (Lemma 1), so a watched vertex v of T in the
+ * class of x_k members lies in C(x_k - 1, 2) of the C(x_k, 3) bicliques of
+ * that class. Summed over all anchors and pairs, this is the number of
+ * balanced (3,3)-bicliques that contain v. */
+typedef struct {
+    const int32_t *idx;  /* per opposite vertex: its index in the watch list, or -1 */
+    i128 *tally;         /* per watched vertex (this thread's part) */
+    int32_t *hit;        /* scratch: (watch index, wedge type) of the watched members of T */
+} watch_t;
+
 /* Optional record of one anchor's intermediate values (for the worked
  * example of Fig. 4): the candidate set C and, for every pair A of C, |T| and
  * the type histogram x. */
@@ -359,7 +371,7 @@ static void scratch_free(scratch_t *w)
  * every balanced biclique containing u exactly once. per_s (optional) gets
  * each counted biclique's contribution added to u, w1 and w2. */
 static void bbvp_anchor(const graph_t *g, uint32_t u, int oriented, scratch_t *w, tally_t *t,
-                        i128 *per_s, trace_t *tr, int q)
+                        i128 *per_s, trace_t *tr, int q, watch_t *wt)
 {
 #if ORC_MUTANT == 4
     const int q_prune = q + 1;
@@ -435,6 +447,7 @@ static void bbvp_anchor(const graph_t *g, uint32_t u, int oriented, scratch_t *w
             t->candidates++;
             uint64_t x[4] = {0, 0, 0, 0};
             uint64_t size_t_ = 0;
+            int64_t n_hit = 0;
             for (int64_t b = w->l_off[j]; b < w->l_off[j + 1]; b++) {
                 const int8_t s_w1v = w->mark[w->l_pos[b]];
                 if (!s_w1v) continue;   /* v not in L[w1] */
@@ -445,6 +458,10 @@ static void bbvp_anchor(const graph_t *g, uint32_t u, int oriented, scratch_t *w
 #endif
                 x[kappa]++;
                 size_t_++;
+                if (wt) {
+                    const int32_t h = wt->idx[g->adj_s[g->off_s[u] + w->l_pos[b]]];
+                    if (h >= 0) { wt->hit[2 * n_hit] = h; wt->hit[2 * n_hit + 1] = kappa; n_hit++; }
+                }
             }
             if (tr && tr->n_pairs < tr->cap_pairs) {
                 int64_t *r = tr->pairs + 7 * tr->n_pairs++;
@@ -460,6 +477,10 @@ static void bbvp_anchor(const graph_t *g, uint32_t u, int oriented, scratch_t *w
             for (int k = 0; k < 4; k++) add += q == 3 ? (i128)choose3(x[k]) : choose_k(x[k], q);
 #endif
             t->total += add;
+            for (int64_t h = 0; h < n_hit; h++) {
+                const uint64_t r = x[wt->hit[2 * h + 1]] - 1;   /* the other members of v's class */
+                wt->tally[wt->hit[2 * h]] += (i128)(r * (r - (r > 0)) / 2);
+            }
             if (per_s && add) {
                 per_s[u] += add;
                 per_s[w->cand[i]] += add;
@@ -638,6 +659,10 @@ typedef struct {
     int p, q;
     tally_t tally;
     i128 *per_s;             /* shared per-vertex, merged under the lock */
+    const int32_t *watch_idx;  /* optional watch list (watch_t), NULL for none */
+    int64_t n_watch;
+    i128 *watch_tally;       /* merged under the lock */
+    const uint8_t *anchor_on;  /* optional: only anchors u with anchor_on[u] != 0 */
 } job_t;
 
 static void *worker(void *arg)
@@ -649,6 +674,13 @@ static void *worker(void *arg)
     tally_t t = {0, 0, 0};
     i128 *per = NULL;
     if (jb->want_per_vertex) per = calloc(g->n_s + 1, sizeof(i128));
+    watch_t wv, *wt = NULL;
+    if (jb->watch_idx) {
+        wv.idx = jb->watch_idx;
+        wv.tally = calloc(jb->n_watch + 1, sizeof(i128));
+        wv.hit = malloc(sizeof(int32_t) * 2 * (jb->n_watch + 1));
+        wt = &wv;
+    }
     const int64_t chunk = 64;
     for (;;) {
         pthread_mutex_lock(&jb->lock);
@@ -659,9 +691,10 @@ static void *worker(void *arg)
         int64_t end = begin + chunk < g->n_s ? begin + chunk : g->n_s;
         for (int64_t u = begin; u < end; u++) {
             if (u % jb->stride != jb->residue) continue;
+            if (jb->anchor_on && !jb->anchor_on[u]) continue;
             if (jb->p == 4) bbvp_anchor_p4(g, (uint32_t)u, &w, &t, jb->q);
             else if (jb->p > 4 || jb->p < 0) bbvp_anchor_dense(g, (uint32_t)u, &w, &t, jb->p < 0 ? -jb->p : jb->p, jb->q);
-            else bbvp_anchor(g, (uint32_t)u, 1, &w, &t, per, NULL, jb->q);
+            else bbvp_anchor(g, (uint32_t)u, 1, &w, &t, per, NULL, jb->q, wt);
         }
     }
     pthread_mutex_lock(&jb->lock);
@@ -669,8 +702,10 @@ static void *worker(void *arg)
     jb->tally.feasible += t.feasible;
     jb->tally.candidates += t.candidates;
     if (per) for (int64_t i = 0; i < g->n_s; i++) jb->per_s[i] += per[i];
+    if (wt) for (int64_t i = 0; i < jb->n_watch; i++) jb->watch_tally[i] += wt->tally[i];
     pthread_mutex_unlock(&jb->lock);
     free(per);
+    if (wt) { free(wv.tally); free(wv.hit); }
     scratch_free(&w);
     return NULL;
 }
@@ -694,7 +729,8 @@ static void *worker(void *arg)
 static int count_bbvp_part(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
                            const uint32_t *ev, const int8_t *sign, int side, int n_threads,
                            int64_t anchor_stride, int64_t residue, int q, uint64_t *out_total,
-                           uint64_t *out_stats, int64_t *per_vertex)
+                           uint64_t *out_stats, int64_t *per_vertex, int64_t n_watch,
+                           const uint32_t *watch, const uint8_t *anchor_on, uint64_t *watch_out)
 {
     if (q < 3 || q > 7) return -1;
     if (anchor_stride < 1) anchor_stride = 1;
@@ -713,12 +749,33 @@ static int count_bbvp_part(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *
     jb.q = q;
     pthread_mutex_init(&jb.lock, NULL);
     if (per_vertex) jb.per_s = calloc(g.n_s + 1, sizeof(i128));
+    int32_t *widx = NULL;
+    if (watch && n_watch > 0) {
+        widx = malloc(sizeof(int32_t) * (g.n_o + 1));
+        for (int64_t i = 0; i < g.n_o; i++) widx[i] = -1;
+        for (int64_t i = 0; i < n_watch; i++) {
+            if ((int64_t)watch[i] >= g.n_o || widx[watch[i]] >= 0) { free(widx); free(jb.per_s); free_graph(&g); return -1; }
+            widx[watch[i]] = (int32_t)i;
+        }
+        jb.watch_idx = widx;
+        jb.n_watch = n_watch;
+        jb.watch_tally = calloc(n_watch, sizeof(i128));
+    }
+    jb.anchor_on = anchor_on;
     pthread_t *th = malloc(sizeof(pthread_t) * n_threads);
     for (int i = 0; i < n_threads; i++) pthread_create(&th[i], NULL, worker, &jb);
     for (int i = 0; i < n_threads; i++) pthread_join(th[i], NULL);
     free(th);
     pthread_mutex_destroy(&jb.lock);
     int rc = 0;
+    if (widx) {
+        for (int64_t i = 0; i < n_watch; i++) {
+            watch_out[2 * i] = (uint64_t)jb.watch_tally[i];
+            watch_out[2 * i + 1] = (uint64_t)(jb.watch_tally[i] >> 64);
+        }
+        free(jb.watch_tally);
+        free(widx);
+    }
     out_total[0] = (uint64_t)jb.tally.total;
     out_total[1] = (uint64_t)(jb.tally.total >> 64);
     if (out_stats) {
@@ -781,7 +838,7 @@ int orc_count_bbvp_q(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
                      int64_t *per_vertex)
 {
     return count_bbvp_part(n_u, n_v, m, eu, ev, sign, side, n_threads, anchor_stride, 0, q,
-                           out_total, out_stats, per_vertex);
+                           out_total, out_stats, per_vertex, 0, NULL, NULL, NULL);
 }
 
 int orc_count_bbvp_shard(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
@@ -790,7 +847,27 @@ int orc_count_bbvp_shard(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu
                          uint64_t *out_stats, int64_t *per_vertex)
 {
     return count_bbvp_part(n_u, n_v, m, eu, ev, sign, side, n_threads, n_shards, shard, 3,
-                           out_total, out_stats, per_vertex);
+                           out_total, out_stats, per_vertex, 0, NULL, NULL, NULL);
+}
+
+/* orc_count_bbvp_shard with a watch list of n_watch distinct opposite-side
+ * vertices (watch_t): watch_out gets, per watched vertex, the number of
+ * balanced (3,3)-bicliques that contain it and whose anchor is in this shard
+ * (128-bit, words lo, hi). anchor_on (optional, one byte per anchor-side
+ * vertex) skips the anchors it marks 0; a biclique that contains a watched
+ * vertex v is anchored at a neighbour of v, so keeping the neighbours of the
+ * watched vertices keeps every contribution to watch_out. Returns 0, or -1
+ * on a bad edge list, shard or watch list. */
+int orc_count_bbvp_watch(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu,
+                         const uint32_t *ev, const int8_t *sign, int side, int n_threads,
+                         int64_t n_shards, int64_t shard, int64_t n_watch, const uint32_t *watch,
+                         const uint8_t *anchor_on, uint64_t *out_total, uint64_t *out_stats,
+                         uint64_t *watch_out)
+{
+    if (side != 0 && side != 1) return -1;
+    if (n_watch < 1 || !watch || !watch_out) return -1;
+    return count_bbvp_part(n_u, n_v, m, eu, ev, sign, side, n_threads, n_shards, shard, 3,
+                           out_total, out_stats, NULL, n_watch, watch, anchor_on, watch_out);
 }
 
 int orc_count_bbvp(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu, const uint32_t *ev,
@@ -817,7 +894,7 @@ int orc_vertex_counts(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu, c
     for (int64_t i = 0; i < n_x; i++) {
         if ((int64_t)xs[i] >= g.n_s) { rc = -1; break; }
         tally_t t = {0, 0, 0};
-        bbvp_anchor(&g, xs[i], 0, &w, &t, NULL, NULL, 3);
+        bbvp_anchor(&g, xs[i], 0, &w, &t, NULL, NULL, 3, NULL);
         out_counts[2 * i] = (uint64_t)t.total;
         out_counts[2 * i + 1] = (uint64_t)(t.total >> 64);
     }
@@ -843,7 +920,7 @@ int orc_anchor_detail(int64_t n_u, int64_t n_v, int64_t m, const uint32_t *eu, c
     scratch_init(&w, &g);
     trace_t tr = {cap_c, 0, cand, cap_pairs, 0, pairs};
     tally_t t = {0, 0, 0};
-    bbvp_anchor(&g, u, oriented, &w, &t, NULL, &tr, 3);
+    bbvp_anchor(&g, u, oriented, &w, &t, NULL, &tr, 3, NULL);
     *n_cand = tr.n_c;
     *n_pairs = tr.n_pairs;
     out_total[0] = (uint64_t)t.total;

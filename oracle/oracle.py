@@ -77,6 +77,11 @@ def _bind(L):
                                        _u32p, _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                        ctypes.c_int64, _u64p, _u64p, _i64p]
     L.orc_count_bbvp_shard.restype = ctypes.c_int
+    L.orc_count_bbvp_watch.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _u32p,
+                                       _u32p, _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                       ctypes.c_int64, ctypes.c_int64, _u32p,
+                                       ctypes.POINTER(ctypes.c_uint8), _u64p, _u64p, _u64p]
+    L.orc_count_bbvp_watch.restype = ctypes.c_int
     L.orc_count_bbvp_q.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _u32p, _u32p,
                                    _i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                    _u64p, _u64p, _i64p]
@@ -190,6 +195,45 @@ def count_bbvp_shard(g, side: int, n_shards: int, shard: int, threads: int = 1,
     if per_vertex:
         res["per_vertex"] = pv[:n_side].copy()
     return res
+
+
+def count_bbvp_watch(g, side: int, watch, n_shards: int = 1, shard: int = 0, threads: int = 1,
+                     anchor_on=None) -> dict:
+    """count_bbvp_shard with a watch list of distinct vertices of the opposite
+    side: for each, the number of balanced (3,3)-bicliques that contain it and
+    are anchored in this shard (Lemma 1: a watched vertex in the wedge-type
+    class of x members lies in C(x - 1, 2) of its class's bicliques).
+    anchor_on: optional boolean array over the anchor side; anchors marked
+    False are skipped (every biclique through a watched vertex is anchored at
+    one of its neighbours).
+
+    Returns dict(total, feasible, candidates, side, watch=[int per vertex])."""
+    w = np.ascontiguousarray(np.asarray(watch, dtype=np.uint32))
+    if w.size == 0:
+        r = count_bbvp_shard(g, side, n_shards, shard, threads)
+        r["watch"] = []
+        return r
+    eu, ev, sg = _arrs(g)
+    out = np.zeros(2, np.uint64)
+    st = np.zeros(3, np.uint64)
+    wo = np.zeros(2 * max(w.size, 1), np.uint64)
+    on = None
+    if anchor_on is not None:
+        on = np.ascontiguousarray(np.asarray(anchor_on, dtype=np.uint8))
+        n_side = g.n_v if side == 1 else g.n_u
+        if on.size != n_side:
+            raise ValueError("anchor_on needs one entry per anchor-side vertex")
+    rc = lib().orc_count_bbvp_watch(g.n_u, g.n_v, eu.size, _p(eu, _u32p), _p(ev, _u32p),
+                                    _p(sg, _i8p), side, threads, n_shards, shard, w.size,
+                                    _p(w, _u32p),
+                                    on.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+                                    if on is not None else None,
+                                    _p(out, _u64p), _p(st, _u64p), _p(wo, _u64p))
+    if rc != 0:
+        raise ValueError(f"orc_count_bbvp_watch failed ({rc})")
+    total = int(out[0]) | (int(out[1]) << 64)
+    return {"total": total, "feasible": int(st[0]), "candidates": int(st[1]), "side": int(st[2]),
+            "watch": [int(wo[2 * i]) | (int(wo[2 * i + 1]) << 64) for i in range(w.size)]}
 
 
 def count_bbvp_q(g, q: int, side: int = 0, threads: int = 1, anchor_stride: int = 1) -> dict:

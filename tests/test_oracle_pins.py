@@ -189,6 +189,37 @@ def test_bruteforce_equals_bbvp_denser(oracle):
         assert oracle.count_bbvp(g, 1)["total"] == b
 
 
+def test_watch_list_counts_the_opposite_side(oracle):
+    """Opposite-side watch lists of the anchored run: on random tiny graphs each
+    watched V vertex gets the definition's per-vertex count (brute force),
+    from U anchors; the anchors' neighbours alone, and the shards summed, give
+    the same values; on K_{n,m} every V vertex lies in C(m - 1, 2) C(n, 3)
+    bicliques."""
+    rng = np.random.default_rng(77)
+    for it in range(400):
+        g = G.tiny_random(rng, 8, 8)
+        b, pu, pv = oracle.count_bruteforce(g, per_vertex=True)
+        ids = list(range(g.n_v))
+        r = oracle.count_bbvp_watch(g, 0, ids)
+        assert r["total"] == b and r["watch"] == [int(x) for x in pv], it
+    g = G.config1(3)
+    ids = [int(x) for x in np.argsort(-np.bincount(g.ev, minlength=g.n_v), kind="stable")[:12]]
+    whole = oracle.count_bbvp_watch(g, 0, ids, threads=4)
+    assert whole["watch"] == oracle.vertex_counts(g, 1, ids)
+    on = np.zeros(g.n_u, bool)
+    on[np.unique(g.eu[np.isin(g.ev, ids)])] = True
+    near = oracle.count_bbvp_watch(g, 0, ids, threads=4, anchor_on=on)
+    assert near["watch"] == whole["watch"] and near["total"] < whole["total"]
+    parts = [oracle.count_bbvp_watch(g, 0, ids, n_shards=5, shard=r, threads=2) for r in range(5)]
+    assert [sum(p["watch"][i] for p in parts) for i in range(len(ids))] == whole["watch"]
+    n, m = 9, 7
+    u, v = np.divmod(np.arange(n * m, dtype=np.int64), m)
+    kg = G._finish(n, m, u, v, np.ones(n * m, np.int8))
+    assert oracle.count_bbvp_watch(kg, 0, list(range(m)))["watch"] == [math.comb(m - 1, 2) * C3(n)] * m
+    with pytest.raises(ValueError):
+        oracle.count_bbvp_watch(kg, 0, [0, 0])
+
+
 def test_vertex_counts_match_per_vertex(oracle):
     g = G.config1(3)
     for side in (0, 1):
