@@ -420,6 +420,25 @@ def test_config4_batch(ctx, oracle):
     assert sum(want) > 0
 
 
+def test_config4_full_batch(ctx):
+    """All 8192 graphs of config 4 seed 1 in one batch (3.3e8 edges), built
+    and counted once and replayed, against the oracle's stored per-graph
+    counts (their sum and the sha256 of the int64 array)."""
+    gold = golden("cfg4_seed1.json")
+    say("config4 full batch: generate")
+    gs = G.config4(1, n_graphs=gold["n_graphs"])
+    want = np.array(gold["counts"], np.int64)
+    nu, nv, off, eu, ev, sg = G.concat(gs)
+    say("config4 full batch: build and count")
+    hs = ctx.build_csr_batch(nu, nv, off, eu, ev, sg)
+    got = np.asarray(ctx.count_batch(hs), np.int64)
+    assert (got == want).all()
+    assert int(got.sum()) == gold["sum"] and _digest(got) == gold["sha256"]
+    assert (np.asarray(ctx.count_batch(hs), np.int64) == want).all()
+    for h in hs:
+        h.free()
+
+
 def test_batch_rebuild_cycles(ctx, oracle):
     """Regression: batches built, counted, freed and rebuilt (new device
     buffers each time) must not replay a launch captured for an earlier
