@@ -37,11 +37,13 @@ def submit_all(ctx, gs):
 # GPU twice: an allocation that failed inside the count workspace's sizing
 # left a stale capacity beside a null buffer, and the worker's retry of each
 # request alone counted through that null buffer. The sizing now clears a
-# capacity before reallocating it; the case stays off the GPU until the next
-# round, as its fix has not been run there.
+# capacity before reallocating it, but these two cases, which make
+# allocations fail under the cap on purpose, are kept off the GPU: their fix
+# has not run there. The cap is exercised instead by the two tests at the end
+# of this file, whose allocations stay far below it.
 CAP_CASE_SKIP = pytest.mark.skip(
-    reason="faulted the GPU before the stale-capacity fix in ensure_work; held off the GPU "
-           "until its fix is tested in a later session")
+    reason="faulted the GPU before the stale-capacity fix in ensure_work; kept off the GPU "
+           "(allocation failures under the cap are not run there)")
 
 
 @CAP_CASE_SKIP
@@ -185,3 +187,78 @@ def test_large_requests_counted_in_anchor_ranges(B, mix):
             assert ctx.wait(tp) == gold["total"] + preload
             h.free()
         ctx.set_test_hook(B.BBC_HOOK_PRELOAD_COUNT, 0)
+
+
+def _complete(n):
+    """K_{n,n} with every sign +1, as COO: C(n, 3)^2 balanced (3,3)-bicliques."""
+    u, v = np.divmod(np.arange(n * n, dtype=np.int64), n)
+    return G._finish(n, n, u, v, np.ones(n * n, np.int8))
+
+
+def _c3(n):
+    return n * (n - 1) * (n - 2) // 6
+
+
+def test_cap_admits_large_requests_one_at_a_time(B, mix):
+    """The cap binds: a cap is chosen so that one K_{1024,1024} request
+    (2^20 edges, a batch of its own) fits under it beside the workers' kept
+    workspaces and two do not, although two large requests may otherwise be
+    in flight together. Three of them among 40 small requests are then
+    admitted one at a time and every count equals its closed form or the
+    oracle's. Each reservation is an upper bound of what its batch allocates,
+    with a wide margin here, so no allocation meets the cap."""
+    gs, want = mix
+    kn = _complete(1024)
+    want_k = _c3(1024) ** 2
+    # the reservation of one such request, read on a context whose cap
+    # admits everything
+    with B.Context(0, mem_cap=64 << 30) as ctx:
+        say("one large request under a 64 GiB cap")
+        assert ctx.wait(ctx.submit_coo(kn.n_u, kn.n_v, kn.eu, kn.ev, kn.sign)) == want_k
+        one = ctx.memory_stats()["serve_peak_admitted_bytes"]
+    assert one > 0
+    # admission room = cap - 4 x cap / 16 (the kept-workspace allowance of the
+    # four workers) = 1.5 reservations of one large request
+    cap = -(-2 * one // MiB) * MiB
+    room = cap - 4 * (cap // 16)
+    assert one <= room < 2 * one
+    with B.Context(0, mem_cap=cap) as ctx:
+        say("three large requests under a cap of", cap >> 20, "MiB")
+        order = list(range(40)) + [-1, -2, -3]
+        np.random.default_rng(11).shuffle(order)
+        tickets = []
+        for i in order:
+            g = kn if i < 0 else gs[i]
+            tickets.append((i, ctx.submit_coo(g.n_u, g.n_v, g.eu, g.ev, g.sign)))
+        for i, t in tickets:
+            assert ctx.wait(t) == (want_k if i < 0 else want[i])
+        m = ctx.memory_stats()
+        say("memory", m)
+        assert m["cap_bytes"] == cap
+        assert one <= m["serve_peak_admitted_bytes"] <= room
+        assert m["peak_reserved_bytes"] <= cap
+        assert m["serve_admitted_bytes"] == 0 and m["serve_queued"] == 0
+
+
+def test_request_over_cap_rejected_at_admission(B, mix):
+    """A request whose reservation alone passes the cap (K_{2048,2048}: 4.2M
+    edges and 4.3e9 oriented wedges, more than 10 GB of count workspace
+    reserved, under a 4 GiB cap) fails with BBC_E_NOMEM before anything is
+    allocated for it; the small requests submitted before and after it
+    complete with the oracle's counts. Counted without a cap, the same
+    request returns C(2048, 3)^2."""
+    gs, want = mix
+    kn = _complete(2048)
+    with B.Context(0, mem_cap=4 << 30) as ctx:
+        say("request over the cap")
+        before = [ctx.submit_coo(g.n_u, g.n_v, g.eu, g.ev, g.sign) for g in gs[:30]]
+        tb = ctx.submit_coo(kn.n_u, kn.n_v, kn.eu, kn.ev, kn.sign)
+        after = [ctx.submit_coo(g.n_u, g.n_v, g.eu, g.ev, g.sign) for g in gs[30:60]]
+        with pytest.raises(B.BBCError) as ei:
+            ctx.wait(tb)
+        assert ei.value.name == "BBC_E_NOMEM"
+        assert [ctx.wait(t) for t in before + after] == want[:60]
+        assert ctx.memory_stats()["peak_reserved_bytes"] <= 4 << 30
+    with B.Context(0) as ctx:
+        say("the same request without a cap")
+        assert ctx.wait(ctx.submit_coo(kn.n_u, kn.n_v, kn.eu, kn.ev, kn.sign)) == _c3(2048) ** 2
