@@ -21,6 +21,8 @@ Also reported on the same JSON line:
                  algorithmic HBM bytes (4.25 B per oriented 2-hop wedge)
   cpu_baseline   the CPU oracle on a bounded sample of config 3, all host
                  threads of this process
+  cpu_single_thread  the oracle on one thread: config 1, and the first 256
+                 graphs of config 4 one by one
   config2        config 2 (100k x 50k, 2M edges) build + global count + the
                  per-U-vertex counts, checked against the oracle's values
   batched        the 8192-graph batch (one build + one persistent,
@@ -30,6 +32,8 @@ Also reported on the same JSON line:
                  graphs under a 64 GiB admission cap: p50 / p99 latency
                  (all requests, and small and config-2 sized ones apart),
                  graphs/s, counts checked against the oracle's
+  served_load_sweep  the same stream at 0.5, 0.8 and 0.95 of the measured
+                 capacity (half as many requests each)
 """
 import argparse
 import hashlib
@@ -135,6 +139,29 @@ def cpu_baseline(g, stride, threads):
                       f"(os.cpu_count {os.cpu_count()}); {r['feasible']} triplets, "
                       f"{r['candidates']} candidate pairs, {dt:.1f} s including the oracle's "
                       f"CSR build"}
+
+
+def cpu_single_thread(gs4):
+    """The oracle on one thread: config 1 seed 1, and the first 256 graphs of
+    config 4 seed 1 one by one (each with its own CSR build)."""
+    from oracle import oracle as O
+    from paper_2605_03603_amd import generators as G
+    O.use_library(O.build(native=True))
+    g1 = G.config1(1)
+    t = time.time()
+    r1 = O.count_bbvp(g1, side=0, threads=1)
+    dt1 = time.time() - t
+    t = time.time()
+    feas = 0
+    for g in gs4:
+        feas += O.count_bbvp(g, side=0, threads=1)["feasible"]
+    dt4 = time.time() - t
+    return {"cores": 1, "kind": "oracle", "cpu": cpu_model(),
+            "config1": {"ms": round(1e3 * dt1, 3), "count": r1["total"],
+                        "triplets_per_s": round(r1["feasible"] / dt1, 1)},
+            "config4_first_256": {"s": round(dt4, 3), "graphs_per_s": round(len(gs4) / dt4, 1),
+                                  "edges": int(sum(g.m for g in gs4)),
+                                  "triplets_per_s": round(feas / dt4, 1)}}
 
 
 def run_batched(ctx, gs, torch, want):
@@ -458,10 +485,14 @@ def main():
         log("cpu baseline: oracle on every", args.cpu_stride, "th anchor,", threads, "threads")
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_stride, threads)
 
-    if not args.no_batched or not args.no_serve:
+    if not args.no_batched or not args.no_serve or not args.no_cpu:
         gold4 = load_json("cfg4_seed1.json")
         log("generating", args.batch_graphs, "batched graphs")
         gs = G.config4(1, n_graphs=args.batch_graphs)
+    if not args.no_cpu:
+        log("cpu baseline, one thread: config 1 and 256 graphs of config 4")
+        out["cpu_single_thread"] = cpu_single_thread(gs[:256])
+    if not args.no_batched or not args.no_serve:
         want4 = None
         if gold4 is not None and len(gs) == gold4["n_graphs"]:
             want4 = np.array(gold4["counts"], np.int64)
@@ -481,6 +512,16 @@ def main():
             sctx = bbc.Context(0, mem_cap=SERVE_CAP)
             out["served"] = run_served(sctx, gs, pool_counts, [g2], [gold2["total"]],
                                        args.serve_requests, qps, 1)
+            # the same stream at other offered loads (fewer requests each)
+            sweep = []
+            for frac in (0.5, 0.8, 0.95):
+                log("serving at", frac, "of capacity")
+                r = run_served(sctx, gs, pool_counts, [g2], [gold2["total"]],
+                               max(args.serve_requests // 2, 1), frac / per_req_s, 2)
+                sweep.append({"load": frac, **{k: r[k] for k in ("offered_qps", "graphs_per_s",
+                                                                 "p50_ms", "p99_ms", "max_ms",
+                                                                 "wrong_counts")}})
+            out["served_load_sweep"] = sweep
             sctx.close()
     ctx.close()
     print(json.dumps(out))
