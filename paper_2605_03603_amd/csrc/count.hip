@@ -38,6 +38,7 @@
 // i % 8): a workgroup drains its own slice first, so consecutive anchors
 // and the units of one anchor share an L2, then steals from the others.
 #include "bbc_count.h"
+#include <type_traits>
 
 namespace bbc {
 
@@ -2296,7 +2297,11 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
         for (int sb = 0; sb < 4; sb++)
             acc[tt][sb] = MODE == 0 ? (v4f32){kDInit, kDInit, kDInit, kDInit} : (v4f32){0.f, 0.f, 0.f, 0.f};
     const uint32_t Wf = W & ~(KW - 1);
-    for (uint32_t w0 = 0; w0 < Wf; w0 += KW) {
+    // One K-block of 16 words. NTC is the number of column tiles when it is
+    // known at compile time (4: a full unit, the common case, whose K-block
+    // then has no branches), else 0 and the unit's nt is tested per tile.
+    auto kblock = [&](uint32_t w0, auto ntc) {
+        constexpr int NTC = decltype(ntc)::value;
         const Rsrc rr = mask_rsrc(M + w0, rbytes - 4u * w0), rc_ = mask_rsrc(M + w0, cbytes - 4u * w0);
         uint32_t ra[4][4], rc[4][4];
 #pragma unroll
@@ -2317,7 +2322,7 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
         }
 #pragma unroll
         for (int tt = 0; tt < 4; tt++) {
-            if ((uint32_t)tt >= nt) break;
+            if (NTC == 0 && (uint32_t)tt >= nt) break;
             const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(rc_, (int)co[tt], 0, 0);
             rc[tt][0] = v.x; rc[tt][1] = v.y; rc[tt][2] = v.z; rc[tt][3] = v.w;
         }
@@ -2328,12 +2333,17 @@ __device__ uint64_t tri_rows_mfma_wide(const Unit &un, const AnchorRec &a,
             for (int sb = 0; sb < 4; sb++) A[sb] = spread_row(ra[sb][t]);
 #pragma unroll
             for (int tt = 0; tt < 4; tt++) {
-                if ((uint32_t)tt >= nt) break;
+                if (NTC == 0 && (uint32_t)tt >= nt) break;
                 const v8i32 B = spread_col(rc[tt][t]);
 #pragma unroll
                 for (int sb = 0; sb < 4; sb++) acc[tt][sb] = mfma_fp4(A[sb], B, acc[tt][sb]);
             }
         }
+    };
+    if (nt == 4) {
+        for (uint32_t w0 = 0; w0 < Wf; w0 += KW) kblock(w0, std::integral_constant<int, 4>{});
+    } else {
+        for (uint32_t w0 = 0; w0 < Wf; w0 += KW) kblock(w0, std::integral_constant<int, 0>{});
     }
     // the last W mod 16 words by chunks of four: lane group g takes word
     // w + g, at byte offset ro - 12 g from the chunk's first word; a word at
