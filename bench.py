@@ -19,6 +19,8 @@ Also reported on the same JSON line:
   roofline       the dominant phase of a step, priced against its bound
   roofline_other_phases  the other phases; the pair phase is priced by its
                  algorithmic HBM bytes (4.25 B per oriented 2-hop wedge)
+  per_triplet    algorithmic HBM bytes, candidate pairs examined and
+                 dense-equivalent matrix operations per feasible triplet
   cpu_baseline   the CPU oracle on a bounded sample of config 3, all host
                  threads of this process
   cpu_single_thread  the oracle on one thread: config 1, and the first 256
@@ -443,6 +445,13 @@ def main():
         "step_algorithmic_hbm": {"bytes": 17.5 * g.m + 4.25 * w2, "achieved_gbs": round(whole_gbs, 1),
                                  "frac": round(whole_gbs / HBM_PEAK_GBS, 4)},
     }
+    if triplets:
+        # the work of the method per unit of output (a feasible triplet)
+        out["per_triplet"] = {
+            "algorithmic_hbm_bytes": round((17.5 * g.m + 4.25 * w2) / triplets, 4),
+            "candidate_pairs": round(st["candidate_pairs"] / triplets, 3),
+            "dense_equivalent_matrix_ops": round(64.0 * st["pair_words"] / triplets, 1),
+        }
     d_eu = d_ev = d_sg = None
 
     if not args.no_config2:
