@@ -87,7 +87,7 @@ constexpr int kUnroll = 4;              // independent neighbour-list loads per 
 constexpr int kRThreads = 1024;
 constexpr uint32_t kRWin = 1u << 17;
 constexpr uint32_t kRWords = 38912;
-constexpr uint32_t kRMinWedges = 32768;
+constexpr uint32_t kRMinWedges = 16384;
 constexpr int kListR = 4;               // index of its anchor list (defer[], n_list[])
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t x, int log2h)

@@ -1,6 +1,6 @@
 """GPU parity of the rank-window pair tier.
 
-Heavy anchors (at least 32768 wedges) whose partners all rank within 2^17
+Heavy anchors (at least 16384 wedges) whose partners all rank within 2^17
 above them are counted with a table indexed by partner rank instead of a hash
 table. Each case is checked against a closed form or the CPU oracle, and
 against the same graph counted with the rank-window tier switched off (the
@@ -117,7 +117,7 @@ def test_window_tier_per_vertex_closed_form(ctx):
 
 def test_window_tier_vs_oracle(ctx, B, oracle):
     """A dense random signed graph (700 x 400, edge probability 0.5, 80%
-    positive): about half of the U anchors reach 32768 wedges. Totals on both
+    positive): about three quarters of the U anchors reach 16384 wedges. Totals on both
     anchor sides and per-vertex counts of both sides against the oracle."""
     g = dense(1)
     say("window tier vs oracle: oracle")
