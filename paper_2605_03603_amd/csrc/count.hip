@@ -1885,7 +1885,7 @@ __device__ uint64_t tri_rows_wide(const Unit &un, const AnchorRec &a,
 
 constexpr int kTThreads = 256;
 constexpr uint32_t kMaxChunk = 2048;
-constexpr uint32_t kUnitGrab = 8;   // units per queue take of a triplet wave
+constexpr uint32_t kUnitGrab = 4;   // units per queue take of a triplet wave
 
 // ---------------------------------------------- matrix-core triplet path
 // The counts |M_x n M_y| of one unit form an integer matrix product of
