@@ -358,10 +358,11 @@ struct Work {
     }
 };
 
-// Launch shape. The defaults, measured on config 3 (2M x 500k, 40M edges) and
-// config 2 (100k x 50k, 2M edges): a unit column base of 4096 against 2048
-// is 2.3% faster on config 3 and neutral on config 2; 4 triplet workgroups
-// per compute unit against 6 are 2% faster on config 2 and neutral on config 3.
+// Launch shape. The defaults, measured on the Chung-Lu graphs of 2M x 500k
+// vertices and 40M edges and of 100k x 50k vertices and 2M edges: a unit
+// column base of 4096 against 2048 is 2.3% faster on the larger and neutral
+// on the smaller; 4 triplet workgroups per compute unit against 6 are 2%
+// faster on the smaller and neutral on the larger.
 struct Shape {
     uint32_t chunk_base = 4096;
     uint32_t grid_a_per_cu = 2;
@@ -1021,8 +1022,9 @@ LaunchArgs make_args(bbc_ctx *ctx, Work &w, const CountReq &r, const Shape &shp)
     // The totals of one graph with 2^32 or more oriented wedges take units twice
     // as long unless the caller forced a shape: with anchors of thousands of
     // candidates, the longer units spread each row once for more columns
-    // (config 3, 40M edges: triplets 508 -> 504 ms; config 2, 3.3e8 wedges,
-    // measured 6% slower in its triplet phase and keeps the default).
+    // (the 40M-edge Chung-Lu graph, 1.5e10 wedges: triplets 508 -> 504 ms;
+    // the 2M-edge one, 3.3e8 wedges, measured 6% slower in its triplet phase
+    // and keeps the default).
     if (r.mode == 0 && !ctx->hook_shape_set && set.G == 1 && shp.chunk_base == Shape().chunk_base &&
         set.wedges_o >= (1ull << 32))
         L.P.chunk_base = 2 * shp.chunk_base;
